@@ -1,0 +1,215 @@
+"""Benchmark: CP-ALS-QR sweeps per second on one MI355X.
+
+Workload: dense 1000 x 1000 x 1000 FP32 tensor (4 GB) with a rank-16 ground
+truth whose factor columns have pairwise congruence 0.99, plus 1e-3 relative
+Gaussian noise; CP-ALS-QR at rank 16 from a seeded random start.  A step is
+one full sweep of Alg. 2 over the three modes (Khatri-Rao QR, Multi-TTM,
+Q_0 application, solve, normalization, factor QR) plus the efficient error.
+The Multi-TTM runs in FP32 on the matrix cores; every other step is FP64.
+
+Prints one JSON line.  Besides the throughput it reports the roofline of the
+dominant kernel (the first Multi-TTM contraction, which streams the whole
+tensor) from HIP events recorded on the launch stream during the timed
+sweeps, and the FP64 CPU oracle timed on the host on a bounded sample of the
+same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Multi-TTM GB/s (% HBM peak); CP-ALS-QR sweeps/s; time-to-fit vs plain form"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1000, help="mode size of the cubic tensor")
+    ap.add_argument("--rank", type=int, default=16)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle timing sample")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_src_sha):
+    """HBM bytes per launch of the first contraction from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ttm_first_1000cube_r16_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("|") and ":" not in line:
+            continue
+        if "=" in line and line.strip().startswith("-"):
+            k, v = line.strip("- \n").split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_src_sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import hashlib
+
+    import torch
+
+    from paper_2112_10855_amd import cpqr as C
+    from paper_2112_10855_amd import synth
+
+    if not os.path.exists(C.LIBPATH):
+        log("libcpqr.so missing; building")
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    n, R = args.n, args.rank
+    shape = (n, n, n)
+    t0 = time.time()
+    d = synth.workload_large3(n=n, R=R)
+    X = d["X"]
+    log("generated %s FP32 tensor in %.1f s" % (shape, time.time() - t0))
+    flat = torch.from_numpy(X.reshape(-1, order="F"))
+    Xd = flat.to("cuda").view(tuple(reversed(shape))).permute(2, 1, 0)
+    torch.cuda.synchronize()
+    log("uploaded")
+
+    prec = C.PREC_F32 if args.prec == "f32" else C.PREC_F64
+    if prec == C.PREC_F64:
+        Xd = Xd.double()
+    st = C.AlsState(Xd, d["init"], prec=prec)
+    st.init()
+    for _ in range(args.warmup):
+        st.sweep(1)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    rel = torch.empty(args.steps, dtype=torch.float64, device="cuda")
+    C.cpqr_timing_reset()
+    C.cpqr_timing_enable(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    e0.record(stream)
+    st.sweep(args.steps, rel)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    h1 = time.perf_counter()
+    C.cpqr_timing_enable(False)
+    phases = C.cpqr_timing_read()
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    relerr = rel.cpu().numpy()
+    log("timed %d sweeps: %.3f ms/sweep (host clock %.3f ms/sweep); relerr %.6e"
+        % (args.steps, ms_per_step, (h1 - h0) * 1e3 / args.steps, relerr[-1]))
+
+    xbytes = X.size * X.itemsize
+    first_ms, first_cnt = phases["ttm_first"]
+    first_avg_s = first_ms / max(first_cnt, 1) / 1e3
+    achieved = xbytes / first_avg_s / 1e9
+    mt_ms, mt_cnt = phases["multittm"]
+    ybytes = n * R ** 2 * 4
+    qbytes = 2 * n * R * 8
+    mt_gbs = (xbytes + ybytes + qbytes) / (mt_ms / max(mt_cnt, 1) / 1e3) / 1e9
+    src = open(os.path.join(ROOT, "paper_2112_10855_amd", "csrc", "multittm.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()
+    traffic = traffic_from_profiles(sha)
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "cp_als_qr_dense3_%dcube_%s_r%d" % (n, args.prec, R),
+            "shape": list(shape), "rank": R, "multittm_precision": args.prec,
+            "small_steps_precision": "f64", "solver": "qr", "error": "efficient",
+            "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
+        },
+        "roofline": {
+            "kernel": "first Multi-TTM contraction (streams X once)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": xbytes,
+            "avg_launch_ms": round(first_avg_s * 1e3, 4),
+            "launches": first_cnt,
+        },
+        "multittm_gbps": round(mt_gbs, 1),
+        "phases_ms_per_sweep": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
+        "relerr_last": float(relerr[-1]),
+    }
+
+    if not args.no_cpu_baseline:
+        import threadpoolctl
+
+        import oracle.cp_als_qr as OQ
+        log("oracle timing sample (FP64 numpy on host cores)")
+        X64 = X.astype(np.float64)
+        xn2 = float(np.einsum("i,i->", X64.reshape(-1, order="F"), X64.reshape(-1, order="F")))
+        ost = OQ.init_state(d["init"])
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+        sweeps, t = 0, 0.0
+        while sweeps < 1 or (t < args.cpu_seconds and sweeps < 5):
+            a = time.perf_counter()
+            orel, _ = OQ.sweep(X64, ost, xnorm2=xn2)
+            t += time.perf_counter() - a
+            sweeps += 1
+            log("oracle sweep %d: %.2f s, relerr %.6e" % (sweeps, t, orel))
+        out["cpu_baseline"] = {
+            "value": round(sweeps / t, 4),
+            "unit": "sweeps/s",
+            "cores": cores,
+            "kind": "oracle",
+            "sample": "%d full sweep(s) of the same %dx%dx%d workload from the same start, FP64 numpy" % (
+                sweeps, n, n, n),
+        }
+        # the GPU path after the same number of sweeps from the same start
+        st2 = C.AlsState(Xd, d["init"], prec=prec)
+        st2.init()
+        grel = st2.sweep(sweeps).cpu().numpy()
+        out["cpu_baseline"]["gpu_vs_oracle_relerr_after_sample"] = [float(grel[-1]), float(orel)]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * cpqr.h -- C ABI of libcpqr, the MI355X (gfx950) hot path of QR-based CP-ALS
+ * (CP-ALS-QR and CP-ALS-QR-SVD) from Minster, Viviano, Liu and Ballard,
+ * "CP Decomposition for Tensors via Alternating Least Squares with QR
+ * Decomposition", arXiv:2112.10855.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named as device pointers are caller-owned device memory on the
+ *    current HIP device.  The library never frees or keeps them.  Arrays of
+ *    pointers (for example `const double* const* Q`) are HOST arrays whose
+ *    elements are device pointers.
+ *  - Matrices are column-major with the stated leading dimension.
+ *  - A tensor X of sizes I[0..N-1] is stored column-major: mode 1 (I[0])
+ *    varies fastest.  This is the layout of a contiguous torch tensor of
+ *    shape (I[N-1], ..., I[0]).
+ *  - The mode-n unfolding X_(n) (section 2.2) has I[n] rows; its columns
+ *    are ordered with the lowest remaining mode fastest.  Y_(n) of the
+ *    Multi-TTM has I[n] rows and R^(N-1) columns in that order, which is the
+ *    row order of the Khatri-Rao product V_n of the triangular factors.
+ *  - Modes are 0-based: paper mode n is `n-1` here.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on it and returns; no call synchronizes
+ *    the device or allocates device memory.
+ *  - Scratch memory is caller-provided: each entry point that needs it
+ *    takes (work, work_bytes) and has a *_work query returning the bytes it
+ *    needs.  work must be 256-byte aligned.  Calls that share one work
+ *    buffer must be ordered on one stream.
+ *  - Return value: CPQR_OK or a negative CPQR_ERR_* code.  On error nothing
+ *    has been enqueued and cpqr_last_error() gives a thread-local message.
+ *  - Numerical conditions found on the device are OR-ed into an optional
+ *    device int (`status`, may be NULL) as CPQR_STATUS_* bits.
+ *
+ * Limits: 2 <= N <= CPQR_MAX_MODES, 1 <= R <= CPQR_MAX_RANK, I[k] >= R for
+ * every factor that is QR-factorized (its thin QR needs I[k] >= R).
+ */
+#ifndef CPQR_H
+#define CPQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPQR_MAX_MODES 10
+#define CPQR_MAX_RANK 32
+
+/* return codes */
+#define CPQR_OK 0
+#define CPQR_ERR_ARG (-1)         /* null pointer, bad enum, bad count */
+#define CPQR_ERR_SHAPE (-2)       /* sizes out of range or inconsistent */
+#define CPQR_ERR_DTYPE (-3)       /* dtype / precision combination not offered */
+#define CPQR_ERR_WORKSPACE (-4)   /* work buffer missing, small or misaligned */
+#define CPQR_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define CPQR_ERR_UNSUPPORTED (-6) /* valid request this build does not implement */
+
+/* element types */
+#define CPQR_F32 0
+#define CPQR_F64 1
+
+/* arithmetic of the Multi-TTM contractions */
+#define CPQR_PREC_F64 0    /* FP64 products and sums (X may be F32 or F64) */
+#define CPQR_PREC_F32 1    /* FP32 MFMA products, FP32 sums (X must be F32) */
+#define CPQR_PREC_BF16X2 2 /* split bfloat16 hi/lo, 3 MFMA products, FP32 sums */
+#define CPQR_PREC_BF16 3   /* operands rounded to bfloat16, FP32 sums */
+
+/* status bits OR-ed into the optional device status word */
+#define CPQR_STATUS_SINGULAR 1   /* R_0 has a zero or non-finite diagonal (substitution) */
+#define CPQR_STATUS_NONFINITE 2  /* a solved factor holds Inf/NaN */
+#define CPQR_STATUS_TRUNCATED 4  /* the SVD solve dropped singular values */
+#define CPQR_STATUS_ZERO_COLUMN 8 /* a solved factor column has zero norm */
+
+/* error forms of section 3.3.1 */
+#define CPQR_ERROR_EFFICIENT 0 /* from W_N, R_0, R_N and lambda; accurate to ~sqrt(eps) */
+#define CPQR_ERROR_DIRECT 1    /* ||X - [[lambda; A]]|| streamed over X in FP64 */
+#define CPQR_ERROR_NONE 2      /* skip the error */
+
+/* Thread-local message for the last failed call on this thread. */
+const char* cpqr_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int cpqr_version(void);
+
+/*
+ * Compact QR of one factor matrix, A = Q R (Alg. 2, the factor QR before
+ * the loop and after each mode update).  Householder reflections on the
+ * GPU (a tall-skinny tree over 64-row blocks), Q formed explicitly.
+ *   A   : device, I x R, column-major, lda >= I (read only)
+ *   Q   : device, I x R, column-major, ldq >= I (written)
+ *   Rk  : device, R x R upper triangular, column-major, ldr >= R (written,
+ *         including the zeros below the diagonal)
+ * Requires I >= R.  Signs of the diagonal of Rk are not normalized.
+ */
+size_t cpqr_factor_qr_work(int64_t I, int R);
+int cpqr_factor_qr(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
+                   double* Rk, int64_t ldr, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Khatri-Rao product of the triangular factors and its QR (section 3.1,
+ * eq. Z_qr): V_n = R_N (.) ... (.) R_{n+1} (.) R_{n-1} (.) ... (.) R_1,
+ * V_n = Q_0 R_0 with Q_0 explicit.  V_n is generated on the fly.
+ *   Rk  : host array of N device pointers; Rk[k] is R x R column-major with
+ *         leading dimension ldr; Rk[n] is not read
+ *   Q0  : device, R^(N-1) x R, column-major, leading dimension R^(N-1)
+ *   R0  : device, R x R upper triangular, column-major, leading dimension R
+ */
+size_t cpqr_krp_qr_work(int N, int R);
+int cpqr_krp_qr(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0, double* R0,
+                void* work, size_t work_bytes, void* stream);
+
+/*
+ * Multi-TTM in every mode except n (section 2.2, eq. multittm; Alg. 2):
+ * Y = X x_k Q_k^T for all k != n, returned as the unfolding Y_(n).
+ *   I     : host array of N mode sizes
+ *   X     : device tensor, column-major, element type xdtype
+ *   Q     : host array of N device pointers; Q[k] is I[k] x R column-major
+ *           FP64 with leading dimension I[k]; Q[n] is not read
+ *   prec  : CPQR_PREC_*.  F32, BF16X2 and BF16 need xdtype == CPQR_F32.
+ *   Y     : device, I[n] x R^(N-1) column-major (leading dimension I[n]);
+ *           FP64 when prec == CPQR_PREC_F64, otherwise FP32
+ * The contractions run largest mode first.  The first one streams X once.
+ */
+size_t cpqr_multittm_work(int N, const int64_t* I, int n, int R, int prec);
+int cpqr_multittm(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                  const double* const* Q, int prec, void* Y, void* work, size_t work_bytes,
+                  void* stream);
+
+/*
+ * Apply Q_0 (Alg. 2, eq. ls-qr-q0-step): W = Y_(n) Q_0 in FP64.
+ *   Y   : device, In x K column-major (leading dimension In), ydtype F32/F64
+ *   Q0  : device, K x R column-major (leading dimension K)
+ *   W   : device, In x R column-major (leading dimension In)
+ */
+size_t cpqr_apply_q0_work(int64_t In, int64_t K, int R);
+int cpqr_apply_q0(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                  double* W, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Solve and normalize (Alg. 2, section 3.1): Ahat R_0^T = W by substitution
+ * (use_svd == 0, CP-ALS-QR) or Ahat = W U S^+ V^T from the SVD R_0 = U S V^T
+ * (use_svd != 0, CP-ALS-QR-SVD; singular values <= rtol * sigma_max are
+ * dropped; rtol < 0 selects R * 2^-52).  Then lambda_r = ||Ahat(:,r)||_2 and
+ * A = Ahat diag(lambda)^-1 (a zero column stays zero with lambda_r = 0).
+ *   W      : device, In x R column-major (leading dimension In)
+ *   R0     : device, R x R upper triangular (leading dimension R)
+ *   A      : device, In x R column-major (leading dimension In), written
+ *   lambda : device, R doubles, written
+ *   status : device int or NULL; CPQR_STATUS_* bits OR-ed in
+ */
+size_t cpqr_solve_rsvd_work(int64_t In, int R);
+int cpqr_solve_rsvd(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
+                    double* A, double* lambda, int* status, void* work, size_t work_bytes,
+                    void* stream);
+
+/*
+ * Direct residual of a Kruskal model (section 3.3.1, the accurate form):
+ * out[0] = ||X - [[lambda; A_1..A_N]]||_F^2 and out[1] = ||X||_F^2, both
+ * accumulated in FP64.  A is a host array of N device pointers to I[k] x R
+ * column-major FP64 factors (leading dimension I[k]); out is device memory.
+ */
+size_t cpqr_fit_direct_work(int N, const int64_t* I, int R);
+int cpqr_fit_direct(int N, const int64_t* I, int xdtype, const void* X, int R, const double* lambda,
+                    const double* const* A, double* out, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Whole sweeps of CP-ALS-QR / CP-ALS-QR-SVD (Alg. 2): for n = 1..N the
+ * Khatri-Rao QR, Multi-TTM, Q_0 application, solve, normalization and
+ * factor QR, then the relative error.  The ALS state lives in caller
+ * memory described by cpqr_problem; the work buffer also keeps ||X||^2
+ * between calls, so pass the same buffer to cpqr_als_init and every
+ * cpqr_als_sweep of one problem.
+ */
+typedef struct cpqr_problem {
+  int N;                          /* number of modes */
+  int R;                          /* CP rank */
+  int64_t I[CPQR_MAX_MODES];      /* mode sizes */
+  int xdtype;                     /* CPQR_F32 or CPQR_F64 */
+  const void* X;                  /* device tensor, column-major */
+  double* A[CPQR_MAX_MODES];      /* device I[k] x R factors (normalized after each update) */
+  double* Q[CPQR_MAX_MODES];      /* device I[k] x R orthonormal factors */
+  double* Rf[CPQR_MAX_MODES];     /* device R x R triangular factors (leading dimension R) */
+  double* lambda;                 /* device, R weights */
+  int prec;                       /* CPQR_PREC_* of the Multi-TTM */
+  int use_svd;                    /* 0: substitution, 1: SVD solve */
+  double rtol;                    /* SVD cutoff (negative: default) */
+  int error_mode;                 /* CPQR_ERROR_* */
+  int* status;                    /* device int or NULL */
+} cpqr_problem;
+
+size_t cpqr_als_work(const cpqr_problem* p);
+
+/* Alg. 2 set-up: compact QRs of the initial A[1..N-1] (A[0] is not read)
+ * and ||X||^2 into the work buffer. */
+int cpqr_als_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream);
+
+/* nsweeps full sweeps; relerr (device, nsweeps doubles, or NULL) receives
+ * the relative error after each sweep (NaN when error_mode is NONE). */
+int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, size_t work_bytes,
+                   void* stream);
+
+/*
+ * Phase timers (the per-iteration breakdown of the paper's performance
+ * section): when enabled, eager calls record HIP events around each phase on
+ * the launch stream.  cpqr_timing_read synchronizes those events and returns
+ * accumulated milliseconds and launch counts per phase since the last reset.
+ * Phases: 0 Multi-TTM, 1 first (tensor-streaming) contraction, 2 factor QR,
+ * 3 computing Q_0, 4 applying Q_0, 5 solve + normalize, 6 error.
+ */
+#define CPQR_NPHASES 7
+int cpqr_timing_enable(int on);
+int cpqr_timing_reset(void);
+int cpqr_timing_read(double* ms, int64_t* counts, int nphases);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPQR_H */

@@ -1,0 +1,371 @@
+"""ctypes binding of libcpqr (include/cpqr.h).
+
+Argument marshalling only: every step of CP-ALS-QR runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  The
+functions keep the C names.
+
+Layout conventions for torch tensors:
+  * a column-major I x R matrix is a 2-D tensor of shape (I, R) with strides
+    (1, I) -- see :func:`colmajor`;
+  * a column-major tensor of sizes (I_1, ..., I_N) has strides
+    (1, I_1, I_1 I_2, ...) -- see :func:`colmajor`.
+There is no CPU fallback: if the library is missing, or a tensor is not on a
+GPU, the call raises.
+"""
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcpqr.so")
+
+MAX_MODES = 10
+MAX_RANK = 32
+
+F32, F64 = 0, 1
+PREC_F64, PREC_F32, PREC_BF16X2, PREC_BF16 = 0, 1, 2, 3
+STATUS_SINGULAR, STATUS_NONFINITE, STATUS_TRUNCATED, STATUS_ZERO_COLUMN = 1, 2, 4, 8
+ERROR_EFFICIENT, ERROR_DIRECT, ERROR_NONE = 0, 1, 2
+NPHASES = 7
+PHASES = ["multittm", "ttm_first", "factor_qr", "q0", "apply_q0", "solve", "error"]
+
+PREC_NAMES = {"f64": PREC_F64, "f32": PREC_F32, "bf16x2": PREC_BF16X2, "bf16": PREC_BF16}
+
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+class CpqrError(RuntimeError):
+    """A libcpqr entry point returned an error code."""
+
+    def __init__(self, name, code, msg):
+        super().__init__("%s failed (%d): %s" % (name, code, msg))
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    """Mirror of ``cpqr_problem``."""
+    _fields_ = [
+        ("N", ctypes.c_int), ("R", ctypes.c_int),
+        ("I", _i64 * MAX_MODES),
+        ("xdtype", ctypes.c_int), ("X", _vp),
+        ("A", _vp * MAX_MODES), ("Q", _vp * MAX_MODES), ("Rf", _vp * MAX_MODES),
+        ("lam", _vp),
+        ("prec", ctypes.c_int), ("use_svd", ctypes.c_int), ("rtol", ctypes.c_double),
+        ("error_mode", ctypes.c_int), ("status", _vp),
+    ]
+
+
+_lib = None
+
+_SIGS = {
+    "cpqr_last_error": (ctypes.c_char_p, []),
+    "cpqr_version": (ctypes.c_int, []),
+    "cpqr_factor_qr_work": (_sz, [_i64, ctypes.c_int]),
+    "cpqr_factor_qr": (ctypes.c_int, [_i64, ctypes.c_int, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "cpqr_krp_qr_work": (_sz, [ctypes.c_int, ctypes.c_int]),
+    "cpqr_krp_qr": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), _i64,
+                                   _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_multittm_work": (_sz, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "cpqr_multittm": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int,
+                                     ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_apply_q0_work": (_sz, [_i64, _i64, ctypes.c_int]),
+    "cpqr_apply_q0": (ctypes.c_int, [_i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_solve_rsvd_work": (_sz, [_i64, ctypes.c_int]),
+    "cpqr_solve_rsvd": (ctypes.c_int, [_i64, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp,
+                                       _vp, _vp, _sz, _vp]),
+    "cpqr_fit_direct_work": (_sz, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int]),
+    "cpqr_fit_direct": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int, _vp,
+                                       ctypes.POINTER(_vp), _vp, _vp, _sz, _vp]),
+    "cpqr_als_work": (_sz, [ctypes.POINTER(Problem)]),
+    "cpqr_als_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
+    "cpqr_als_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "cpqr_timing_reset": (ctypes.c_int, []),
+    "cpqr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]),
+}
+
+EXPORTED = sorted(_SIGS)
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libcpqr.so is not built (expected at %s); run __graft_entry__.build()" % LIBPATH)
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    rc = getattr(lib(), name)(*args)
+    if rc != 0:
+        raise CpqrError(name, rc, lib().cpqr_last_error().decode())
+    return rc
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    return t
+
+
+def _work(nbytes, device):
+    """Scratch buffer of at least nbytes, 256-byte aligned; returns (keepalive, ptr)."""
+    if nbytes == 0:
+        return None, None
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    p = buf.data_ptr()
+    return buf, p + ((-p) % 256)
+
+
+def colmajor(x):
+    """Same values, column-major strides (first index fastest)."""
+    nd = x.dim()
+    perm = list(reversed(range(nd)))
+    return x.permute(perm).contiguous().permute(perm)
+
+
+def empty_colmajor(shape, dtype, device):
+    rev = list(reversed(shape))
+    perm = list(reversed(range(len(shape))))
+    return torch.empty(rev, dtype=dtype, device=device).permute(perm)
+
+
+def _check_colmajor(x, what):
+    exp = 1
+    for d in range(x.dim()):
+        if x.shape[d] > 1 and x.stride(d) != exp:
+            raise ValueError("%s must be column-major (first index fastest)" % what)
+        exp *= x.shape[d]
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("tensor dtype must be float32 or float64")
+
+
+def _ptr_array(ts):
+    arr = (_vp * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _i64_array(v):
+    arr = (_i64 * len(v))()
+    for i, x in enumerate(v):
+        arr[i] = int(x)
+    return arr
+
+
+# ------------------------------------------------------------------ entry points
+
+def cpqr_version():
+    return lib().cpqr_version()
+
+
+def cpqr_factor_qr(A):
+    """Thin QR of an (I, R) column-major FP64 matrix -> (Q, Rk)."""
+    _dev(A, "A")
+    _check_colmajor(A, "A")
+    I, R = A.shape
+    Q = empty_colmajor((I, R), torch.float64, A.device)
+    Rk = empty_colmajor((R, R), torch.float64, A.device)
+    keep, w = _work(lib().cpqr_factor_qr_work(I, R), A.device)
+    _call("cpqr_factor_qr", I, R, A.data_ptr(), I, Q.data_ptr(), I, Rk.data_ptr(), R, w,
+          0 if keep is None else keep.numel() - 256, _stream())
+    return Q, Rk
+
+
+def cpqr_krp_qr(Rks, n):
+    """QR of V_n = Khatri-Rao of the triangular factors (all but mode n).
+    Rks: list of N (R, R) column-major FP64 tensors (entry n may be None)."""
+    N = len(Rks)
+    ref = next(r for r in Rks if r is not None)
+    R = ref.shape[0]
+    for k, r in enumerate(Rks):
+        if k != n:
+            _dev(r, "Rk")
+            _check_colmajor(r, "Rk")
+    K = R ** (N - 1)
+    Q0 = empty_colmajor((K, R), torch.float64, ref.device)
+    R0 = empty_colmajor((R, R), torch.float64, ref.device)
+    keep, w = _work(lib().cpqr_krp_qr_work(N, R), ref.device)
+    _call("cpqr_krp_qr", N, n, R, _ptr_array(Rks), R, Q0.data_ptr(), R0.data_ptr(), w,
+          0 if keep is None else keep.numel() - 256, _stream())
+    return Q0, R0
+
+
+def cpqr_multittm(X, Qs, n, prec=PREC_F32):
+    """Y_(n) of Y = X x_k Q_k^T (k != n).  X: column-major tensor (FP32 or
+    FP64); Qs: list of (I_k, R) column-major FP64 (entry n may be None)."""
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    prec = PREC_NAMES.get(prec, prec)
+    N = X.dim()
+    ref = next(q for q in Qs if q is not None)
+    R = ref.shape[1]
+    for k, q in enumerate(Qs):
+        if k != n:
+            _dev(q, "Q")
+            _check_colmajor(q, "Q")
+    I = _i64_array(X.shape)
+    K = R ** (N - 1)
+    ydt = torch.float64 if prec == PREC_F64 else torch.float32
+    Y = empty_colmajor((X.shape[n], K), ydt, X.device)
+    keep, w = _work(lib().cpqr_multittm_work(N, I, n, R, prec), X.device)
+    _call("cpqr_multittm", N, I, _dtype_code(X), X.data_ptr(), n, R, _ptr_array(Qs), prec, Y.data_ptr(), w,
+          0 if keep is None else keep.numel() - 256, _stream())
+    return Y
+
+
+def cpqr_apply_q0(Y, Q0):
+    """W = Y_(n) Q_0 in FP64."""
+    _dev(Y, "Y")
+    _dev(Q0, "Q0")
+    _check_colmajor(Y, "Y")
+    _check_colmajor(Q0, "Q0")
+    In, K = Y.shape
+    R = Q0.shape[1]
+    W = empty_colmajor((In, R), torch.float64, Y.device)
+    keep, w = _work(lib().cpqr_apply_q0_work(In, K, R), Y.device)
+    _call("cpqr_apply_q0", In, K, R, _dtype_code(Y), Y.data_ptr(), Q0.data_ptr(), W.data_ptr(), w,
+          0 if keep is None else keep.numel() - 256, _stream())
+    return W
+
+
+def cpqr_solve_rsvd(W, R0, use_svd=False, rtol=-1.0, status=None):
+    """Solve Ahat R_0^T = W (substitution or SVD) and normalize -> (A, lambda)."""
+    _dev(W, "W")
+    _dev(R0, "R0")
+    _check_colmajor(W, "W")
+    _check_colmajor(R0, "R0")
+    In, R = W.shape
+    A = empty_colmajor((In, R), torch.float64, W.device)
+    lam = torch.empty(R, dtype=torch.float64, device=W.device)
+    keep, w = _work(lib().cpqr_solve_rsvd_work(In, R), W.device)
+    _call("cpqr_solve_rsvd", In, R, W.data_ptr(), R0.data_ptr(), int(bool(use_svd)), float(rtol), A.data_ptr(),
+          lam.data_ptr(), None if status is None else status.data_ptr(), w,
+          0 if keep is None else keep.numel() - 256, _stream())
+    return A, lam
+
+
+def cpqr_fit_direct(X, lam, As):
+    """(||X - [[lam; A]]||^2, ||X||^2) as a 2-element FP64 device tensor."""
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    N = X.dim()
+    R = As[0].shape[1]
+    I = _i64_array(X.shape)
+    out = torch.empty(2, dtype=torch.float64, device=X.device)
+    keep, w = _work(lib().cpqr_fit_direct_work(N, I, R), X.device)
+    _call("cpqr_fit_direct", N, I, _dtype_code(X), X.data_ptr(), R, lam.data_ptr(), _ptr_array(As),
+          out.data_ptr(), w, 0 if keep is None else keep.numel() - 256, _stream())
+    return out
+
+
+class AlsState:
+    """Device buffers of one CP-ALS-QR problem, wired into ``cpqr_problem``."""
+
+    def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT):
+        _dev(X, "X")
+        _check_colmajor(X, "X")
+        prec = PREC_NAMES.get(prec, prec)
+        dev = X.device
+        N = X.dim()
+        R = init[1].shape[1]
+        self.X, self.N, self.R = X, N, R
+        self.A = [colmajor(torch.as_tensor(init[k], dtype=torch.float64).to(dev)) if k > 0 else
+                  empty_colmajor((X.shape[0], R), torch.float64, dev) for k in range(N)]
+        if N > 0:
+            self.A[0].zero_()
+        self.Q = [empty_colmajor((X.shape[k], R), torch.float64, dev) for k in range(N)]
+        self.Rf = [empty_colmajor((R, R), torch.float64, dev) for k in range(N)]
+        self.lam = torch.ones(R, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        p = Problem()
+        p.N, p.R = N, R
+        for k in range(N):
+            p.I[k] = X.shape[k]
+            p.A[k] = self.A[k].data_ptr()
+            p.Q[k] = self.Q[k].data_ptr()
+            p.Rf[k] = self.Rf[k].data_ptr()
+        p.xdtype = _dtype_code(X)
+        p.X = X.data_ptr()
+        p.lam = self.lam.data_ptr()
+        p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(bool(use_svd)), float(rtol), error_mode
+        p.status = self.status.data_ptr()
+        self.p = p
+        nbytes = lib().cpqr_als_work(ctypes.byref(p))
+        if nbytes == 0:
+            raise CpqrError("cpqr_als_work", -1, lib().cpqr_last_error().decode())
+        self._wkeep, self._w = _work(nbytes, dev)
+        self._wbytes = nbytes
+
+    def init(self):
+        _call("cpqr_als_init", ctypes.byref(self.p), self._w, self._wbytes, _stream())
+
+    def sweep(self, nsweeps=1, relerr=None):
+        """Run nsweeps sweeps; returns the device tensor of relative errors."""
+        if relerr is None:
+            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.X.device)
+        _call("cpqr_als_sweep", ctypes.byref(self.p), int(nsweeps), relerr.data_ptr(), self._w, self._wbytes,
+              _stream())
+        return relerr
+
+
+def cpqr_als_init(state):
+    state.init()
+
+
+def cpqr_als_sweep(state, nsweeps=1, relerr=None):
+    return state.sweep(nsweeps, relerr)
+
+
+def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=-1.0,
+              error_mode=ERROR_EFFICIENT):
+    """Alg. 2 driven from the host: sweeps until |relerr change| < tol or
+    maxiters (reads the error back after each sweep only when tol > 0)."""
+    st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode)
+    st.init()
+    if tol <= 0:
+        rel = st.sweep(maxiters)
+        return st, rel.cpu().tolist()
+    hist = []
+    for s in range(maxiters):
+        hist.append(float(st.sweep(1)[0].item()))
+        if s >= 1 and abs(hist[-2] - hist[-1]) < tol:
+            break
+    return st, hist
+
+
+def cpqr_timing_enable(on=True):
+    _call("cpqr_timing_enable", int(bool(on)))
+
+
+def cpqr_timing_reset():
+    _call("cpqr_timing_reset")
+
+
+def cpqr_timing_read():
+    ms = (ctypes.c_double * NPHASES)()
+    cnt = (_i64 * NPHASES)()
+    _call("cpqr_timing_read", ms, cnt, NPHASES)
+    return {PHASES[i]: (ms[i], cnt[i]) for i in range(NPHASES)}

@@ -1,0 +1,410 @@
+// C ABI of libcpqr (include/cpqr.h): argument validation, scratch sizing,
+// phase timers and the CP-ALS-QR sweep driver (paper Alg. 2).  Kernels live
+// in tsqr.hip (QRs), multittm.hip (Multi-TTM) and small.hip (apply Q_0,
+// solves, errors).
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace cpqr {
+
+namespace {
+thread_local std::string g_error;
+
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[CPQR_NPHASES] = {};
+  int64_t count[CPQR_NPHASES] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+TimingState& timing() {
+  static TimingState t;
+  return t;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CPQR_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return CPQR_OK;
+}
+
+int check_work(void* work, size_t have, size_t need) {
+  if (need == 0) return CPQR_OK;
+  if (!work) return fail(CPQR_ERR_WORKSPACE, "work buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(CPQR_ERR_WORKSPACE, "work buffer must be 256-byte aligned");
+  if (have < need)
+    return fail(CPQR_ERR_WORKSPACE, "work buffer too small: " + std::to_string(have) + " < " +
+                                        std::to_string(need) + " bytes");
+  return CPQR_OK;
+}
+
+PhaseTimer::PhaseTimer(int ph, hipStream_t s) : phase(ph), stream(s) {
+  if (ph < 0) return;
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  ev0 = t.get();
+  if (ev0 && hipEventRecord(ev0, s) != hipSuccess) ev0 = nullptr;
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!ev0) return;
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  hipEvent_t e1 = t.get();
+  if (!e1 || hipEventRecord(e1, stream) != hipSuccess) return;
+  t.pending.push_back({phase, ev0, e1});
+}
+
+}  // namespace cpqr
+
+using namespace cpqr;
+
+namespace {
+
+int valid_dtype(int d) { return d == CPQR_F32 || d == CPQR_F64; }
+int valid_prec(int p) { return p >= CPQR_PREC_F64 && p <= CPQR_PREC_BF16; }
+
+int check_rank(int R) {
+  if (R < 1 || R > CPQR_MAX_RANK)
+    return fail(CPQR_ERR_SHAPE, "R must be in [1, " + std::to_string(CPQR_MAX_RANK) + "]");
+  return CPQR_OK;
+}
+
+int check_modes(int N, const int64_t* I) {
+  if (!I) return fail(CPQR_ERR_ARG, "mode sizes pointer is NULL");
+  if (N < 2 || N > CPQR_MAX_MODES)
+    return fail(CPQR_ERR_SHAPE, "N must be in [2, " + std::to_string(CPQR_MAX_MODES) + "]");
+  for (int k = 0; k < N; ++k)
+    if (I[k] < 1) return fail(CPQR_ERR_SHAPE, "mode size I[" + std::to_string(k) + "] < 1");
+  return CPQR_OK;
+}
+
+int check_krp_rows(int N, int R) {
+  double rows = std::pow(double(R), N - 1);
+  if (rows > double(1LL << 31))
+    return fail(CPQR_ERR_SHAPE, "R^(N-1) too large for the Khatri-Rao QR");
+  return CPQR_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------ sweep scratch
+struct AlsWs {
+  double* xnorm2;
+  double* Q0;
+  double* R0;
+  void* Y;
+  double* W;
+  double* fit;
+  double* relerr_tmp;
+  void* sub;
+};
+
+size_t als_sub_bytes(const cpqr_problem* p) {
+  const int N = p->N, R = p->R;
+  size_t b = tsqr_work(ipow(R, N - 1), R);
+  const int64_t K = ipow(R, N - 1);
+  int64_t count = 1;
+  for (int k = 0; k < N; ++k) {
+    count *= p->I[k];
+    b = std::max(b, tsqr_work(p->I[k], R));
+    b = std::max(b, multittm_work(N, p->I, k, R, p->prec));
+    b = std::max(b, apply_q0_work(p->I[k], K, R));
+    b = std::max(b, solve_work(p->I[k], R));
+  }
+  b = std::max(b, fit_direct_work(N, p->I, R));
+  b = std::max(b, norm2_work(count));
+  return b;
+}
+
+size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
+  const int N = p->N, R = p->R;
+  const int64_t K = ipow(R, N - 1);
+  int64_t imax = 0;
+  for (int k = 0; k < N; ++k) imax = std::max(imax, p->I[k]);
+  AlsWs w{};
+  w.xnorm2 = cv.take<double>(1);
+  w.Q0 = cv.take<double>(size_t(K) * R);
+  w.R0 = cv.take<double>(size_t(R) * R);
+  w.Y = cv.take<double>(size_t(imax) * K);  // sized for FP64 Y
+  w.W = cv.take<double>(size_t(imax) * R);
+  w.fit = cv.take<double>(2);
+  w.relerr_tmp = cv.take<double>(1);
+  w.sub = cv.take<char>(als_sub_bytes(p));
+  if (ws) *ws = w;
+  return cv.bytes();
+}
+
+int check_problem(const cpqr_problem* p) {
+  if (!p) return fail(CPQR_ERR_ARG, "problem is NULL");
+  CPQR_TRY(check_modes(p->N, p->I));
+  CPQR_TRY(check_rank(p->R));
+  CPQR_TRY(check_krp_rows(p->N, p->R));
+  if (!valid_dtype(p->xdtype)) return fail(CPQR_ERR_DTYPE, "xdtype must be CPQR_F32 or CPQR_F64");
+  if (!valid_prec(p->prec)) return fail(CPQR_ERR_ARG, "unknown precision");
+  if (p->prec != CPQR_PREC_F64 && p->xdtype != CPQR_F32)
+    return fail(CPQR_ERR_DTYPE, "reduced-precision Multi-TTM needs an FP32 tensor");
+  if (p->error_mode < CPQR_ERROR_EFFICIENT || p->error_mode > CPQR_ERROR_NONE)
+    return fail(CPQR_ERR_ARG, "unknown error_mode");
+  if (!p->X || !p->lambda) return fail(CPQR_ERR_ARG, "X or lambda is NULL");
+  for (int k = 0; k < p->N; ++k) {
+    if (!p->A[k] || !p->Q[k] || !p->Rf[k])
+      return fail(CPQR_ERR_ARG, "A/Q/Rf pointer of mode " + std::to_string(k) + " is NULL");
+    if (p->I[k] < p->R)
+      return fail(CPQR_ERR_SHAPE, "mode " + std::to_string(k) + " is smaller than the rank");
+  }
+  return CPQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cpqr_last_error(void) { return g_error.c_str(); }
+
+int cpqr_version(void) { return 100; }
+
+size_t cpqr_factor_qr_work(int64_t I, int R) {
+  if (I < 1 || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return tsqr_work(I, R);
+}
+
+int cpqr_factor_qr(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
+                   double* Rk, int64_t ldr, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_rank(R));
+  if (I < R) return fail(CPQR_ERR_SHAPE, "factor_qr needs I >= R");
+  if (!A || !Q || !Rk) return fail(CPQR_ERR_ARG, "factor_qr: NULL pointer");
+  if (lda < I || ldq < I || ldr < R) return fail(CPQR_ERR_SHAPE, "factor_qr: leading dimension too small");
+  CPQR_TRY(check_work(work, work_bytes, tsqr_work(I, R)));
+  return factor_qr_enqueue(I, R, A, lda, Q, ldq, Rk, ldr, work, as_stream(stream));
+}
+
+size_t cpqr_krp_qr_work(int N, int R) {
+  if (N < 2 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
+  if (check_krp_rows(N, R) != CPQR_OK) return 0;
+  return tsqr_work(ipow(R, N - 1), R);
+}
+
+int cpqr_krp_qr(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0, double* R0,
+                void* work, size_t work_bytes, void* stream) {
+  if (N < 2 || N > CPQR_MAX_MODES) return fail(CPQR_ERR_SHAPE, "krp_qr: N out of range");
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "krp_qr: n out of range");
+  CPQR_TRY(check_rank(R));
+  CPQR_TRY(check_krp_rows(N, R));
+  if (!Rk || !Q0 || !R0) return fail(CPQR_ERR_ARG, "krp_qr: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Rk[k]) return fail(CPQR_ERR_ARG, "krp_qr: Rk[" + std::to_string(k) + "] is NULL");
+  if (ldr < R) return fail(CPQR_ERR_SHAPE, "krp_qr: ldr < R");
+  CPQR_TRY(check_work(work, work_bytes, tsqr_work(ipow(R, N - 1), R)));
+  return krp_qr_enqueue(N, n, R, Rk, ldr, Q0, R0, work, as_stream(stream));
+}
+
+size_t cpqr_multittm_work(int N, const int64_t* I, int n, int R, int prec) {
+  if (check_modes(N, I) != CPQR_OK || n < 0 || n >= N || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return multittm_work(N, I, n, R, prec);
+}
+
+int cpqr_multittm(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                  const double* const* Q, int prec, void* Y, void* work, size_t work_bytes,
+                  void* stream) {
+  CPQR_TRY(check_modes(N, I));
+  CPQR_TRY(check_rank(R));
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "multittm: n out of range");
+  if (!valid_dtype(xdtype)) return fail(CPQR_ERR_DTYPE, "multittm: xdtype must be CPQR_F32 or CPQR_F64");
+  if (!valid_prec(prec)) return fail(CPQR_ERR_ARG, "multittm: unknown precision");
+  if (prec != CPQR_PREC_F64 && xdtype != CPQR_F32)
+    return fail(CPQR_ERR_DTYPE, "multittm: reduced-precision forms need an FP32 tensor");
+  if (!X || !Y || !Q) return fail(CPQR_ERR_ARG, "multittm: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Q[k]) return fail(CPQR_ERR_ARG, "multittm: Q[" + std::to_string(k) + "] is NULL");
+  CPQR_TRY(check_krp_rows(N, R));
+  CPQR_TRY(check_work(work, work_bytes, multittm_work(N, I, n, R, prec)));
+  return multittm_enqueue(N, I, xdtype, X, n, R, Q, prec, Y, work, as_stream(stream));
+}
+
+size_t cpqr_apply_q0_work(int64_t In, int64_t K, int R) {
+  if (In < 1 || K < 1 || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return apply_q0_work(In, K, R);
+}
+
+int cpqr_apply_q0(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                  double* W, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_rank(R));
+  if (In < 1 || K < R) return fail(CPQR_ERR_SHAPE, "apply_q0: need In >= 1 and K >= R");
+  if (!valid_dtype(ydtype)) return fail(CPQR_ERR_DTYPE, "apply_q0: ydtype must be CPQR_F32 or CPQR_F64");
+  if (!Y || !Q0 || !W) return fail(CPQR_ERR_ARG, "apply_q0: NULL pointer");
+  CPQR_TRY(check_work(work, work_bytes, apply_q0_work(In, K, R)));
+  return apply_q0_enqueue(In, K, R, ydtype, Y, Q0, W, work, as_stream(stream));
+}
+
+size_t cpqr_solve_rsvd_work(int64_t In, int R) {
+  if (In < 1 || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return solve_work(In, R);
+}
+
+int cpqr_solve_rsvd(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
+                    double* A, double* lambda, int* status, void* work, size_t work_bytes,
+                    void* stream) {
+  CPQR_TRY(check_rank(R));
+  if (In < 1) return fail(CPQR_ERR_SHAPE, "solve_rsvd: In < 1");
+  if (!W || !R0 || !A || !lambda) return fail(CPQR_ERR_ARG, "solve_rsvd: NULL pointer");
+  if (std::isnan(rtol)) return fail(CPQR_ERR_ARG, "solve_rsvd: rtol is NaN");
+  CPQR_TRY(check_work(work, work_bytes, solve_work(In, R)));
+  return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, as_stream(stream));
+}
+
+size_t cpqr_fit_direct_work(int N, const int64_t* I, int R) {
+  if (check_modes(N, I) != CPQR_OK || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return fit_direct_work(N, I, R);
+}
+
+int cpqr_fit_direct(int N, const int64_t* I, int xdtype, const void* X, int R, const double* lambda,
+                    const double* const* A, double* out, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_modes(N, I));
+  CPQR_TRY(check_rank(R));
+  if (!valid_dtype(xdtype)) return fail(CPQR_ERR_DTYPE, "fit_direct: xdtype must be CPQR_F32 or CPQR_F64");
+  if (!X || !lambda || !A || !out) return fail(CPQR_ERR_ARG, "fit_direct: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (!A[k]) return fail(CPQR_ERR_ARG, "fit_direct: A[" + std::to_string(k) + "] is NULL");
+  CPQR_TRY(check_work(work, work_bytes, fit_direct_work(N, I, R)));
+  return fit_direct_enqueue(N, I, xdtype, X, R, lambda, A, out, work, as_stream(stream));
+}
+
+size_t cpqr_als_work(const cpqr_problem* p) {
+  if (check_problem(p) != CPQR_OK) return 0;
+  Carver cv(nullptr);
+  return als_carve(cv, p, nullptr);
+}
+
+int cpqr_als_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_problem(p));
+  Carver cv(nullptr);
+  CPQR_TRY(check_work(work, work_bytes, als_carve(cv, p, nullptr)));
+  AlsWs w;
+  Carver c2(work);
+  als_carve(c2, p, &w);
+  hipStream_t s = as_stream(stream);
+  const int N = p->N, R = p->R;
+  for (int k = 1; k < N; ++k)
+    CPQR_TRY(factor_qr_enqueue(p->I[k], R, p->A[k], p->I[k], p->Q[k], p->I[k], p->Rf[k], R, w.sub, s));
+  CPQR_TRY(fill_enqueue(p->lambda, R, 1.0, s));
+  int64_t count = 1;
+  for (int k = 0; k < N; ++k) count *= p->I[k];
+  return norm2_enqueue(count, p->xdtype, p->X, w.xnorm2, w.sub, s);
+}
+
+int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, size_t work_bytes,
+                   void* stream) {
+  CPQR_TRY(check_problem(p));
+  if (nsweeps < 0) return fail(CPQR_ERR_ARG, "nsweeps < 0");
+  Carver cv(nullptr);
+  CPQR_TRY(check_work(work, work_bytes, als_carve(cv, p, nullptr)));
+  AlsWs w;
+  Carver c2(work);
+  als_carve(c2, p, &w);
+  hipStream_t s = as_stream(stream);
+  const int N = p->N, R = p->R;
+  const int64_t K = ipow(R, N - 1);
+  const int ydt = p->prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int n = 0; n < N; ++n) {
+      CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.sub, s));
+      CPQR_TRY(multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, p->Q, p->prec, w.Y, w.sub, s));
+      CPQR_TRY(apply_q0_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.W, w.sub, s));
+      CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda,
+                             p->status, w.sub, s));
+      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s));
+    }
+    double* out = relerr ? relerr + sw : w.relerr_tmp;
+    if (p->error_mode == CPQR_ERROR_EFFICIENT) {
+      CPQR_TRY(error_efficient_enqueue(p->I[N - 1], R, w.W, p->A[N - 1], p->lambda, w.R0, p->Rf[N - 1],
+                                       w.xnorm2, out, s));
+    } else if (p->error_mode == CPQR_ERROR_DIRECT) {
+      const double* Ap[CPQR_MAX_MODES];
+      for (int k = 0; k < N; ++k) Ap[k] = p->A[k];
+      CPQR_TRY(fit_direct_enqueue(N, p->I, p->xdtype, p->X, R, p->lambda, Ap, w.fit, w.sub, s));
+      CPQR_TRY(error_from_fit_enqueue(w.fit, out, s));
+    } else {
+      CPQR_TRY(fill_enqueue(out, 1, std::nan(""), s));
+    }
+  }
+  return CPQR_OK;
+}
+
+int cpqr_timing_enable(int on) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.on = on != 0;
+  return CPQR_OK;
+}
+
+int cpqr_timing_reset(void) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto& pe : t.pending) {
+    (void)hipEventSynchronize(pe.b);
+    t.pool.push_back(pe.a);
+    t.pool.push_back(pe.b);
+  }
+  t.pending.clear();
+  for (int i = 0; i < CPQR_NPHASES; ++i) {
+    t.ms[i] = 0.0;
+    t.count[i] = 0;
+  }
+  return CPQR_OK;
+}
+
+int cpqr_timing_read(double* ms, int64_t* counts, int nphases) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto& pe : t.pending) {
+    CPQR_HIP(hipEventSynchronize(pe.b));
+    float el = 0.f;
+    CPQR_HIP(hipEventElapsedTime(&el, pe.a, pe.b));
+    t.ms[pe.phase] += el;
+    t.count[pe.phase] += 1;
+    t.pool.push_back(pe.a);
+    t.pool.push_back(pe.b);
+  }
+  t.pending.clear();
+  for (int i = 0; i < nphases && i < CPQR_NPHASES; ++i) {
+    if (ms) ms[i] = t.ms[i];
+    if (counts) counts[i] = t.count[i];
+  }
+  return CPQR_OK;
+}
+
+}  // extern "C"

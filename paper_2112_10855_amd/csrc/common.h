@@ -1,0 +1,111 @@
+// Internal helpers shared by the libcpqr sources: error reporting, HIP
+// status checks, scratch carving, launch-shape helpers and the declarations
+// of each translation unit's enqueue functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/cpqr.h"
+
+namespace cpqr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define CPQR_HIP(expr)                                                               \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::cpqr::fail(CPQR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CPQR_TRY(expr)              \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != CPQR_OK) return rc_; \
+  } while (0)
+
+// Launch status right after a kernel launch.
+int check_launch(const char* what);
+
+// ---------------------------------------------------------------- scratch
+// Carves 256-byte aligned pieces from a caller buffer.  With base == nullptr
+// it only measures.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  size_t bytes() const { return (used + 255) & ~size_t(255); }
+};
+
+int check_work(void* work, size_t have, size_t need);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int round_rank(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
+inline int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// ---------------------------------------------------------------- timing
+enum Phase { PH_MULTITTM = 0, PH_TTM_FIRST = 1, PH_FACTOR_QR = 2, PH_Q0 = 3, PH_APPLY_Q0 = 4,
+             PH_SOLVE = 5, PH_ERROR = 6 };
+// Scoped phase timer: records an event pair on `stream` when timing is on.
+struct PhaseTimer {
+  int phase;
+  hipStream_t stream;
+  hipEvent_t ev0 = nullptr;
+  PhaseTimer(int ph, hipStream_t s);
+  ~PhaseTimer();
+};
+
+// ---------------------------------------------------------------- pieces
+// Each returns CPQR_OK or an error code; arguments are validated by callers.
+
+// tsqr.hip
+size_t tsqr_work(int64_t rows, int R);
+int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
+                      double* Rk, int64_t ldr, void* work, hipStream_t s);
+int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
+                   double* R0, void* work, hipStream_t s);
+
+// multittm.hip
+size_t multittm_work(int N, const int64_t* I, int n, int R, int prec);
+int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                     const double* const* Q, int prec, void* Y, void* work, hipStream_t s);
+
+// small.hip
+size_t apply_q0_work(int64_t In, int64_t K, int R);
+int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                     double* W, void* work, hipStream_t s);
+size_t solve_work(int64_t In, int R);
+int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
+                  double* A, double* lambda, int* status, void* work, hipStream_t s);
+size_t fit_direct_work(int N, const int64_t* I, int R);
+int fit_direct_enqueue(int N, const int64_t* I, int xdtype, const void* X, int R,
+                       const double* lambda, const double* const* A, double* out, void* work,
+                       hipStream_t s);
+// ||X||^2 into out[0] (device double)
+size_t norm2_work(int64_t count);
+int norm2_enqueue(int64_t count, int xdtype, const void* X, double* out, void* work, hipStream_t s);
+// efficient relative error into *relerr (device): section 3.3.1
+int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
+                            const double* lambda, const double* R0, const double* RN,
+                            const double* xnorm2, double* relerr, hipStream_t s);
+// relerr = sqrt(max(out[0],0) / out[1]) from a fit_direct result
+int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s);
+int fill_enqueue(double* p, int64_t count, double v, hipStream_t s);
+
+}  // namespace cpqr

@@ -1,0 +1,498 @@
+// Multi-TTM Y = X x_k Q_k^T for all k != n (paper section 2.2, eq. multittm;
+// Alg. 2), returned as the unfolding Y_(n).  This is the dominant cost of
+// CP-ALS-QR (section 3.2): the first contraction streams the whole tensor,
+// each later one works on a tensor R/I_k times smaller.
+//
+// Every contraction is "contract the middle index of a [P, K, S] array":
+//     T'[p, r, s] = sum_i T[p, i, s] U[i, r],   U = Q_k (K x R),
+// where P (S) is the product of the sizes of the modes before (after) the
+// contracted mode in the current tensor, all column-major.  The output keeps
+// the column-major layout with the contracted mode resized to R.
+//
+// Kernels (gfx950, wave64):
+//  * ttm_mfma_m: P a multiple of 4.  Rows m = p + P s of the [M = P S, K]
+//    matrix go on the MFMA M dimension.  Each lane loads a float4 of four
+//    consecutive p (16 lanes cover 64 contiguous floats = 256 B per K index)
+//    and feeds its four components to four v_mfma_f32_16x16x4f32 calls that
+//    share the B operand (16 columns of U).  One wavefront owns 64 rows and
+//    all R outputs; the K range can be split across workgroups (split-K) with
+//    a deterministic reduction.
+//  * ttm_mfma_k: P = 1 (contract the fastest mode), K a multiple of 4.  Each
+//    lane loads a float4 of four consecutive i of one column s; U is stored
+//    with four consecutive i interleaved so one float4 load feeds the four
+//    MFMAs.  The output is R x S.
+//  * ttm_valu: anything else, and the FP64 path: one thread per row m, all R
+//    outputs in registers, FMA on the vector ALUs.
+//  The last contraction lands in the tensor layout [P_n, I_n, S_n]; unless
+//  n is the first mode a permute kernel writes the unfolding Y_(n).
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace cpqr {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr int WPB = 4;
+constexpr int TARGET_WAVES = 4096;  // enough wavefronts to fill 256 CUs
+
+// ------------------------------------------------------------ U preparation
+// Row-major K x RP, zero padded: U[i*RP + r] = Q[i + r*ldq] (r < R).
+template <class T>
+__global__ void prep_u_rows(const double* __restrict__ Q, int64_t K, int64_t ldq, int R, int RP,
+                            T* __restrict__ U) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= K * RP) return;
+  const int64_t i = e / RP;
+  const int r = int(e % RP);
+  U[e] = r < R ? T(Q[i + r * ldq]) : T(0);
+}
+
+// Interleaved by four: U4[((i/4)*RP + r)*4 + i%4] = Q[i + r*ldq]; K % 4 == 0.
+__global__ void prep_u_quads(const double* __restrict__ Q, int64_t K, int64_t ldq, int R, int RP,
+                             float* __restrict__ U) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= K * RP) return;
+  const int64_t q = e / (int64_t(RP) * 4);
+  const int rem = int(e % (int64_t(RP) * 4));
+  const int r = rem / 4, t = rem % 4;
+  const int64_t i = q * 4 + t;
+  U[e] = r < R ? float(Q[i + r * ldq]) : 0.0f;
+}
+
+// ------------------------------------------------------------ MFMA, P % 4 == 0
+template <int NB, int UN>
+__global__ __launch_bounds__(WAVE* WPB) void ttm_mfma_m(const float* __restrict__ X,
+                                                        const float* __restrict__ U,
+                                                        float* __restrict__ out, int64_t P,
+                                                        int64_t K, int64_t S, int R, int RP,
+                                                        int64_t kchunk, int64_t split_stride) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int64_t M = P * S;
+  const int64_t mt = (int64_t(blockIdx.x) * WPB + w) * 64;
+  if (mt >= M) return;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  const int64_t mrow = mt + 4 * l16;
+  const bool mvalid = mrow < M;  // M % 4 == 0, so the four rows are valid together
+  const int64_t p = mvalid ? mrow % P : 0, s = mvalid ? mrow / P : 0;
+  const float* base = X + p + s * P * K;
+
+  floatx4 acc[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[b][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  int64_t i = k0;
+  for (; i + 4 * UN <= k1; i += 4 * UN) {
+    float4 xv[UN];
+    float bv[UN][NB];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t ii = i + 4 * u + kq;
+      xv[u] = mvalid ? *reinterpret_cast<const float4*>(base + ii * P) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[u][b] = U[ii * RP + b * 16 + l16];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].x, bv[u][b], acc[b][0], 0, 0, 0);
+        acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].y, bv[u][b], acc[b][1], 0, 0, 0);
+        acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].z, bv[u][b], acc[b][2], 0, 0, 0);
+        acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].w, bv[u][b], acc[b][3], 0, 0, 0);
+      }
+  }
+  for (; i < k1; i += 4) {
+    const int64_t ii = i + kq;
+    const bool ok = ii < k1;
+    const float4 xv = (mvalid && ok) ? *reinterpret_cast<const float4*>(base + ii * P)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float bv = ok ? U[ii * RP + b * 16 + l16] : 0.f;
+      acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[b][0], 0, 0, 0);
+      acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[b][1], 0, 0, 0);
+      acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[b][2], 0, 0, 0);
+      acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[b][3], 0, 0, 0);
+    }
+  }
+  // D layout: lane holds rows 4*kq + v (v = 0..3) of column l16.
+  float* o = out + int64_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int r = b * 16 + l16;
+    if (r >= R) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = mt + 4 * (4 * kq + v) + j;
+        if (m < M) {
+          const int64_t pp = m % P, ss = m / P;
+          o[pp + r * P + ss * P * R] = acc[b][j][v];
+        }
+      }
+  }
+}
+
+// ------------------------------------------------------------ MFMA, P == 1
+// out[r + R*s] = sum_i U[i, r] X[i + K*s]
+template <int NB, int UN>
+__global__ __launch_bounds__(WAVE* WPB) void ttm_mfma_k(const float* __restrict__ X,
+                                                        const float* __restrict__ U4,
+                                                        float* __restrict__ out, int64_t K,
+                                                        int64_t S, int R, int RP, int64_t kchunk,
+                                                        int64_t split_stride) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int64_t st = (int64_t(blockIdx.x) * WPB + w) * 16;
+  if (st >= S) return;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  const int64_t s = st + l16;
+  const bool svalid = s < S;
+  const float* col = X + (svalid ? s : 0) * K;
+
+  floatx4 acc[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[b][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  int64_t i = k0;
+  for (; i + 16 * UN <= k1; i += 16 * UN) {
+    float4 xv[UN];
+    float4 av[UN][NB];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t ii = i + 16 * u + 4 * kq;
+      xv[u] = svalid ? *reinterpret_cast<const float4*>(col + ii) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        av[u][b] = *reinterpret_cast<const float4*>(U4 + ((ii / 4) * RP + b * 16 + l16) * 4);
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].x, xv[u].x, acc[b][0], 0, 0, 0);
+        acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].y, xv[u].y, acc[b][1], 0, 0, 0);
+        acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].z, xv[u].z, acc[b][2], 0, 0, 0);
+        acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].w, xv[u].w, acc[b][3], 0, 0, 0);
+      }
+  }
+  for (; i < k1; i += 16) {
+    const int64_t ii = i + 4 * kq;
+    const bool ok = ii < k1;  // K % 4 == 0 and kchunk % 16 == 0: four valid together
+    const float4 xv = (svalid && ok) ? *reinterpret_cast<const float4*>(col + ii)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float4 av = ok ? *reinterpret_cast<const float4*>(U4 + ((ii / 4) * RP + b * 16 + l16) * 4)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[b][0], 0, 0, 0);
+      acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[b][1], 0, 0, 0);
+      acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[b][2], 0, 0, 0);
+      acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[b][3], 0, 0, 0);
+    }
+  }
+  // The four MFMAs of one step cover different i, so their sums add up.
+  float* o = out + int64_t(blockIdx.y) * split_stride;
+  if (!svalid) return;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const floatx4 t = acc[b][0] + acc[b][1] + acc[b][2] + acc[b][3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = b * 16 + 4 * kq + v;
+      if (r < R) o[r + int64_t(R) * s] = t[v];
+    }
+  }
+}
+
+// ------------------------------------------------------------ VALU fallback
+template <class TX, class TA, int RM>
+__global__ __launch_bounds__(256) void ttm_valu(const TX* __restrict__ X, const TA* __restrict__ U,
+                                                TA* __restrict__ out, int64_t P, int64_t K,
+                                                int64_t S, int R, int RP, int64_t kchunk,
+                                                int64_t split_stride) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t M = P * S;
+  if (m >= M) return;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  const int64_t p = m % P, s = m / P;
+  const TX* base = X + p + s * P * K;
+  TA acc[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) acc[r] = TA(0);
+  for (int64_t i = k0; i < k1; ++i) {
+    const TA x = TA(base[i * P]);
+    const TA* u = U + i * RP;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) acc[r] += x * u[r];
+  }
+  TA* o = out + int64_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+    if (r < R) o[p + r * P + s * P * R] = acc[r];
+}
+
+// ------------------------------------------------------------ reductions
+template <class T>
+__global__ void sum_splits(const T* __restrict__ part, int splits, int64_t count, T* __restrict__ dst) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  T acc = part[e];
+  for (int t = 1; t < splits; ++t) acc += part[int64_t(t) * count + e];
+  dst[e] = acc;
+}
+
+// Y_(n)[i + In*(p + Pn*s)] = T[p + Pn*i + Pn*In*s]
+template <class T>
+__global__ void unfold_copy(const T* __restrict__ src, int64_t Pn, int64_t In, int64_t Sn,
+                            T* __restrict__ dst) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= Pn * In * Sn) return;
+  const int64_t i = e % In, c = e / In;
+  const int64_t p = c % Pn, s = c / Pn;
+  dst[e] = src[p + Pn * i + Pn * In * s];
+}
+
+// ------------------------------------------------------------ planning
+enum Kind { K_MFMA_M, K_MFMA_K, K_VALU };
+
+struct Step {
+  int k;          // mode contracted
+  int64_t P, K, S;
+  Kind kind;
+  int splits;
+  int64_t kchunk;
+  int64_t out_count;  // P * R * S
+};
+
+struct Plan {
+  int nsteps;
+  Step st[CPQR_MAX_MODES];
+  int64_t buf_count[2];  // elements of the two ping-pong buffers
+  int64_t part_count;    // elements of the split-K partial buffer
+  int64_t final_count;   // elements of Y
+  int acc_bytes;
+  int RP;
+};
+
+bool uses_mfma(int prec) { return prec == CPQR_PREC_F32; }
+
+Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned = true) {
+  Plan pl{};
+  pl.RP = ((R + 15) / 16) * 16;
+  pl.acc_bytes = prec == CPQR_PREC_F64 ? 8 : 4;
+  int order[CPQR_MAX_MODES];
+  int no = 0;
+  for (int k = 0; k < N; ++k)
+    if (k != n) order[no++] = k;
+  std::stable_sort(order, order + no, [&](int a, int b) { return I[a] > I[b]; });
+  int64_t D[CPQR_MAX_MODES];
+  for (int k = 0; k < N; ++k) D[k] = I[k];
+  pl.nsteps = no;
+  for (int t = 0; t < no; ++t) {
+    Step s{};
+    s.k = order[t];
+    s.P = 1;
+    for (int m = 0; m < s.k; ++m) s.P *= D[m];
+    s.K = D[s.k];
+    s.S = 1;
+    for (int m = s.k + 1; m < N; ++m) s.S *= D[m];
+    s.out_count = s.P * R * s.S;
+    int64_t units;  // independent work units without splitting K
+    // float4 loads of the tensor need 16-byte alignment (carved buffers have it)
+    const bool vec_ok = t > 0 || x_aligned;
+    if (uses_mfma(prec) && vec_ok && s.P % 4 == 0) {
+      s.kind = K_MFMA_M;
+      units = ceil_div(s.P * s.S, 64);
+    } else if (uses_mfma(prec) && vec_ok && s.P == 1 && s.K % 4 == 0) {
+      s.kind = K_MFMA_K;
+      units = ceil_div(s.S, 16);
+    } else {
+      s.kind = K_VALU;
+      units = ceil_div(s.P * s.S, 64);
+    }
+    const int64_t quantum = 16;
+    int64_t splits = 1;
+    if (units < TARGET_WAVES) splits = std::min<int64_t>(ceil_div(TARGET_WAVES, units), std::max<int64_t>(1, s.K / 64));
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
+    s.kchunk = ceil_div(ceil_div(s.K, splits), quantum) * quantum;
+    s.splits = int(ceil_div(s.K, s.kchunk));
+    if (s.splits > 1) pl.part_count = std::max(pl.part_count, s.out_count * s.splits);
+    D[s.k] = R;
+    pl.st[t] = s;
+    pl.buf_count[t % 2] = std::max(pl.buf_count[t % 2], s.out_count);
+  }
+  pl.final_count = I[n] * ipow(R, N - 1);
+  return pl;
+}
+
+struct Bufs {
+  void* U[CPQR_MAX_MODES];
+  void* buf[2];
+  void* part;
+};
+
+size_t carve(Carver& cv, const Plan& pl, int N, const int64_t* I, int n, Bufs* b) {
+  Bufs tmp{};
+  for (int t = 0; t < pl.nsteps; ++t) {
+    const int k = pl.st[t].k;
+    tmp.U[k] = cv.take<char>(size_t(I[k] + 4) * pl.RP * pl.acc_bytes);
+  }
+  for (int j = 0; j < 2; ++j) tmp.buf[j] = cv.take<char>(size_t(pl.buf_count[j]) * pl.acc_bytes);
+  tmp.part = cv.take<char>(size_t(pl.part_count) * pl.acc_bytes);
+  if (b) *b = tmp;
+  return cv.bytes();
+}
+
+template <class TA, int RM>
+int launch_valu(const void* src, int src_dtype, const TA* U, TA* dst, const Step& s, int R, int RP,
+                hipStream_t st) {
+  const dim3 grd(unsigned(ceil_div(s.P * s.S, 256)), unsigned(s.splits));
+  if (src_dtype == CPQR_F64)
+    hipLaunchKernelGGL((ttm_valu<double, TA, RM>), grd, dim3(256), 0, st,
+                       static_cast<const double*>(src), U, dst, s.P, s.K, s.S, R, RP, s.kchunk,
+                       s.out_count);
+  else
+    hipLaunchKernelGGL((ttm_valu<float, TA, RM>), grd, dim3(256), 0, st,
+                       static_cast<const float*>(src), U, dst, s.P, s.K, s.S, R, RP, s.kchunk,
+                       s.out_count);
+  return check_launch("ttm_valu");
+}
+
+template <class TA>
+int launch_valu_r(const void* src, int src_dtype, const TA* U, TA* dst, const Step& s, int R,
+                  int RP, hipStream_t st) {
+  switch (round_rank(R)) {
+    case 8: return launch_valu<TA, 8>(src, src_dtype, U, dst, s, R, RP, st);
+    case 16: return launch_valu<TA, 16>(src, src_dtype, U, dst, s, R, RP, st);
+    default: return launch_valu<TA, 32>(src, src_dtype, U, dst, s, R, RP, st);
+  }
+}
+
+int launch_mfma(const float* src, const float* U, float* dst, const Step& s, int R, int RP,
+                hipStream_t st) {
+  const int NB = RP / 16;
+  constexpr int UN = 4;
+  if (s.kind == K_MFMA_M) {
+    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64), WPB)), unsigned(s.splits));
+    if (NB == 1)
+      hipLaunchKernelGGL((ttm_mfma_m<1, UN>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.P, s.K, s.S,
+                         R, RP, s.kchunk, s.out_count);
+    else
+      hipLaunchKernelGGL((ttm_mfma_m<2, UN>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.P, s.K, s.S,
+                         R, RP, s.kchunk, s.out_count);
+    return check_launch("ttm_mfma_m");
+  }
+  const dim3 grd(unsigned(ceil_div(ceil_div(s.S, 16), WPB)), unsigned(s.splits));
+  if (NB == 1)
+    hipLaunchKernelGGL((ttm_mfma_k<1, 2>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.K, s.S, R,
+                       RP, s.kchunk, s.out_count);
+  else
+    hipLaunchKernelGGL((ttm_mfma_k<2, 2>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.K, s.S, R,
+                       RP, s.kchunk, s.out_count);
+  return check_launch("ttm_mfma_k");
+}
+
+}  // namespace
+
+size_t multittm_work(int N, const int64_t* I, int n, int R, int prec) {
+  Plan pl = make_plan(N, I, n, R, prec);
+  Carver cv(nullptr);
+  return carve(cv, pl, N, I, n, nullptr);
+}
+
+int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                     const double* const* Q, int prec, void* Y, void* work, hipStream_t st) {
+  PhaseTimer whole(PH_MULTITTM, st);
+  if (prec == CPQR_PREC_BF16 || prec == CPQR_PREC_BF16X2)
+    return fail(CPQR_ERR_UNSUPPORTED, "multittm: bfloat16 forms are not built in this library");
+  const Plan pl = make_plan(N, I, n, R, prec, reinterpret_cast<uintptr_t>(X) % 16 == 0);
+  Bufs b;
+  Carver cv(work);
+  carve(cv, pl, N, I, n, &b);
+  const int RP = pl.RP;
+  const bool f64 = prec == CPQR_PREC_F64;
+
+  // operand preparation
+  for (int t = 0; t < pl.nsteps; ++t) {
+    const Step& s = pl.st[t];
+    const int64_t cnt = s.K * RP;
+    const dim3 grd(unsigned(ceil_div(cnt, 256)));
+    if (f64)
+      hipLaunchKernelGGL(prep_u_rows<double>, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
+                         static_cast<double*>(b.U[s.k]));
+    else if (s.kind == K_MFMA_K)
+      hipLaunchKernelGGL(prep_u_quads, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
+                         static_cast<float*>(b.U[s.k]));
+    else
+      hipLaunchKernelGGL(prep_u_rows<float>, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
+                         static_cast<float*>(b.U[s.k]));
+    CPQR_TRY(check_launch("prep_u"));
+  }
+
+  const void* cur = X;
+  int cur_dtype = xdtype;
+  int64_t Pn = 1, Sn = 1;
+  for (int t = 0; t < pl.nsteps; ++t) {
+    const Step& s = pl.st[t];
+    const bool last = t + 1 == pl.nsteps;
+    void* dst = (last && n == 0) ? Y : b.buf[t % 2];
+    void* kout = s.splits > 1 ? b.part : dst;
+    {
+      PhaseTimer first(t == 0 ? PH_TTM_FIRST : -1, st);
+      if (f64) {
+        CPQR_TRY(launch_valu_r<double>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
+                                       static_cast<double*>(kout), s, R, RP, st));
+      } else if (s.kind == K_VALU) {
+        CPQR_TRY(launch_valu_r<float>(cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
+                                      static_cast<float*>(kout), s, R, RP, st));
+      } else {
+        CPQR_TRY(launch_mfma(static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
+                             static_cast<float*>(kout), s, R, RP, st));
+      }
+      if (s.splits > 1) {
+        const dim3 grd(unsigned(ceil_div(s.out_count, 256)));
+        if (f64)
+          hipLaunchKernelGGL(sum_splits<double>, grd, dim3(256), 0, st,
+                             static_cast<const double*>(b.part), s.splits, s.out_count,
+                             static_cast<double*>(dst));
+        else
+          hipLaunchKernelGGL(sum_splits<float>, grd, dim3(256), 0, st,
+                             static_cast<const float*>(b.part), s.splits, s.out_count,
+                             static_cast<float*>(dst));
+        CPQR_TRY(check_launch("sum_splits"));
+      }
+    }
+    cur = dst;
+    cur_dtype = f64 ? CPQR_F64 : CPQR_F32;
+  }
+  if (n != 0) {
+    for (int m = 0; m < n; ++m) Pn *= R;
+    for (int m = n + 1; m < N; ++m) Sn *= R;
+    const int64_t cnt = Pn * I[n] * Sn;
+    const dim3 grd(unsigned(ceil_div(cnt, 256)));
+    if (f64)
+      hipLaunchKernelGGL(unfold_copy<double>, grd, dim3(256), 0, st, static_cast<const double*>(cur),
+                         Pn, I[n], Sn, static_cast<double*>(Y));
+    else
+      hipLaunchKernelGGL(unfold_copy<float>, grd, dim3(256), 0, st, static_cast<const float*>(cur),
+                         Pn, I[n], Sn, static_cast<float*>(Y));
+    CPQR_TRY(check_launch("unfold_copy"));
+  }
+  return CPQR_OK;
+}
+
+}  // namespace cpqr

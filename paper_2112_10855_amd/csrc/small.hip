@@ -1,0 +1,564 @@
+// The small FP64 steps of a CP-ALS-QR mode update (paper Alg. 2, section 3.1)
+// and the error forms of section 3.3.1:
+//   apply_q0     W = Y_(n) Q_0                   (split over the long K index)
+//   solve        Ahat R_0^T = W by substitution, or Ahat = W U S^+ V^T from a
+//                one-sided Jacobi SVD of R_0 (CP-ALS-QR-SVD)
+//   normalize    lambda_r = ||Ahat(:,r)||_2, A = Ahat / lambda
+//   errors       efficient (from W_N, R_0, R_N, lambda) and direct (stream X)
+// Everything is FP64; reductions are two-level and deterministic.
+
+#include "common.h"
+
+namespace cpqr {
+namespace {
+
+constexpr int BLK = 256;
+
+template <class T>
+__device__ inline T block_sum(T v, T* sh) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T t = 0;
+  const int nw = blockDim.x / 64;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  return t;
+}
+
+// ------------------------------------------------------------ apply Q_0
+// part[split][i + c*In] = sum over this split's rho of Y[i + rho*In] Q0[rho + c*K]
+template <class TY, int RM>
+__global__ __launch_bounds__(BLK) void apply_q0_kernel(const TY* __restrict__ Y,
+                                                       const double* __restrict__ Q0, double* part,
+                                                       int64_t In, int64_t K, int R, int64_t kchunk) {
+  __shared__ double q0s[64][RM];
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  double acc[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) acc[c] = 0.0;
+  for (int64_t t0 = k0; t0 < k1; t0 += 64) {
+    const int nt = int(min<int64_t>(64, k1 - t0));
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * RM; e += BLK) {
+      const int rr = e % 64, c = e / 64;
+      q0s[rr][c] = (rr < nt && c < R) ? Q0[t0 + rr + int64_t(c) * K] : 0.0;
+    }
+    __syncthreads();
+    if (i < In) {
+      for (int rr = 0; rr < nt; ++rr) {
+        const double y = double(Y[i + (t0 + rr) * In]);
+#pragma unroll
+        for (int c = 0; c < RM; ++c) acc[c] += y * q0s[rr][c];
+      }
+    }
+  }
+  if (i < In) {
+    double* o = part + int64_t(blockIdx.y) * In * R;
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      if (c < R) o[i + c * In] = acc[c];
+  }
+}
+
+__global__ void sum_parts(const double* __restrict__ part, int splits, int64_t count, double* dst) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double a = part[e];
+  for (int t = 1; t < splits; ++t) a += part[int64_t(t) * count + e];
+  dst[e] = a;
+}
+
+// ------------------------------------------------------------ solves
+// Back substitution per row: R0 ahat = w  <=>  ahat^T R0^T = w^T.
+template <int RM>
+__global__ __launch_bounds__(BLK) void solve_tri_kernel(const double* __restrict__ W,
+                                                        const double* __restrict__ R0, double* A,
+                                                        int64_t In, int R, int* status) {
+  __shared__ double r0[RM][RM + 1];
+  for (int e = threadIdx.x; e < R * R; e += BLK) r0[e % R][e / R] = R0[e];
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && status) {
+    int bad = 0;
+    for (int j = 0; j < R; ++j) {
+      const double d = r0[j][j];
+      if (d == 0.0 || !isfinite(d)) bad = 1;
+    }
+    if (bad) atomicOr(status, CPQR_STATUS_SINGULAR);
+  }
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (i >= In) return;
+  double a[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) a[c] = c < R ? W[i + c * In] : 0.0;
+#pragma unroll
+  for (int j = RM - 1; j >= 0; --j) {
+    if (j >= R) continue;
+    double v = a[j];
+#pragma unroll
+    for (int c = j + 1; c < RM; ++c)
+      if (c < R) v -= r0[j][c] * a[c];
+    a[j] = v / r0[j][j];
+  }
+  bool nonfinite = false;
+#pragma unroll
+  for (int c = 0; c < RM; ++c)
+    if (c < R) {
+      A[i + c * In] = a[c];
+      nonfinite |= !isfinite(a[c]);
+    }
+  if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
+}
+
+// One-sided Jacobi SVD of R0 (R x R, R <= 32) in one workgroup, then
+// M = U S^+ V^T with singular values <= rtol * sigma_max dropped.
+// Thread layout: 16 pairs x 32 rows; a pair's dot products are reductions
+// over the 32 lanes of a half wavefront.
+__global__ __launch_bounds__(512) void svd_pinv_kernel(const double* __restrict__ R0, int R,
+                                                       double rtol, double* M, int* kept_out,
+                                                       int* status) {
+  __shared__ double G[32][33];  // columns of R0 V (rows x cols)
+  __shared__ double Vm[32][33];
+  __shared__ double sig[32];
+  __shared__ int rotated;
+  const int tid = threadIdx.x;
+  const int pr = tid / 32, row = tid % 32;
+  for (int e = tid; e < 32 * 32; e += 512) {
+    const int i = e % 32, j = e / 32;
+    G[i][j] = (i < R && j < R) ? R0[i + j * R] : 0.0;
+    Vm[i][j] = (i == j && i < R) ? 1.0 : 0.0;
+  }
+  const int Rp = R + (R & 1);  // even number of players for the round robin
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < Rp - 1; ++round) {
+      int p = -1, q = -1;
+      if (pr < Rp / 2) {
+        auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (Rp - 1)) + 1; };
+        p = pos(pr);
+        q = pos(Rp - 1 - pr);
+        if (p > q) { int t = p; p = q; q = t; }
+      }
+      const bool active = p >= 0 && q < R;
+      double gp = active ? G[row][p] : 0.0, gq = active ? G[row][q] : 0.0;
+      double al = gp * gp, be = gq * gq, ga = gp * gq;
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, 32);
+        be += __shfl_xor(be, off, 32);
+        ga += __shfl_xor(ga, off, 32);
+      }
+      __syncthreads();
+      if (active && fabs(ga) > eps * sqrt(al * be) && ga != 0.0) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        G[row][p] = c * gp - s * gq;
+        G[row][q] = s * gp + c * gq;
+        const double vp = Vm[row][p], vq = Vm[row][q];
+        Vm[row][p] = c * vp - s * vq;
+        Vm[row][q] = s * vp + c * vq;
+        if (row == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid < 32) {
+    double s2 = 0.0;
+    for (int i = 0; i < R; ++i) s2 += G[i][tid] * G[i][tid];
+    sig[tid] = tid < R ? sqrt(s2) : 0.0;
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int j = 0; j < R; ++j) smax = fmax(smax, sig[j]);
+  const double tau = rtol * smax;
+  // M = sum over kept j of (G(:,j)/sigma_j^2) V(:,j)^T   (U_j = G(:,j)/sigma_j)
+  for (int e = tid; e < R * R; e += 512) {
+    const int a = e % R, b = e / R;
+    double v = 0.0;
+    for (int j = 0; j < R; ++j)
+      if (sig[j] > tau && sig[j] > 0.0) v += G[a][j] * Vm[b][j] / (sig[j] * sig[j]);
+    M[a + b * R] = v;
+  }
+  if (tid == 0) {
+    int kept = 0;
+    for (int j = 0; j < R; ++j) kept += (sig[j] > tau && sig[j] > 0.0) ? 1 : 0;
+    *kept_out = kept;
+    if (kept < R && status) atomicOr(status, CPQR_STATUS_TRUNCATED);
+  }
+}
+
+// Ahat = W M (row by row)
+template <int RM>
+__global__ __launch_bounds__(BLK) void rowmul_kernel(const double* __restrict__ W,
+                                                     const double* __restrict__ Mm, double* A,
+                                                     int64_t In, int R, int* status) {
+  __shared__ double m[RM][RM];
+  for (int e = threadIdx.x; e < R * R; e += BLK) m[e % R][e / R] = Mm[e];
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (i >= In) return;
+  double w[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) w[c] = c < R ? W[i + c * In] : 0.0;
+  bool nonfinite = false;
+#pragma unroll
+  for (int b = 0; b < RM; ++b) {
+    if (b >= R) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < RM; ++a)
+      if (a < R) v += w[a] * m[a][b];
+    A[i + b * In] = v;
+    nonfinite |= !isfinite(v);
+  }
+  if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
+}
+
+// lambda_c = ||A(:,c)||, A(:,c) /= lambda_c (one workgroup per column)
+__global__ __launch_bounds__(BLK) void normalize_kernel(double* A, double* lambda, int64_t In,
+                                                        int* status) {
+  __shared__ double sh[BLK / 64];
+  const int c = blockIdx.x;
+  double* col = A + int64_t(c) * In;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < In; i += BLK) s += col[i] * col[i];
+  const double nrm = sqrt(block_sum(s, sh));
+  if (threadIdx.x == 0) {
+    lambda[c] = nrm;
+    if (nrm == 0.0 && status) atomicOr(status, CPQR_STATUS_ZERO_COLUMN);
+  }
+  if (nrm > 0.0) {
+    const double inv = 1.0 / nrm;
+    for (int64_t i = threadIdx.x; i < In; i += BLK) col[i] *= inv;
+  }
+}
+
+// ------------------------------------------------------------ errors
+// relerr = sqrt(max(x2 - 2 ip + nn, 0) / x2) with
+// ip = <W, Ahat R0^T>, Ahat = A diag(lambda), nn = <R0^T R0, diag(l) RN^T RN diag(l)>
+template <int RM>
+__global__ __launch_bounds__(BLK) void error_efficient_kernel(
+    const double* __restrict__ W, const double* __restrict__ A, const double* __restrict__ lam,
+    const double* __restrict__ R0, const double* __restrict__ RN, int64_t In, int R,
+    const double* __restrict__ xnorm2, double* relerr) {
+  __shared__ double r0[RM][RM + 1];
+  __shared__ double l[RM];
+  __shared__ double sh[BLK / 64];
+  for (int e = threadIdx.x; e < R * R; e += BLK) r0[e % R][e / R] = R0[e];
+  for (int e = threadIdx.x; e < R; e += BLK) l[e] = lam[e];
+  __syncthreads();
+  double ip = 0.0;
+  for (int64_t i = threadIdx.x; i < In; i += BLK) {
+    double ah[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) ah[k] = k < R ? A[i + k * In] * l[k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      if (c >= R) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k >= c && k < R) v += ah[k] * r0[c][k];
+      ip += W[i + c * In] * v;
+    }
+  }
+  ip = block_sum(ip, sh);
+  double nn = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += BLK) {
+    const int a = e % R, b = e / R;
+    double g0 = 0.0, gn = 0.0;
+    for (int k = 0; k < R; ++k) {
+      g0 += r0[k][a] * r0[k][b];
+      gn += RN[k + a * R] * RN[k + b * R];
+    }
+    nn += g0 * l[a] * l[b] * gn;
+  }
+  nn = block_sum(nn, sh);
+  if (threadIdx.x == 0) {
+    const double x2 = *xnorm2;
+    const double r2 = x2 - 2.0 * ip + nn;
+    *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
+  }
+}
+
+__global__ void error_from_fit_kernel(const double* fit, double* relerr) {
+  const double r2 = fit[0];
+  *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / fit[1]);
+}
+
+__global__ void fill_kernel(double* p, int64_t count, double v) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = v;
+}
+
+// partial sums of x^2 (grid-stride), then a one-block final sum
+template <class TX>
+__global__ __launch_bounds__(BLK) void norm2_partial(const TX* __restrict__ X, int64_t count,
+                                                     double* part) {
+  __shared__ double sh[BLK / 64];
+  double s = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * BLK + threadIdx.x; e < count; e += int64_t(gridDim.x) * BLK) {
+    const double v = double(X[e]);
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BLK) void sum_final(const double* part, int n, int stride, double* out) {
+  __shared__ double sh[BLK / 64];
+  for (int c = 0; c < stride; ++c) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n; e += BLK) s += part[int64_t(e) * stride + c];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[c] = s;
+    __syncthreads();
+  }
+}
+
+struct FactorPtrs {
+  const double* A[CPQR_MAX_MODES];
+  int64_t I[CPQR_MAX_MODES];
+};
+
+// Direct residual: X viewed as [I0, S]; workgroup = 256 rows x CS columns.
+// The coefficients lambda_r prod_{k>0} A_k(i_k, r) of CS columns are built in
+// LDS; each thread keeps its row of A_0 in registers.
+constexpr int CS = 64;
+template <class TX, int RM>
+__global__ __launch_bounds__(BLK) void fit_direct_kernel(const TX* __restrict__ X, FactorPtrs f,
+                                                         int N, const double* __restrict__ lam,
+                                                         int R, int64_t I0, int64_t S,
+                                                         double* part) {
+  __shared__ double coef[CS][RM + 1];
+  __shared__ double sh[BLK / 64];
+  const int64_t i = int64_t(blockIdx.y) * BLK + threadIdx.x;
+  const int64_t s0 = int64_t(blockIdx.x) * CS;
+  const int ns = int(min<int64_t>(CS, S - s0));
+  for (int e = threadIdx.x; e < CS * R; e += BLK) {
+    const int sl = e % CS, r = e / CS;
+    double v = 0.0;
+    if (sl < ns) {
+      v = lam[r];
+      int64_t rest = s0 + sl;
+      for (int k = 1; k < N; ++k) {
+        const int64_t ik = rest % f.I[k];
+        rest /= f.I[k];
+        v *= f.A[k][ik + int64_t(r) * f.I[k]];
+      }
+    }
+    coef[sl][r] = v;
+  }
+  __syncthreads();
+  double d2 = 0.0, x2 = 0.0;
+  if (i < I0) {
+    double a[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) a[r] = r < R ? f.A[0][i + int64_t(r) * I0] : 0.0;
+    for (int sl = 0; sl < ns; ++sl) {
+      double mdl = 0.0;
+#pragma unroll
+      for (int r = 0; r < RM; ++r) mdl += a[r] * coef[sl][r];
+      const double x = double(X[i + (s0 + sl) * I0]);
+      const double d = x - mdl;
+      d2 += d * d;
+      x2 += x * x;
+    }
+  }
+  d2 = block_sum(d2, sh);
+  x2 = block_sum(x2, sh);
+  if (threadIdx.x == 0) {
+    const int64_t b = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;  // < gridDim.x * gridDim.y
+    part[2 * b] = d2;
+    part[2 * b + 1] = x2;
+  }
+}
+
+int64_t apply_splits(int64_t In, int64_t K) {
+  const int64_t rb = ceil_div(In, BLK);
+  int64_t sp = std::max<int64_t>(1, std::min<int64_t>(ceil_div(1024, rb), ceil_div(K, 64)));
+  return std::min<int64_t>(sp, 512);
+}
+
+constexpr int NORM_BLOCKS = 2048;
+
+}  // namespace
+
+size_t apply_q0_work(int64_t In, int64_t K, int R) {
+  Carver cv(nullptr);
+  cv.take<double>(size_t(apply_splits(In, K)) * In * R);
+  return cv.bytes();
+}
+
+int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                     double* W, void* work, hipStream_t s) {
+  PhaseTimer pt(PH_APPLY_Q0, s);
+  const int64_t sp = apply_splits(In, K);
+  const int64_t kchunk = ceil_div(ceil_div(K, sp), 64) * 64;
+  const int64_t splits = ceil_div(K, kchunk);
+  Carver cv(work);
+  double* part = cv.take<double>(size_t(sp) * In * R);
+  const dim3 grd(unsigned(ceil_div(In, BLK)), unsigned(splits));
+  const int RM = round_rank(R);
+#define APPLY(TY, RMV)                                                                             \
+  hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, \
+                     splits > 1 ? part : W, In, K, R, kchunk)
+  if (ydtype == CPQR_F64) {
+    if (RM == 8) APPLY(double, 8); else if (RM == 16) APPLY(double, 16); else APPLY(double, 32);
+  } else {
+    if (RM == 8) APPLY(float, 8); else if (RM == 16) APPLY(float, 16); else APPLY(float, 32);
+  }
+#undef APPLY
+  CPQR_TRY(check_launch("apply_q0"));
+  if (splits > 1) {
+    const int64_t cnt = In * R;
+    hipLaunchKernelGGL(sum_parts, dim3(unsigned(ceil_div(cnt, BLK))), dim3(BLK), 0, s, part,
+                       int(splits), cnt, W);
+    CPQR_TRY(check_launch("apply_q0 sum"));
+  }
+  return CPQR_OK;
+}
+
+size_t solve_work(int64_t In, int R) {
+  (void)In;
+  Carver cv(nullptr);
+  cv.take<double>(size_t(R) * R);
+  cv.take<int>(4);
+  return cv.bytes();
+}
+
+int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
+                  double* A, double* lambda, int* status, void* work, hipStream_t s) {
+  PhaseTimer pt(PH_SOLVE, s);
+  Carver cv(work);
+  double* M = cv.take<double>(size_t(R) * R);
+  int* kept = cv.take<int>(4);
+  const dim3 grd(unsigned(ceil_div(In, BLK)));
+  const int RM = round_rank(R);
+  if (!use_svd) {
+    if (RM == 8)
+      hipLaunchKernelGGL((solve_tri_kernel<8>), grd, dim3(BLK), 0, s, W, R0, A, In, R, status);
+    else if (RM == 16)
+      hipLaunchKernelGGL((solve_tri_kernel<16>), grd, dim3(BLK), 0, s, W, R0, A, In, R, status);
+    else
+      hipLaunchKernelGGL((solve_tri_kernel<32>), grd, dim3(BLK), 0, s, W, R0, A, In, R, status);
+    CPQR_TRY(check_launch("solve_tri"));
+  } else {
+    if (rtol < 0) rtol = R * 2.220446049250313e-16;
+    hipLaunchKernelGGL(svd_pinv_kernel, dim3(1), dim3(512), 0, s, R0, R, rtol, M, kept, status);
+    CPQR_TRY(check_launch("svd_pinv"));
+    if (RM == 8)
+      hipLaunchKernelGGL((rowmul_kernel<8>), grd, dim3(BLK), 0, s, W, M, A, In, R, status);
+    else if (RM == 16)
+      hipLaunchKernelGGL((rowmul_kernel<16>), grd, dim3(BLK), 0, s, W, M, A, In, R, status);
+    else
+      hipLaunchKernelGGL((rowmul_kernel<32>), grd, dim3(BLK), 0, s, W, M, A, In, R, status);
+    CPQR_TRY(check_launch("rowmul"));
+  }
+  hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
+  return check_launch("normalize");
+}
+
+size_t norm2_work(int64_t count) {
+  (void)count;
+  Carver cv(nullptr);
+  cv.take<double>(NORM_BLOCKS);
+  return cv.bytes();
+}
+
+int norm2_enqueue(int64_t count, int xdtype, const void* X, double* out, void* work, hipStream_t s) {
+  Carver cv(work);
+  double* part = cv.take<double>(NORM_BLOCKS);
+  const int nb = int(std::min<int64_t>(NORM_BLOCKS, std::max<int64_t>(1, ceil_div(count, BLK * 8))));
+  if (xdtype == CPQR_F64)
+    hipLaunchKernelGGL(norm2_partial<double>, dim3(nb), dim3(BLK), 0, s, static_cast<const double*>(X),
+                       count, part);
+  else
+    hipLaunchKernelGGL(norm2_partial<float>, dim3(nb), dim3(BLK), 0, s, static_cast<const float*>(X),
+                       count, part);
+  CPQR_TRY(check_launch("norm2"));
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(BLK), 0, s, part, nb, 1, out);
+  return check_launch("norm2 final");
+}
+
+int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
+                            const double* lambda, const double* R0, const double* RN,
+                            const double* xnorm2, double* relerr, hipStream_t s) {
+  PhaseTimer pt(PH_ERROR, s);
+  const int RM = round_rank(R);
+  if (RM == 8)
+    hipLaunchKernelGGL((error_efficient_kernel<8>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
+                       R, xnorm2, relerr);
+  else if (RM == 16)
+    hipLaunchKernelGGL((error_efficient_kernel<16>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
+                       R, xnorm2, relerr);
+  else
+    hipLaunchKernelGGL((error_efficient_kernel<32>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
+                       R, xnorm2, relerr);
+  return check_launch("error_efficient");
+}
+
+int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s) {
+  hipLaunchKernelGGL(error_from_fit_kernel, dim3(1), dim3(1), 0, s, fit, relerr);
+  return check_launch("error_from_fit");
+}
+
+int fill_enqueue(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return CPQR_OK;
+  hipLaunchKernelGGL(fill_kernel, dim3(unsigned(ceil_div(count, BLK))), dim3(BLK), 0, s, p, count, v);
+  return check_launch("fill");
+}
+
+size_t fit_direct_work(int N, const int64_t* I, int R) {
+  (void)R;
+  int64_t S = 1;
+  for (int k = 1; k < N; ++k) S *= I[k];
+  const int64_t nb = ceil_div(I[0], BLK) * ceil_div(S, CS);
+  Carver cv(nullptr);
+  cv.take<double>(size_t(2 * nb));
+  return cv.bytes();
+}
+
+int fit_direct_enqueue(int N, const int64_t* I, int xdtype, const void* X, int R,
+                       const double* lambda, const double* const* A, double* out, void* work,
+                       hipStream_t s) {
+  PhaseTimer pt(PH_ERROR, s);
+  FactorPtrs f{};
+  int64_t S = 1;
+  for (int k = 0; k < N; ++k) {
+    f.A[k] = A[k];
+    f.I[k] = I[k];
+    if (k > 0) S *= I[k];
+  }
+  // column chunks on x (up to 2^31-1), row blocks on y (up to 65535)
+  const int64_t gx = ceil_div(S, CS), gy = ceil_div(I[0], BLK);
+  if (gx > 0x7fffffff || gy > 65535) return fail(CPQR_ERR_SHAPE, "fit_direct: tensor too large");
+  Carver cv(work);
+  double* part = cv.take<double>(size_t(2 * gx * gy));
+  const dim3 grd{unsigned(gx), unsigned(gy)};
+  const int RM = round_rank(R);
+#define FIT(TX, RMV)                                                                                \
+  hipLaunchKernelGGL((fit_direct_kernel<TX, RMV>), grd, dim3(BLK), 0, s, static_cast<const TX*>(X), f, N, \
+                     lambda, R, I[0], S, part)
+  if (xdtype == CPQR_F64) {
+    if (RM == 8) FIT(double, 8); else if (RM == 16) FIT(double, 16); else FIT(double, 32);
+  } else {
+    if (RM == 8) FIT(float, 8); else if (RM == 16) FIT(float, 16); else FIT(float, 32);
+  }
+#undef FIT
+  CPQR_TRY(check_launch("fit_direct"));
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(BLK), 0, s, part, int(gx * gy), 2, out);
+  return check_launch("fit_direct final");
+}
+
+}  // namespace cpqr

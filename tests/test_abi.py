@@ -1,0 +1,113 @@
+"""The C-ABI library loads on a host without a GPU, exports every symbol
+include/cpqr.h declares, and rejects bad arguments with the documented error
+codes before touching the device (no compute calls here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2112_10855_amd import cpqr as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(C.LIBPATH):
+        from paper_2112_10855_amd import build
+        build.build()
+    return C.lib()
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "cpqr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpqr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(C.EXPORTED)
+
+
+def test_version(L):
+    assert L.cpqr_version() == 100
+
+
+def code(rc):
+    return rc
+
+
+def test_validation_codes(L):
+    P = 4096  # fake, never dereferenced: validation fails first
+    assert L.cpqr_factor_qr(10, 0, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
+    assert L.cpqr_factor_qr(10, 33, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
+    assert L.cpqr_factor_qr(3, 4, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
+    assert L.cpqr_factor_qr(10, 4, None, 10, P, 10, P, 10, P, 1 << 20, None) == -1
+    assert L.cpqr_factor_qr(10, 4, P, 9, P, 10, P, 10, P, 1 << 20, None) == -2
+    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, None, 0, None) == -4
+    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, P + 8, 1 << 20, None) == -4
+    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, P, 16, None) == -4
+    assert b"too small" in L.cpqr_last_error()
+
+    I = C._i64_array([10, 11, 12])
+    Qs = C._ptr_array([None, None, None])
+    assert L.cpqr_multittm(3, I, 0, P, 0, 4, Qs, 1, P, P, 1 << 30, None) == -1  # Q[1] NULL
+    Qs = (ctypes.c_void_p * 3)(P, P, P)
+    assert L.cpqr_multittm(3, I, 1, P, 0, 4, Qs, 1, P, P, 1 << 30, None) == -3  # F64 X with F32 prec
+    assert L.cpqr_multittm(3, I, 0, P, 3, 4, Qs, 1, P, P, 1 << 30, None) == -1  # n out of range
+    assert L.cpqr_multittm(1, I, 0, P, 0, 4, Qs, 1, P, P, 1 << 30, None) == -2  # N < 2
+    assert L.cpqr_multittm(3, I, 0, P, 0, 4, Qs, 9, P, P, 1 << 30, None) == -1  # bad precision
+    I0 = C._i64_array([10, 0, 12])
+    assert L.cpqr_multittm(3, I0, 0, P, 0, 4, Qs, 1, P, P, 1 << 30, None) == -2
+
+    assert L.cpqr_krp_qr(3, 3, 4, Qs, 4, P, P, P, 1 << 30, None) == -1
+    assert L.cpqr_krp_qr(11, 0, 4, Qs, 4, P, P, P, 1 << 30, None) == -2
+    assert L.cpqr_krp_qr(3, 0, 4, Qs, 3, P, P, P, 1 << 30, None) == -2
+    assert L.cpqr_apply_q0(10, 3, 4, 0, P, P, P, P, 1 << 30, None) == -2
+    assert L.cpqr_apply_q0(10, 16, 4, 7, P, P, P, P, 1 << 30, None) == -3
+    assert L.cpqr_solve_rsvd(0, 4, P, P, 0, -1.0, P, P, None, P, 1 << 30, None) == -2
+    assert L.cpqr_solve_rsvd(10, 4, None, P, 0, -1.0, P, P, None, P, 1 << 30, None) == -1
+    assert L.cpqr_solve_rsvd(10, 4, P, P, 0, float("nan"), P, P, None, P, 1 << 30, None) == -1
+    assert L.cpqr_fit_direct(3, I, 2, P, 4, P, Qs, P, P, 1 << 30, None) == -3
+
+    p = C.Problem()
+    p.N, p.R = 3, 4
+    for k in range(3):
+        p.I[k] = 10
+        p.A[k] = p.Q[k] = p.Rf[k] = P
+    p.X, p.lam, p.xdtype, p.prec, p.error_mode = P, P, 0, 1, 0
+    assert L.cpqr_als_work(ctypes.byref(p)) > 0
+    p.I[2] = 3  # smaller than the rank
+    assert L.cpqr_als_work(ctypes.byref(p)) == 0
+    assert L.cpqr_als_init(ctypes.byref(p), P, 1 << 30, None) == -2
+    p.I[2] = 10
+    p.error_mode = 5
+    assert L.cpqr_als_sweep(ctypes.byref(p), 1, None, P, 1 << 30, None) == -1
+    p.error_mode = 0
+    assert L.cpqr_als_sweep(ctypes.byref(p), -1, None, P, 1 << 30, None) == -1
+    assert L.cpqr_als_sweep(ctypes.byref(p), 1, None, P, 16, None) == -4
+    assert L.cpqr_als_sweep(None, 1, None, P, 16, None) == -1
+
+
+def test_workspace_queries(L):
+    assert L.cpqr_factor_qr_work(1000, 16) > 0
+    assert L.cpqr_factor_qr_work(1000, 0) == 0
+    assert L.cpqr_krp_qr_work(4, 32) >= 32768 * 32 * 8
+    for n in range(3):
+        w = L.cpqr_multittm_work(3, C._i64_array([1000, 1000, 1000]), n, 16, 1)
+        assert 64e6 <= w < 200e6  # one 64 MB intermediate plus small pieces
+    assert L.cpqr_apply_q0_work(200, 32768, 32) > 0
+    assert L.cpqr_fit_direct_work(3, C._i64_array([50, 50, 50]), 5) > 0
+
+
+def test_no_cpu_fallback():
+    """The binding refuses host tensors instead of computing on the CPU."""
+    import torch
+    with pytest.raises(TypeError):
+        C.cpqr_factor_qr(torch.zeros(8, 2, dtype=torch.float64))

@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full size and launch configuration: the
+1000 x 1000 x 1000 FP32 tensor at rank 16 (4 GB), through the same C-ABI
+calls bench.py times.
+
+  * Multi-TTM for every mode: sampled rows of Y_(n), each computed by the
+    oracle from the single slab X(.., i_n, ..) it depends on, including the
+    first and last row (ragged tile tails).
+  * One full CP-ALS-QR sweep from the shared start, against one oracle
+    sweep on the same bytes (FP64): relative error and Kruskal model.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.cp_als_qr as OQ
+from oracle import tensor as OT
+from paper_2112_10855_amd import cpqr as C
+from paper_2112_10855_amd import synth
+from helpers import relnorm, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+N1 = 1000
+R = 16
+
+
+@pytest.fixture(scope="module")
+def big():
+    print("\n[fullsize] generating %d^3 FP32 workload" % N1, flush=True)
+    d = synth.workload_large3(n=N1, R=R)
+    X = d["X"]
+    Xd = torch.from_numpy(X.reshape(-1, order="F")).to("cuda").view(N1, N1, N1).permute(2, 1, 0)
+    torch.cuda.synchronize()
+    return d, Xd
+
+
+def test_multittm_sampled_rows(big):
+    d, Xd = big
+    X = d["X"]
+    Qs = [synth.orthonormal_columns(N1, R, 50 + k) for k in range(3)]
+    Qd = [torch.from_numpy(q).to("cuda").t().contiguous().t() for q in Qs]
+    for n in range(3):
+        print("[fullsize] multittm mode %d" % n, flush=True)
+        Y = to_np(C.cpqr_multittm(Xd, [None if k == n else Qd[k] for k in range(3)], n, C.PREC_F32))
+        for i in (0, 1, 63, 64, 517, N1 - 1):
+            sl = [slice(None)] * 3
+            sl[n] = slice(i, i + 1)
+            sub = X[tuple(sl)].astype(np.float64)
+            yo = OQ.multittm_unfolded(sub, Qs, n)[0]
+            assert relnorm(Y[i], yo) < 1e-5, (n, i, relnorm(Y[i], yo))
+
+
+def test_one_sweep_against_oracle(big):
+    d, Xd = big
+    st = C.AlsState(Xd, d["init"], prec=C.PREC_F32)
+    st.init()
+    rel = st.sweep(1).cpu().numpy()
+    lam = to_np(st.lam)
+    A = [to_np(a) for a in st.A]
+    print("[fullsize] oracle sweep", flush=True)
+    X64 = d["X"].astype(np.float64)
+    ost = OQ.init_state(d["init"])
+    orel, _ = OQ.sweep(X64, ost)
+    assert abs(rel[0] ** 2 - orel ** 2) < 2e-6
+    for k in range(3):
+        # factors agree column by column (same normalization, no sign freedom)
+        assert relnorm(A[k], ost.A[k]) < 1e-4, (k, relnorm(A[k], ost.A[k]))
+    assert relnorm(lam, ost.lam) < 1e-4
