@@ -37,7 +37,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
 constexpr int WPB = 4;
-constexpr int TARGET_WAVES = 4096;  // enough wavefronts to fill 256 CUs
+constexpr int TARGET_WAVES = 2048;  // wavefronts wanted when K is split (8 per CU)
+constexpr int MIN_WAVES = 1024;     // below this many wavefronts, split K
 
 // ------------------------------------------------------------ U preparation
 // Row-major K x RP, zero padded: U[i*RP + r] = Q[i + r*ldq] (r < R).
@@ -63,66 +64,112 @@ __global__ void prep_u_quads(const double* __restrict__ Q, int64_t K, int64_t ld
   U[e] = r < R ? float(Q[i + r * ldq]) : 0.0f;
 }
 
-// ------------------------------------------------------------ MFMA, P % 4 == 0
-template <int NB, int UN>
-__global__ __launch_bounds__(WAVE* WPB) void ttm_mfma_m(const float* __restrict__ X,
-                                                        const float* __restrict__ U,
-                                                        float* __restrict__ out, int64_t P,
-                                                        int64_t K, int64_t S, int R, int RP,
-                                                        int64_t kchunk, int64_t split_stride) {
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int64_t M = P * S;
-  const int64_t mt = (int64_t(blockIdx.x) * WPB + w) * 64;
-  if (mt >= M) return;
-  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
-  const int64_t k1 = min(K, k0 + kchunk);
-  const int l16 = lane % 16, kq = lane / 16;
-  const int64_t mrow = mt + 4 * l16;
-  const bool mvalid = mrow < M;  // M % 4 == 0, so the four rows are valid together
-  const int64_t p = mvalid ? mrow % P : 0, s = mvalid ? mrow / P : 0;
-  const float* base = X + p + s * P * K;
+// ------------------------------------------------------------ MFMA kernels
+// Both MFMA kernels stage the contraction operand U in LDS, KC rows at a time
+// (KC * RP floats <= 64 KB), shared by the NWV wavefronts of the workgroup.
+// Inside a chunk the tensor loads are software pipelined with two register
+// buffers (A, B): the loads of step t+1 are in flight while step t runs on the
+// matrix cores.  Main-loop loads are unconditional (invalid rows and columns
+// read a clamped in-bounds address and are never stored), so the compiler
+// keeps them branch-free; the chunk tail is a separate masked step.
+constexpr int LDS_FLOATS = 16384;  // 64 KB
 
-  floatx4 acc[NB][4];
+// ---------------- P % 4 == 0: rows m = p + P s on the MFMA M dimension
+template <int NB, int UN, int MG, int NWV>
+__global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__ X,
+                                                       const float* __restrict__ U,
+                                                       float* __restrict__ out, int64_t P,
+                                                       int64_t K, int64_t S, int R, int RP,
+                                                       int64_t kchunk, int64_t split_stride) {
+  extern __shared__ float us[];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int64_t M = P * S;
+  const int64_t mt = (int64_t(blockIdx.x) * NWV + w) * 64 * MG;
+  const bool active = mt < M;
+  const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t kb1 = min(K, kb0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  const float* base[MG];
+#pragma unroll
+  for (int g = 0; g < MG; ++g) {
+    int64_t mrow = mt + 64 * g + 4 * l16;
+    mrow = mrow < M ? mrow : M - 4;
+    const int64_t p = mrow % P, s = mrow / P;
+    base[g] = X + p + s * P * K + kq * P;
+  }
+  floatx4 acc[NB][MG][4];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[b][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  int64_t i = k0;
-  for (; i + 4 * UN <= k1; i += 4 * UN) {
-    float4 xv[UN];
-    float bv[UN][NB];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const int64_t ii = i + 4 * u + kq;
-      xv[u] = mvalid ? *reinterpret_cast<const float4*>(base + ii * P) : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) bv[u][b] = U[ii * RP + b * 16 + l16];
+  constexpr int STEP = 4 * UN;
+  const int KC = (LDS_FLOATS / RP) / STEP * STEP;
+  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+    const int64_t c1 = min(kb1, c0 + KC);
+    __syncthreads();
+    for (int e = tid; e < KC * RP; e += NWV * 64) {
+      const int64_t ii = c0 + e / RP;
+      us[e] = ii < c1 ? U[ii * RP + e % RP] : 0.f;
     }
+    __syncthreads();
+    if (!active) continue;
+    const int64_t nfull = (c1 - c0) / STEP;
+    const int64_t last = nfull > 0 ? c0 + (nfull - 1) * STEP : c0;
+    float4 A[UN][MG], B[UN][MG];
+    auto load = [&](float4(&dst)[UN][MG], int64_t t) {
+      const int64_t i0 = min(c0 + t * STEP, last);
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int g = 0; g < MG; ++g)
+          dst[u][g] = *reinterpret_cast<const float4*>(base[g] + (i0 + 4 * u) * P);
+    };
+    auto compute = [&](const float4(&src)[UN][MG], int64_t t) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float bv = us[(t * STEP + 4 * u + kq) * RP + b * 16 + l16];
+#pragma unroll
+          for (int g = 0; g < MG; ++g) {
+            acc[b][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[u][g].x, bv, acc[b][g][0], 0, 0, 0);
+            acc[b][g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[u][g].y, bv, acc[b][g][1], 0, 0, 0);
+            acc[b][g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[u][g].z, bv, acc[b][g][2], 0, 0, 0);
+            acc[b][g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[u][g].w, bv, acc[b][g][3], 0, 0, 0);
+          }
+        }
+    };
+    if (nfull > 0) {
+      load(A, 0);
+      for (int64_t t = 0; t < nfull; t += 2) {
+        load(B, t + 1);
+        compute(A, t);
+        load(A, t + 2);
+        if (t + 1 < nfull) compute(B, t + 1);
+      }
+    }
+    for (int64_t i = c0 + nfull * STEP; i < c1; i += 4) {  // chunk tail
+      const int64_t ii = i + kq;
+      const bool ok = ii < c1;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].x, bv[u][b], acc[b][0], 0, 0, 0);
-        acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].y, bv[u][b], acc[b][1], 0, 0, 0);
-        acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].z, bv[u][b], acc[b][2], 0, 0, 0);
-        acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[u].w, bv[u][b], acc[b][3], 0, 0, 0);
-      }
-  }
-  for (; i < k1; i += 4) {
-    const int64_t ii = i + kq;
-    const bool ok = ii < k1;
-    const float4 xv = (mvalid && ok) ? *reinterpret_cast<const float4*>(base + ii * P)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float bv = ok ? us[(ii - c0) * RP + b * 16 + l16] : 0.f;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float bv = ok ? U[ii * RP + b * 16 + l16] : 0.f;
-      acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[b][0], 0, 0, 0);
-      acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[b][1], 0, 0, 0);
-      acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[b][2], 0, 0, 0);
-      acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[b][3], 0, 0, 0);
+        for (int g = 0; g < MG; ++g) {
+          const float4 xv = ok ? *reinterpret_cast<const float4*>(base[g] + i * P)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+          acc[b][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[b][g][0], 0, 0, 0);
+          acc[b][g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[b][g][1], 0, 0, 0);
+          acc[b][g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[b][g][2], 0, 0, 0);
+          acc[b][g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[b][g][3], 0, 0, 0);
+        }
+      }
     }
   }
+  if (!active) return;
   // D layout: lane holds rows 4*kq + v (v = 0..3) of column l16.
   float* o = out + int64_t(blockIdx.y) * split_stride;
 #pragma unroll
@@ -130,82 +177,104 @@ __global__ __launch_bounds__(WAVE* WPB) void ttm_mfma_m(const float* __restrict_
     const int r = b * 16 + l16;
     if (r >= R) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int g = 0; g < MG; ++g)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = mt + 4 * (4 * kq + v) + j;
-        if (m < M) {
-          const int64_t pp = m % P, ss = m / P;
-          o[pp + r * P + ss * P * R] = acc[b][j][v];
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = mt + 64 * g + 4 * (4 * kq + v) + j;
+          if (m < M) {
+            const int64_t pp = m % P, ss = m / P;
+            o[pp + r * P + ss * P * R] = acc[b][g][j][v];
+          }
         }
-      }
   }
 }
 
-// ------------------------------------------------------------ MFMA, P == 1
-// out[r + R*s] = sum_i U[i, r] X[i + K*s]
-template <int NB, int UN>
-__global__ __launch_bounds__(WAVE* WPB) void ttm_mfma_k(const float* __restrict__ X,
-                                                        const float* __restrict__ U4,
-                                                        float* __restrict__ out, int64_t K,
-                                                        int64_t S, int R, int RP, int64_t kchunk,
-                                                        int64_t split_stride) {
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int64_t st = (int64_t(blockIdx.x) * WPB + w) * 16;
-  if (st >= S) return;
-  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
-  const int64_t k1 = min(K, k0 + kchunk);
+// ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
+// U4 holds four consecutive i interleaved per r, so one float4 read feeds the
+// four MFMAs of a step.  K % 4 == 0.
+template <int NB, int UN, int NWV>
+__global__ __launch_bounds__(NWV * 64) void ttm_mfma_k(const float* __restrict__ X,
+                                                       const float* __restrict__ U4,
+                                                       float* __restrict__ out, int64_t K,
+                                                       int64_t S, int R, int RP, int64_t kchunk,
+                                                       int64_t split_stride) {
+  extern __shared__ float4 us4[];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int64_t st = (int64_t(blockIdx.x) * NWV + w) * 16;
+  const bool active = st < S;
+  const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t kb1 = min(K, kb0 + kchunk);
   const int l16 = lane % 16, kq = lane / 16;
-  const int64_t s = st + l16;
-  const bool svalid = s < S;
-  const float* col = X + (svalid ? s : 0) * K;
-
+  int64_t scl = st + l16;
+  scl = scl < S ? scl : S - 1;
+  const float* col = X + scl * K + 4 * kq;
   floatx4 acc[NB][4];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[b][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  int64_t i = k0;
-  for (; i + 16 * UN <= k1; i += 16 * UN) {
-    float4 xv[UN];
-    float4 av[UN][NB];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const int64_t ii = i + 16 * u + 4 * kq;
-      xv[u] = svalid ? *reinterpret_cast<const float4*>(col + ii) : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        av[u][b] = *reinterpret_cast<const float4*>(U4 + ((ii / 4) * RP + b * 16 + l16) * 4);
+  constexpr int STEP = 16 * UN;
+  const int KC = (LDS_FLOATS / RP) / STEP * STEP;  // rows of U per chunk
+  const float4* U4v = reinterpret_cast<const float4*>(U4);
+  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+    const int64_t c1 = min(kb1, c0 + KC);
+    __syncthreads();
+    for (int e = tid; e < (KC / 4) * RP; e += NWV * 64) {
+      const int64_t q = c0 / 4 + e / RP;
+      us4[e] = q * 4 < c1 ? U4v[q * RP + e % RP] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    __syncthreads();
+    if (!active) continue;
+    const int64_t nfull = (c1 - c0) / STEP;
+    const int64_t last = nfull > 0 ? c0 + (nfull - 1) * STEP : c0;
+    float4 A[UN], B[UN];
+    auto load = [&](float4(&dst)[UN], int64_t t) {
+      const int64_t i0 = min(c0 + t * STEP, last);
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
+      for (int u = 0; u < UN; ++u) dst[u] = *reinterpret_cast<const float4*>(col + i0 + 16 * u);
+    };
+    auto compute = [&](const float4(&src)[UN], int64_t t) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float4 av = us4[((t * STEP + 16 * u) / 4 + kq) * RP + b * 16 + l16];
+          acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, src[u].x, acc[b][0], 0, 0, 0);
+          acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, src[u].y, acc[b][1], 0, 0, 0);
+          acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, src[u].z, acc[b][2], 0, 0, 0);
+          acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, src[u].w, acc[b][3], 0, 0, 0);
+        }
+    };
+    if (nfull > 0) {
+      load(A, 0);
+      for (int64_t t = 0; t < nfull; t += 2) {
+        load(B, t + 1);
+        compute(A, t);
+        load(A, t + 2);
+        if (t + 1 < nfull) compute(B, t + 1);
+      }
+    }
+    for (int64_t i = c0 + nfull * STEP; i < c1; i += 16) {  // chunk tail
+      const int64_t ii = i + 4 * kq;
+      const bool ok = ii < c1;  // c1 % 4 == 0: four valid together
+      const float4 xv = ok ? *reinterpret_cast<const float4*>(col + i) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].x, xv[u].x, acc[b][0], 0, 0, 0);
-        acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].y, xv[u].y, acc[b][1], 0, 0, 0);
-        acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].z, xv[u].z, acc[b][2], 0, 0, 0);
-        acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][b].w, xv[u].w, acc[b][3], 0, 0, 0);
+        const float4 av = ok ? us4[((i - c0) / 4 + kq) * RP + b * 16 + l16] : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[b][0], 0, 0, 0);
+        acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[b][1], 0, 0, 0);
+        acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[b][2], 0, 0, 0);
+        acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[b][3], 0, 0, 0);
       }
-  }
-  for (; i < k1; i += 16) {
-    const int64_t ii = i + 4 * kq;
-    const bool ok = ii < k1;  // K % 4 == 0 and kchunk % 16 == 0: four valid together
-    const float4 xv = (svalid && ok) ? *reinterpret_cast<const float4*>(col + ii)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float4 av = ok ? *reinterpret_cast<const float4*>(U4 + ((ii / 4) * RP + b * 16 + l16) * 4)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
-      acc[b][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xv.x, acc[b][0], 0, 0, 0);
-      acc[b][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xv.y, acc[b][1], 0, 0, 0);
-      acc[b][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xv.z, acc[b][2], 0, 0, 0);
-      acc[b][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xv.w, acc[b][3], 0, 0, 0);
     }
   }
   // The four MFMAs of one step cover different i, so their sums add up.
+  const int64_t s = st + l16;
+  if (!active || s >= S) return;
   float* o = out + int64_t(blockIdx.y) * split_stride;
-  if (!svalid) return;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const floatx4 t = acc[b][0] + acc[b][1] + acc[b][2] + acc[b][3];
@@ -299,6 +368,25 @@ Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned =
   for (int k = 0; k < N; ++k)
     if (k != n) order[no++] = k;
   std::stable_sort(order, order + no, [&](int a, int b) { return I[a] > I[b]; });
+  // The first contraction streams the whole tensor.  Contracting the fastest
+  // mode first (P = 1) has the least favourable access pattern for the matrix
+  // cores, so when another contracted mode is at least half as large and its
+  // index stride is small (rows at most 256 KB apart), start with the largest
+  // such mode; the flop count of the first contraction is the same and the
+  // later ones change by a factor of at most two.
+  if (uses_mfma(prec) && no > 1 && order[0] == 0) {
+    for (int t = 1; t < no; ++t) {
+      int64_t stride = 1;  // elements between consecutive indices of that mode
+      for (int m = 0; m < order[t]; ++m) stride *= I[m];
+      // large strides walk the tensor page by page: keep those for later
+      if (2 * I[order[t]] >= I[0] && stride % 4 == 0 && stride <= 65536) {
+        const int k = order[t];
+        for (int u = t; u > 0; --u) order[u] = order[u - 1];
+        order[0] = k;
+        break;
+      }
+    }
+  }
   int64_t D[CPQR_MAX_MODES];
   for (int k = 0; k < N; ++k) D[k] = I[k];
   pl.nsteps = no;
@@ -316,7 +404,7 @@ Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned =
     const bool vec_ok = t > 0 || x_aligned;
     if (uses_mfma(prec) && vec_ok && s.P % 4 == 0) {
       s.kind = K_MFMA_M;
-      units = ceil_div(s.P * s.S, 64);
+      units = ceil_div(s.P * s.S, 64 * 4);
     } else if (uses_mfma(prec) && vec_ok && s.P == 1 && s.K % 4 == 0) {
       s.kind = K_MFMA_K;
       units = ceil_div(s.S, 16);
@@ -324,9 +412,11 @@ Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned =
       s.kind = K_VALU;
       units = ceil_div(s.P * s.S, 64);
     }
+    // Split K only when the rows alone leave the GPU under-filled.
     const int64_t quantum = 16;
     int64_t splits = 1;
-    if (units < TARGET_WAVES) splits = std::min<int64_t>(ceil_div(TARGET_WAVES, units), std::max<int64_t>(1, s.K / 64));
+    if (units < MIN_WAVES)
+      splits = std::min<int64_t>(ceil_div(TARGET_WAVES, units), std::max<int64_t>(1, s.K / quantum));
     splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
     s.kchunk = ceil_div(ceil_div(s.K, splits), quantum) * quantum;
     s.splits = int(ceil_div(s.K, s.kchunk));
@@ -385,23 +475,26 @@ int launch_valu_r(const void* src, int src_dtype, const TA* U, TA* dst, const St
 int launch_mfma(const float* src, const float* U, float* dst, const Step& s, int R, int RP,
                 hipStream_t st) {
   const int NB = RP / 16;
-  constexpr int UN = 4;
+  constexpr int NWV = 8;
+  const size_t lds = LDS_FLOATS * sizeof(float);
   if (s.kind == K_MFMA_M) {
-    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64), WPB)), unsigned(s.splits));
+    constexpr int UN = 2, MG = 4;
+    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
     if (NB == 1)
-      hipLaunchKernelGGL((ttm_mfma_m<1, UN>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.P, s.K, s.S,
-                         R, RP, s.kchunk, s.out_count);
+      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+                         s.S, R, RP, s.kchunk, s.out_count);
     else
-      hipLaunchKernelGGL((ttm_mfma_m<2, UN>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.P, s.K, s.S,
-                         R, RP, s.kchunk, s.out_count);
+      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+                         s.S, R, RP, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m");
   }
-  const dim3 grd(unsigned(ceil_div(ceil_div(s.S, 16), WPB)), unsigned(s.splits));
+  constexpr int UN = 4;
+  const dim3 grd(unsigned(ceil_div(ceil_div(s.S, 16), NWV)), unsigned(s.splits));
   if (NB == 1)
-    hipLaunchKernelGGL((ttm_mfma_k<1, 2>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.K, s.S, R,
+    hipLaunchKernelGGL((ttm_mfma_k<1, UN, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S, R,
                        RP, s.kchunk, s.out_count);
   else
-    hipLaunchKernelGGL((ttm_mfma_k<2, 2>), grd, dim3(WAVE * WPB), 0, st, src, U, dst, s.K, s.S, R,
+    hipLaunchKernelGGL((ttm_mfma_k<2, UN, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S, R,
                        RP, s.kchunk, s.out_count);
   return check_launch("ttm_mfma_k");
 }

@@ -3,18 +3,28 @@
 // V_n = Q_0 R_0 (paper section 3.1, Alg. 2), both with the orthonormal
 // factor formed explicitly.
 //
-// Design.  One wavefront (64 lanes) owns one block of at most 64 rows; lane
-// l holds row l of the block in registers (R <= 32 doubles).  A block is
-// factorized with Householder reflections whose column norms and
-// reflector-times-matrix products are wavefront reductions, so no barrier is
-// needed inside a block.  Blocks are combined in a tree: the triangular
-// factors of up to 64/R children are stacked and factorized again, level by
-// level, until one block remains (its R is the answer).  Q is then formed top
+// Design.  One workgroup of NT threads owns one block ("node") of at most NT
+// rows; thread t holds row t of the block in registers (R <= 32 doubles).
+// Column j of the Householder factorization needs two reductions over the
+// rows: the norm of the sub-column, and one batched reduction that returns at
+// once the trailing products w_c = v_j^T A(:,c) (c > j) and the reflector
+// Gram entries G(i,j) = v_i^T v_j (i < j).  Reductions are reduce-scatter
+// butterflies inside each wavefront followed by one LDS pass across
+// wavefronts; their order is fixed, so results are bitwise reproducible.
+// The orthonormal factor uses the compact WY form of the reflectors,
+// H_0 ... H_{R-1} = I - V T V^T with T upper triangular built from G, so
+// forming Q needs no further reductions: Q [C; 0] = [C; 0] - V (T V_1^T C),
+// V_1 being the top R x R block of V.
+//
+// Blocks larger than one workgroup are combined in a tree: the triangular
+// factors of up to NT/R children are stacked and factorized again, level by
+// level, until one block remains (its R is the answer).  Q is formed top
 // down: each node applies its reflectors to [C; 0], where C is the node's
 // R x R slice of its parent's Q, and hands R x R slices to its children.
-// Every step is a genuine Householder reflection of the real rows (rows past
-// a block's end are never touched), so Q has orthonormal columns even when
-// the input is rank deficient.
+// Every step is a genuine Householder reflection of the real rows, so Q has
+// orthonormal columns even when the input is rank deficient.
+
+#include <algorithm>
 
 #include "common.h"
 
@@ -22,62 +32,99 @@ namespace cpqr {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int WPB = 4;  // wavefronts per workgroup; each owns one tree node
 
 enum Src { SRC_MATRIX = 0, SRC_KRP = 1, SRC_STACK = 2 };
 
 struct KrpSrc {
   const double* Rk[CPQR_MAX_MODES];
-  int modes[CPQR_MAX_MODES];  // the N-1 modes k != n, ascending (lowest fastest)
-  int nm;
+  int nm;  // the N-1 modes k != n, ascending (lowest varies fastest)
   int64_t ldr;
 };
 
 struct Level {
+  int nt;             // rows per node (threads per workgroup)
   int64_t nodes;      // nodes at this level
-  int64_t rows;       // leaves: rows of the input; else unused
+  int64_t rows;       // leaf level: rows of the input
   int64_t prev_nodes; // internal levels: nodes of the level below
   int g;              // internal levels: children per node
-  double* V;          // nodes x RMAX x 64 (column c of node j at (j*RMAX + c)*64)
-  double* tau;        // nodes x RMAX
+  double* V;          // nodes x RMAX x nt reflectors (column c of node j at (j*RMAX + c)*nt)
+  double* T;          // nodes x RMAX x RMAX compact-WY factors
   double* Rin;        // internal levels: prev_nodes blocks of RMAX x RMAX (stacked R's)
 };
 
-__device__ inline double wave_sum(double x) {
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Sum over all threads of the workgroup of each x[i] (V a power of two <= 32).
+// Result in res[0..V-1] (LDS), visible to every thread on return.
+template <int V, int NW>
+__device__ inline void block_sum_vec(double (&x)[V], double* red, double* res, int tid) {
+  const int lane = tid % WAVE, w = tid / WAVE;
+  constexpr int L = ilog2(V);
+  int idx = 0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
-  return x;
+  for (int l = 0; l < L; ++l) {
+    const int mask = 32 >> l;
+    const int half = V >> (l + 1);
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double send = hi ? x[i] : x[half + i];
+      const double got = __shfl_xor(send, mask, WAVE);
+      x[i] = (hi ? x[half + i] : x[i]) + got;
+    }
+    idx += hi ? half : 0;
+  }
+#pragma unroll
+  for (int mask = 32 >> L; mask >= 1; mask >>= 1) x[0] += __shfl_xor(x[0], mask, WAVE);
+  if ((lane & ((64 >> L) - 1)) == 0) red[w * V + idx] = x[0];
+  __syncthreads();
+  if (tid < V) {
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) s += red[ww * V + tid];
+    res[tid] = s;
+  }
+  __syncthreads();
 }
 
-// Orders LDS writes by some lanes before reads by others within one
-// wavefront.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// LDS workspace of one node.
+template <int RMAX, int NT>
+struct Shared {
+  double red[(NT / WAVE) * RMAX];
+  double res[RMAX];
+  double alpha;
+  double tau[RMAX];
+  double G[RMAX][RMAX + 1];   // reflector Gram (strict upper part), later V1^T C
+  double T[RMAX][RMAX + 1];   // compact WY factor
+  double V1[RMAX][RMAX + 1];  // top R x R block of V
+  double C[RMAX][RMAX + 1];   // input slice of the parent's Q
+  double M[RMAX][RMAX + 1];   // T V1^T C
+};
 
-// Balanced leaf partition: leaf b of nl covering `rows` rows.
-__device__ __host__ inline void leaf_range(int64_t rows, int64_t nl, int64_t b, int64_t& start,
-                                           int& m) {
-  int64_t base = rows / nl, rem = rows % nl;
-  m = int(base + (b < rem ? 1 : 0));
-  start = b * base + (b < rem ? b : rem);
-}
-
-// Householder QR of the wavefront's block (rows in a[], one per lane,
-// lanes >= m hold zeros).  On return lanes < R hold R's rows (entries at
-// c >= lane), lanes > j hold reflector j below the diagonal in a[j], and
-// tau_s[j] holds the reflector scalars (H_j = I - tau_j v_j v_j^T, v_j(j)=1).
+// Reflector component of row `row` for reflector c, from the factorized a[].
 template <int RMAX>
-__device__ void house_factor(double (&a)[RMAX], double* tau_s, int m, int R, int lane) {
+__device__ inline double vcomp(const double (&a)[RMAX], int c, int row, int m) {
+  return row == c ? 1.0 : ((row > c && row < m) ? a[c] : 0.0);
+}
+
+// Householder QR of the node block (row `tid` in a[], rows >= m are zero).
+// On return rows < R hold R's rows (entries at c >= row), rows > c hold
+// reflector c below the diagonal in a[c]; sh.tau and the strict upper part of
+// sh.G are filled.
+template <int RMAX, int NT>
+__device__ void wg_factor(double (&a)[RMAX], int tid, int m, int R, Shared<RMAX, NT>& sh) {
+  constexpr int NW = NT / WAVE;
+  // The column loop stays rolled; a[j] is picked and replaced through compare
+  // chains so the register array is only ever indexed by constants.
+#pragma unroll 1
+  for (int j = 0; j < R; ++j) {
+    double aj = 0.0;
 #pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    if (j < R) {
-    const double aj = a[j];
-    const double alpha = __shfl(aj, j, WAVE);
-    const double below = (lane > j && lane < m) ? aj : 0.0;
-    const double sub2 = wave_sum(below * below);
+    for (int c = 0; c < RMAX; ++c) aj = (c == j) ? a[c] : aj;
+    if (tid == j) sh.alpha = aj;
+    double x1[1] = {(tid > j && tid < m) ? aj * aj : 0.0};
+    block_sum_vec<1, NW>(x1, sh.red, sh.res, tid);
+    const double alpha = sh.alpha, sub2 = sh.res[0];
     double t = 0.0, beta = alpha, scal = 0.0;
     if (sub2 > 0.0) {
       const double nrm = sqrt(alpha * alpha + sub2);
@@ -85,77 +132,110 @@ __device__ void house_factor(double (&a)[RMAX], double* tau_s, int m, int R, int
       t = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    const double v = (lane == j) ? 1.0 : ((lane > j && lane < m) ? aj * scal : 0.0);
-    a[j] = (lane == j) ? beta : ((lane > j) ? v : aj);
-    if (lane == 0) tau_s[j] = t;
-    if (t != 0.0) {
+    const double v = (tid == j) ? 1.0 : ((tid > j && tid < m) ? aj * scal : 0.0);
+    const double newj = (tid == j) ? beta : ((tid > j) ? v : aj);
 #pragma unroll
-      for (int c = j + 1; c < RMAX; ++c) {
-        if (c < R) {
-          const double w = wave_sum(v * a[c]);
-          a[c] -= t * v * w;
-        }
+    for (int c = 0; c < RMAX; ++c) a[c] = (c == j) ? newj : a[c];
+    if (tid == 0) sh.tau[j] = t;
+    double x[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c)
+      x[c] = (c < j) ? vcomp<RMAX>(a, c, tid, m) * v : ((c > j && c < R) ? v * a[c] : 0.0);
+    block_sum_vec<RMAX, NW>(x, sh.red, sh.res, tid);
+    const double tv = t * v;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) a[c] = (c > j && c < R) ? a[c] - tv * sh.res[c] : a[c];
+    if (tid < j) sh.G[tid][j] = sh.res[tid];
+  }
+  __syncthreads();
+}
+
+// T of the compact WY form: T(j,j) = tau_j,
+// T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One wavefront, lane = row of T.
+template <int RMAX, int NT>
+__device__ void wg_build_t(int tid, int R, Shared<RMAX, NT>& sh) {
+  if (tid < WAVE) {
+    for (int j = 0; j < R; ++j) {
+      double v = 0.0;
+      if (tid < j) {
+        for (int k = tid; k < j; ++k) v += sh.T[tid][k] * sh.G[k][j];
+        v *= -sh.tau[j];
+      } else if (tid == j) {
+        v = sh.tau[j];
       }
+      if (tid < RMAX) sh.T[tid][j] = v;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    }
+  }
+  __syncthreads();
+}
+
+// Rows of this node's Q: q = [C; 0](row) - v(row) M with M = T V1^T C.
+// Expects sh.T and sh.C filled; uses sh.V1, sh.G (as scratch) and sh.M.
+template <int RMAX, int NT>
+__device__ void wg_form_q(const double (&a)[RMAX], double (&q)[RMAX], int tid, int m, int R,
+                          Shared<RMAX, NT>& sh) {
+  if (tid < R) {
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sh.V1[tid][c] = (c < R) ? vcomp<RMAX>(a, c, tid, m) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < R * R; e += NT) {  // B = V1^T C
+    const int k = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = k; i < R; ++i) s += sh.V1[i][k] * sh.C[i][c];
+    sh.G[k][c] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < R * R; e += NT) {  // M = T B
+    const int k = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = k; i < R; ++i) s += sh.T[k][i] * sh.G[i][c];
+    sh.M[k][c] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) q[c] = (tid < R && c < R) ? sh.C[tid][c] : 0.0;
+#pragma unroll 1
+  for (int k = 0; k < R; ++k) {
+    double vk = 0.0;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) vk = (c == k) ? vcomp<RMAX>(a, c, tid, m) : vk;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) q[c] -= vk * sh.M[k][c];
   }
 }
 
-// q <- H_0 H_1 ... H_{R-1} q for the block's reflectors (held as in
-// house_factor's output a[]).  q enters as [C; 0] and leaves as the block's
-// rows of the orthonormal factor.
-template <int RMAX>
-__device__ void house_apply_q(const double (&a)[RMAX], const double* tau_s, double (&q)[RMAX],
-                              int m, int R, int lane) {
-#pragma unroll
-  for (int j = RMAX - 1; j >= 0; --j) {
-    const double t = j < R ? tau_s[j] : 0.0;
-    if (t != 0.0) {
-      const double v = (lane == j) ? 1.0 : ((lane > j && lane < m) ? a[j] : 0.0);
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        if (c < R) {
-          const double w = wave_sum(v * q[c]);
-          q[c] -= t * v * w;
-        }
-      }
-    }
-  }
-}
-
-template <int RMAX>
-__device__ inline void store_block(double* V, int64_t node, const double (&a)[RMAX], int lane) {
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) V[(node * RMAX + c) * WAVE + lane] = a[c];
-}
-
-template <int RMAX>
-__device__ inline void load_block(const double* V, int64_t node, double (&a)[RMAX], int lane) {
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) a[c] = V[(node * RMAX + c) * WAVE + lane];
+// Balanced leaf partition: leaf b of nl covering `rows` rows.
+__device__ __host__ inline void leaf_range(int64_t rows, int64_t nl, int64_t b, int64_t& start,
+                                           int& m) {
+  const int64_t base = rows / nl, rem = rows % nl;
+  m = int(base + (b < rem ? 1 : 0));
+  start = b * base + (b < rem ? b : rem);
 }
 
 // Rows of the node's input block.
 template <int RMAX, int SRC>
-__device__ inline int load_rows(double (&a)[RMAX], const Level& L, int64_t node, int R, int lane,
-                                const double* A, int64_t lda, const KrpSrc& krp,
-                                int64_t& start) {
+__device__ inline int load_rows(double (&a)[RMAX], const Level& L, int64_t node, int R, int tid,
+                                const double* A, int64_t lda, const KrpSrc& krp, int64_t& start) {
   int m;
   if (SRC == SRC_STACK) {
     const int64_t c0 = node * L.g;
     const int64_t nch = min<int64_t>(L.g, L.prev_nodes - c0);
     m = int(nch) * R;
     start = 0;
-    const int child = lane / R, i = lane % R;
+    const int child = tid / R, i = tid % R;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
-      a[c] = (lane < m && c < R) ? L.Rin[((c0 + child) * RMAX + c) * RMAX + i] : 0.0;
+      a[c] = (tid < m && c < R) ? L.Rin[((c0 + child) * RMAX + c) * RMAX + i] : 0.0;
   } else {
     leaf_range(L.rows, L.nodes, node, start, m);
-    const int64_t g = start + lane;
+    const int64_t g = start + tid;
     if (SRC == SRC_MATRIX) {
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) a[c] = (lane < m && c < R) ? A[g + c * lda] : 0.0;
+      for (int c = 0; c < RMAX; ++c) a[c] = (tid < m && c < R) ? A[g + c * lda] : 0.0;
     } else {
       int digit[CPQR_MAX_MODES];
       int64_t d = g;
@@ -166,10 +246,10 @@ __device__ inline int load_rows(double (&a)[RMAX], const Level& L, int64_t node,
       }
 #pragma unroll
       for (int c = 0; c < RMAX; ++c) {
-        double p = (lane < m && c < R) ? 1.0 : 0.0;
+        double p = (tid < m && c < R) ? 1.0 : 0.0;
 #pragma unroll
         for (int t = 0; t < CPQR_MAX_MODES; ++t)
-          if (t < krp.nm && lane < m && c < R) p *= krp.Rk[t][digit[t] + c * krp.ldr];
+          if (t < krp.nm && tid < m && c < R) p *= krp.Rk[t][digit[t] + c * krp.ldr];
         a[c] = p;
       }
     }
@@ -177,77 +257,79 @@ __device__ inline int load_rows(double (&a)[RMAX], const Level& L, int64_t node,
   return m;
 }
 
-// Write a formed Q block: to the output matrix (leaves) or as the R x R
-// C blocks of the node's children (internal nodes).
 template <int RMAX>
 __device__ inline void write_q(const double (&q)[RMAX], bool leaf, int64_t start, int m,
                                double* Qout, int64_t ldq, double* Cchild, int64_t node, int g,
-                               int R, int lane) {
-  if (lane >= m) return;
+                               int R, int tid) {
+  if (tid >= m) return;
   if (leaf) {
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
-      if (c < R) Qout[start + lane + c * ldq] = q[c];
+      if (c < R) Qout[start + tid + c * ldq] = q[c];
   } else {
-    const int64_t child = node * g + lane / R;
-    const int i = lane % R;
+    const int64_t child = node * g + tid / R;
+    const int i = tid % R;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
       if (c < R) Cchild[(child * RMAX + c) * RMAX + i] = q[c];
   }
 }
 
-// Up-sweep of one level.  At the root (nodes == 1) also writes R to Rout and
-// forms the root's Q from C = I.
-template <int RMAX, int SRC>
-__global__ __launch_bounds__(WAVE* WPB) void tsqr_up(Level L, int R, const double* A, int64_t lda,
-                                                     KrpSrc krp, double* Rnext, double* Rout,
-                                                     int64_t ldr_out, double* Qout, int64_t ldq,
-                                                     double* Cchild, int gchild) {
-  __shared__ double tau_s[WPB][RMAX];
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int64_t node = int64_t(blockIdx.x) * WPB + w;
-  if (node >= L.nodes) return;
+// Up-sweep of one level (factorize, store reflectors and T, pass R up).  At
+// the root (nodes == 1) also writes R to Rout and forms the root's Q from
+// C = I.
+template <int RMAX, int NT, int SRC>
+__global__ __launch_bounds__(NT) void tsqr_up(Level L, int R, const double* A, int64_t lda,
+                                              KrpSrc krp, double* Rnext, double* Rout,
+                                              int64_t ldr_out, double* Qout, int64_t ldq,
+                                              double* Cchild, int gchild) {
+  __shared__ Shared<RMAX, NT> sh;
+  const int tid = threadIdx.x;
+  const int64_t node = blockIdx.x;
   double a[RMAX];
   int64_t start;
-  const int m = load_rows<RMAX, SRC>(a, L, node, R, lane, A, lda, krp, start);
-  house_factor<RMAX>(a, tau_s[w], m, R, lane);
-  wave_sync();
-  store_block<RMAX>(L.V, node, a, lane);
-  if (lane < RMAX) L.tau[node * RMAX + lane] = lane < R ? tau_s[w][lane] : 0.0;
+  const int m = load_rows<RMAX, SRC>(a, L, node, R, tid, A, lda, krp, start);
+  wg_factor<RMAX, NT>(a, tid, m, R, sh);
+  wg_build_t<RMAX, NT>(tid, R, sh);
   if (L.nodes > 1) {
-    if (lane < R) {
+    double* V = L.V + node * RMAX * NT;
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) Rnext[(node * RMAX + c) * RMAX + lane] = (c >= lane) ? a[c] : 0.0;
+    for (int c = 0; c < RMAX; ++c) V[c * NT + tid] = a[c];
+    for (int e = tid; e < RMAX * RMAX; e += NT)
+      L.T[node * RMAX * RMAX + e] = (e / RMAX < R && e % RMAX < R) ? sh.T[e / RMAX][e % RMAX] : 0.0;
+    if (tid < R) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) Rnext[(node * RMAX + c) * RMAX + tid] = (c >= tid) ? a[c] : 0.0;
     }
     return;
   }
-  // root
-  if (lane < R) {
+  if (tid < R) {
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
-      if (c < R) Rout[lane + c * ldr_out] = (c >= lane) ? a[c] : 0.0;
+      if (c < R) Rout[tid + c * ldr_out] = (c >= tid) ? a[c] : 0.0;
   }
+  for (int e = tid; e < RMAX * RMAX; e += NT) sh.C[e / RMAX][e % RMAX] = (e / RMAX == e % RMAX) ? 1.0 : 0.0;
+  __syncthreads();
   double q[RMAX];
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) q[c] = (lane < R && c == lane) ? 1.0 : 0.0;
-  house_apply_q<RMAX>(a, tau_s[w], q, m, R, lane);
-  write_q<RMAX>(q, SRC != SRC_STACK, start, m, Qout, ldq, Cchild, node, gchild, R, lane);
+  wg_form_q<RMAX, NT>(a, q, tid, m, R, sh);
+  write_q<RMAX>(q, SRC != SRC_STACK, start, m, Qout, ldq, Cchild, node, gchild, R, tid);
 }
 
 // Down-sweep of one non-root level: form each node's Q from its C block.
-template <int RMAX, bool LEAF>
-__global__ __launch_bounds__(WAVE* WPB) void tsqr_down(Level L, int R, const double* Cin,
-                                                       double* Qout, int64_t ldq, double* Cchild,
-                                                       int gchild) {
-  __shared__ double tau_s[WPB][RMAX];
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int64_t node = int64_t(blockIdx.x) * WPB + w;
-  if (node >= L.nodes) return;
+template <int RMAX, int NT, bool LEAF>
+__global__ __launch_bounds__(NT) void tsqr_down(Level L, int R, const double* Cin, double* Qout,
+                                                int64_t ldq, double* Cchild, int gchild) {
+  __shared__ Shared<RMAX, NT> sh;
+  const int tid = threadIdx.x;
+  const int64_t node = blockIdx.x;
   double a[RMAX], q[RMAX];
-  load_block<RMAX>(L.V, node, a, lane);
-  if (lane < RMAX) tau_s[w][lane] = L.tau[node * RMAX + lane];
-  wave_sync();
+  const double* V = L.V + node * RMAX * NT;
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) a[c] = V[c * NT + tid];
+  for (int e = tid; e < RMAX * RMAX; e += NT) {
+    sh.T[e / RMAX][e % RMAX] = L.T[node * RMAX * RMAX + e];
+    sh.C[e % RMAX][e / RMAX] = Cin[node * RMAX * RMAX + e];  // C blocks are column-major
+  }
   int m;
   int64_t start = 0;
   if (LEAF) {
@@ -256,107 +338,151 @@ __global__ __launch_bounds__(WAVE* WPB) void tsqr_down(Level L, int R, const dou
     const int64_t c0 = node * L.g;
     m = int(min<int64_t>(L.g, L.prev_nodes - c0)) * R;
   }
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c)
-    q[c] = (lane < R && c < R) ? Cin[(node * RMAX + c) * RMAX + lane] : 0.0;
-  house_apply_q<RMAX>(a, tau_s[w], q, m, R, lane);
-  write_q<RMAX>(q, LEAF, start, m, Qout, ldq, Cchild, node, gchild, R, lane);
+  __syncthreads();
+  wg_form_q<RMAX, NT>(a, q, tid, m, R, sh);
+  write_q<RMAX>(q, LEAF, start, m, Qout, ldq, Cchild, node, gchild, R, tid);
 }
 
-// Tree shape for `rows` input rows at rank R.
+// ------------------------------------------------------------ host side
+constexpr int ntmax_for(int RM) { return RM <= 16 ? 1024 : 512; }
+
+int pick_nt(int64_t rows, int RM) {
+  if (rows <= 64) return 64;
+  if (rows <= 256) return 256;
+  return ntmax_for(RM);
+}
+
 struct Tree {
   int nlev = 0;
-  int64_t nodes[40];
-  int g = 2;
+  Level lev[40];
 };
 
-Tree make_tree(int64_t rows, int R) {
+Tree make_tree(int64_t rows, int R, int RM) {
   Tree t;
-  t.g = std::max(2, WAVE / R);
-  int64_t n = rows <= WAVE ? 1 : ceil_div(rows, WAVE);
-  t.nodes[t.nlev++] = n;
-  while (n > 1) {
-    n = ceil_div(n, t.g);
-    t.nodes[t.nlev++] = n;
+  const int ntm = ntmax_for(RM);
+  Level L{};
+  L.nodes = rows <= ntm ? 1 : ceil_div(rows, ntm);
+  L.rows = rows;
+  L.nt = L.nodes == 1 ? pick_nt(rows, RM) : ntm;
+  t.lev[t.nlev++] = L;
+  while (t.lev[t.nlev - 1].nodes > 1) {
+    const int64_t prev = t.lev[t.nlev - 1].nodes;
+    Level U{};
+    U.g = ntm / R;
+    U.prev_nodes = prev;
+    U.nodes = ceil_div(prev, U.g);
+    const int64_t rows_here = std::min<int64_t>(U.g, prev) * R;
+    U.nt = U.nodes == 1 ? pick_nt(rows_here, RM) : ntm;
+    t.lev[t.nlev++] = U;
   }
   return t;
 }
 
-size_t tsqr_carve(Carver& cv, const Tree& t, int RM, Level* lev) {
+size_t carve_tree(Carver& cv, Tree& t, int RM) {
   for (int l = 0; l < t.nlev; ++l) {
-    Level L{};
-    L.nodes = t.nodes[l];
-    L.V = cv.take<double>(size_t(L.nodes) * RM * WAVE);
-    L.tau = cv.take<double>(size_t(L.nodes) * RM);
-    if (l > 0) {
-      L.prev_nodes = t.nodes[l - 1];
-      L.g = t.g;
-      L.Rin = cv.take<double>(size_t(L.prev_nodes) * RM * RM);
-    }
-    if (lev) lev[l] = L;
+    Level& L = t.lev[l];
+    L.V = cv.take<double>(size_t(L.nodes) * RM * L.nt);
+    L.T = cv.take<double>(size_t(L.nodes) * RM * RM);
+    if (l > 0) L.Rin = cv.take<double>(size_t(L.prev_nodes) * RM * RM);
   }
   return cv.bytes();
 }
 
-template <int RMAX, int SRC>
-int tsqr_run(int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
-             int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
-  Tree t = make_tree(rows, R);
-  Level lev[40];
+template <int RMAX, int NT>
+int launch_up(int src, const Level& L, int R, const double* A, int64_t lda, const KrpSrc& krp,
+              double* Rnext, double* Rout, int64_t ldr_out, double* Q, int64_t ldq, double* Cchild,
+              int gchild, hipStream_t s) {
+  const dim3 grd(unsigned(L.nodes)), blk(NT);
+  if (src == SRC_MATRIX)
+    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_MATRIX>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
+                       ldr_out, Q, ldq, Cchild, gchild);
+  else if (src == SRC_KRP)
+    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_KRP>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
+                       ldr_out, Q, ldq, Cchild, gchild);
+  else
+    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_STACK>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
+                       ldr_out, Q, ldq, Cchild, gchild);
+  return check_launch("tsqr_up");
+}
+
+template <int RMAX, int NT>
+int launch_down(bool leaf, const Level& L, int R, const double* Cin, double* Q, int64_t ldq,
+                double* Cchild, int gchild, hipStream_t s) {
+  const dim3 grd(unsigned(L.nodes)), blk(NT);
+  if (leaf)
+    hipLaunchKernelGGL((tsqr_down<RMAX, NT, true>), grd, blk, 0, s, L, R, Cin, Q, ldq, Cchild, gchild);
+  else
+    hipLaunchKernelGGL((tsqr_down<RMAX, NT, false>), grd, blk, 0, s, L, R, Cin, Q, ldq, Cchild, gchild);
+  return check_launch("tsqr_down");
+}
+
+template <int RMAX>
+int dispatch_up(int nt, int src, const Level& L, int R, const double* A, int64_t lda,
+                const KrpSrc& krp, double* Rnext, double* Rout, int64_t ldr_out, double* Q,
+                int64_t ldq, double* Cchild, int gchild, hipStream_t s) {
+  constexpr int NTM = ntmax_for(RMAX);
+  if (nt == 64)
+    return launch_up<RMAX, 64>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
+  if (nt == 256)
+    return launch_up<RMAX, 256>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
+  return launch_up<RMAX, NTM>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
+}
+
+template <int RMAX>
+int dispatch_down(int nt, bool leaf, const Level& L, int R, const double* Cin, double* Q,
+                  int64_t ldq, double* Cchild, int gchild, hipStream_t s) {
+  constexpr int NTM = ntmax_for(RMAX);
+  if (nt == 64) return launch_down<RMAX, 64>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
+  if (nt == 256) return launch_down<RMAX, 256>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
+  return launch_down<RMAX, NTM>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
+}
+
+template <int RMAX>
+int tsqr_run(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
+             double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
+  Tree t = make_tree(rows, R, RMAX);
   Carver cv(work);
-  tsqr_carve(cv, t, RMAX, lev);
-  lev[0].rows = rows;
-  const dim3 blk(WAVE * WPB);
-  // up-sweep
+  carve_tree(cv, t, RMAX);
   for (int l = 0; l < t.nlev; ++l) {
-    const dim3 grd(unsigned(ceil_div(lev[l].nodes, WPB)));
-    double* Rnext = (l + 1 < t.nlev) ? lev[l + 1].Rin : nullptr;
-    double* Cchild = l > 0 ? lev[l].Rin : nullptr;
-    if (l == 0)
-      hipLaunchKernelGGL((tsqr_up<RMAX, SRC>), grd, blk, 0, s, lev[l], R, A, lda, krp, Rnext, Rout,
-                         ldr_out, Q, ldq, Cchild, t.g);
-    else
-      hipLaunchKernelGGL((tsqr_up<RMAX, SRC_STACK>), grd, blk, 0, s, lev[l], R, A, lda, krp, Rnext,
-                         Rout, ldr_out, Q, ldq, Cchild, t.g);
-    CPQR_TRY(check_launch("tsqr_up"));
+    const Level& L = t.lev[l];
+    double* Rnext = (l + 1 < t.nlev) ? t.lev[l + 1].Rin : nullptr;
+    double* Cchild = l > 0 ? L.Rin : nullptr;
+    const int gchild = l > 0 ? L.g : 0;
+    CPQR_TRY(dispatch_up<RMAX>(L.nt, l == 0 ? src : SRC_STACK, L, R, A, lda, krp, Rnext, Rout,
+                               ldr_out, Q, ldq, Cchild, gchild, s));
   }
-  // down-sweep below the root: level l reads its C blocks from level l+1's Rin
   for (int l = t.nlev - 2; l >= 0; --l) {
-    const dim3 grd(unsigned(ceil_div(lev[l].nodes, WPB)));
-    const double* Cin = lev[l + 1].Rin;
-    if (l == 0)
-      hipLaunchKernelGGL((tsqr_down<RMAX, true>), grd, blk, 0, s, lev[l], R, Cin, Q, ldq, nullptr, t.g);
-    else
-      hipLaunchKernelGGL((tsqr_down<RMAX, false>), grd, blk, 0, s, lev[l], R, Cin, Q, ldq,
-                         lev[l].Rin, t.g);
-    CPQR_TRY(check_launch("tsqr_down"));
+    const Level& L = t.lev[l];
+    const double* Cin = t.lev[l + 1].Rin;
+    CPQR_TRY(dispatch_down<RMAX>(L.nt, l == 0, L, R, Cin, Q, ldq, l > 0 ? L.Rin : nullptr,
+                                 l > 0 ? L.g : 0, s));
   }
   return CPQR_OK;
 }
 
-template <int SRC>
-int tsqr_dispatch(int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
-                  int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
+int tsqr_dispatch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
+                  double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
   switch (round_rank(R)) {
-    case 8: return tsqr_run<8, SRC>(rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-    case 16: return tsqr_run<16, SRC>(rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-    default: return tsqr_run<32, SRC>(rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+    case 8: return tsqr_run<8>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+    case 16: return tsqr_run<16>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+    default: return tsqr_run<32>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
   }
 }
 
 }  // namespace
 
 size_t tsqr_work(int64_t rows, int R) {
-  Tree t = make_tree(rows, R);
+  const int RM = round_rank(R);
+  Tree t = make_tree(rows, R, RM);
   Carver cv(nullptr);
-  return tsqr_carve(cv, t, round_rank(R), nullptr);
+  return carve_tree(cv, t, RM);
 }
 
 int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
                       double* Rk, int64_t ldr, void* work, hipStream_t s) {
   PhaseTimer pt(PH_FACTOR_QR, s);
   KrpSrc none{};
-  return tsqr_dispatch<SRC_MATRIX>(I, R, A, lda, none, Q, ldq, Rk, ldr, work, s);
+  return tsqr_dispatch(SRC_MATRIX, I, R, A, lda, none, Q, ldq, Rk, ldr, work, s);
 }
 
 int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
@@ -367,12 +493,10 @@ int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, do
   krp.ldr = ldr;
   for (int k = 0; k < N; ++k) {
     if (k == n) continue;
-    krp.Rk[krp.nm] = Rk[k];
-    krp.modes[krp.nm] = k;
-    ++krp.nm;
+    krp.Rk[krp.nm++] = Rk[k];
   }
   const int64_t rows = ipow(R, N - 1);
-  return tsqr_dispatch<SRC_KRP>(rows, R, nullptr, 0, krp, Q0, rows, R0, R, work, s);
+  return tsqr_dispatch(SRC_KRP, rows, R, nullptr, 0, krp, Q0, rows, R0, R, work, s);
 }
 
 }  // namespace cpqr
