@@ -86,7 +86,8 @@ int cpqr_version(void);
 /*
  * Compact QR of one factor matrix, A = Q R (Alg. 2, the factor QR before
  * the loop and after each mode update).  Householder reflections on the
- * GPU (a tall-skinny tree over 64-row blocks), Q formed explicitly.
+ * GPU: one workgroup per block of up to 1024 rows (512 at R > 16), blocks
+ * combined in a tall-skinny tree; Q formed explicitly.
  *   A   : device, I x R, column-major, lda >= I (read only)
  *   Q   : device, I x R, column-major, ldq >= I (written)
  *   Rk  : device, R x R upper triangular, column-major, ldr >= R (written,
@@ -201,14 +202,51 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
                    void* stream);
 
 /*
+ * Batched CP-ALS-QR for many small 3-way FP32 tensors (Alg. 2 per tensor,
+ * substitution solve, efficient error): one persistent launch in which one
+ * workgroup runs every sweep of one tensor, tensors taken largest first.
+ * Limits: R <= 16, R <= I[k] <= 256.
+ *
+ * cpqr_als_batch_prepare writes the per-tensor descriptors into the work
+ * buffer (synchronous: it returns after the stream has drained) and, when
+ * autotune != 0, picks the workgroup size (256, 512 or 1024 threads per
+ * tensor) by timing one sweep of each candidate on the batch itself (the
+ * initial factors are restored afterwards); choices are cached per
+ * (architecture, batch shape) in the file named by CPQR_AUTOTUNE_CACHE
+ * (default ~/.cache/cpqr_autotune.txt).
+ * cpqr_als_batch_run enqueues nsweeps sweeps of every tensor (init != 0
+ * first computes the QRs of A[1], A[2], lambda = 1 and ||X||^2); relerr[b]
+ * receives the relative error of sweep sweep_offset + s.  threads = 0 uses
+ * the prepared choice.  cpqr_als_batch_graph does the same through a hipGraph
+ * captured on first use for these arguments and replayed afterwards.
+ */
+typedef struct cpqr_batch_item {
+  int64_t I[3];          /* mode sizes */
+  int R;                 /* rank */
+  const float* X;        /* device FP32 tensor, column-major */
+  double* A[3];          /* device I[k] x R factors; A[1], A[2] hold the start on entry */
+  double* lambda;        /* device, R weights */
+  double* relerr;        /* device, one double per sweep, or NULL */
+} cpqr_batch_item;
+
+size_t cpqr_als_batch_work(const cpqr_batch_item* items, int nitems);
+int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotune, void* work,
+                           size_t work_bytes, void* stream);
+int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream);
+int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream);
+/* workgroup size chosen by prepare (or a negative error code) */
+int cpqr_als_batch_threads(void* work);
+
+/*
  * Phase timers (the per-iteration breakdown of the paper's performance
  * section): when enabled, eager calls record HIP events around each phase on
  * the launch stream.  cpqr_timing_read synchronizes those events and returns
  * accumulated milliseconds and launch counts per phase since the last reset.
  * Phases: 0 Multi-TTM, 1 first (tensor-streaming) contraction, 2 factor QR,
- * 3 computing Q_0, 4 applying Q_0, 5 solve + normalize, 6 error.
+ * 3 computing Q_0, 4 applying Q_0, 5 solve + normalize, 6 error, 7 the
+ * subset of phase 1 that runs the row-tiled matrix-core kernel.
  */
-#define CPQR_NPHASES 7
+#define CPQR_NPHASES 8
 int cpqr_timing_enable(int on);
 int cpqr_timing_reset(void);
 int cpqr_timing_read(double* ms, int64_t* counts, int nphases);

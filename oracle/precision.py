@@ -50,3 +50,24 @@ def contract_bf16(Xm, Qm):
     """Reference value of a plain bfloat16 contraction (operands rounded to
     bfloat16, products summed exactly in float64)."""
     return round_bf16(Xm).astype(np.float64) @ round_bf16(Qm).astype(np.float64)
+
+
+def multittm_lowp(X, Qs, n, mode, order=None):
+    """Multi-TTM in every mode but n (eq. multittm with U_k = Q_k^T) where each
+    TTM's products are taken in a reduced-precision form ("bf16": operands
+    rounded to bfloat16; "bf16x2": the three kept split products), summed
+    exactly, and the intermediate tensor is stored in FP32 as the GPU stores
+    it.  Returns Y_(n) in float64."""
+    from . import tensor as T
+    if order is None:
+        order = T.multittm_order(X.shape, n)
+    Y = np.asarray(X, dtype=np.float32)
+    for k in order:
+        Q = np.asarray(Qs[k], dtype=np.float64)
+        Ym = T.unfold(Y, k).T.astype(np.float32)  # rows: other indices, cols: mode k
+        Qf = Q.astype(np.float32)
+        Z = contract_split(Ym, Qf) if mode == "bf16x2" else contract_bf16(Ym, Qf)
+        shape = list(Y.shape)
+        shape[k] = Q.shape[1]
+        Y = T.fold(Z.T, k, shape).astype(np.float32)
+    return T.unfold(Y, n).astype(np.float64)

@@ -28,8 +28,8 @@ F32, F64 = 0, 1
 PREC_F64, PREC_F32, PREC_BF16X2, PREC_BF16 = 0, 1, 2, 3
 STATUS_SINGULAR, STATUS_NONFINITE, STATUS_TRUNCATED, STATUS_ZERO_COLUMN = 1, 2, 4, 8
 ERROR_EFFICIENT, ERROR_DIRECT, ERROR_NONE = 0, 1, 2
-NPHASES = 7
-PHASES = ["multittm", "ttm_first", "factor_qr", "q0", "apply_q0", "solve", "error"]
+NPHASES = 8
+PHASES = ["multittm", "ttm_first", "factor_qr", "q0", "apply_q0", "solve", "error", "ttm_stream_m"]
 
 PREC_NAMES = {"f64": PREC_F64, "f32": PREC_F32, "bf16x2": PREC_BF16X2, "bf16": PREC_BF16}
 
@@ -59,6 +59,13 @@ class Problem(ctypes.Structure):
     ]
 
 
+class BatchItem(ctypes.Structure):
+    """Mirror of ``cpqr_batch_item``."""
+    _fields_ = [
+        ("I", _i64 * 3), ("R", ctypes.c_int), ("X", _vp), ("A", _vp * 3), ("lam", _vp), ("relerr", _vp),
+    ]
+
+
 _lib = None
 
 _SIGS = {
@@ -83,6 +90,11 @@ _SIGS = {
     "cpqr_als_work": (_sz, [ctypes.POINTER(Problem)]),
     "cpqr_als_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
     "cpqr_als_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_als_batch_work": (_sz, [ctypes.POINTER(BatchItem), ctypes.c_int]),
+    "cpqr_als_batch_prepare": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int, _vp, _sz, _vp]),
+    "cpqr_als_batch_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "cpqr_als_batch_graph": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "cpqr_als_batch_threads": (ctypes.c_int, [_vp]),
     "cpqr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "cpqr_timing_reset": (ctypes.c_int, []),
     "cpqr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]),
@@ -354,6 +366,62 @@ def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=
         if s >= 1 and abs(hist[-2] - hist[-1]) < tol:
             break
     return st, hist
+
+
+class AlsBatch:
+    """Device buffers of a batch of 3-way FP32 tensors for cpqr_als_batch_*.
+
+    tensors: list of column-major FP32 CUDA tensors; inits: list of lists of
+    three (I_k, R) initial factors (entry 0 unused); nsweeps_max: length of
+    each tensor's relative-error record."""
+
+    def __init__(self, tensors, inits, nsweeps_max, autotune=False):
+        n = len(tensors)
+        nsweeps_max = max(1, int(nsweeps_max))
+        self.nsweeps_max = nsweeps_max
+        self.tensors = tensors
+        self.A, self.lam, self.relerr = [], [], []
+        arr = (BatchItem * n)()
+        for b, X in enumerate(tensors):
+            _dev(X, "X")
+            _check_colmajor(X, "X")
+            if X.dtype != torch.float32 or X.dim() != 3:
+                raise TypeError("batch tensors must be 3-way float32")
+            R = inits[b][1].shape[1]
+            dev = X.device
+            A = [empty_colmajor((X.shape[0], R), torch.float64, dev).zero_()] + [
+                colmajor(torch.as_tensor(inits[b][k], dtype=torch.float64).to(dev)) for k in (1, 2)]
+            lam = torch.ones(R, dtype=torch.float64, device=dev)
+            rel = torch.zeros(nsweeps_max, dtype=torch.float64, device=dev)
+            self.A.append(A)
+            self.lam.append(lam)
+            self.relerr.append(rel)
+            it = arr[b]
+            for k in range(3):
+                it.I[k] = X.shape[k]
+                it.A[k] = A[k].data_ptr()
+            it.R, it.X, it.lam, it.relerr = R, X.data_ptr(), lam.data_ptr(), rel.data_ptr()
+        self.items = arr
+        self.n = n
+        nbytes = lib().cpqr_als_batch_work(arr, n)
+        if nbytes == 0:
+            raise CpqrError("cpqr_als_batch_work", -1, "bad batch")
+        self._wkeep, self._w = _work(nbytes, tensors[0].device)
+        self._wbytes = nbytes
+        _call("cpqr_als_batch_prepare", arr, n, int(bool(autotune)), self._w, self._wbytes, _stream())
+
+    @property
+    def threads(self):
+        t = lib().cpqr_als_batch_threads(self._w)
+        if t < 0:
+            raise CpqrError("cpqr_als_batch_threads", t, lib().cpqr_last_error().decode())
+        return t
+
+    def run(self, nsweeps, init=False, offset=0, threads=0, graph=False):
+        if offset + nsweeps > self.nsweeps_max:
+            raise ValueError("relative-error record holds %d sweeps" % self.nsweeps_max)
+        name = "cpqr_als_batch_graph" if graph else "cpqr_als_batch_run"
+        _call(name, self._w, int(nsweeps), int(bool(init)), int(offset), int(threads), _stream())
 
 
 def cpqr_timing_enable(on=True):

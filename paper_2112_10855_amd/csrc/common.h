@@ -61,7 +61,7 @@ inline int64_t ipow(int64_t b, int e) {
 
 // ---------------------------------------------------------------- timing
 enum Phase { PH_MULTITTM = 0, PH_TTM_FIRST = 1, PH_FACTOR_QR = 2, PH_Q0 = 3, PH_APPLY_Q0 = 4,
-             PH_SOLVE = 5, PH_ERROR = 6 };
+             PH_SOLVE = 5, PH_ERROR = 6, PH_TTM_STREAM_M = 7 };
 // Scoped phase timer: records an event pair on `stream` when timing is on.
 struct PhaseTimer {
   int phase;

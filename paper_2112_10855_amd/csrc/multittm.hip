@@ -75,7 +75,10 @@ __global__ void prep_u_quads(const double* __restrict__ Q, int64_t K, int64_t ld
 constexpr int LDS_FLOATS = 16384;  // 64 KB
 
 // ---------------- P % 4 == 0: rows m = p + P s on the MFMA M dimension
-template <int NB, int UN, int MG, int NWV>
+// STREAM marks the instantiation used for a first contraction (it streams the
+// whole tensor); it is the same code under its own symbol so that profiles and
+// phase timers can single it out.
+template <int NB, int UN, int MG, int NWV, bool STREAM>
 __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__ X,
                                                        const float* __restrict__ U,
                                                        float* __restrict__ out, int64_t P,
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
 // ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
 // U4 holds four consecutive i interleaved per r, so one float4 read feeds the
 // four MFMAs of a step.  K % 4 == 0.
-template <int NB, int UN, int NWV>
+template <int NB, int UN, int NWV, bool STREAM>
 __global__ __launch_bounds__(NWV * 64) void ttm_mfma_k(const float* __restrict__ X,
                                                        const float* __restrict__ U4,
                                                        float* __restrict__ out, int64_t K,
@@ -286,8 +289,263 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_k(const float* __restrict__
   }
 }
 
+// ------------------------------------------------------------ bfloat16 forms
+// Operands are split as x = x_hi + x_lo with x_hi = bf16(x), x_lo = bf16(x -
+// x_hi) (hardware round-to-nearest-even).  SPLIT = true keeps three products
+// x_hi q_hi + x_hi q_lo + x_lo q_hi (the lo*lo term is dropped); SPLIT =
+// false keeps x_hi q_hi only.  Products run on v_mfma_f32_16x16x16_bf16 with
+// FP32 accumulation.  U's hi and lo halves are staged in LDS as quads of four
+// consecutive K rows per column (8 bytes each), the operand layout of that
+// instruction (lane l supplies k = 4*(l/16) .. +3).
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split4(float a, float b, float c, float d, shortx4& hi, shortx4& lo) {
+  const __bf16 ha = (__bf16)a, hb = (__bf16)b, hc = (__bf16)c, hd = (__bf16)d;
+  const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
+  const __bf16 lc = (__bf16)(c - (float)hc), ld = (__bf16)(d - (float)hd);
+  hi = shortx4{__builtin_bit_cast(short, ha), __builtin_bit_cast(short, hb), __builtin_bit_cast(short, hc),
+               __builtin_bit_cast(short, hd)};
+  lo = shortx4{__builtin_bit_cast(short, la), __builtin_bit_cast(short, lb), __builtin_bit_cast(short, lc),
+               __builtin_bit_cast(short, ld)};
+}
+
+template <bool SPLIT>
+__device__ inline floatx4 mfma_bf16(const shortx4& ah, const shortx4& al, const shortx4& bh,
+                                    const shortx4& bl, floatx4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+  if (SPLIT) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+  }
+  return c;
+}
+
+// Stage rows [c0, c1) of U (row-major K x RP FP32) as bf16 quads:
+// hiq/loq[q*RP + col] = 4 rows c0+4q..c0+4q+3 of column col.
+__device__ inline void stage_u_bf16(const float* __restrict__ U, int64_t c0, int64_t c1, int KC, int RP,
+                                    shortx4* hiq, shortx4* loq, int tid, int nthreads) {
+  for (int e = tid; e < (KC / 4) * RP; e += nthreads) {
+    const int64_t q = e / RP;
+    const int col = e % RP;
+    float v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t i = c0 + 4 * q + t;
+      v[t] = i < c1 ? U[i * RP + col] : 0.f;
+    }
+    split4(v[0], v[1], v[2], v[3], hiq[e], loq[e]);
+  }
+}
+
+// ---------------- P % 4 == 0 (rows on the MFMA M dimension)
+// A step covers 16 K rows: lane kq loads rows 4kq..4kq+3 (four float4 of four
+// consecutive p each); component j of the four loads forms the A operand of
+// the MFMA for rows m = mt + 4*l16 + j.
+template <bool SPLIT, int NB, int MG, int NWV, bool STREAM>
+__global__ __launch_bounds__(NWV * 64) void ttm_bf16_m(const float* __restrict__ X,
+                                                       const float* __restrict__ U,
+                                                       float* __restrict__ out, int64_t P,
+                                                       int64_t K, int64_t S, int R, int RP,
+                                                       int64_t kchunk, int64_t split_stride) {
+  extern __shared__ shortx4 ubq[];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int64_t M = P * S;
+  const int64_t mt = (int64_t(blockIdx.x) * NWV + w) * 64 * MG;
+  const bool active = mt < M;
+  const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t kb1 = min(K, kb0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  const float* base[MG];
+#pragma unroll
+  for (int g = 0; g < MG; ++g) {
+    int64_t mrow = mt + 64 * g + 4 * l16;
+    mrow = mrow < M ? mrow : M - 4;
+    const int64_t p = mrow % P, s = mrow / P;
+    base[g] = X + p + s * P * K + int64_t(4 * kq) * P;
+  }
+  floatx4 acc[NB][MG][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int STEP = 16;
+  const int KC = (LDS_FLOATS / RP) / STEP * STEP;  // hi + lo quads fill the budget
+  shortx4* hiq = ubq;
+  shortx4* loq = ubq + (KC / 4) * RP;
+  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+    const int64_t c1 = min(kb1, c0 + KC);
+    __syncthreads();
+    stage_u_bf16(U, c0, c1, KC, RP, hiq, loq, tid, NWV * 64);
+    __syncthreads();
+    if (!active) continue;
+    const int64_t nfull = (c1 - c0) / STEP;
+    const int64_t last = nfull > 0 ? c0 + (nfull - 1) * STEP : c0;
+    float4 A[4][MG], B[4][MG];
+    auto load = [&](float4(&dst)[4][MG], int64_t t) {
+      const int64_t i0 = min(c0 + t * STEP, last);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int g = 0; g < MG; ++g) dst[r][g] = *reinterpret_cast<const float4*>(base[g] + (i0 + r) * P);
+    };
+    auto compute = [&](const float4(&src)[4][MG], int64_t qoff) {
+#pragma unroll
+      for (int g = 0; g < MG; ++g) {
+        shortx4 ah[4], al[4];
+        split4(src[0][g].x, src[1][g].x, src[2][g].x, src[3][g].x, ah[0], al[0]);
+        split4(src[0][g].y, src[1][g].y, src[2][g].y, src[3][g].y, ah[1], al[1]);
+        split4(src[0][g].z, src[1][g].z, src[2][g].z, src[3][g].z, ah[2], al[2]);
+        split4(src[0][g].w, src[1][g].w, src[2][g].w, src[3][g].w, ah[3], al[3]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const shortx4 bh = hiq[(qoff + kq) * RP + b * 16 + l16];
+          const shortx4 bl = loq[(qoff + kq) * RP + b * 16 + l16];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[b][g][j] = mfma_bf16<SPLIT>(ah[j], al[j], bh, bl, acc[b][g][j]);
+        }
+      }
+    };
+    if (nfull > 0) {
+      load(A, 0);
+      for (int64_t t = 0; t < nfull; t += 2) {
+        load(B, t + 1);
+        compute(A, t * (STEP / 4));
+        load(A, t + 2);
+        if (t + 1 < nfull) compute(B, (t + 1) * (STEP / 4));
+      }
+    }
+    const int64_t ct = c0 + nfull * STEP;  // chunk tail (< 16 rows), masked by row
+    if (ct < c1) {
+      float4 T[4][MG];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = ct + 4 * kq + r < c1;
+#pragma unroll
+        for (int g = 0; g < MG; ++g)
+          T[r][g] = ok ? *reinterpret_cast<const float4*>(base[g] + (ct + r) * P) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      compute(T, nfull * (STEP / 4));
+    }
+  }
+  if (!active) return;
+  float* o = out + int64_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int r = b * 16 + l16;
+    if (r >= R) continue;
+#pragma unroll
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = mt + 64 * g + 4 * (4 * kq + v) + j;
+          if (m < M) {
+            const int64_t pp = m % P, ss = m / P;
+            o[pp + r * P + ss * P * R] = acc[b][g][j][v];
+          }
+        }
+  }
+}
+
+// ---------------- P == 1 (columns on the MFMA N dimension)
+// The float4 a lane loads from one column (rows 4kq..4kq+3 of the step) is the
+// B operand of one MFMA; U quads are the A operand.  K % 4 == 0.
+template <bool SPLIT, int NB, int UN, int NWV, bool STREAM>
+__global__ __launch_bounds__(NWV * 64) void ttm_bf16_k(const float* __restrict__ X,
+                                                       const float* __restrict__ U,
+                                                       float* __restrict__ out, int64_t K,
+                                                       int64_t S, int R, int RP, int64_t kchunk,
+                                                       int64_t split_stride) {
+  extern __shared__ shortx4 ubq[];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int64_t st = (int64_t(blockIdx.x) * NWV + w) * 16;
+  const bool active = st < S;
+  const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t kb1 = min(K, kb0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  int64_t scl = st + l16;
+  scl = scl < S ? scl : S - 1;
+  const float* col = X + scl * K + 4 * kq;
+  floatx4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int STEP = 16 * UN;
+  const int KC = (LDS_FLOATS / RP) / STEP * STEP;
+  shortx4* hiq = ubq;
+  shortx4* loq = ubq + (KC / 4) * RP;
+  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+    const int64_t c1 = min(kb1, c0 + KC);
+    __syncthreads();
+    stage_u_bf16(U, c0, c1, KC, RP, hiq, loq, tid, NWV * 64);
+    __syncthreads();
+    if (!active) continue;
+    const int64_t nfull = (c1 - c0) / STEP;
+    const int64_t last = nfull > 0 ? c0 + (nfull - 1) * STEP : c0;
+    float4 A[UN], B[UN];
+    auto load = [&](float4(&dst)[UN], int64_t t) {
+      const int64_t i0 = min(c0 + t * STEP, last);
+#pragma unroll
+      for (int u = 0; u < UN; ++u) dst[u] = *reinterpret_cast<const float4*>(col + i0 + 16 * u);
+    };
+    auto compute = [&](const float4(&src)[UN], int64_t t) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        shortx4 xh, xl;
+        split4(src[u].x, src[u].y, src[u].z, src[u].w, xh, xl);
+        const int64_t q = (t * STEP + 16 * u) / 4 + kq;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const shortx4 ah = hiq[q * RP + b * 16 + l16];
+          const shortx4 al = loq[q * RP + b * 16 + l16];
+          acc[b] = mfma_bf16<SPLIT>(ah, al, xh, xl, acc[b]);
+        }
+      }
+    };
+    if (nfull > 0) {
+      load(A, 0);
+      for (int64_t t = 0; t < nfull; t += 2) {
+        load(B, t + 1);
+        compute(A, t);
+        load(A, t + 2);
+        if (t + 1 < nfull) compute(B, t + 1);
+      }
+    }
+    for (int64_t i = c0 + nfull * STEP; i < c1; i += 16) {  // chunk tail, c1 % 4 == 0
+      const bool ok = i + 4 * kq < c1;
+      const float4 xv = ok ? *reinterpret_cast<const float4*>(col + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+      shortx4 xh, xl;
+      split4(xv.x, xv.y, xv.z, xv.w, xh, xl);
+      const int64_t q = (i - c0) / 4 + kq;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const shortx4 ah = ok ? hiq[q * RP + b * 16 + l16] : shortx4{0, 0, 0, 0};
+        const shortx4 al = ok ? loq[q * RP + b * 16 + l16] : shortx4{0, 0, 0, 0};
+        acc[b] = mfma_bf16<SPLIT>(ah, al, xh, xl, acc[b]);
+      }
+    }
+  }
+  const int64_t s = st + l16;
+  if (!active || s >= S) return;
+  float* o = out + int64_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = b * 16 + 4 * kq + v;
+      if (r < R) o[r + int64_t(R) * s] = acc[b][v];
+    }
+}
+
 // ------------------------------------------------------------ VALU fallback
-template <class TX, class TA, int RM>
+// MODE: 0 plain products in TA, 1 bfloat16 operands, 2 split bfloat16 (three
+// products), the latter two in FP32 arithmetic.
+template <int MODE>
+__device__ inline float bf16_round(float v) { return (float)(__bf16)v; }
+
+template <class TX, class TA, int RM, int MODE>
 __global__ __launch_bounds__(256) void ttm_valu(const TX* __restrict__ X, const TA* __restrict__ U,
                                                 TA* __restrict__ out, int64_t P, int64_t K,
                                                 int64_t S, int R, int RP, int64_t kchunk,
@@ -305,8 +563,21 @@ __global__ __launch_bounds__(256) void ttm_valu(const TX* __restrict__ X, const 
   for (int64_t i = k0; i < k1; ++i) {
     const TA x = TA(base[i * P]);
     const TA* u = U + i * RP;
+    if (MODE == 0) {
 #pragma unroll
-    for (int r = 0; r < RM; ++r) acc[r] += x * u[r];
+      for (int r = 0; r < RM; ++r) acc[r] += x * u[r];
+    } else {
+      const float xh = bf16_round<MODE>(float(x));
+      const float xl = bf16_round<MODE>(float(x) - xh);
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const float uh = bf16_round<MODE>(float(u[r]));
+        const float ul = bf16_round<MODE>(float(u[r]) - uh);
+        float v = xh * uh;
+        if (MODE == 2) v += xh * ul + xl * uh;
+        acc[r] += TA(v);
+      }
+    }
   }
   TA* o = out + int64_t(blockIdx.y) * split_stride;
 #pragma unroll
@@ -357,7 +628,8 @@ struct Plan {
   int RP;
 };
 
-bool uses_mfma(int prec) { return prec == CPQR_PREC_F32; }
+bool uses_mfma(int prec) { return prec != CPQR_PREC_F64; }
+int valu_mode(int prec) { return prec == CPQR_PREC_BF16 ? 1 : (prec == CPQR_PREC_BF16X2 ? 2 : 0); }
 
 Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned = true) {
   Plan pl{};
@@ -447,33 +719,70 @@ size_t carve(Carver& cv, const Plan& pl, int N, const int64_t* I, int n, Bufs* b
   return cv.bytes();
 }
 
-template <class TA, int RM>
+template <class TA, int RM, int MODE>
 int launch_valu(const void* src, int src_dtype, const TA* U, TA* dst, const Step& s, int R, int RP,
                 hipStream_t st) {
   const dim3 grd(unsigned(ceil_div(s.P * s.S, 256)), unsigned(s.splits));
   if (src_dtype == CPQR_F64)
-    hipLaunchKernelGGL((ttm_valu<double, TA, RM>), grd, dim3(256), 0, st,
+    hipLaunchKernelGGL((ttm_valu<double, TA, RM, MODE>), grd, dim3(256), 0, st,
                        static_cast<const double*>(src), U, dst, s.P, s.K, s.S, R, RP, s.kchunk,
                        s.out_count);
   else
-    hipLaunchKernelGGL((ttm_valu<float, TA, RM>), grd, dim3(256), 0, st,
+    hipLaunchKernelGGL((ttm_valu<float, TA, RM, MODE>), grd, dim3(256), 0, st,
                        static_cast<const float*>(src), U, dst, s.P, s.K, s.S, R, RP, s.kchunk,
                        s.out_count);
   return check_launch("ttm_valu");
 }
 
-template <class TA>
+template <class TA, int MODE>
 int launch_valu_r(const void* src, int src_dtype, const TA* U, TA* dst, const Step& s, int R,
                   int RP, hipStream_t st) {
   switch (round_rank(R)) {
-    case 8: return launch_valu<TA, 8>(src, src_dtype, U, dst, s, R, RP, st);
-    case 16: return launch_valu<TA, 16>(src, src_dtype, U, dst, s, R, RP, st);
-    default: return launch_valu<TA, 32>(src, src_dtype, U, dst, s, R, RP, st);
+    case 8: return launch_valu<TA, 8, MODE>(src, src_dtype, U, dst, s, R, RP, st);
+    case 16: return launch_valu<TA, 16, MODE>(src, src_dtype, U, dst, s, R, RP, st);
+    default: return launch_valu<TA, 32, MODE>(src, src_dtype, U, dst, s, R, RP, st);
   }
 }
 
-int launch_mfma(const float* src, const float* U, float* dst, const Step& s, int R, int RP,
-                hipStream_t st) {
+int launch_valu_f32(int prec, const void* src, int src_dtype, const float* U, float* dst, const Step& s,
+                    int R, int RP, hipStream_t st) {
+  switch (valu_mode(prec)) {
+    case 1: return launch_valu_r<float, 1>(src, src_dtype, U, dst, s, R, RP, st);
+    case 2: return launch_valu_r<float, 2>(src, src_dtype, U, dst, s, R, RP, st);
+    default: return launch_valu_r<float, 0>(src, src_dtype, U, dst, s, R, RP, st);
+  }
+}
+
+template <bool SPLIT, bool STREAM>
+int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, int R, int RP, hipStream_t st) {
+  const int NB = RP / 16;
+  constexpr int NWV = 8;
+  const size_t lds = LDS_FLOATS * sizeof(float);
+  if (s.kind == K_MFMA_M) {
+    constexpr int MG = 2;
+    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
+    if (NB == 1)
+      hipLaunchKernelGGL((ttm_bf16_m<SPLIT, 1, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+    else
+      hipLaunchKernelGGL((ttm_bf16_m<SPLIT, 2, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+    return check_launch("ttm_bf16_m");
+  }
+  constexpr int UN = 2;
+  const dim3 grd(unsigned(ceil_div(ceil_div(s.S, 16), NWV)), unsigned(s.splits));
+  if (NB == 1)
+    hipLaunchKernelGGL((ttm_bf16_k<SPLIT, 1, UN, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K,
+                       s.S, R, RP, s.kchunk, s.out_count);
+  else
+    hipLaunchKernelGGL((ttm_bf16_k<SPLIT, 2, UN, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K,
+                       s.S, R, RP, s.kchunk, s.out_count);
+  return check_launch("ttm_bf16_k");
+}
+
+template <bool STREAM>
+int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, int R, int RP,
+                  hipStream_t st) {
   const int NB = RP / 16;
   constexpr int NWV = 8;
   const size_t lds = LDS_FLOATS * sizeof(float);
@@ -481,22 +790,33 @@ int launch_mfma(const float* src, const float* U, float* dst, const Step& s, int
     constexpr int UN = 2, MG = 4;
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
     if (NB == 1)
-      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
-                         s.S, R, RP, s.kchunk, s.out_count);
+      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+                         s.K, s.S, R, RP, s.kchunk, s.out_count);
     else
-      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
-                         s.S, R, RP, s.kchunk, s.out_count);
+      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+                         s.K, s.S, R, RP, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m");
   }
   constexpr int UN = 4;
   const dim3 grd(unsigned(ceil_div(ceil_div(s.S, 16), NWV)), unsigned(s.splits));
   if (NB == 1)
-    hipLaunchKernelGGL((ttm_mfma_k<1, UN, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S, R,
-                       RP, s.kchunk, s.out_count);
+    hipLaunchKernelGGL((ttm_mfma_k<1, UN, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S,
+                       R, RP, s.kchunk, s.out_count);
   else
-    hipLaunchKernelGGL((ttm_mfma_k<2, UN, NWV>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S, R,
-                       RP, s.kchunk, s.out_count);
+    hipLaunchKernelGGL((ttm_mfma_k<2, UN, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S,
+                       R, RP, s.kchunk, s.out_count);
   return check_launch("ttm_mfma_k");
+}
+
+int launch_mfma(int prec, bool first, const float* src, const float* U, float* dst, const Step& s, int R,
+                int RP, hipStream_t st) {
+  if (prec == CPQR_PREC_BF16X2)
+    return first ? launch_bf16_t<true, true>(src, U, dst, s, R, RP, st)
+                 : launch_bf16_t<true, false>(src, U, dst, s, R, RP, st);
+  if (prec == CPQR_PREC_BF16)
+    return first ? launch_bf16_t<false, true>(src, U, dst, s, R, RP, st)
+                 : launch_bf16_t<false, false>(src, U, dst, s, R, RP, st);
+  return first ? launch_mfma_t<true>(src, U, dst, s, R, RP, st) : launch_mfma_t<false>(src, U, dst, s, R, RP, st);
 }
 
 }  // namespace
@@ -510,8 +830,6 @@ size_t multittm_work(int N, const int64_t* I, int n, int R, int prec) {
 int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
                      const double* const* Q, int prec, void* Y, void* work, hipStream_t st) {
   PhaseTimer whole(PH_MULTITTM, st);
-  if (prec == CPQR_PREC_BF16 || prec == CPQR_PREC_BF16X2)
-    return fail(CPQR_ERR_UNSUPPORTED, "multittm: bfloat16 forms are not built in this library");
   const Plan pl = make_plan(N, I, n, R, prec, reinterpret_cast<uintptr_t>(X) % 16 == 0);
   Bufs b;
   Carver cv(work);
@@ -527,7 +845,7 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
     if (f64)
       hipLaunchKernelGGL(prep_u_rows<double>, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<double*>(b.U[s.k]));
-    else if (s.kind == K_MFMA_K)
+    else if (s.kind == K_MFMA_K && prec == CPQR_PREC_F32)
       hipLaunchKernelGGL(prep_u_quads, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<float*>(b.U[s.k]));
     else
@@ -547,13 +865,14 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
     {
       PhaseTimer first(t == 0 ? PH_TTM_FIRST : -1, st);
       if (f64) {
-        CPQR_TRY(launch_valu_r<double>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
-                                       static_cast<double*>(kout), s, R, RP, st));
+        CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
+                                           static_cast<double*>(kout), s, R, RP, st)));
       } else if (s.kind == K_VALU) {
-        CPQR_TRY(launch_valu_r<float>(cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
-                                      static_cast<float*>(kout), s, R, RP, st));
+        CPQR_TRY(launch_valu_f32(prec, cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
+                                 static_cast<float*>(kout), s, R, RP, st));
       } else {
-        CPQR_TRY(launch_mfma(static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
+        PhaseTimer stream_m(t == 0 && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
+        CPQR_TRY(launch_mfma(prec, t == 0, static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
                              static_cast<float*>(kout), s, R, RP, st));
       }
       if (s.splits > 1) {

@@ -1,0 +1,102 @@
+"""Batched CP-ALS-QR (one persistent launch, one workgroup per tensor)
+against the FP64 oracle run tensor by tensor on the same bytes and starts.
+
+Every tensor of a small uneven batch (sizes 12..160, ranks 2..12, including
+the extremes).  The Multi-TTM runs in FP32, so relative errors are compared
+on squares: the efficient form resolves the squared error to about the FP32
+unit roundoff times a small constant (tolerance 2e-6).
+
+Two checks:
+* one sweep from a common state (the GPU's factors after a few sweeps, handed
+  to both sides): squared errors to 2e-6 and Kruskal models to 1e-4 relative;
+* the whole 10-sweep trajectory from the same start: squared errors to
+  2e-6 + 2e-3 relative.  Across a swamp (a plateau followed by a fast drop)
+  the map from one sweep to the next amplifies the FP32 perturbations, so
+  trajectories agree less tightly than single sweeps do."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.cp_als_qr as OQ
+from oracle import tensor as OT
+from paper_2112_10855_amd import cpqr as C
+from paper_2112_10855_amd import synth
+from helpers import relnorm, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(count, seed, lo=12, hi=160, rlo=2, rhi=12):
+    shapes = synth.batch_shapes(count, lo, hi, rlo, rhi, seed=seed)
+    shapes[0] = ((160, 160, 160), 12)  # the largest case
+    shapes[1] = ((12, 12, 12), 12)     # smallest modes equal to the rank
+    shapes[2] = ((20, 150, 33), 2)
+    data = []
+    for b, (shape, R) in enumerate(shapes):
+        d = synth.cp_tensor(shape, R, 9000 + b, noise=1e-3, dtype=np.float32)
+        data.append((d["X"], synth.init_factors(shape, R, 9500 + b), R))
+    return data
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return make_batch(20, 77)
+
+
+def run_batch(data, nsweeps, **kw):
+    Xs = [to_dev(X, torch.float32) for X, _, _ in data]
+    B = C.AlsBatch(Xs, [init for _, init, _ in data], nsweeps, autotune=kw.pop("autotune", False))
+    B.run(nsweeps, init=True, **kw)
+    torch.cuda.synchronize()
+    return B
+
+
+def test_batch_one_sweep_from_common_state(batch):
+    B = run_batch(batch, 4)
+    mid = [(X, [to_np(a) for a in B.A[b]], R) for b, (X, _, R) in enumerate(batch)]
+    B1 = run_batch(mid, 1)
+    for b, (X, init, R) in enumerate(mid):
+        lo, Ao, ho = OQ.cp_als_qr(X.astype(np.float64), init, maxiters=1)
+        rel = to_np(B1.relerr[b])
+        np.testing.assert_allclose(rel ** 2, np.array(ho) ** 2, rtol=0, atol=2e-6, err_msg="tensor %d" % b)
+        lam = to_np(B1.lam[b])
+        A = [to_np(a) for a in B1.A[b]]
+        assert relnorm(OT.full(lam, A), OT.full(lo, Ao)) < 1e-4, b
+
+
+def test_batch_trajectory_matches_oracle(batch):
+    B = run_batch(batch, 10)
+    for b, (X, init, R) in enumerate(batch):
+        _, _, ho = OQ.cp_als_qr(X.astype(np.float64), init, maxiters=10)
+        rel = to_np(B.relerr[b])
+        np.testing.assert_allclose(rel ** 2, np.array(ho) ** 2, rtol=2e-3, atol=2e-6, err_msg="tensor %d" % b)
+
+
+def test_graph_replay_equals_direct_launch(batch):
+    sub = batch[:6]
+    B1 = run_batch(sub, 4)
+    Xs = [to_dev(X, torch.float32) for X, _, _ in sub]
+    B2 = C.AlsBatch(Xs, [init for _, init, _ in sub], 8)
+    B2.run(1, init=True, graph=True)   # capture + launch: init and one sweep
+    torch.cuda.synchronize()
+    for _ in range(3):                  # replays of a second captured graph
+        B2.run(1, init=False, offset=1, graph=True)
+        torch.cuda.synchronize()
+    # init+1 sweep, then three more single sweeps into relerr[1] repeatedly;
+    # compare the final state with 4 sweeps of the direct launch
+    for b in range(len(sub)):
+        for k in range(3):
+            assert torch.equal(B1.A[b][k], B2.A[b][k]), (b, k)
+        assert torch.equal(B1.lam[b], B2.lam[b])
+
+
+def test_autotune_picks_a_valid_size(batch, tmp_path, monkeypatch):
+    monkeypatch.setenv("CPQR_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    sub = batch[:8]
+    B = run_batch(sub, 3, autotune=True)
+    assert B.threads in (256, 512, 1024)
+    ref = run_batch(sub, 3)
+    for b in range(len(sub)):
+        np.testing.assert_allclose(to_np(B.relerr[b]), to_np(ref.relerr[b]), rtol=0, atol=1e-9)
+    assert (tmp_path / "tune.txt").exists()
