@@ -203,22 +203,33 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
 
 /*
  * Batched CP-ALS-QR for many small 3-way FP32 tensors (Alg. 2 per tensor,
- * substitution solve, efficient error): one persistent launch in which one
- * workgroup runs every sweep of one tensor, tensors taken largest first.
- * Limits: R <= 16, R <= I[k] <= 256.
+ * substitution solve, efficient error of section 3.3.1) in one persistent
+ * launch: one workgroup runs every sweep of one tensor, tensors taken
+ * largest first, no waits between workgroups.  The contraction X x_3 Q_3^T
+ * is shared by the updates of modes 1 and 2 (reuse of partial TTMs across
+ * modes), so a sweep reads each tensor twice.  Contractions in FP32, all
+ * else FP64.  Limits: R <= 16, R <= I[k] <= 256; X 4-byte aligned.
  *
+ * Ownership: every pointer in an item is caller-owned device memory that
+ * must stay valid while the prepared work buffer is used; A[0] is written
+ * only.  relerr (nullable) must hold sweep_offset + nsweeps doubles.
+ *
+ * cpqr_als_batch_work returns the work-buffer size (0 for invalid items).
  * cpqr_als_batch_prepare writes the per-tensor descriptors into the work
- * buffer (synchronous: it returns after the stream has drained) and, when
- * autotune != 0, picks the workgroup size (256, 512 or 1024 threads per
- * tensor) by timing one sweep of each candidate on the batch itself (the
- * initial factors are restored afterwards); choices are cached per
- * (architecture, batch shape) in the file named by CPQR_AUTOTUNE_CACHE
- * (default ~/.cache/cpqr_autotune.txt).
+ * buffer (synchronous: it returns after the stream has drained).  With
+ * autotune != 0 it picks the streaming-pass shape (tensor columns per
+ * thread, contraction steps in flight) and the row-block height by timing
+ * an init + one sweep of each candidate on the batch itself (the initial
+ * factors are restored afterwards); choices are cached per (architecture,
+ * batch shape) in the file named by CPQR_AUTOTUNE_CACHE (default
+ * ~/.cache/cpqr_autotune.txt).
  * cpqr_als_batch_run enqueues nsweeps sweeps of every tensor (init != 0
- * first computes the QRs of A[1], A[2], lambda = 1 and ||X||^2); relerr[b]
- * receives the relative error of sweep sweep_offset + s.  threads = 0 uses
- * the prepared choice.  cpqr_als_batch_graph does the same through a hipGraph
- * captured on first use for these arguments and replayed afterwards.
+ * first computes the QRs of A[1], A[2] and sets lambda = 1); relerr[b][s +
+ * sweep_offset] receives the relative error of sweep s.  variant = 0 uses
+ * the prepared streaming shape, 1..3 force one (all give identical results).
+ * cpqr_als_batch_graph does the same through a hipGraph captured on first
+ * use for these arguments and replayed afterwards.  Calls on one work
+ * buffer must not overlap.
  */
 typedef struct cpqr_batch_item {
   int64_t I[3];          /* mode sizes */
@@ -232,10 +243,10 @@ typedef struct cpqr_batch_item {
 size_t cpqr_als_batch_work(const cpqr_batch_item* items, int nitems);
 int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotune, void* work,
                            size_t work_bytes, void* stream);
-int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream);
-int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream);
-/* workgroup size chosen by prepare (or a negative error code) */
-int cpqr_als_batch_threads(void* work);
+int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream);
+int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream);
+/* the configuration chosen by prepare (any output may be NULL) */
+int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* rows);
 
 /*
  * Phase timers (the per-iteration breakdown of the paper's performance

@@ -94,7 +94,8 @@ _SIGS = {
     "cpqr_als_batch_prepare": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int, _vp, _sz, _vp]),
     "cpqr_als_batch_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "cpqr_als_batch_graph": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
-    "cpqr_als_batch_threads": (ctypes.c_int, [_vp]),
+    "cpqr_als_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int)]),
     "cpqr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "cpqr_timing_reset": (ctypes.c_int, []),
     "cpqr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]),
@@ -411,17 +412,17 @@ class AlsBatch:
         _call("cpqr_als_batch_prepare", arr, n, int(bool(autotune)), self._w, self._wbytes, _stream())
 
     @property
-    def threads(self):
-        t = lib().cpqr_als_batch_threads(self._w)
-        if t < 0:
-            raise CpqrError("cpqr_als_batch_threads", t, lib().cpqr_last_error().decode())
-        return t
+    def config(self):
+        """(tensor columns per thread, steps in flight, row-block height)."""
+        c, u, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _call("cpqr_als_batch_config", self._w, ctypes.byref(c), ctypes.byref(u), ctypes.byref(r))
+        return c.value, u.value, r.value
 
-    def run(self, nsweeps, init=False, offset=0, threads=0, graph=False):
+    def run(self, nsweeps, init=False, offset=0, variant=0, graph=False):
         if offset + nsweeps > self.nsweeps_max:
             raise ValueError("relative-error record holds %d sweeps" % self.nsweeps_max)
         name = "cpqr_als_batch_graph" if graph else "cpqr_als_batch_run"
-        _call(name, self._w, int(nsweeps), int(bool(init)), int(offset), int(threads), _stream())
+        _call(name, self._w, int(nsweeps), int(bool(init)), int(offset), int(variant), _stream())
 
 
 def cpqr_timing_enable(on=True):

@@ -1,19 +1,24 @@
 // Batched CP-ALS-QR (paper Alg. 2) for many small 3-way tensors in one
 // persistent launch.
 //
-// Design.  One workgroup owns one tensor for the whole run: every sweep's
-// Khatri-Rao QR, Multi-TTM, Q_0 application, solve, normalization, factor QR
-// and efficient error execute inside that workgroup, with workgroup barriers
-// between steps and no dependency on any other workgroup, so a single launch
-// carries all sweeps of all tensors.  Tensors are dispatched largest first
-// (longest-processing-time order) so the big ones start early.  Per-tensor
-// scratch (intermediates, Q_k, R_k, Q_0, R_0) lives in the caller's work
-// buffer; the tensor and the factors stay in HBM and the small intermediates
-// stay in L2.
+// Design.  One workgroup owns one tensor for the whole launch and runs every
+// sweep of it: no workgroup ever waits on another, so the launch carries
+// all sweeps of all tensors with workgroup barriers only.  Tensors are taken
+// largest first.  A sweep (modes counted from 1 as in the paper):
+//   Z = X x_3 Q_3^T                        streams X (and gives ||X||^2)
+//   mode 1: Y_(1) = Z x_2 Q_2^T by row blocks, W = Y Q_0, solve A R_0^T = W,
+//           then normalize, factor QR of A_1, Khatri-Rao QR for mode 2
+//   mode 2: Y_(2) = Z x_1 Q_1^T (new Q_1), W, solve, normalize, QRs
+//   T = X x_2 Q_2^T (new Q_2)              streams X
+//   mode 3: Y_(3) = T x_1 Q_1^T, W, solve, normalize, QRs, efficient error
+// Z serves modes 1 and 2 (Q_3 does not change between them), so a sweep
+// reads each tensor twice instead of three times: the reuse of partial TTMs
+// across modes (dimension trees) that the paper names for Multi-TTM.  The
+// results equal the per-mode Multi-TTMs up to FP32 rounding order.
 //
-// Limits: N = 3, R <= 16, I_k <= NT (the factor QR keeps one row per thread),
-// R^2 <= NT.  Arithmetic: Multi-TTM in FP32 on the vector ALUs (the tensors are
-// small and the contractions short), everything else FP64.
+// Arithmetic: contractions in FP32 on FP32 copies of Q_k, everything else
+// in FP64.  Limits: R <= 16, R <= I_k <= 256 (the factor QR keeps one row
+// per thread).
 
 #include <sys/stat.h>
 
@@ -33,99 +38,257 @@ namespace {
 
 using namespace wgqr;
 
-constexpr int RB = 16;     // register width for factor rows (R <= 16)
-constexpr int UROWS = 256; // rows of a contraction operand staged in LDS
+constexpr int NT = 256;    // threads per workgroup
+constexpr int NW = NT / WAVE;
+constexpr int RB = 16;     // register width for rank-indexed rows (R <= 16)
+constexpr int IMAX = 256;  // largest mode size
+constexpr int YS = 4096;   // floats of Y rows held per row block
 
 struct BItem {
   int64_t I[3];
   int R;
-  int pad;
+  int nB[3];     // row blocks per mode
+  int rows[3];   // rows per block per mode
   const float* X;
   double* A[3];
-  double* Q[3];
-  double* Rf[3];
   double* lam;
   double* relerr;
-  float* T;    // first contraction output
-  float* T2;   // second contraction output before unfolding
-  float* Y;    // Y_(n), I_n x R^2
-  double* Q0;  // R^2 x R
-  double* R0;  // R x R
-  double* xnorm2;
+  double* Q[3];    // Q_k, column-major I_k x R (FP64)
+  float* Qf[3];    // FP32 copy of Q_k, row-major I_k x RB, zero past R
+  double* Rf[3];   // R_k, column-major R x R
+  double* Q0b[3];  // Q_0 for mode n, row-major R^2 x R
+  double* R0b[3];  // R_0 for mode n, column-major R x R
+  float* Z;        // Z[i1 + I1 i2 + I1 I2 r3]
+  float* T;        // T[i1 + I1 r2 + I1 R i3]
+  double* lamp;    // [block][RB] column sums of squares of A rows per block
+  double* ipp;     // [block] <W, A R_0^T> per block (mode 3)
+  double* xnorm2;  // ||X||^2
 };
 
-template <int NT>
 struct BShared {
-  Shared<RB, NT> qr;
   union alignas(16) {
-    float us[UROWS * RB];     // contraction operand, row-major (i, r) -- Multi-TTM
-    double q0s[UROWS * RB];   // Q_0 rows, row-major (rho, c) -- Khatri-Rao QR to solve
+    float us[IMAX * RB];  // contraction operand (FP32), later W rows (FP64)
+    double ws[IMAX * RB / 2];
   };
-  double r0[RB][RB + 1];      // R_0
-  double rn[RB][RB + 1];      // R_n of the last factor QR
+  union alignas(16) {
+    float ys[YS];  // Y rows of a block, row-major nb x R^2
+    Shared<RB, NT> qr;
+  };
+  double r0[RB][RB + 1];
+  double rn[RB][RB + 1];
   double lam[RB];
+  double red[NW * RB];
+  double res[RB];
 };
 
-// T'[p, r, s] = sum_i T[p, i, s] U[i, r] with U in LDS (row-major, RB wide).
-// One thread per (p, s); R accumulators; RR is R rounded up to a multiple of 4.
-template <int NT, int RR>
-__device__ void wg_ttm(const float* __restrict__ src, float* __restrict__ dst, int64_t P, int64_t K,
-                       int64_t S, int R, const float* us, int tid) {
-  const int64_t M = P * S;
-  for (int64_t m = tid; m < M; m += NT) {
-    const int64_t p = m % P, s = m / P;
-    const float* base = src + p + s * P * K;
-    float acc[RR];
+__device__ inline void stage_qf(const float* Qf, int rows, float* us, int tid) {
+  const float4* src = reinterpret_cast<const float4*>(Qf);
+  float4* dst = reinterpret_cast<float4*>(us);
+  for (int e = tid; e < rows * (RB / 4); e += NT) dst[e] = src[e];
+}
+
+template <int RR>
+__device__ inline void fma_row(float (&acc)[RR], float x, const float* urow) {
+  const float4* ur = reinterpret_cast<const float4*>(urow);
 #pragma unroll
-    for (int r = 0; r < RR; ++r) acc[r] = 0.f;
-    for (int64_t i = 0; i < K; ++i) {
-      const float x = base[i * P];
-      const float4* u = reinterpret_cast<const float4*>(us + i * RB);
+  for (int q = 0; q < RR / 4; ++q) {
+    const float4 uv = ur[q];
+    acc[4 * q] = fmaf(x, uv.x, acc[4 * q]);
+    acc[4 * q + 1] = fmaf(x, uv.y, acc[4 * q + 1]);
+    acc[4 * q + 2] = fmaf(x, uv.z, acc[4 * q + 2]);
+    acc[4 * q + 3] = fmaf(x, uv.w, acc[4 * q + 3]);
+  }
+}
+
+// ------------------------------------------------- streaming tile (AZ, AT)
+// out[p + P r + P R s] = sum_k X[p + P k + P K s] U[k, r] for the columns
+// m = p + P s in [m0, m1); U rows in LDS.  xx += sum of x^2 when want_sq.
+template <int RR, int CPT, int U>
+__device__ void stream_tile(const float* __restrict__ X, float* __restrict__ out, int64_t P, int K, int R,
+                            int64_t m0, int64_t m1, const float* us, bool want_sq, double& xx, int tid) {
+  for (int64_t base = m0; base < m1; base += NT * CPT) {
+    const float* xp[CPT];
+    int64_t ob[CPT];
+    bool valid[CPT];
 #pragma unroll
-      for (int q = 0; q < RR / 4; ++q) {
-        const float4 uv = u[q];
-        acc[4 * q] += x * uv.x;
-        acc[4 * q + 1] += x * uv.y;
-        acc[4 * q + 2] += x * uv.z;
-        acc[4 * q + 3] += x * uv.w;
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t m = base + tid + NT * j;
+      valid[j] = m < m1;
+      const int64_t mm = valid[j] ? m : m0;
+      const int64_t s = mm / P, p = mm - s * P;
+      xp[j] = X + p + P * K * s;
+      ob[j] = p + P * R * s;
+    }
+    float acc[CPT][RR], sq[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      sq[j] = 0.f;
+#pragma unroll
+      for (int r = 0; r < RR; ++r) acc[j][r] = 0.f;
+    }
+    int k = 0;
+    for (; k + U <= K; k += U) {
+      float x[CPT][U];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[j][u] = valid[j] ? xp[j][int64_t(k + u) * P] : 0.f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          fma_row<RR>(acc[j], x[j][u], us + (k + u) * RB);
+          sq[j] = fmaf(x[j][u], x[j][u], sq[j]);
+        }
+      }
+    }
+    for (; k < K; ++k) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const float xv = valid[j] ? xp[j][int64_t(k) * P] : 0.f;
+        fma_row<RR>(acc[j], xv, us + k * RB);
+        sq[j] = fmaf(xv, xv, sq[j]);
       }
     }
 #pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (!valid[j]) continue;
+      if (want_sq) xx += double(sq[j]);
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+        if (r < R) out[ob[j] + P * r] = acc[j][r];
+    }
+  }
+}
+
+// ---------------------------------------------------- Y rows of a block
+// ys[rl R^2 + ru + R rt] = sum_i U[i, ru] src[(a + rl) srow + i si + rt srt]
+template <int RR>
+__device__ void y_rows(const float* __restrict__ src, int64_t srow, int64_t si, int64_t srt, int Kc, int a,
+                       int nb, int R, const float* us, float* ys, int tid) {
+  for (int e = tid; e < nb * R; e += NT) {
+    const int rl = e % nb, rt = e / nb;
+    const float* ptr = src + int64_t(a + rl) * srow + int64_t(rt) * srt;
+    float acc[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) acc[r] = 0.f;
+    int i = 0;
+    for (; i + 4 <= Kc; i += 4) {
+      float x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = ptr[int64_t(i + u) * si];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fma_row<RR>(acc, x[u], us + (i + u) * RB);
+    }
+    for (; i < Kc; ++i) fma_row<RR>(acc, ptr[int64_t(i) * si], us + i * RB);
+    float* yr = ys + rl * R * R + R * rt;
+#pragma unroll
     for (int r = 0; r < RR; ++r)
-      if (r < R) dst[p + r * P + s * P * R] = acc[r];
+      if (r < R) yr[r] = acc[r];
   }
 }
 
-template <int NT>
-__device__ void wg_ttm_r(const float* src, float* dst, int64_t P, int64_t K, int64_t S, int R,
-                         const float* us, int tid) {
-  if (R <= 4) wg_ttm<NT, 4>(src, dst, P, K, S, R, us, tid);
-  else if (R <= 8) wg_ttm<NT, 8>(src, dst, P, K, S, R, us, tid);
-  else if (R <= 12) wg_ttm<NT, 12>(src, dst, P, K, S, R, us, tid);
-  else wg_ttm<NT, 16>(src, dst, P, K, S, R, us, tid);
+__device__ inline void wg_sum16(double (&x)[RB], BShared& sh, int tid) {
+  block_sum_vec<RB, NW>(x, sh.red, sh.res, tid);
 }
 
-// Stage Q_k (I_k x R FP64, column-major) as FP32 rows into us; zeros past R.
-template <int NT>
-__device__ void stage_u(const double* Q, int64_t Ik, int R, float* us, int tid) {
-  for (int e = tid; e < Ik * RB; e += NT) {
-    const int i = e / RB, r = e % RB;
-    us[e] = r < R ? float(Q[i + int64_t(r) * Ik]) : 0.f;
+__device__ inline double wg_sum1(double v, BShared& sh, int tid) {
+  double x[1] = {v};
+  block_sum_vec<1, NW>(x, sh.red, sh.res, tid);
+  return sh.res[0];
+}
+
+// ------------------------------------------------------------- B task
+// Rows [a, a + nb) of mode n: Y rows, W = Y Q_0, A R_0^T = W, partials.
+__device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, int a, int nb, int slot, BShared& sh, int tid) {
+  const int R = it.R;
+  const int64_t I0 = it.I[0], I1 = it.I[1];
+  const float* src;
+  int64_t srow, si, srt;
+  int Kc, um;
+  if (n == 0) {         // Y_(1)(i1, r2 + R r3) = sum_i2 Q_2(i2, r2) Z(i1, i2, r3)
+    src = it.Z, srow = 1, si = I0, srt = I0 * I1, Kc = int(I1), um = 1;
+  } else if (n == 1) {  // Y_(2)(i2, r1 + R r3) = sum_i1 Q_1(i1, r1) Z(i1, i2, r3)
+    src = it.Z, srow = I0, si = 1, srt = I0 * I1, Kc = int(I0), um = 0;
+  } else {              // Y_(3)(i3, r1 + R r2) = sum_i1 Q_1(i1, r1) T(i1, r2, i3)
+    src = it.T, srow = I0 * R, si = 1, srt = I0, Kc = int(I0), um = 0;
+  }
+  stage_qf(it.Qf[um], Kc, sh.us, tid);
+  const int K0 = R * R;
+  for (int e = tid; e < R * R; e += NT) sh.r0[e % R][e / R] = it.R0b[n][e];
+  __syncthreads();
+  if (R <= 4) y_rows<4>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
+  else if (R <= 8) y_rows<8>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
+  else if (R <= 12) y_rows<12>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
+  else y_rows<16>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
+  __syncthreads();
+  // W rows (FP64) into sh.ws, row-major nb x RB (the U operand is dead now);
+  // Q_0 (at most 32 KB) is read through the caches
+  const double* q0 = it.Q0b[n];
+  for (int e = tid; e < nb * R; e += NT) {
+    const int rl = e % nb, c = e / nb;
+    const float* yr = sh.ys + rl * K0;
+    double w = 0.0;
+    for (int rho = 0; rho < K0; ++rho) w += double(yr[rho]) * q0[rho * R + c];
+    sh.ws[rl * RB + c] = w;
+  }
+  __syncthreads();
+  double arow[RB], x[RB];
+#pragma unroll
+  for (int c = 0; c < RB; ++c) arow[c] = 0.0;
+  double ip = 0.0;
+  const int64_t In = it.I[n];
+  if (tid < nb) {
+    const double* w = sh.ws + tid * RB;
+#pragma unroll
+    for (int j = RB - 1; j >= 0; --j) {
+      if (j < R) {
+        double v = w[j];
+#pragma unroll
+        for (int c = j + 1; c < RB; ++c)
+          if (c < R) v -= sh.r0[j][c] * arow[c];
+        arow[j] = v / sh.r0[j][j];
+      }
+    }
+    double* An = it.A[n] + a + tid;
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c < R) An[int64_t(c) * In] = arow[c];
+    if (n == 2) {
+#pragma unroll
+      for (int c = 0; c < RB; ++c) {
+        if (c >= R) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+          if (k >= c && k < R) v += sh.r0[c][k] * arow[k];
+        ip += w[c] * v;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < RB; ++c) x[c] = arow[c] * arow[c];
+  wg_sum16(x, sh, tid);
+  if (tid < RB) it.lamp[slot * RB + tid] = sh.res[tid];
+  if (n == 2) {
+    ip = wg_sum1(ip, sh, tid);
+    if (tid == 0) it.ipp[slot] = ip;
   }
 }
 
-// Factor QR of the block held in a[] (one row per thread, m rows): writes
-// Q (m x R, ld m) and R (R x R) to global, and R into sh.rn.
-template <int NT>
-__device__ void wg_qr_store(double (&a)[RB], int m, int R, BShared<NT>& sh, double* Qout, int64_t ldq,
-                            double* Rout, int tid) {
+// ------------------------------------------------------------ QR helper
+// Householder QR of a (one row per thread, m rows).  Writes R (column-major
+// R x R) to Rout and, if keep_rn, into sh.rn; Q as requested: column-major
+// FP64 (ld m), row-major FP32 padded to RB, row-major FP64 (ld R).
+__device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, int R, BShared& sh, double* Qcm, float* Qf, double* Qrm,
+                         double* Rout, bool keep_rn, int tid) {
   wg_factor<RB, NT>(a, tid, m, R, sh.qr);
   wg_build_t<RB, NT>(tid, R, sh.qr);
   if (tid < R) {
 #pragma unroll
     for (int c = 0; c < RB; ++c) {
       const double v = (c >= tid && c < R) ? a[c] : 0.0;
-      sh.rn[tid][c] = v;
+      if (keep_rn) sh.rn[tid][c] = v;
       if (c < R) Rout[tid + c * R] = v;
     }
   }
@@ -135,281 +298,262 @@ __device__ void wg_qr_store(double (&a)[RB], int m, int R, BShared<NT>& sh, doub
   wg_form_q<RB, NT>(a, q, tid, m, R, sh.qr);
   if (tid < m) {
 #pragma unroll
-    for (int c = 0; c < RB; ++c)
-      if (c < R) Qout[tid + c * ldq] = q[c];
+    for (int c = 0; c < RB; ++c) {
+      if (Qcm && c < R) Qcm[tid + int64_t(c) * m] = q[c];
+      if (Qrm && c < R) Qrm[tid * R + c] = q[c];
+    }
+    if (Qf) {
+      float4* dst = reinterpret_cast<float4*>(Qf + tid * RB);
+#pragma unroll
+      for (int g = 0; g < RB / 4; ++g) {
+        float4 v;
+        v.x = 4 * g < R ? float(q[4 * g]) : 0.f;
+        v.y = 4 * g + 1 < R ? float(q[4 * g + 1]) : 0.f;
+        v.z = 4 * g + 2 < R ? float(q[4 * g + 2]) : 0.f;
+        v.w = 4 * g + 3 < R ? float(q[4 * g + 3]) : 0.f;
+        dst[g] = v;
+      }
+    }
   }
   __syncthreads();
 }
 
-template <int NT>
-__device__ double block_sum1(double v, Shared<RB, NT>& q, int tid) {
-  double x[1] = {v};
-  block_sum_vec<1, NT / WAVE>(x, q.red, q.res, tid);
-  return q.res[0];
+// QR of V_n = R_mb (.) R_ma (rows: index of ma fastest) into Q0b[n], R0b[n].
+__device__ __attribute__((always_inline)) void krp_qr(const BItem& it, int n, BShared& sh, int tid) {
+  const int R = it.R;
+  const int ma = n == 0 ? 1 : 0, mb = n == 2 ? 1 : 2;
+  const int K0 = R * R;
+  double a[RB];
+  const int da = tid % R, db = tid / R;
+#pragma unroll
+  for (int c = 0; c < RB; ++c)
+    a[c] = (tid < K0 && c < R) ? it.Rf[ma][da + c * R] * it.Rf[mb][db + c * R] : 0.0;
+  qr_store(a, K0, R, sh, nullptr, nullptr, it.Q0b[n], it.R0b[n], false, tid);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void als_batch_kernel(const BItem* __restrict__ items,
-                                                       const int* __restrict__ order, int nsweeps,
-                                                       int do_init, int sweep_offset) {
-  __shared__ BShared<NT> sh;
-  const int tid = threadIdx.x;
-  const BItem it = items[order[blockIdx.x]];
+__device__ __attribute__((always_inline)) void task_init(const BItem& it, BShared& sh, int tid) {
   const int R = it.R;
-  const int64_t I0 = it.I[0], I1 = it.I[1], I2 = it.I[2];
-
-  if (do_init) {
-    for (int k = 1; k < 3; ++k) {
-      double a[RB];
+  for (int k = 1; k < 3; ++k) {
+    const int64_t Ik = it.I[k];
+    double a[RB];
 #pragma unroll
-      for (int c = 0; c < RB; ++c) a[c] = (tid < it.I[k] && c < R) ? it.A[k][tid + c * it.I[k]] : 0.0;
-      wg_qr_store<NT>(a, int(it.I[k]), R, sh, it.Q[k], it.I[k], it.Rf[k], tid);
-    }
-    for (int c = tid; c < R; c += NT) it.lam[c] = 1.0;
+    for (int c = 0; c < RB; ++c) a[c] = (tid < Ik && c < R) ? it.A[k][tid + c * Ik] : 0.0;
+    qr_store(a, int(Ik), R, sh, it.Q[k], it.Qf[k], nullptr, it.Rf[k], false, tid);
+  }
+  for (int c = tid; c < R; c += NT) it.lam[c] = 1.0;
+  krp_qr(it, 0, sh, tid);
+}
+
+// Normalize A_n, factor QR of A_n, efficient error after mode 3, Khatri-Rao
+// QR for the next mode.
+__device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, int sweep, int offset, BShared& sh, int tid) {
+  const int R = it.R;
+  const int64_t In = it.I[n];
+  const int nb = it.nB[n];
+  if (tid < RB) {
     double s = 0.0;
-    const int64_t cnt = I0 * I1 * I2;
-    for (int64_t e = tid; e < cnt; e += NT) {
-      const double v = double(it.X[e]);
-      s += v * v;
+    for (int b = 0; b < nb; ++b) s += it.lamp[b * RB + tid];
+    sh.lam[tid] = tid < R ? sqrt(s) : 0.0;
+  }
+  __syncthreads();
+  double a[RB];
+#pragma unroll
+  for (int c = 0; c < RB; ++c) {
+    const double l = sh.lam[c];
+    const double v = (tid < In && c < R) ? it.A[n][tid + c * In] : 0.0;
+    a[c] = l > 0.0 ? v / l : 0.0;
+  }
+  if (tid < In) {
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c < R) it.A[n][tid + c * In] = a[c];
+  }
+  for (int c = tid; c < R; c += NT) it.lam[c] = sh.lam[c];
+  qr_store(a, int(In), R, sh, it.Q[n], it.Qf[n], nullptr, it.Rf[n], true, tid);
+  if (n == 2) {  // ||X||^2 - 2 <W, A R_0^T> + <R_0^T R_0, L R_3^T R_3 L>   (section 3.3.1)
+    for (int e = tid; e < R * R; e += NT) sh.r0[e % R][e / R] = it.R0b[2][e];
+    double ip = 0.0, x2 = 0.0;
+    for (int b = tid; b < nb; b += NT) ip += it.ipp[b];
+    if (tid == 0) x2 = *it.xnorm2;
+    __syncthreads();
+    double nn = 0.0;
+    for (int e = tid; e < R * R; e += NT) {
+      const int p = e % R, q = e / R;
+      double g0 = 0.0, gn = 0.0;
+      for (int k = 0; k < R; ++k) {
+        g0 += sh.r0[k][p] * sh.r0[k][q];
+        gn += sh.rn[k][p] * sh.rn[k][q];
+      }
+      nn += g0 * sh.lam[p] * sh.lam[q] * gn;
     }
-    s = block_sum1<NT>(s, sh.qr, tid);
-    if (tid == 0) *it.xnorm2 = s;
+    ip = wg_sum1(ip, sh, tid);
+    x2 = wg_sum1(x2, sh, tid);
+    nn = wg_sum1(nn, sh, tid);
+    if (tid == 0 && it.relerr) {
+      const double r2 = x2 - 2.0 * ip + nn;
+      it.relerr[offset + sweep] = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
+    }
     __syncthreads();
   }
+  krp_qr(it, n == 2 ? 0 : n + 1, sh, tid);
+}
 
-  const int64_t K0 = int64_t(R) * R;  // rows of V_n, columns of Y_(n)
-  for (int sw = 0; sw < nsweeps; ++sw) {
+template <int RR, int CPT, int U>
+__device__ void task_a_r(const BItem& it, bool isz, BShared& sh, int tid) {
+  const int64_t I0 = it.I[0], I1 = it.I[1], I2 = it.I[2];
+  const int64_t P = isz ? I0 * I1 : I0;
+  const int K = int(isz ? I2 : I1);
+  const int64_t M = isz ? I0 * I1 : I0 * I2;
+  double xx = 0.0;
+  stream_tile<RR, CPT, U>(it.X, isz ? it.Z : it.T, P, K, it.R, 0, M, sh.us, isz, xx, tid);
+  if (isz) {
+    xx = wg_sum1(xx, sh, tid);
+    if (tid == 0) *it.xnorm2 = xx;
+  }
+}
+
+// First contraction over the whole tensor: Z = X x_3 Q_3^T (isz) or
+// T = X x_2 Q_2^T.  Z also yields ||X||^2.
+template <int CPT, int U>
+__device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz, BShared& sh, int tid) {
+  const int k = isz ? 2 : 1;
+  stage_qf(it.Qf[k], int(it.I[k]), sh.us, tid);
+  __syncthreads();
+  const int R = it.R;
+  if (R <= 4) task_a_r<4, CPT, U>(it, isz, sh, tid);
+  else if (R <= 8) task_a_r<8, CPT, U>(it, isz, sh, tid);
+  else if (R <= 12) task_a_r<12, CPT, U>(it, isz, sh, tid);
+  else task_a_r<16, CPT, U>(it, isz, sh, tid);
+}
+
+// One sweep schedule per tensor; CPT tensor columns per thread and U
+// contraction steps in flight per column in the streaming passes.
+template <int CPT, int U>
+__global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restrict__ items,
+                                                          const int* __restrict__ order, int nsweeps, int do_init,
+                                                          int offset) {
+  __shared__ BShared sh;
+  const int tid = threadIdx.x;
+  const BItem& it = items[order[blockIdx.x]];
+  if (do_init) {
+    task_init(it, sh, tid);
+    __syncthreads();
+  }
+  for (int s = 0; s < nsweeps; ++s) {
     for (int n = 0; n < 3; ++n) {
-      const int ma = n == 0 ? 1 : 0, mb = n == 2 ? 1 : 2;  // the two other modes, ascending
-      // ---- Multi-TTM: Y_(n), first contraction over a mode with P > 1
-      int64_t Pn, In, Sn;  // layout of the second contraction's output [Pn, In, Sn]
-      if (n == 0) {
-        stage_u<NT>(it.Q[1], I1, R, sh.us, tid);
+      if (n == 0 || n == 2) {
+        task_a<CPT, U>(it, n == 0, sh, tid);
         __syncthreads();
-        wg_ttm_r<NT>(it.X, it.T, I0, I1, I2, R, sh.us, tid);  // T[i0, r1, i2]
-        __syncthreads();
-        stage_u<NT>(it.Q[2], I2, R, sh.us, tid);
-        __syncthreads();
-        wg_ttm_r<NT>(it.T, it.Y, I0 * R, I2, 1, R, sh.us, tid);  // Y[i0, r1, r2] = Y_(1)
-        Pn = 1;
-        In = I0;
-        Sn = K0;
-      } else if (n == 1) {
-        stage_u<NT>(it.Q[2], I2, R, sh.us, tid);
-        __syncthreads();
-        wg_ttm_r<NT>(it.X, it.T, I0 * I1, I2, 1, R, sh.us, tid);  // T[i0, i1, r2]
-        __syncthreads();
-        stage_u<NT>(it.Q[0], I0, R, sh.us, tid);
-        __syncthreads();
-        wg_ttm_r<NT>(it.T, it.T2, 1, I0, I1 * R, R, sh.us, tid);  // T2[r0, i1, r2]
-        Pn = R;
-        In = I1;
-        Sn = R;
-      } else {
-        stage_u<NT>(it.Q[1], I1, R, sh.us, tid);
-        __syncthreads();
-        wg_ttm_r<NT>(it.X, it.T, I0, I1, I2, R, sh.us, tid);  // T[i0, r1, i2]
-        __syncthreads();
-        stage_u<NT>(it.Q[0], I0, R, sh.us, tid);
-        __syncthreads();
-        wg_ttm_r<NT>(it.T, it.T2, 1, I0, R * I2, R, sh.us, tid);  // T2[r0, r1, i2]
-        Pn = K0;
-        In = I2;
-        Sn = 1;
       }
+      for (int blk = 0; blk < it.nB[n]; ++blk) {
+        const int a = blk * it.rows[n];
+        const int cnt = int(it.I[n] - a < it.rows[n] ? it.I[n] - a : it.rows[n]);
+        task_b(it, n, a, cnt, blk, sh, tid);
+        __syncthreads();
+      }
+      task_c(it, n, s, offset, sh, tid);
       __syncthreads();
-      if (n != 0) {  // Y_(n)[i + In (p + Pn s)] = T2[p + Pn i + Pn In s]
-        const int64_t cnt = Pn * In * Sn;
-        for (int64_t e = tid; e < cnt; e += NT) {
-          const int64_t i = e % In, c = e / In;
-          const int64_t p = c % Pn, s = c / Pn;
-          it.Y[e] = it.T2[p + Pn * i + Pn * In * s];
-        }
-        __syncthreads();
-      }
-      // ---- V_n = R_mb (.) R_ma, QR with Q_0 explicit (rows: index of ma fastest)
-      {
-        double a[RB];
-        const int rho = tid, da = rho % R, db = rho / R;
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          a[c] = (rho < K0 && c < R) ? it.Rf[ma][da + c * R] * it.Rf[mb][db + c * R] : 0.0;
-        wg_factor<RB, NT>(a, tid, int(K0), R, sh.qr);
-        wg_build_t<RB, NT>(tid, R, sh.qr);
-        if (tid < R) {
-#pragma unroll
-          for (int c = 0; c < RB; ++c) sh.r0[tid][c] = (c >= tid && c < R) ? a[c] : 0.0;
-        }
-        for (int e = tid; e < RB * RB; e += NT) sh.qr.C[e / RB][e % RB] = (e / RB == e % RB) ? 1.0 : 0.0;
-        __syncthreads();
-        double q[RB];
-        wg_form_q<RB, NT>(a, q, tid, int(K0), R, sh.qr);
-        if (tid < K0) {
-#pragma unroll
-          for (int c = 0; c < RB; ++c) sh.q0s[tid * RB + c] = c < R ? q[c] : 0.0;
-        }
-        __syncthreads();
-      }
-      // ---- W = Y_(n) Q_0, solve A R_0^T = W, per row; keep rows in registers
-      double arow[RB], wrow[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) arow[c] = wrow[c] = 0.0;
-      const int64_t Inn = it.I[n];
-      if (tid < Inn) {
-        for (int64_t rho = 0; rho < K0; ++rho) {
-          const double y = double(it.Y[tid + rho * Inn]);
-#pragma unroll
-          for (int c = 0; c < RB; ++c) wrow[c] += y * sh.q0s[rho * RB + c];
-        }
-#pragma unroll
-        for (int j = RB - 1; j >= 0; --j) {
-          if (j < R) {
-            double v = wrow[j];
-#pragma unroll
-            for (int c = j + 1; c < RB; ++c)
-              if (c < R) v -= sh.r0[j][c] * arow[c];
-            arow[j] = v / sh.r0[j][j];
-          }
-        }
-      }
-      // <W, Ahat R_0^T> of this row, needed by the error after the last mode
-      double ip = 0.0;
-      if (n == 2 && tid < Inn) {
-#pragma unroll
-        for (int c = 0; c < RB; ++c) {
-          if (c >= R) continue;
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < RB; ++k)
-            if (k >= c && k < R) v += arow[k] * sh.r0[c][k];
-          ip += wrow[c] * v;
-        }
-      }
-      // ---- normalize: lambda_c = ||A(:, c)||
-      {
-        double x[RB];
-#pragma unroll
-        for (int c = 0; c < RB; ++c) x[c] = arow[c] * arow[c];
-        block_sum_vec<RB, NT / WAVE>(x, sh.qr.red, sh.qr.res, tid);
-        if (tid < RB) sh.lam[tid] = tid < R ? sqrt(sh.qr.res[tid]) : 0.0;
-        __syncthreads();
-      }
-      double anorm[RB];
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const double l = sh.lam[c];
-        anorm[c] = (c < R && l > 0.0) ? arow[c] / l : 0.0;
-      }
-      if (tid < Inn) {
-#pragma unroll
-        for (int c = 0; c < RB; ++c)
-          if (c < R) it.A[n][tid + c * Inn] = anorm[c];
-      }
-      for (int c = tid; c < R; c += NT) it.lam[c] = sh.lam[c];
-      // ---- factor QR of the normalized A_n
-      {
-        double a[RB];
-#pragma unroll
-        for (int c = 0; c < RB; ++c) a[c] = tid < Inn ? anorm[c] : 0.0;
-        wg_qr_store<NT>(a, int(Inn), R, sh, it.Q[n], Inn, it.Rf[n], tid);
-      }
-      // ---- efficient error after the last mode (section 3.3.1)
-      if (n == 2) {
-        ip = block_sum1<NT>(ip, sh.qr, tid);
-        double nn = 0.0;
-        for (int e = tid; e < R * R; e += NT) {
-          const int a = e % R, b = e / R;
-          double g0 = 0.0, gn = 0.0;
-          for (int k = 0; k < R; ++k) {
-            g0 += sh.r0[k][a] * sh.r0[k][b];
-            gn += sh.rn[k][a] * sh.rn[k][b];
-          }
-          nn += g0 * sh.lam[a] * sh.lam[b] * gn;
-        }
-        nn = block_sum1<NT>(nn, sh.qr, tid);
-        if (tid == 0 && it.relerr) {
-          const double x2 = *it.xnorm2;
-          const double r2 = x2 - 2.0 * ip + nn;
-          it.relerr[sweep_offset + sw] = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
-        }
-        __syncthreads();
-      }
     }
   }
 }
 
 // ------------------------------------------------------------ host side
-struct Layout {
-  BItem* items;  // device
-  int* order;    // device
-  int n;
-  char* scratch;
+// Streaming-pass shapes the autotuner chooses from: (CPT, U).
+constexpr int NVAR = 3;
+constexpr int VAR_CPT[NVAR] = {4, 4, 2};
+constexpr int VAR_U[NVAR] = {4, 8, 8};
+constexpr int ROWS_MIN = 32;
+
+struct Config {
+  int var;   // streaming-pass shape
+  int rows;  // rows per block of the row steps (before the LDS cap)
 };
+
+int rows_for(int rows_cfg, int R) { return std::max(1, std::min(rows_cfg, YS / (R * R))); }
+
+int blocks_max(const cpqr_batch_item& b) {
+  const int r = rows_for(ROWS_MIN, b.R);
+  return int(ceil_div(std::max(b.I[0], std::max(b.I[1], b.I[2])), int64_t(r)));
+}
 
 size_t item_scratch(const cpqr_batch_item& b) {
   const int64_t R = b.R;
   const int64_t i0 = b.I[0], i1 = b.I[1], i2 = b.I[2];
-  const int64_t imax = std::max(i0, std::max(i1, i2));
-  const int64_t t1 = std::max(i0 * R * i2, i0 * i1 * R);
-  const int64_t t2 = R * R * imax;
+  const int nbmax = blocks_max(b);
   Carver cv(nullptr);
-  for (int k = 0; k < 3; ++k) cv.take<double>(size_t(b.I[k]) * R);  // Q
-  for (int k = 0; k < 3; ++k) cv.take<double>(size_t(R) * R);       // Rf
-  cv.take<float>(t1);
-  cv.take<float>(t2);
-  cv.take<float>(t2);                 // Y
-  cv.take<double>(size_t(R * R) * R);  // Q0
-  cv.take<double>(size_t(R) * R);      // R0
-  cv.take<double>(1);                  // xnorm2
+  for (int m = 0; m < 3; ++m) cv.take<double>(size_t(b.I[m]) * R);  // Q
+  for (int m = 0; m < 3; ++m) cv.take<float>(size_t(b.I[m]) * RB);  // Qf
+  for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R);       // Rf
+  for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R * R);   // Q0b
+  for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R);       // R0b
+  cv.take<float>(size_t(i0 * i1 * R));                             // Z
+  cv.take<float>(size_t(i0 * R * i2));                             // T
+  cv.take<double>(size_t(nbmax) * RB);                             // lamp
+  cv.take<double>(size_t(nbmax));                                  // ipp
+  cv.take<double>(1);                                              // xnorm2
   return cv.bytes();
 }
 
-int nt_needed(const cpqr_batch_item* items, int n) {
-  int64_t need = 1;
-  for (int b = 0; b < n; ++b) {
-    need = std::max(need, std::max(items[b].I[0], std::max(items[b].I[1], items[b].I[2])));
-    need = std::max<int64_t>(need, int64_t(items[b].R) * items[b].R);
+// What cpqr_als_batch_prepare decided for one work buffer (host side).
+struct BatchState {
+  int n = 0;
+  Config cfg{};
+  std::vector<BItem> h;  // host copy of the device descriptors
+  BItem* items_dev = nullptr;
+  int* order_dev = nullptr;
+};
+
+std::mutex g_batch_mu;
+std::map<const void*, BatchState> g_batch;
+
+int upload(BatchState& st, hipStream_t s) {
+  for (auto& d : st.h) {
+    for (int m = 0; m < 3; ++m) {
+      d.rows[m] = rows_for(st.cfg.rows, d.R);
+      d.nB[m] = int(ceil_div(d.I[m], int64_t(d.rows[m])));
+    }
   }
-  return int(need);
+  CPQR_HIP(hipMemcpyAsync(st.items_dev, st.h.data(), sizeof(BItem) * st.n, hipMemcpyHostToDevice, s));
+  CPQR_HIP(hipStreamSynchronize(s));  // the host copy may change after this call
+  return CPQR_OK;
 }
 
-int launch_batch(int nt, const Layout& L, int nsweeps, int do_init, int offset, hipStream_t s) {
-  const dim3 grd(unsigned(L.n));
-  if (nt == 256)
-    hipLaunchKernelGGL(als_batch_kernel<256>, grd, dim3(256), 0, s, L.items, L.order, nsweeps, do_init, offset);
-  else if (nt == 512)
-    hipLaunchKernelGGL(als_batch_kernel<512>, grd, dim3(512), 0, s, L.items, L.order, nsweeps, do_init, offset);
-  else
-    hipLaunchKernelGGL(als_batch_kernel<1024>, grd, dim3(1024), 0, s, L.items, L.order, nsweeps, do_init, offset);
+int launch_batch(const BatchState& st, int var, int nsweeps, int do_init, int offset, hipStream_t s) {
+  const dim3 grd(unsigned(st.n)), blk(NT);
+  switch (var) {
+    case 0:
+      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[0], VAR_U[0]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+                         nsweeps, do_init, offset);
+      break;
+    case 1:
+      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[1], VAR_U[1]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+                         nsweeps, do_init, offset);
+      break;
+    default:
+      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[2], VAR_U[2]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+                         nsweeps, do_init, offset);
+      break;
+  }
   return check_launch("als_batch_kernel");
 }
 
-// What cpqr_als_batch_prepare decided for one work buffer (host side).
-struct BatchHeader {
-  int n;
-  int nt;      // workgroup size chosen
-  int min_nt;  // smallest workgroup size that fits the batch
-};
-std::mutex g_batch_mu;
-std::map<const void*, BatchHeader> g_batch;
-
 struct GraphKey {
   const void* work;
-  int nsweeps, init, offset, nt;
+  int nsweeps, init, offset, var;
   bool operator<(const GraphKey& o) const {
     if (work != o.work) return work < o.work;
     if (nsweeps != o.nsweeps) return nsweeps < o.nsweeps;
     if (init != o.init) return init < o.init;
     if (offset != o.offset) return offset < o.offset;
-    return nt < o.nt;
+    return var < o.var;
   }
 };
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 hipStream_t g_capture_stream = nullptr;
 
-// autotune cache: key -> threads per tensor
+// ------------------------------------------------------------ autotune cache
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune;
+std::map<std::string, Config> g_tune;
 bool g_tune_loaded = false;
 
 std::string tune_path() {
@@ -425,21 +569,18 @@ void tune_load() {
   FILE* f = fopen(tune_path().c_str(), "r");
   if (!f) return;
   char key[256];
-  int v;
-  while (fscanf(f, "%255s %d", key, &v) == 2) g_tune[key] = v;
+  Config c{};
+  while (fscanf(f, "%255s %d %d", key, &c.var, &c.rows) == 3) g_tune[key] = c;
   fclose(f);
 }
 
 void tune_store() {
   const std::string p = tune_path();
   const size_t slash = p.find_last_of('/');
-  if (slash != std::string::npos) {
-    const std::string dir = p.substr(0, slash);
-    mkdir(dir.c_str(), 0755);  // best effort; fopen below reports nothing on failure
-  }
+  if (slash != std::string::npos) mkdir(p.substr(0, slash).c_str(), 0755);  // best effort
   FILE* f = fopen(p.c_str(), "w");
   if (!f) return;
-  for (auto& kv : g_tune) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+  for (auto& kv : g_tune) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.var, kv.second.rows);
   fclose(f);
 }
 
@@ -460,9 +601,20 @@ std::string tune_key(const cpqr_batch_item* items, int n) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n, (long long)((maxi + 31) / 32 * 32),
-           maxr, lg);
+  snprintf(buf, sizeof(buf), "batch2|%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n,
+           (long long)((maxi + 31) / 32 * 32), maxr, lg);
   return buf;
+}
+
+int batch_lookup(void* work, int variant, BatchState*& st, int& var) {
+  if (!work) return fail(CPQR_ERR_WORKSPACE, "als_batch: work buffer is NULL");
+  std::lock_guard<std::mutex> g(g_batch_mu);
+  auto f = g_batch.find(work);
+  if (f == g_batch.end()) return fail(CPQR_ERR_WORKSPACE, "als_batch: work buffer not prepared");
+  st = &f->second;
+  if (variant < 0 || variant > NVAR) return fail(CPQR_ERR_ARG, "als_batch: variant must be 0 (tuned) or 1..3");
+  var = variant > 0 ? variant - 1 : st->cfg.var;
+  return CPQR_OK;
 }
 
 }  // namespace
@@ -474,6 +626,8 @@ extern "C" {
 
 size_t cpqr_als_batch_work(const cpqr_batch_item* items, int nitems) {
   if (!items || nitems < 1) return 0;
+  for (int b = 0; b < nitems; ++b)
+    if (items[b].R < 1 || items[b].R > RB || items[b].I[0] < 1 || items[b].I[1] < 1 || items[b].I[2] < 1) return 0;
   Carver cv(nullptr);
   cv.take<BItem>(nitems);
   cv.take<int>(nitems);
@@ -490,29 +644,32 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
   if (!items || nitems < 1) return fail(CPQR_ERR_ARG, "als_batch: no items");
   for (int b = 0; b < nitems; ++b) {
     const cpqr_batch_item& it = items[b];
-    if (it.R < 1 || it.R > 16) return fail(CPQR_ERR_SHAPE, "als_batch: R must be in [1, 16]");
+    if (it.R < 1 || it.R > RB) return fail(CPQR_ERR_SHAPE, "als_batch: R must be in [1, 16]");
     for (int k = 0; k < 3; ++k) {
-      if (it.I[k] < it.R || it.I[k] > UROWS)
-        return fail(CPQR_ERR_SHAPE, "als_batch: mode sizes must be in [R, 256]");
+      if (it.I[k] < it.R || it.I[k] > IMAX) return fail(CPQR_ERR_SHAPE, "als_batch: mode sizes must be in [R, 256]");
       if (!it.A[k]) return fail(CPQR_ERR_ARG, "als_batch: NULL factor");
     }
     if (!it.X || !it.lambda) return fail(CPQR_ERR_ARG, "als_batch: NULL tensor or lambda");
+    if (reinterpret_cast<uintptr_t>(it.X) % 4 != 0) return fail(CPQR_ERR_ARG, "als_batch: X must be 4-byte aligned");
   }
   CPQR_TRY(check_work(work, work_bytes, cpqr_als_batch_work(items, nitems)));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  BatchState st;
+  st.n = nitems;
   Carver cv(work);
-  BItem* items_dev = cv.take<BItem>(nitems);
-  int* order_dev = cv.take<int>(nitems);
+  st.items_dev = cv.take<BItem>(nitems);
+  st.order_dev = cv.take<int>(nitems);
   std::vector<double*> saved(2 * nitems);
   for (int b = 0; b < nitems; ++b) {
     saved[2 * b] = cv.take<double>(size_t(items[b].I[1]) * items[b].R);
     saved[2 * b + 1] = cv.take<double>(size_t(items[b].I[2]) * items[b].R);
   }
-  std::vector<BItem> h(nitems);
+  st.h.resize(nitems);
   for (int b = 0; b < nitems; ++b) {
     const cpqr_batch_item& it = items[b];
     Carver c2(cv.take<char>(item_scratch(it)));
-    BItem& d = h[b];
+    const int nbmax = blocks_max(it);
+    BItem& d = st.h[b];
     d = BItem{};
     for (int k = 0; k < 3; ++k) d.I[k] = it.I[k];
     d.R = it.R;
@@ -520,80 +677,81 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
     for (int k = 0; k < 3; ++k) d.A[k] = it.A[k];
     d.lam = it.lambda;
     d.relerr = it.relerr;
-    const int64_t R = it.R, imax = std::max(it.I[0], std::max(it.I[1], it.I[2]));
+    const int64_t R = it.R;
     for (int k = 0; k < 3; ++k) d.Q[k] = c2.take<double>(size_t(it.I[k]) * R);
+    for (int k = 0; k < 3; ++k) d.Qf[k] = c2.take<float>(size_t(it.I[k]) * RB);
     for (int k = 0; k < 3; ++k) d.Rf[k] = c2.take<double>(size_t(R) * R);
-    d.T = c2.take<float>(std::max(it.I[0] * R * it.I[2], it.I[0] * it.I[1] * R));
-    d.T2 = c2.take<float>(R * R * imax);
-    d.Y = c2.take<float>(R * R * imax);
-    d.Q0 = c2.take<double>(size_t(R * R) * R);
-    d.R0 = c2.take<double>(size_t(R) * R);
+    for (int k = 0; k < 3; ++k) d.Q0b[k] = c2.take<double>(size_t(R) * R * R);
+    for (int k = 0; k < 3; ++k) d.R0b[k] = c2.take<double>(size_t(R) * R);
+    d.Z = c2.take<float>(size_t(it.I[0] * it.I[1] * R));
+    d.T = c2.take<float>(size_t(it.I[0] * R * it.I[2]));
+    d.lamp = c2.take<double>(size_t(nbmax) * RB);
+    d.ipp = c2.take<double>(size_t(nbmax));
     d.xnorm2 = c2.take<double>(1);
   }
+  // larger tensors first (longest-processing-time order)
   std::vector<int> order(nitems);
   for (int b = 0; b < nitems; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const auto w = [&](int t) { return items[t].I[0] * items[t].I[1] * items[t].I[2] * items[t].R; };
-    return w(a) > w(b);
-  });
-  const int need = nt_needed(items, nitems);
-  const int min_nt = need <= 256 ? 256 : (need <= 512 ? 512 : 1024);
-  BatchHeader hdr{};
-  hdr.n = nitems;
-  hdr.min_nt = min_nt;
-  hdr.nt = min_nt;
-  CPQR_HIP(hipMemcpy(items_dev, h.data(), sizeof(BItem) * nitems, hipMemcpyHostToDevice));
-  CPQR_HIP(hipMemcpy(order_dev, order.data(), sizeof(int) * nitems, hipMemcpyHostToDevice));
+  const auto work_of = [&](int t) {
+    return double(items[t].I[0]) * double(items[t].I[1]) * double(items[t].I[2]) * (2.0 + items[t].R);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work_of(a) > work_of(b); });
+  CPQR_HIP(hipMemcpyAsync(st.order_dev, order.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s));
   for (int b = 0; b < nitems; ++b) {
     CPQR_HIP(hipMemcpyAsync(saved[2 * b], items[b].A[1], sizeof(double) * items[b].I[1] * items[b].R,
                             hipMemcpyDeviceToDevice, s));
     CPQR_HIP(hipMemcpyAsync(saved[2 * b + 1], items[b].A[2], sizeof(double) * items[b].I[2] * items[b].R,
                             hipMemcpyDeviceToDevice, s));
   }
-  Layout L{items_dev, order_dev, nitems, nullptr};
+  st.cfg = Config{1, 64};
   if (autotune) {
     const std::string key = tune_key(items, nitems);
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load();
     auto found = g_tune.find(key);
-    if (found != g_tune.end() && found->second >= min_nt) {
-      hdr.nt = found->second;
+    if (found != g_tune.end() && found->second.var >= 0 && found->second.var < NVAR &&
+        found->second.rows >= ROWS_MIN) {
+      st.cfg = found->second;
     } else {
       // time one init + sweep per candidate, restoring the initial factors after each
       hipEvent_t e0, e1;
       CPQR_HIP(hipEventCreate(&e0));
       CPQR_HIP(hipEventCreate(&e1));
       float best = 1e30f;
-      for (int nt : {256, 512, 1024}) {
-        if (nt < min_nt) continue;
-        CPQR_TRY(launch_batch(nt, L, 1, 1, 0, s));  // warm
-        CPQR_HIP(hipEventRecord(e0, s));
-        CPQR_TRY(launch_batch(nt, L, 1, 1, 0, s));
-        CPQR_HIP(hipEventRecord(e1, s));
-        CPQR_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CPQR_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          hdr.nt = nt;
-        }
-        for (int b = 0; b < nitems; ++b) {
-          CPQR_HIP(hipMemcpyAsync(items[b].A[1], saved[2 * b], sizeof(double) * items[b].I[1] * items[b].R,
-                                  hipMemcpyDeviceToDevice, s));
-          CPQR_HIP(hipMemcpyAsync(items[b].A[2], saved[2 * b + 1], sizeof(double) * items[b].I[2] * items[b].R,
-                                  hipMemcpyDeviceToDevice, s));
+      Config bestc = st.cfg;
+      for (int var = 0; var < NVAR; ++var) {
+        for (int rows : {32, 64}) {
+          st.cfg = Config{var, rows};
+          CPQR_TRY(upload(st, s));
+          CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));  // warm
+          CPQR_HIP(hipEventRecord(e0, s));
+          CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));
+          CPQR_HIP(hipEventRecord(e1, s));
+          CPQR_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          CPQR_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            bestc = st.cfg;
+          }
+          for (int b = 0; b < nitems; ++b) {
+            CPQR_HIP(hipMemcpyAsync(items[b].A[1], saved[2 * b], sizeof(double) * items[b].I[1] * items[b].R,
+                                    hipMemcpyDeviceToDevice, s));
+            CPQR_HIP(hipMemcpyAsync(items[b].A[2], saved[2 * b + 1], sizeof(double) * items[b].I[2] * items[b].R,
+                                    hipMemcpyDeviceToDevice, s));
+          }
         }
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
-      g_tune[key] = hdr.nt;
+      st.cfg = bestc;
+      g_tune[key] = bestc;
       tune_store();
     }
   }
-  CPQR_HIP(hipStreamSynchronize(s));
+  CPQR_TRY(upload(st, s));
   {
     std::lock_guard<std::mutex> g(g_batch_mu);
-    g_batch[work] = hdr;
     for (auto it = g_graphs.begin(); it != g_graphs.end();) {  // graphs of an older layout
       if (it->first.work == work) {
         (void)hipGraphExecDestroy(it->second);
@@ -602,46 +760,25 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
         ++it;
       }
     }
+    g_batch[work] = std::move(st);
   }
   return CPQR_OK;
 }
 
-static int batch_lookup(void* work, int threads, BatchHeader& hdr, int& nt) {
-  if (!work) return fail(CPQR_ERR_WORKSPACE, "als_batch: work buffer is NULL");
-  {
-    std::lock_guard<std::mutex> g(g_batch_mu);
-    auto f = g_batch.find(work);
-    if (f == g_batch.end()) return fail(CPQR_ERR_WORKSPACE, "als_batch: work buffer not prepared");
-    hdr = f->second;
-  }
-  nt = threads > 0 ? threads : hdr.nt;
-  if (nt != 256 && nt != 512 && nt != 1024) return fail(CPQR_ERR_ARG, "als_batch: threads must be 256, 512 or 1024");
-  if (nt < hdr.min_nt) return fail(CPQR_ERR_SHAPE, "als_batch: threads too few for the largest item");
-  return CPQR_OK;
-}
-
-static Layout batch_layout(void* work, int n) {
-  Carver cv(work);
-  BItem* items_dev = cv.take<BItem>(n);
-  int* order_dev = cv.take<int>(n);
-  return Layout{items_dev, order_dev, n, nullptr};
-}
-
-int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream) {
+int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream) {
   if (nsweeps < 0 || sweep_offset < 0) return fail(CPQR_ERR_ARG, "als_batch: negative sweep count");
-  BatchHeader hdr;
-  int nt;
-  CPQR_TRY(batch_lookup(work, threads, hdr, nt));
-  return launch_batch(nt, batch_layout(work, hdr.n), nsweeps, init ? 1 : 0, sweep_offset,
-                      static_cast<hipStream_t>(stream));
+  BatchState* st;
+  int var;
+  CPQR_TRY(batch_lookup(work, variant, st, var));
+  return launch_batch(*st, var, nsweeps, init ? 1 : 0, sweep_offset, static_cast<hipStream_t>(stream));
 }
 
-int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int threads, void* stream) {
+int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream) {
   if (nsweeps < 0 || sweep_offset < 0) return fail(CPQR_ERR_ARG, "als_batch: negative sweep count");
-  BatchHeader hdr;
-  int nt;
-  CPQR_TRY(batch_lookup(work, threads, hdr, nt));
-  const GraphKey key{work, nsweeps, init ? 1 : 0, sweep_offset, nt};
+  BatchState* st;
+  int var;
+  CPQR_TRY(batch_lookup(work, variant, st, var));
+  const GraphKey key{work, nsweeps, init ? 1 : 0, sweep_offset, var};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> g(g_batch_mu);
@@ -651,7 +788,7 @@ int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, in
   if (!exec) {
     if (!g_capture_stream) CPQR_HIP(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
     CPQR_HIP(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
-    const int rc = launch_batch(nt, batch_layout(work, hdr.n), nsweeps, init ? 1 : 0, sweep_offset, g_capture_stream);
+    const int rc = launch_batch(*st, var, nsweeps, init ? 1 : 0, sweep_offset, g_capture_stream);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(g_capture_stream, &graph);
     if (rc != CPQR_OK) return rc;
@@ -666,11 +803,14 @@ int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, in
   return CPQR_OK;
 }
 
-int cpqr_als_batch_threads(void* work) {
-  BatchHeader hdr;
-  int nt;
-  CPQR_TRY(batch_lookup(work, 0, hdr, nt));
-  return nt;
+int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* rows) {
+  BatchState* st;
+  int var;
+  CPQR_TRY(batch_lookup(work, 0, st, var));
+  if (cols_per_thread) *cols_per_thread = VAR_CPT[var];
+  if (unroll) *unroll = VAR_U[var];
+  if (rows) *rows = st->cfg.rows;
+  return CPQR_OK;
 }
 
 }  // extern "C"

@@ -95,8 +95,18 @@ def test_autotune_picks_a_valid_size(batch, tmp_path, monkeypatch):
     monkeypatch.setenv("CPQR_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     sub = batch[:8]
     B = run_batch(sub, 3, autotune=True)
-    assert B.threads in (256, 512, 1024)
-    ref = run_batch(sub, 3)
-    for b in range(len(sub)):
-        np.testing.assert_allclose(to_np(B.relerr[b]), to_np(ref.relerr[b]), rtol=0, atol=1e-9)
+    cpt, unroll, rows = B.config
+    assert (cpt, unroll) in ((4, 4), (4, 8), (2, 8)) and rows in (32, 64)
     assert (tmp_path / "tune.txt").exists()
+
+
+def test_streaming_shapes_give_identical_results(batch):
+    """The streaming-pass shapes only change how many loads are in flight,
+    not the order of any sum, so every variant gives bitwise the same run."""
+    sub = batch[:5]
+    runs = [run_batch(sub, 3, variant=v) for v in (1, 2, 3)]
+    for B in runs[1:]:
+        for b in range(len(sub)):
+            for k in range(3):
+                assert torch.equal(runs[0].A[b][k], B.A[b][k]), (b, k)
+            assert torch.equal(runs[0].relerr[b], B.relerr[b])
