@@ -23,6 +23,8 @@ Modules
   costs      -- the flop model of section 3.2 (eq. QRcost, eq. TTMcost)
   precision  -- bit-level bfloat16 rounding and split-bfloat16 products, the
                 reduced-precision Multi-TTM forms the GPU offers
+  learned    -- the learned initializer: tensor sketch, three-layer MLP,
+                Kruskal-form loss and its gradient, Adam
 
 Pins.  Every function here is pinned by ``tests/test_oracle_*.py`` to facts
 the paper and the mathematics fix (brute-force index loops, identities,
@@ -30,4 +32,4 @@ invariants, closed forms), never to itself.  Functions without such a pin say
 "parity unpinned" in their docstring.
 """
 
-from . import tensor, cp_als_qr, cp_als, costs, precision  # noqa: F401
+from . import tensor, cp_als_qr, cp_als, costs, precision, learned  # noqa: F401
