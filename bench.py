@@ -41,10 +41,14 @@ def parse():
     ap.add_argument("--n", type=int, default=1000, help="mode size of the cubic tensor")
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x2", "bf16"])
-    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch"],
+    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned"],
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
+    ap.add_argument("--train", type=int, default=20000, help="training tensors for --workload learned")
+    ap.add_argument("--epochs", type=int, default=20, help="training epochs for --workload learned")
+    ap.add_argument("--heldout", type=int, default=256, help="held-out tensors (loss) for --workload learned")
+    ap.add_argument("--fit-heldout", type=int, default=32, help="held-out tensors timed to relerr 1e-6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle timing sample")
     return ap.parse_args()
@@ -185,16 +189,66 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_learned(args):
+    """Learned initializer on 256^3 FP32 rank-10 tensors (congruence 0.9, no
+    noise): method-generated training set, GPU training, then sweeps and GPU
+    time to direct relerr <= 1e-6 from learned and from random starts."""
+    import torch
+
+    from paper_2112_10855_amd import learned as LI
+
+    t0 = time.time()
+    model = LI.LearnedInit()
+    xs, tg = LI.make_dataset(model, args.train, seed0=1000000, sweeps=100, log=log)
+    t_data = time.time() - t0
+    base = LI.heldout_loss(model, args.heldout, 2000000)
+    log("held-out Kruskal loss before training %.4f" % base)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hist = LI.train(model, xs, tg, args.epochs, batch=256, lr=1e-3, log=log)
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / 1e3
+    after = LI.heldout_loss(model, args.heldout, 2000000)
+    log("held-out Kruskal loss after training %.4f" % after)
+    recs = LI.evaluate(model, args.fit_heldout, 2000000, log=log)
+
+    def summ(key):
+        hits = [r[key] for r in recs if r[key][0] is not None]
+        return {"reached": len(hits), "of": len(recs),
+                "median_sweeps": float(np.median([h[0] for h in hits])) if hits else None,
+                "median_seconds": float(np.median([h[1] for h in hits])) if hits else None,
+                "median_final_relerr": float(np.median([r[key][2] for r in recs])),
+                "mean_log10_final_relerr": float(np.mean([np.log10(max(r[key][2], 1e-300)) for r in recs]))}
+
+    rnd, lrn = summ("random"), summ("learned")
+    out = {
+        "metric": METRIC, "value": lrn["median_seconds"], "unit": "s to direct relerr 1e-6 (median, learned init)",
+        "n_gpus": 1, "steps": args.epochs, "warmup": 0, "ms_per_step": round(t_train * 1e3 / max(args.epochs, 1), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 MLP, f32 Multi-TTM",
+        "data": "synthetic",
+        "config": {"workload": "learned_init_256cube_r10_sketch64_mlp512", "train_tensors": args.train,
+                   "epochs": args.epochs, "heldout_loss_tensors": args.heldout, "heldout_fit_tensors": args.fit_heldout,
+                   "target_sweeps": 100, "ground_truth": "rank 10, congruence 0.9, no noise"},
+        "random_init": rnd, "learned_init": lrn,
+        "prediction_used": sum(1 for r in recs if r["used_prediction"]),
+        "heldout_loss_untrained": base, "heldout_loss_trained": after,
+        "train_loss_first_last": [hist[0], hist[-1]] if hist else None,
+        "dataset_seconds": round(t_data, 1), "train_seconds": round(t_train, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("dense4", "batch"):
+    if args.workload in ("dense4", "batch", "learned"):
         import torch
         torch.cuda.set_device(0)
-        return run_dense4(args) if args.workload == "dense4" else run_batch(args)
+        return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned}[args.workload](args)
 
     import hashlib
 

@@ -249,6 +249,69 @@ int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, in
 int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* rows);
 
 /*
+ * Learned initialization (the project's initializer for CP-ALS-QR; the paper
+ * runs Alg. 2 from random starts).  A sketch of the tensor feeds a
+ * three-layer MLP whose output holds initial factor matrices; the network
+ * is trained on factors the method itself produced, with a loss that
+ * compares Kruskal tensors through R x R Gram matrices (the identity behind
+ * the efficient error of section 3.3.1).  bfloat16 values are passed as
+ * uint16_t bit patterns (round to nearest even).  All pointers are device
+ * memory owned by the caller; calls are asynchronous on `stream`.
+ *
+ * cpqr_sketch3: xs = X x_1 S[0] x_2 S[1] x_3 S[2] with X column-major
+ * I[0] x I[1] x I[2] FP32 and S[k] row-major J[k] x I[k] bfloat16; xs (FP32)
+ * is stored with the mode-2 index fastest, then mode 1, then mode 3:
+ * xs[j2 + J[1] j1 + J[1] J[0] j3].  xs_bf16 (nullable) receives xs / ||xs||.
+ * bfloat16 operands, FP32 accumulation.  I[k] multiples of 32, I[2] and
+ * I[1] I[2] multiples of 64, J[k] multiples of 64.
+ */
+size_t cpqr_sketch3_work(const int64_t* I, const int* J);
+int cpqr_sketch3(const int64_t* I, const float* X, const int* J, const uint16_t* const* S, float* xs,
+                 uint16_t* xs_bf16, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Three-layer MLP y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 on a batch of
+ * row vectors (x: batch x din, row-major bfloat16).  W[l] row-major
+ * (out x in) bfloat16, b[l] FP32.  Widths and the batch are multiples of 64.
+ * forward writes the activations h1, h2 (batch x hidden, bfloat16) and y
+ * (batch x dout, FP32).  backward takes dL/dy (FP32 and its bfloat16 copy)
+ * and writes FP32 gradients dW[l] (same layout as W[l]) and db[l]; every
+ * sum has a fixed order.
+ */
+typedef struct cpqr_mlp {
+  int din, hidden, dout;
+  const uint16_t* W[3];
+  const float* b[3];
+} cpqr_mlp;
+
+size_t cpqr_mlp_work(const cpqr_mlp* net, int batch);
+int cpqr_mlp_forward(const cpqr_mlp* net, int batch, const uint16_t* x, uint16_t* h1, uint16_t* h2, float* y,
+                     void* work, size_t work_bytes, void* stream);
+int cpqr_mlp_backward(const cpqr_mlp* net, int batch, const uint16_t* x, const uint16_t* h1, const uint16_t* h2,
+                      const float* dy, const uint16_t* dy_bf16, float* const* dW, float* const* db, void* work,
+                      size_t work_bytes, void* stream);
+
+/*
+ * Per sample b: L_b = ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2 where Ahat are
+ * the three column-major factor matrices (I[k] x R) packed one after the
+ * other in row b of y (leading dimension ldy) and A those of the target
+ * (rank Rt, leading dimension ldt).  loss (nullable) receives L_b; dy
+ * receives scale * dL_b/dy (and its bfloat16 copy if dy_bf16 != NULL).
+ * I[k] <= 256, R, Rt <= 16.  Gram sums in FP64.
+ */
+int cpqr_kruskal_loss_grad(int batch, const int64_t* I, int R, int Rt, const float* y, int64_t ldy,
+                           const float* target, int64_t ldt, float* loss, float* dy, uint16_t* dy_bf16,
+                           float scale, void* stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) at step >= 1 on n
+ * FP32 parameters; w_bf16 (nullable) receives the updated weights. */
+int cpqr_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w_bf16, int step, float lr,
+              float beta1, float beta2, float eps, void* stream);
+
+/* y = bfloat16(x), round to nearest even. */
+int cpqr_to_bf16(const float* x, int64_t n, uint16_t* y, void* stream);
+
+/*
  * Phase timers (the per-iteration breakdown of the paper's performance
  * section): when enabled, eager calls record HIP events around each phase on
  * the launch stream.  cpqr_timing_read synchronizes those events and returns

@@ -64,31 +64,41 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
-def mlp_forward(params, x):
+def _keep(v):
+    return v
+
+
+def mlp_forward(params, x, store=_keep):
     """params = (W1, b1, W2, b2, W3, b3); x is (batch, in).  Returns y and the
-    activations needed by the backward pass."""
+    activations needed by the backward pass.  ``store`` is applied to each
+    hidden activation as it is kept (identity by default; a rounding
+    function models a lower-precision activation store)."""
     W1, b1, W2, b2, W3, b3 = params
     z1 = x @ W1.T + b1
-    h1 = relu(z1)
+    h1 = store(relu(z1))
     z2 = h1 @ W2.T + b2
-    h2 = relu(z2)
+    h2 = store(relu(z2))
     y = h2 @ W3.T + b3
     return y, (x, z1, h1, z2, h2)
 
 
-def mlp_backward(params, cache, dy):
+def mlp_backward(params, cache, dy, store=_keep):
     """Gradients of a scalar loss with respect to the parameters, given dL/dy
-    for every sample (chain rule through the three affine maps and ReLUs)."""
+    for every sample (chain rule through the three affine maps and ReLUs).
+    ``store`` is applied to the back-propagated hidden gradients before they
+    are used in the next product (identity by default)."""
     W1, b1, W2, b2, W3, b3 = params
     x, z1, h1, z2, h2 = cache
     dW3 = dy.T @ h2
     db3 = dy.sum(axis=0)
     dh2 = (dy @ W3) * (z2 > 0)
-    dW2 = dh2.T @ h1
     db2 = dh2.sum(axis=0)
+    dh2 = store(dh2)
+    dW2 = dh2.T @ h1
     dh1 = (dh2 @ W2) * (z1 > 0)
-    dW1 = dh1.T @ x
     db1 = dh1.sum(axis=0)
+    dh1 = store(dh1)
+    dW1 = dh1.T @ x
     return (dW1, db1, dW2, db2, dW3, db3)
 
 

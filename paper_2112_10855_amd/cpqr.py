@@ -66,6 +66,12 @@ class BatchItem(ctypes.Structure):
     ]
 
 
+class Mlp(ctypes.Structure):
+    """Mirror of ``cpqr_mlp``."""
+    _fields_ = [("din", ctypes.c_int), ("hidden", ctypes.c_int), ("dout", ctypes.c_int),
+                ("W", _vp * 3), ("b", _vp * 3)]
+
+
 _lib = None
 
 _SIGS = {
@@ -96,6 +102,18 @@ _SIGS = {
     "cpqr_als_batch_graph": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "cpqr_als_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                              ctypes.POINTER(ctypes.c_int)]),
+    "cpqr_sketch3_work": (_sz, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int)]),
+    "cpqr_sketch3": (ctypes.c_int, [ctypes.POINTER(_i64), _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
+                                    _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_mlp_work": (_sz, [ctypes.POINTER(Mlp), ctypes.c_int]),
+    "cpqr_mlp_forward": (ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_mlp_backward": (ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _sz, _vp]),
+    "cpqr_kruskal_loss_grad": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int, _vp,
+                                              _i64, _vp, _i64, _vp, _vp, _vp, ctypes.c_float, _vp]),
+    "cpqr_adam": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, _vp]),
+    "cpqr_to_bf16": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "cpqr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "cpqr_timing_reset": (ctypes.c_int, []),
     "cpqr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]),
@@ -438,3 +456,110 @@ def cpqr_timing_read():
     cnt = (_i64 * NPHASES)()
     _call("cpqr_timing_read", ms, cnt, NPHASES)
     return {PHASES[i]: (ms[i], cnt[i]) for i in range(NPHASES)}
+
+
+# ---------------------------------------------------------------- learned init
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _contig(t, dtype, what):
+    _dev(t, what)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (what, dtype))
+    return t
+
+
+def cpqr_to_bf16(x):
+    """bfloat16 copy of a contiguous FP32 tensor (returned as torch.bfloat16)."""
+    _contig(x, torch.float32, "x")
+    y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    _call("cpqr_to_bf16", x.data_ptr(), x.numel(), y.data_ptr(), _stream())
+    return y
+
+
+def cpqr_sketch3(X, S_bf16, normalized=True):
+    """Sketch of a column-major FP32 3-way tensor: returns (xs FP32 vector,
+    xs / ||xs|| as bfloat16 or None)."""
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    I = (_i64 * 3)(*X.shape)
+    J = (ctypes.c_int * 3)(*[int(s.shape[0]) for s in S_bf16])
+    for k in range(3):
+        _contig(S_bf16[k], torch.bfloat16, "S")
+    Sp = (_vp * 3)(*[s.data_ptr() for s in S_bf16])
+    n = J[0] * J[1] * J[2]
+    xs = torch.empty(n, dtype=torch.float32, device=X.device)
+    xb = torch.empty(n, dtype=torch.bfloat16, device=X.device) if normalized else None
+    nbytes = lib().cpqr_sketch3_work(I, J)
+    if nbytes == 0:
+        raise CpqrError("cpqr_sketch3_work", -2, "unsupported sketch shape")
+    keep, w = _work(nbytes, X.device)
+    _call("cpqr_sketch3", I, X.data_ptr(), J, Sp, xs.data_ptr(), _ptr(xb), w, nbytes, _stream())
+    return xs, xb
+
+
+class MlpNet:
+    """Device views of a three-layer MLP: W[l] bfloat16 (out, in) and b[l]
+    FP32; the struct passed to cpqr_mlp_*."""
+
+    def __init__(self, W_bf16, b_f32):
+        self.W, self.b = W_bf16, b_f32
+        for t in W_bf16:
+            _contig(t, torch.bfloat16, "W")
+        for t in b_f32:
+            _contig(t, torch.float32, "b")
+        self.din, self.hidden, self.dout = W_bf16[0].shape[1], W_bf16[0].shape[0], W_bf16[2].shape[0]
+        self.c = Mlp(self.din, self.hidden, self.dout, (_vp * 3)(*[w.data_ptr() for w in W_bf16]),
+                     (_vp * 3)(*[b.data_ptr() for b in b_f32]))
+        self._wk = {}
+
+    def work(self, batch, device):
+        if batch not in self._wk:
+            nbytes = lib().cpqr_mlp_work(ctypes.byref(self.c), batch)
+            if nbytes == 0:
+                raise CpqrError("cpqr_mlp_work", -2, "unsupported MLP or batch shape")
+            self._wk[batch] = (nbytes,) + _work(nbytes, device)
+        return self._wk[batch]
+
+    def forward(self, x_bf16):
+        _contig(x_bf16, torch.bfloat16, "x")
+        B = x_bf16.shape[0]
+        dev = x_bf16.device
+        h1 = torch.empty(B, self.hidden, dtype=torch.bfloat16, device=dev)
+        h2 = torch.empty(B, self.hidden, dtype=torch.bfloat16, device=dev)
+        y = torch.empty(B, self.dout, dtype=torch.float32, device=dev)
+        nbytes, keep, w = self.work(B, dev)
+        _call("cpqr_mlp_forward", ctypes.byref(self.c), B, x_bf16.data_ptr(), h1.data_ptr(), h2.data_ptr(),
+              y.data_ptr(), w, nbytes, _stream())
+        return y, (x_bf16, h1, h2)
+
+    def backward(self, cache, dy, dy_bf16, dW, db):
+        x, h1, h2 = cache
+        B = x.shape[0]
+        nbytes, keep, w = self.work(B, x.device)
+        _call("cpqr_mlp_backward", ctypes.byref(self.c), B, x.data_ptr(), h1.data_ptr(), h2.data_ptr(),
+              dy.data_ptr(), dy_bf16.data_ptr(), (_vp * 3)(*[t.data_ptr() for t in dW]),
+              (_vp * 3)(*[t.data_ptr() for t in db]), w, nbytes, _stream())
+
+
+def cpqr_kruskal_loss_grad(y, target, I, R, Rt, scale=1.0):
+    """Per-sample Kruskal losses and scale * dL/dy (FP32 and bfloat16)."""
+    _contig(y, torch.float32, "y")
+    _contig(target, torch.float32, "target")
+    B = y.shape[0]
+    loss = torch.empty(B, dtype=torch.float32, device=y.device)
+    dy = torch.empty_like(y)
+    dyb = torch.empty(y.shape, dtype=torch.bfloat16, device=y.device)
+    _call("cpqr_kruskal_loss_grad", B, (_i64 * 3)(*I), R, Rt, y.data_ptr(), y.shape[1], target.data_ptr(),
+          target.shape[1], loss.data_ptr(), dy.data_ptr(), dyb.data_ptr(), float(scale), _stream())
+    return loss, dy, dyb
+
+
+def cpqr_adam(w, g, m, v, w_bf16, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    for t, nm in ((w, "w"), (g, "g"), (m, "m"), (v, "v")):
+        _contig(t, torch.float32, nm)
+    if w_bf16 is not None:
+        _contig(w_bf16, torch.bfloat16, "w_bf16")
+    _call("cpqr_adam", w.numel(), w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), _ptr(w_bf16), int(step),
+          float(lr), float(beta1), float(beta2), float(eps), _stream())
