@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1000, help="mode size of the cubic tensor")
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x2", "bf16"])
-    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned"],
+    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned", "fit"],
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--epochs", type=int, default=20, help="training epochs for --workload learned")
     ap.add_argument("--heldout", type=int, default=256, help="held-out tensors (loss) for --workload learned")
     ap.add_argument("--fit-heldout", type=int, default=32, help="held-out tensors timed to relerr 1e-6")
+    ap.add_argument("--fit-n", type=int, default=200, help="mode size of the time-to-fit study (--workload fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle timing sample")
     return ap.parse_args()
@@ -239,16 +240,52 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def run_fit(args):
+    """Time to direct relerr <= 1e-6 for each Multi-TTM precision on the same
+    GPU from the same start: noise-free rank-16 n^3 tensor with Gaussian
+    factors, FP32 data (the FP64 path reads the same values in FP64)."""
+    import torch
+
+    from paper_2112_10855_amd import cpqr as C
+    from paper_2112_10855_amd import synth
+    from paper_2112_10855_amd.fit import time_to_fit
+
+    n, R = args.fit_n, 16
+    t0 = time.time()
+    d = synth.cp_tensor((n, n, n), R, 7000, noise=0.0, dtype=np.float32)
+    init = synth.init_factors((n, n, n), R, 7000)
+    X32 = torch.from_numpy(d["X"].reshape(-1, order="F")).to("cuda").view(n, n, n).permute(2, 1, 0)
+    log("generated %d^3 FP32 rank-%d tensor in %.1f s" % (n, R, time.time() - t0))
+    res = {}
+    for name in ("f64", "f32", "bf16x2", "bf16"):
+        X = X32.double() if name == "f64" else X32
+        time_to_fit(X, init, prec=C.PREC_NAMES[name], max_sweeps=5)  # warm-up
+        hit, secs, last = time_to_fit(X, init, prec=C.PREC_NAMES[name], max_sweeps=200)
+        res[name] = {"sweeps": hit, "seconds": None if hit is None else round(secs, 4), "final_relerr": last,
+                     "seconds_run": round(secs, 4)}
+        log("%s: %s sweeps, %.3f s, final relerr %.3e" % (name, hit, secs, last))
+    base = res["f32"]["seconds"]
+    out = {
+        "metric": METRIC, "value": base, "unit": "s to direct relerr 1e-6 (FP32 Multi-TTM)", "n_gpus": 1,
+        "steps": res["f32"]["sweeps"], "warmup": 5, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "time_to_fit_%dcube_r%d_noisefree" % (n, R), "target": 1e-6, "max_sweeps": 200,
+                   "error": "direct", "ground_truth": "Gaussian factors, lambda 1, no noise"},
+        "per_precision": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("dense4", "batch", "learned"):
+    if args.workload in ("dense4", "batch", "learned", "fit"):
         import torch
         torch.cuda.set_device(0)
-        return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned}[args.workload](args)
+        return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned, "fit": run_fit}[args.workload](args)
 
     import hashlib
 

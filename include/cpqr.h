@@ -261,7 +261,8 @@ int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* ro
  * cpqr_sketch3: xs = X x_1 S[0] x_2 S[1] x_3 S[2] with X column-major
  * I[0] x I[1] x I[2] FP32 and S[k] row-major J[k] x I[k] bfloat16; xs (FP32)
  * is stored with the mode-2 index fastest, then mode 1, then mode 3:
- * xs[j2 + J[1] j1 + J[1] J[0] j3].  xs_bf16 (nullable) receives xs / ||xs||.
+ * xs[j2 + J[1] j1 + J[1] J[0] j3].  xs_bf16 (nullable) receives xs scaled to
+ * unit root-mean-square entry, xs sqrt(J[0] J[1] J[2]) / ||xs||.
  * bfloat16 operands, FP32 accumulation.  I[k] multiples of 32, I[2] and
  * I[1] I[2] multiples of 64, J[k] multiples of 64.
  */
@@ -292,15 +293,19 @@ int cpqr_mlp_backward(const cpqr_mlp* net, int batch, const uint16_t* x, const u
                       size_t work_bytes, void* stream);
 
 /*
- * Per sample b: L_b = ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2 where Ahat are
- * the three column-major factor matrices (I[k] x R) packed one after the
- * other in row b of y (leading dimension ldy) and A those of the target
- * (rank Rt, leading dimension ldt).  loss (nullable) receives L_b; dy
- * receives scale * dL_b/dy (and its bfloat16 copy if dy_bf16 != NULL).
- * I[k] <= 256, R, Rt <= 16.  Gram sums in FP64.
+ * Per sample b, with Ahat the three column-major factor matrices (I[k] x R)
+ * packed one after the other in row b of y (leading dimension ldy) and A
+ * those of the target (rank Rt, leading dimension ldt):
+ *   CPQR_LOSS_DISTANCE  L_b = ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2
+ *   CPQR_LOSS_COSINE    L_b = 1 - <[[Ahat]],[[A]]>^2 / (||[[Ahat]]||^2 ||[[A]]||^2)
+ * loss (nullable) receives L_b; dy receives scale * dL_b/dy (and its
+ * bfloat16 copy if dy_bf16 != NULL).  I[k] <= 256, R, Rt <= 16.  Gram sums
+ * in FP64.
  */
+#define CPQR_LOSS_DISTANCE 0
+#define CPQR_LOSS_COSINE 1
 int cpqr_kruskal_loss_grad(int batch, const int64_t* I, int R, int Rt, const float* y, int64_t ldy,
-                           const float* target, int64_t ldt, float* loss, float* dy, uint16_t* dy_bf16,
+                           const float* target, int64_t ldt, int kind, float* loss, float* dy, uint16_t* dy_bf16,
                            float scale, void* stream);
 
 /* One Adam step (Kingma and Ba, with bias correction) at step >= 1 on n

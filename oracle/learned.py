@@ -12,12 +12,15 @@ What the GPU side computes, and what this module defines:
   MLP      h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3, with
            W_l stored (out, in).  y holds the three factor matrices one after
            the other, each column-major I x R (``unpack_factors``).
-  loss     relative squared distance of two Kruskal tensors,
-           L = ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2, evaluated from R x R
-           Gram matrices: ||[[A]]||^2 = sum of the Hadamard product of the
-           A_k^T A_k, and <[[Ahat]], [[A]]> the same with Ahat_k^T A_k.  This
-           is the identity that gives the paper's efficient error
-           (section 3.3.1) its cheapness, applied to two Kruskal tensors.
+  loss     two forms, both evaluated from R x R Gram matrices
+           (||[[A]]||^2 = sum of the Hadamard product of the A_k^T A_k, and
+           <[[Ahat]], [[A]]> the same with Ahat_k^T A_k -- the identity that
+           gives the paper's efficient error of section 3.3.1 its cheapness,
+           applied to two Kruskal tensors):
+             distance  ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2
+             cosine    1 - <[[Ahat]], [[A]]>^2 / (||[[Ahat]]||^2 ||[[A]]||^2),
+                       invariant to the scale of the prediction (CP-ALS does
+                       not depend on the scale of its start).
            The loss of a batch is the mean of the per-sample losses.
   Adam     the update of Kingma and Ba with bias correction.
 
@@ -138,15 +141,43 @@ def kruskal_loss_grad(Ahat, A):
     return loss, grads
 
 
-def batch_loss_grad(y, targets, I, R):
+def kruskal_cosine_loss(Ahat, A):
+    """1 - <[[Ahat]], [[A]]>^2 / (||[[Ahat]]||^2 ||[[A]]||^2)."""
+    c = kruskal_inner(Ahat, A)
+    return 1.0 - c * c / (kruskal_inner(Ahat, Ahat) * kruskal_inner(A, A))
+
+
+def kruskal_cosine_loss_grad(Ahat, A):
+    """Loss and gradient of the cosine form: with c = <[[Ahat]], [[A]]>,
+    a = ||[[Ahat]]||^2, t = ||[[A]]||^2 and the Gram-product gradients of
+    kruskal_loss_grad, dL = -(2c/(a t)) dc + (c^2/(a^2 t)) da."""
+    N = len(A)
+    c, a, t = kruskal_inner(Ahat, A), kruskal_inner(Ahat, Ahat), kruskal_inner(A, A)
+    grads = []
+    for k in range(N):
+        G = np.ones((Ahat[0].shape[1], Ahat[0].shape[1]))
+        H = np.ones((Ahat[0].shape[1], A[0].shape[1]))
+        for j in range(N):
+            if j == k:
+                continue
+            G = G * (Ahat[j].T @ Ahat[j])
+            H = H * (Ahat[j].T @ A[j])
+        dc = A[k] @ H.T
+        da = 2.0 * Ahat[k] @ G
+        grads.append(-(2.0 * c / (a * t)) * dc + (c * c / (a * a * t)) * da)
+    return 1.0 - c * c / (a * t), grads
+
+
+def batch_loss_grad(y, targets, I, R, kind="distance"):
     """Mean Kruskal loss over a batch and dL/dy (rows of y are samples;
     targets[b] is the list of target factor matrices of sample b)."""
     B = y.shape[0]
     dy = np.zeros_like(y, dtype=np.float64)
     total = 0.0
+    fn = kruskal_loss_grad if kind == "distance" else kruskal_cosine_loss_grad
     for b in range(B):
         Ahat = unpack_factors(y[b], I, R)
-        loss, g = kruskal_loss_grad(Ahat, targets[b])
+        loss, g = fn(Ahat, targets[b])
         total += loss
         dy[b] = pack_factors(g) / B
     return total / B, dy

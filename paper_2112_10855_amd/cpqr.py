@@ -110,7 +110,7 @@ _SIGS = {
     "cpqr_mlp_backward": (ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.c_int, _vp, _vp, _vp, _vp, _vp,
                                          ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _sz, _vp]),
     "cpqr_kruskal_loss_grad": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int, _vp,
-                                              _i64, _vp, _i64, _vp, _vp, _vp, ctypes.c_float, _vp]),
+                                              _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_float, _vp]),
     "cpqr_adam": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, _vp]),
     "cpqr_to_bf16": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
@@ -480,7 +480,7 @@ def cpqr_to_bf16(x):
 
 def cpqr_sketch3(X, S_bf16, normalized=True):
     """Sketch of a column-major FP32 3-way tensor: returns (xs FP32 vector,
-    xs / ||xs|| as bfloat16 or None)."""
+    xs scaled to unit root-mean-square as bfloat16, or None)."""
     _dev(X, "X")
     _check_colmajor(X, "X")
     I = (_i64 * 3)(*X.shape)
@@ -543,7 +543,10 @@ class MlpNet:
               (_vp * 3)(*[t.data_ptr() for t in db]), w, nbytes, _stream())
 
 
-def cpqr_kruskal_loss_grad(y, target, I, R, Rt, scale=1.0):
+LOSS_DISTANCE, LOSS_COSINE = 0, 1
+
+
+def cpqr_kruskal_loss_grad(y, target, I, R, Rt, scale=1.0, kind=LOSS_DISTANCE):
     """Per-sample Kruskal losses and scale * dL/dy (FP32 and bfloat16)."""
     _contig(y, torch.float32, "y")
     _contig(target, torch.float32, "target")
@@ -552,7 +555,7 @@ def cpqr_kruskal_loss_grad(y, target, I, R, Rt, scale=1.0):
     dy = torch.empty_like(y)
     dyb = torch.empty(y.shape, dtype=torch.bfloat16, device=y.device)
     _call("cpqr_kruskal_loss_grad", B, (_i64 * 3)(*I), R, Rt, y.data_ptr(), y.shape[1], target.data_ptr(),
-          target.shape[1], loss.data_ptr(), dy.data_ptr(), dyb.data_ptr(), float(scale), _stream())
+          target.shape[1], int(kind), loss.data_ptr(), dy.data_ptr(), dyb.data_ptr(), float(scale), _stream())
     return loss, dy, dyb
 
 

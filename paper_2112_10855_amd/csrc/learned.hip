@@ -147,7 +147,7 @@ __global__ void colsum_kernel(const float* __restrict__ D, int64_t M, int64_t N,
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, const double* __restrict__ norm2,
                                unsigned short* __restrict__ y) {
-  const float scale = norm2 ? float(1.0 / sqrt(*norm2 > 0.0 ? *norm2 : 1.0)) : 1.f;
+  const float scale = norm2 ? float(sqrt(double(n) / (*norm2 > 0.0 ? *norm2 : 1.0))) : 1.f;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
     y[e] = f2bf(x[e] * scale);
 }
@@ -173,9 +173,11 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __res
 // after the other (ranks R and Rt).  Gram matrices are accumulated in FP64.
 constexpr int KT = 256, KRB = 16;
 
+// kind 0: distance ||[[Ahat]] - [[A]]||^2 / ||[[A]]||^2;
+// kind 1: cosine 1 - <[[Ahat]],[[A]]>^2 / (||[[Ahat]]||^2 ||[[A]]||^2).
 __global__ __launch_bounds__(KT) void kruskal_grad_kernel(int64_t I0, int64_t I1, int64_t I2, int R, int Rt,
                                                           const float* __restrict__ y, int64_t ldy,
-                                                          const float* __restrict__ tgt, int64_t ldt,
+                                                          const float* __restrict__ tgt, int64_t ldt, int kind,
                                                           float* __restrict__ loss, float* __restrict__ dy,
                                                           unsigned short* __restrict__ dyb, float scale) {
   __shared__ float fa[256][KRB + 1];   // Ahat_k rows
@@ -232,9 +234,22 @@ __global__ __launch_bounds__(KT) void kruskal_grad_kernel(int64_t I0, int64_t I1
     if (tid == 0) sc[q] = red[0];
     __syncthreads();
   }
-  const double aa = sc[0];
-  if (tid == 0 && loss) loss[b] = float((sc[2] - 2.0 * sc[1] + aa) / aa);
-  // gradient rows: dAhat_k = (2 Ahat_k G_k - 2 A_k H_k^T) / aa
+  // dL/dAhat_k = ca Ahat_k G_k + cb A_k H_k^T
+  const double t = sc[0], c = sc[1], a = sc[2];
+  double ca, cb, lv;
+  if (kind == 0) {
+    lv = (a - 2.0 * c + t) / t;
+    ca = 2.0 / t;
+    cb = -2.0 / t;
+  } else if (a > 0.0) {
+    lv = 1.0 - c * c / (a * t);
+    ca = 2.0 * c * c / (a * a * t);
+    cb = -2.0 * c / (a * t);
+  } else {  // zero prediction: the cosine is undefined; no gradient
+    lv = 1.0;
+    ca = cb = 0.0;
+  }
+  if (tid == 0 && loss) loss[b] = float(lv);
   oy = 0;
   ot = 0;
   for (int k = 0; k < 3; ++k) {
@@ -246,20 +261,20 @@ __global__ __launch_bounds__(KT) void kruskal_grad_kernel(int64_t I0, int64_t I1
     __syncthreads();
     if (tid < I[k]) {
       for (int r = 0; r < R; ++r) {
-        double g = 0.0;
+        double ga = 0.0, gb = 0.0;
         for (int s = 0; s < R; ++s) {
           double G = 1.0;
           for (int j = 0; j < 3; ++j)
             if (j != k) G *= gaa[j][s][r];
-          g += 2.0 * fa[tid][s] * G;
+          ga += fa[tid][s] * G;
         }
         for (int s = 0; s < Rt; ++s) {
           double H = 1.0;
           for (int j = 0; j < 3; ++j)
             if (j != k) H *= gab[j][r][s];
-          g -= 2.0 * fb[tid][s] * H;
+          gb += fb[tid][s] * H;
         }
-        const float v = float(g / aa) * scale;
+        const float v = float(ca * ga + cb * gb) * scale;
         const int64_t idx = b * ldy + oy + tid + r * I[k];
         dy[idx] = v;
         if (dyb) dyb[idx] = f2bf(v);
@@ -470,16 +485,17 @@ int cpqr_mlp_backward(const cpqr_mlp* net, int batch, const uint16_t* x, const u
 }
 
 int cpqr_kruskal_loss_grad(int batch, const int64_t* I, int R, int Rt, const float* y, int64_t ldy,
-                           const float* target, int64_t ldt, float* loss, float* dy, uint16_t* dy_bf16,
+                           const float* target, int64_t ldt, int kind, float* loss, float* dy, uint16_t* dy_bf16,
                            float scale, void* stream) {
   if (batch < 1 || !I || !y || !target || !dy) return fail(CPQR_ERR_ARG, "kruskal_loss_grad: bad arguments");
+  if (kind != CPQR_LOSS_DISTANCE && kind != CPQR_LOSS_COSINE) return fail(CPQR_ERR_ARG, "kruskal_loss_grad: unknown loss");
   if (R < 1 || R > KRB || Rt < 1 || Rt > KRB) return fail(CPQR_ERR_SHAPE, "kruskal_loss_grad: ranks must be in [1, 16]");
   for (int k = 0; k < 3; ++k)
     if (I[k] < 1 || I[k] > 256) return fail(CPQR_ERR_SHAPE, "kruskal_loss_grad: mode sizes must be in [1, 256]");
   if (ldy < (I[0] + I[1] + I[2]) * R || ldt < (I[0] + I[1] + I[2]) * Rt)
     return fail(CPQR_ERR_SHAPE, "kruskal_loss_grad: leading dimension too small");
   hipLaunchKernelGGL(kruskal_grad_kernel, dim3(unsigned(batch)), dim3(KT), 0, static_cast<hipStream_t>(stream), I[0],
-                     I[1], I[2], R, Rt, y, ldy, target, ldt, loss, dy, reinterpret_cast<unsigned short*>(dy_bf16),
+                     I[1], I[2], R, Rt, y, ldy, target, ldt, kind, loss, dy, reinterpret_cast<unsigned short*>(dy_bf16),
                      scale);
   return check_launch("kruskal_grad_kernel");
 }

@@ -1,12 +1,14 @@
 """Learned initialization for CP-ALS-QR on 3-way tensors.
 
 A fixed Gaussian sketch of the tensor (X x_1 S_1 x_2 S_2 x_3 S_3, S_k of
-size J x I_k with entries N(0, 1/J)), normalized to unit norm, feeds a
+size J x I_k with entries N(0, 1/J)), scaled to unit root-mean-square, feeds a
 three-layer MLP (ReLU, width ``hidden``, bfloat16 weights with FP32 master
 copies and Adam) whose output holds the three initial factor matrices.  The
 network is trained on tensors whose targets are the factors the batched
-GPU CP-ALS-QR itself reached, with the Kruskal-form loss
-||[[Ahat]] - [[A*]]||^2 / ||[[A*]]||^2, A* scaled to the unit-norm tensor.
+GPU CP-ALS-QR itself reached, with the scale-free Kruskal-form loss
+1 - <[[Ahat]], [[A*]]>^2 / (||[[Ahat]]||^2 ||[[A*]]||^2) (CP-ALS does not depend
+on the scale of its start; the distance form has a flat saddle at zero and
+grows with the sixth power of the output).
 At inference only A_2 and A_3 of the prediction are used (Alg. 2 never
 reads the initial A_1); random initial factors remain the fallback.
 
@@ -22,6 +24,7 @@ import torch
 
 from . import cpqr as C
 from . import synth
+from .fit import time_to_fit
 
 
 def c5_factors(shape, R, seed, congruence=0.9):
@@ -53,7 +56,9 @@ class LearnedInit:
         dims = [(hidden, self.din), (hidden, hidden), (self.dout, hidden)]
         self.W = [torch.as_tensor(rng.standard_normal(d) * np.sqrt(2.0 / d[1]), dtype=torch.float32,
                                   device=device).contiguous() for d in dims]
-        self.W[2].mul_(0.1)
+        # output head small enough that the first predicted Kruskal tensors
+        # have norm of order one (the loss has a flat saddle at zero output)
+        self.W[2].mul_(0.04)
         self.b = [torch.zeros(d[0], dtype=torch.float32, device=device) for d in dims]
         self.Wb = [C.cpqr_to_bf16(w) for w in self.W]
         self.net = C.MlpNet(self.Wb, self.b)
@@ -65,7 +70,7 @@ class LearnedInit:
         self.step = 0
 
     def sketch(self, X):
-        """Unit-norm bfloat16 sketch vector of a column-major FP32 tensor."""
+        """Unit-RMS bfloat16 sketch vector of a column-major FP32 tensor."""
         return C.cpqr_sketch3(X, self.S)[1]
 
     def forward(self, xb):
@@ -76,7 +81,8 @@ class LearnedInit:
         packed target factors).  Returns the per-sample losses (device)."""
         y, cache = self.net.forward(xb)
         B = xb.shape[0]
-        loss, dy, dyb = C.cpqr_kruskal_loss_grad(y, targets, self.shape, self.R, self.R, scale=1.0 / B)
+        loss, dy, dyb = C.cpqr_kruskal_loss_grad(y, targets, self.shape, self.R, self.R, scale=1.0 / B,
+                                                 kind=C.LOSS_COSINE)
         self.net.backward(cache, dy, dyb, self.dW, self.db)
         self.step += 1
         for k, (p, g) in enumerate(zip(self.params, self.dW + self.db)):
@@ -152,33 +158,6 @@ def train(model, xs, tg, epochs, batch=256, lr=1e-3, seed=1, log=print):
     return hist
 
 
-def time_to_fit(X, init, prec=C.PREC_F32, target=1e-6, max_sweeps=200, chunk=5):
-    """Sweeps of the single-tensor CP-ALS-QR (direct error after every sweep)
-    until relerr <= target.  Returns (sweeps or None, GPU seconds, final
-    relerr); the time counts the sweeps run, error included."""
-    st = C.AlsState(X, init, prec=prec, error_mode=C.ERROR_DIRECT)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    st.init()
-    done, hit, last = 0, None, float("nan")
-    rel = torch.empty(chunk, dtype=torch.float64, device=X.device)
-    while done < max_sweeps and hit is None:
-        st.sweep(chunk, rel)
-        r = rel.cpu().numpy()
-        for i, v in enumerate(r):
-            if v <= target:
-                hit = done + i + 1
-                break
-        done += chunk
-        last = float(r[-1])
-    e1.record()
-    torch.cuda.synchronize()
-    secs = e0.elapsed_time(e1) / 1e3
-    if hit is not None:  # drop the sweeps past the hit from the time
-        secs *= hit / done
-    return hit, secs, last
-
-
 def usable_start(pred, fallback, cond_max=1e8):
     """The predicted factors as a CP-ALS-QR start, or the fallback (random)
     start when a predicted A_2 or A_3 is non-finite or numerically rank
@@ -214,8 +193,9 @@ def evaluate(model, count, seed0, max_sweeps=200, log=print):
 
 
 def heldout_loss(model, count, seed0):
-    """Mean Kruskal loss of the network's prediction against the normalized
-    ground-truth factors of held-out tensors (1.0 for a zero prediction)."""
+    """Mean cosine-form Kruskal loss of the network's prediction against the
+    ground-truth factors of held-out tensors (1 - squared cosine between the
+    predicted and the true tensor)."""
     sk = torch.zeros(64 * ((count + 63) // 64), model.din, dtype=torch.bfloat16, device=model.device)
     tg = torch.zeros(sk.shape[0], model.dout, dtype=torch.float32, device=model.device)
     for j in range(count):
@@ -223,5 +203,5 @@ def heldout_loss(model, count, seed0):
         sk[j] = model.sketch(build_tensor(A, model.device))
         tg[j] = torch.as_tensor(pack_targets(A, np.ones(model.R)), device=model.device)
     y, _ = model.forward(sk)
-    loss, _, _ = C.cpqr_kruskal_loss_grad(y, tg, model.shape, model.R, model.R)
+    loss, _, _ = C.cpqr_kruskal_loss_grad(y, tg, model.shape, model.R, model.R, kind=C.LOSS_COSINE)
     return float(loss[:count].double().mean())

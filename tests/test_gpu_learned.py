@@ -86,20 +86,23 @@ def test_mlp_backward_matches_oracle():
         assert relnorm(db[l].cpu().numpy(), g[2 * l + 1]) < 1e-1, l
 
 
+@pytest.mark.parametrize("kind", ["distance", "cosine"])
 @pytest.mark.parametrize("I,R,Rt", [((32, 40, 24), 3, 3), ((256, 256, 256), 10, 10), ((17, 5, 9), 2, 4)])
-def test_kruskal_loss_grad_matches_oracle(I, R, Rt):
+def test_kruskal_loss_grad_matches_oracle(I, R, Rt, kind):
     rng = np.random.default_rng(sum(I) + R)
     B = 5
     y = rng.standard_normal((B, sum(I) * R)).astype(np.float32)
     t = rng.standard_normal((B, sum(I) * Rt)).astype(np.float32)
+    code = C.LOSS_DISTANCE if kind == "distance" else C.LOSS_COSINE
     loss, dy, dyb = C.cpqr_kruskal_loss_grad(torch.as_tensor(y, device="cuda"), torch.as_tensor(t, device="cuda"),
-                                             I, R, Rt, scale=1.0 / B)
+                                             I, R, Rt, scale=1.0 / B, kind=code)
     torch.cuda.synchronize()
     targets = [OL.unpack_factors(t[b].astype(np.float64), I, Rt) for b in range(B)]
-    lo, dyo = OL.batch_loss_grad(y.astype(np.float64), targets, I, R)
+    lo, dyo = OL.batch_loss_grad(y.astype(np.float64), targets, I, R, kind=kind)
+    one = OL.kruskal_loss if kind == "distance" else OL.kruskal_cosine_loss
     assert abs(float(loss.mean()) - lo) < 1e-4 * max(1.0, abs(lo))
     for b in range(B):
-        ob = OL.kruskal_loss(OL.unpack_factors(y[b].astype(np.float64), I, R), targets[b])
+        ob = one(OL.unpack_factors(y[b].astype(np.float64), I, R), targets[b])
         assert abs(float(loss[b]) - ob) < 1e-4 * max(1.0, abs(ob))
     assert relnorm(dy.cpu().numpy(), dyo) < 1e-4
     assert relnorm(up(dyb), dyo) < 1e-2
@@ -117,8 +120,8 @@ def test_sketch_matches_oracle(shape):
     ref = OL.sketch_vector(OL.sketch(X.astype(np.float64), [up(s) for s in Sb]))
     assert relnorm(xs.cpu().numpy(), ref) < 2e-2
     xn = up(xb)
-    assert abs(np.linalg.norm(xn) - 1.0) < 1e-2
-    assert relnorm(xn, ref / np.linalg.norm(ref)) < 2e-2
+    assert abs(np.linalg.norm(xn) / np.sqrt(xn.size) - 1.0) < 1e-2  # unit RMS
+    assert relnorm(xn, ref * np.sqrt(ref.size) / np.linalg.norm(ref)) < 2e-2
 
 
 def test_adam_matches_oracle():
@@ -141,8 +144,8 @@ def test_adam_matches_oracle():
 
 
 def test_training_steps_reduce_the_loss():
-    """A few Adam steps of the GPU forward/backward on one batch lower the
-    Kruskal loss (the gradient points downhill)."""
+    """Adam steps of the GPU forward/backward on one batch lower the cosine
+    Kruskal loss steadily (the gradient points downhill)."""
     rng = np.random.default_rng(13)
     I, R = (32, 32, 32), 2
     din, hid, dout, batch = 128, 64, 3 * 32 * 2, 64
@@ -162,10 +165,11 @@ def test_training_steps_reduce_the_loss():
     losses = []
     for step in range(1, 31):
         y, cache = net.forward(xb)
-        loss, dy, dyb = C.cpqr_kruskal_loss_grad(y, tgt, I, R, R, scale=1.0 / batch)
+        loss, dy, dyb = C.cpqr_kruskal_loss_grad(y, tgt, I, R, R, scale=1.0 / batch, kind=C.LOSS_COSINE)
         losses.append(float(loss.mean()))
         net.backward(cache, dy, dyb, dW, db)
         for k, (p, gr) in enumerate(zip(params, dW + db)):
             C.cpqr_adam(p, gr, mom[k], vel[k], Wb[k] if k < 3 else None, step, 3e-3)
     torch.cuda.synchronize()
-    assert losses[-1] < 0.5 * losses[0], losses
+    assert losses[-1] < 0.95 * losses[0], losses
+    assert all(b <= a + 1e-3 for a, b in zip(losses, losses[1:])), losses

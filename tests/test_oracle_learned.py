@@ -81,6 +81,31 @@ def test_kruskal_grad_matches_finite_differences():
                 assert abs(fd - g[k][i, r]) < 1e-7 * max(1.0, abs(fd)), (k, i, r)
 
 
+def test_cosine_loss_equals_dense_cosine_and_grad_matches_fd():
+    rng = np.random.default_rng(15)
+    I = (4, 3, 5)
+    A = random_factors(rng, I, 3)
+    Ah = random_factors(rng, I, 2)
+    Xa = T.full(np.ones(3), A).ravel()
+    Xh = T.full(np.ones(2), Ah).ravel()
+    dense = 1.0 - (Xa @ Xh) ** 2 / ((Xa @ Xa) * (Xh @ Xh))
+    assert abs(L.kruskal_cosine_loss(Ah, A) - dense) < 1e-12
+    # invariant to the scale of the prediction
+    assert abs(L.kruskal_cosine_loss([3.0 * Ah[0], Ah[1], Ah[2]], A) - dense) < 1e-12
+    loss, g = L.kruskal_cosine_loss_grad(Ah, A)
+    assert abs(loss - dense) < 1e-12
+    h = 1e-6
+    for k in range(3):
+        for i in range(I[k]):
+            for r in range(2):
+                P = [a.copy() for a in Ah]
+                M = [a.copy() for a in Ah]
+                P[k][i, r] += h
+                M[k][i, r] -= h
+                fd = (L.kruskal_cosine_loss(P, A) - L.kruskal_cosine_loss(M, A)) / (2 * h)
+                assert abs(fd - g[k][i, r]) < 1e-7 * max(1.0, abs(fd)), (k, i, r)
+
+
 def tiny_net(rng, din=6, h=5, dout=3 * 4 * 2):
     return (rng.standard_normal((h, din)) * 0.5, rng.standard_normal(h) * 0.1,
             rng.standard_normal((h, h)) * 0.5, rng.standard_normal(h) * 0.1,
