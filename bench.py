@@ -45,6 +45,8 @@ def parse():
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
+    ap.add_argument("--dimtree", type=int, default=-1,
+                    help="Multi-TTM reuse across modes: -1 library choice, 0 one Multi-TTM per mode, h split point")
     ap.add_argument("--train", type=int, default=20000, help="training tensors for --workload learned")
     ap.add_argument("--epochs", type=int, default=20, help="training epochs for --workload learned")
     ap.add_argument("--heldout", type=int, default=256, help="held-out tensors (loss) for --workload learned")
@@ -315,7 +317,7 @@ def main():
     prec = C.PREC_NAMES[args.prec]
     if prec == C.PREC_F64:
         Xd = Xd.double()
-    st = C.AlsState(Xd, d["init"], prec=prec)
+    st = C.AlsState(Xd, d["init"], prec=prec, dimtree=args.dimtree)
     st.init()
     for _ in range(args.warmup):
         st.sweep(1)
@@ -376,7 +378,7 @@ def main():
         "config": {
             "workload": "cp_als_qr_dense3_%dcube_%s_r%d" % (n, args.prec, R),
             "shape": list(shape), "rank": R, "multittm_precision": args.prec,
-            "small_steps_precision": "f64", "solver": "qr", "error": "efficient",
+            "small_steps_precision": "f64", "solver": "qr", "error": "efficient", "dimtree": args.dimtree,
             "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
         },
         "roofline": {

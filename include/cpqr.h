@@ -188,6 +188,11 @@ typedef struct cpqr_problem {
   double rtol;                    /* SVD cutoff (negative: default) */
   int error_mode;                 /* CPQR_ERROR_* */
   int* status;                    /* device int or NULL */
+  int dimtree;                    /* Multi-TTM reuse across modes: 0 off (one Multi-TTM of X
+                                     per mode, as in Alg. 2), h in [1, N-1]: modes 1..h share
+                                     X contracted over modes h+1..N and modes h+1..N share X
+                                     contracted over modes 1..h (two passes over X per sweep),
+                                     -1: the library picks h (off for N = 2) */
 } cpqr_problem;
 
 size_t cpqr_als_work(const cpqr_problem* p);

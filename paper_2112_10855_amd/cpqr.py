@@ -55,7 +55,7 @@ class Problem(ctypes.Structure):
         ("A", _vp * MAX_MODES), ("Q", _vp * MAX_MODES), ("Rf", _vp * MAX_MODES),
         ("lam", _vp),
         ("prec", ctypes.c_int), ("use_svd", ctypes.c_int), ("rtol", ctypes.c_double),
-        ("error_mode", ctypes.c_int), ("status", _vp),
+        ("error_mode", ctypes.c_int), ("status", _vp), ("dimtree", ctypes.c_int),
     ]
 
 
@@ -315,7 +315,7 @@ def cpqr_fit_direct(X, lam, As):
 class AlsState:
     """Device buffers of one CP-ALS-QR problem, wired into ``cpqr_problem``."""
 
-    def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT):
+    def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1):
         _dev(X, "X")
         _check_colmajor(X, "X")
         prec = PREC_NAMES.get(prec, prec)
@@ -342,6 +342,7 @@ class AlsState:
         p.X = X.data_ptr()
         p.lam = self.lam.data_ptr()
         p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(bool(use_svd)), float(rtol), error_mode
+        p.dimtree = int(dimtree)
         p.status = self.status.data_ptr()
         self.p = p
         nbytes = lib().cpqr_als_work(ctypes.byref(p))
@@ -371,10 +372,10 @@ def cpqr_als_sweep(state, nsweeps=1, relerr=None):
 
 
 def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=-1.0,
-              error_mode=ERROR_EFFICIENT):
+              error_mode=ERROR_EFFICIENT, dimtree=-1):
     """Alg. 2 driven from the host: sweeps until |relerr change| < tol or
     maxiters (reads the error back after each sweep only when tol > 0)."""
-    st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode)
+    st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode, dimtree=dimtree)
     st.init()
     if tol <= 0:
         rel = st.sweep(maxiters)

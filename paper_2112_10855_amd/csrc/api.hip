@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -131,12 +132,44 @@ struct AlsWs {
   double* fit;
   double* relerr_tmp;
   void* sub;
+  void* krp_sub;  // scratch of the Khatri-Rao QR, which runs beside the Multi-TTM
+  void* Wt;       // X contracted over one half of the modes (dimension-tree reuse)
 };
+
+// Split point of the dimension-tree reuse (0 = off).
+int dt_split(const cpqr_problem* p) {
+  if (p->dimtree == 0 || p->N < 3) return 0;
+  if (p->dimtree > 0) return p->dimtree;
+  return p->N == 3 ? 2 : p->N / 2;
+}
+
+unsigned range_mask(int lo, int hi) { return ((1u << hi) - 1u) & ~((1u << lo) - 1u); }
+
+// Sizes of X contracted over the modes outside [lo, hi), and its element count.
+int64_t half_dims(const cpqr_problem* p, int lo, int hi, int64_t* D) {
+  int64_t c = 1;
+  for (int k = 0; k < p->N; ++k) {
+    D[k] = (k >= lo && k < hi) ? p->I[k] : p->R;
+    c *= D[k];
+  }
+  return c;
+}
 
 size_t als_sub_bytes(const cpqr_problem* p) {
   const int N = p->N, R = p->R;
   size_t b = tsqr_work(ipow(R, N - 1), R);
   const int64_t K = ipow(R, N - 1);
+  const int h = dt_split(p);
+  if (h > 0) {
+    for (int half = 0; half < 2; ++half) {
+      const int lo = half ? h : 0, hi = half ? N : h;
+      int64_t D[CPQR_MAX_MODES];
+      half_dims(p, lo, hi, D);
+      b = std::max(b, multittm_general_work(N, p->I, ~range_mask(lo, hi) & range_mask(0, N), R, p->prec));
+      for (int n = lo; n < hi; ++n)
+        b = std::max(b, multittm_general_work(N, D, range_mask(lo, hi) & ~(1u << n), R, p->prec));
+    }
+  }
   int64_t count = 1;
   for (int k = 0; k < N; ++k) {
     count *= p->I[k];
@@ -164,8 +197,41 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
   w.fit = cv.take<double>(2);
   w.relerr_tmp = cv.take<double>(1);
   w.sub = cv.take<char>(als_sub_bytes(p));
+  w.krp_sub = cv.take<char>(tsqr_work(K, R));
+  const int h = dt_split(p);
+  int64_t wt = 0;
+  if (h > 0) {
+    int64_t D[CPQR_MAX_MODES];
+    if (h > 1) wt = std::max(wt, half_dims(p, 0, h, D));
+    if (N - h > 1) wt = std::max(wt, half_dims(p, h, N, D));
+  }
+  w.Wt = cv.take<double>(size_t(wt));  // sized for FP64
   if (ws) *ws = w;
   return cv.bytes();
+}
+
+// A second stream per device for the Khatri-Rao QR of a mode, which depends
+// only on the R factors and so runs while the Multi-TTM streams the tensor
+// (default priority, non-blocking), and two events that order it.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
+std::mutex g_side_mu;
+std::map<int, SideStream> g_side;
+
+int side_stream(SideStream& out) {
+  int dev = 0;
+  CPQR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_side_mu);
+  SideStream& ss = g_side[dev];
+  if (!ss.s) {
+    CPQR_HIP(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+    CPQR_HIP(hipEventCreateWithFlags(&ss.ready, hipEventDisableTiming));
+    CPQR_HIP(hipEventCreateWithFlags(&ss.done, hipEventDisableTiming));
+  }
+  out = ss;
+  return CPQR_OK;
 }
 
 int check_problem(const cpqr_problem* p) {
@@ -179,6 +245,8 @@ int check_problem(const cpqr_problem* p) {
     return fail(CPQR_ERR_DTYPE, "reduced-precision Multi-TTM needs an FP32 tensor");
   if (p->error_mode < CPQR_ERROR_EFFICIENT || p->error_mode > CPQR_ERROR_NONE)
     return fail(CPQR_ERR_ARG, "unknown error_mode");
+  if (p->dimtree < -1 || (p->dimtree > 0 && p->dimtree >= p->N))
+    return fail(CPQR_ERR_ARG, "dimtree must be -1, 0 or a split point in [1, N-1]");
   if (!p->X || !p->lambda) return fail(CPQR_ERR_ARG, "X or lambda is NULL");
   for (int k = 0; k < p->N; ++k) {
     if (!p->A[k] || !p->Q[k] || !p->Rf[k])
@@ -339,10 +407,33 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   const int N = p->N, R = p->R;
   const int64_t K = ipow(R, N - 1);
   const int ydt = p->prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
+  SideStream side;
+  CPQR_TRY(side_stream(side));
+  const int h = dt_split(p);
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
-      CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.sub, s));
-      CPQR_TRY(multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, p->Q, p->prec, w.Y, w.sub, s));
+      // Khatri-Rao QR (reads R_k) on the side stream, Multi-TTM (reads Q_k)
+      // on the caller's stream; both start after the previous factor QR.
+      CPQR_HIP(hipEventRecord(side.ready, s));
+      CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
+      CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
+      CPQR_HIP(hipEventRecord(side.done, side.s));
+      const int lo = (h > 0 && n >= h) ? h : 0, hi = (h > 0 && n < h) ? h : N;
+      if (h == 0 || hi - lo == 1) {  // one Multi-TTM of X for this mode
+        CPQR_TRY(multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, p->Q, p->prec, w.Y, w.sub, s));
+      } else {
+        // dimension tree: X contracted over the modes outside [lo, hi) once (when the
+        // first mode of the half is updated; those Q_k do not change while the half
+        // is updated), then the remaining modes of the half for each n
+        if (n == lo)
+          CPQR_TRY(multittm_general_enqueue(N, p->I, p->xdtype, p->X, ~range_mask(lo, hi) & range_mask(0, N), -1,
+                                            R, p->Q, p->prec, w.Wt, w.sub, s, true));
+        int64_t D[CPQR_MAX_MODES];
+        half_dims(p, lo, hi, D);
+        CPQR_TRY(multittm_general_enqueue(N, D, ydt, w.Wt, range_mask(lo, hi) & ~(1u << n), n, R, p->Q, p->prec,
+                                          w.Y, w.sub, s, false));
+      }
+      CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
       CPQR_TRY(apply_q0_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.W, w.sub, s));
       CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda,
                              p->status, w.sub, s));

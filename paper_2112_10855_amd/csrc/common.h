@@ -83,6 +83,15 @@ int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, do
 
 // multittm.hip
 size_t multittm_work(int N, const int64_t* I, int n, int R, int prec);
+// Contract the modes in cmask (bit k = mode k) of a tensor with sizes I (modes
+// already contracted have size R and are left alone); write the result in its
+// natural column-major layout (n_unfold < 0) or unfolded along n_unfold as
+// Y_(n) (columns: lowest remaining mode fastest).  streams_tensor marks calls
+// whose first contraction reads the input tensor (for the phase timers).
+size_t multittm_general_work(int N, const int64_t* I, unsigned cmask, int R, int prec);
+int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X, unsigned cmask, int n_unfold,
+                             int R, const double* const* Q, int prec, void* Y, void* work, hipStream_t st,
+                             bool streams_tensor);
 int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
                      const double* const* Q, int prec, void* Y, void* work, hipStream_t s);
 

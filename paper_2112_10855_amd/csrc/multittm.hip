@@ -78,12 +78,13 @@ constexpr int LDS_FLOATS = 16384;  // 64 KB
 // STREAM marks the instantiation used for a first contraction (it streams the
 // whole tensor); it is the same code under its own symbol so that profiles and
 // phase timers can single it out.
-template <int NB, int UN, int MG, int NWV, bool STREAM>
+template <int NB, int UN, int MG, int NWV, bool STREAM, bool ONE>
 __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__ X,
                                                        const float* __restrict__ U,
                                                        float* __restrict__ out, int64_t P,
-                                                       int64_t K, int64_t S, int R, int RP,
-                                                       int64_t kchunk, int64_t split_stride) {
+                                                       int64_t K, int64_t S, int R, int64_t kchunk,
+                                                       int64_t split_stride) {
+  constexpr int RP = 16 * NB;
   extern __shared__ float us[];
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int64_t M = P * S;
@@ -109,28 +110,23 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
       for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   constexpr int STEP = 4 * UN;
-  const int KC = (LDS_FLOATS / RP) / STEP * STEP;
-  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
-    const int64_t c1 = min(kb1, c0 + KC);
-    __syncthreads();
-    for (int e = tid; e < KC * RP; e += NWV * 64) {
-      const int64_t ii = c0 + e / RP;
-      us[e] = ii < c1 ? U[ii * RP + e % RP] : 0.f;
-    }
-    __syncthreads();
-    if (!active) continue;
-    const int64_t nfull = (c1 - c0) / STEP;
-    const int64_t last = nfull > 0 ? c0 + (nfull - 1) * STEP : c0;
+  // rows [c0, c0 + cn) of U are in LDS (cn <= KC)
+  auto chunk = [&](int64_t c0, int cn) {
+    const int nfull = cn / STEP;
+    const int last = nfull > 0 ? (nfull - 1) * STEP : 0;
+    const float* bp[MG];
+#pragma unroll
+    for (int g = 0; g < MG; ++g) bp[g] = base[g] + c0 * P;
     float4 A[UN][MG], B[UN][MG];
-    auto load = [&](float4(&dst)[UN][MG], int64_t t) {
-      const int64_t i0 = min(c0 + t * STEP, last);
+    auto load = [&](float4(&dst)[UN][MG], int t) {
+      const int i0 = min(t * STEP, last);
 #pragma unroll
       for (int u = 0; u < UN; ++u)
 #pragma unroll
         for (int g = 0; g < MG; ++g)
-          dst[u][g] = *reinterpret_cast<const float4*>(base[g] + (i0 + 4 * u) * P);
+          dst[u][g] = *reinterpret_cast<const float4*>(bp[g] + int64_t(i0 + 4 * u) * P);
     };
-    auto compute = [&](const float4(&src)[UN][MG], int64_t t) {
+    auto compute = [&](const float4(&src)[UN][MG], int t) {
 #pragma unroll
       for (int u = 0; u < UN; ++u)
 #pragma unroll
@@ -147,22 +143,22 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
     };
     if (nfull > 0) {
       load(A, 0);
-      for (int64_t t = 0; t < nfull; t += 2) {
+      for (int t = 0; t < nfull; t += 2) {
         load(B, t + 1);
         compute(A, t);
         load(A, t + 2);
         if (t + 1 < nfull) compute(B, t + 1);
       }
     }
-    for (int64_t i = c0 + nfull * STEP; i < c1; i += 4) {  // chunk tail
-      const int64_t ii = i + kq;
-      const bool ok = ii < c1;
+    for (int i = nfull * STEP; i < cn; i += 4) {  // chunk tail
+      const int ii = i + kq;
+      const bool ok = ii < cn;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const float bv = ok ? us[(ii - c0) * RP + b * 16 + l16] : 0.f;
+        const float bv = ok ? us[ii * RP + b * 16 + l16] : 0.f;
 #pragma unroll
         for (int g = 0; g < MG; ++g) {
-          const float4 xv = ok ? *reinterpret_cast<const float4*>(base[g] + i * P)
+          const float4 xv = ok ? *reinterpret_cast<const float4*>(bp[g] + int64_t(i) * P)
                                : make_float4(0.f, 0.f, 0.f, 0.f);
           acc[b][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[b][g][0], 0, 0, 0);
           acc[b][g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[b][g][1], 0, 0, 0);
@@ -171,8 +167,26 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
         }
       }
     }
+  };
+  if constexpr (ONE) {  // the workgroup's K range fits in LDS: stage once, no chunk loop
+    const int cn = int(kb1 > kb0 ? kb1 - kb0 : 0);
+    const float* Uc = U + kb0 * RP;
+    for (int e = tid; e < cn * RP; e += NWV * 64) us[e] = Uc[e];
+    __syncthreads();
+    if (!active) return;
+    chunk(kb0, cn);
+  } else {
+    constexpr int KC = (LDS_FLOATS / RP) / STEP * STEP;
+    for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+      const int cn = int(min<int64_t>(kb1 - c0, KC));
+      __syncthreads();
+      const float* Uc = U + c0 * RP;
+      for (int e = tid; e < cn * RP; e += NWV * 64) us[e] = Uc[e];
+      __syncthreads();
+      if (active) chunk(c0, cn);
+    }
+    if (!active) return;
   }
-  if (!active) return;
   // D layout: lane holds rows 4*kq + v (v = 0..3) of column l16.
   float* o = out + int64_t(blockIdx.y) * split_stride;
 #pragma unroll
@@ -631,14 +645,15 @@ struct Plan {
 bool uses_mfma(int prec) { return prec != CPQR_PREC_F64; }
 int valu_mode(int prec) { return prec == CPQR_PREC_BF16 ? 1 : (prec == CPQR_PREC_BF16X2 ? 2 : 0); }
 
-Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned = true) {
+// Contract the modes in cmask (bit k = mode k) of a tensor of sizes I.
+Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_aligned = true) {
   Plan pl{};
   pl.RP = ((R + 15) / 16) * 16;
   pl.acc_bytes = prec == CPQR_PREC_F64 ? 8 : 4;
   int order[CPQR_MAX_MODES];
   int no = 0;
   for (int k = 0; k < N; ++k)
-    if (k != n) order[no++] = k;
+    if (cmask >> k & 1u) order[no++] = k;
   std::stable_sort(order, order + no, [&](int a, int b) { return I[a] > I[b]; });
   // The first contraction streams the whole tensor.  Contracting the fastest
   // mode first (P = 1) has the least favourable access pattern for the matrix
@@ -697,9 +712,12 @@ Plan make_plan(int N, const int64_t* I, int n, int R, int prec, bool x_aligned =
     pl.st[t] = s;
     pl.buf_count[t % 2] = std::max(pl.buf_count[t % 2], s.out_count);
   }
-  pl.final_count = I[n] * ipow(R, N - 1);
+  pl.final_count = 1;
+  for (int k = 0; k < N; ++k) pl.final_count *= D[k];
   return pl;
 }
+
+unsigned all_but(int N, int n) { return ((1u << N) - 1u) & ~(1u << n); }
 
 struct Bufs {
   void* U[CPQR_MAX_MODES];
@@ -707,7 +725,7 @@ struct Bufs {
   void* part;
 };
 
-size_t carve(Carver& cv, const Plan& pl, int N, const int64_t* I, int n, Bufs* b) {
+size_t carve(Carver& cv, const Plan& pl, int N, const int64_t* I, Bufs* b) {
   Bufs tmp{};
   for (int t = 0; t < pl.nsteps; ++t) {
     const int k = pl.st[t].k;
@@ -789,12 +807,19 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
   if (s.kind == K_MFMA_M) {
     constexpr int UN = 2, MG = 4;
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
-    if (NB == 1)
-      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
-                         s.K, s.S, R, RP, s.kchunk, s.out_count);
+    const bool one = s.kchunk <= (LDS_FLOATS / RP) / (4 * UN) * (4 * UN);  // K range fits in LDS
+    if (NB == 1 && one)
+      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM, true>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (NB == 1)
+      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM, false>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (one)
+      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM, true>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else
-      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
-                         s.K, s.S, R, RP, s.kchunk, s.out_count);
+      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM, false>), grd, dim3(NWV * 64), lds, st, src, U, dst,
+                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m");
   }
   constexpr int UN = 4;
@@ -821,19 +846,20 @@ int launch_mfma(int prec, bool first, const float* src, const float* U, float* d
 
 }  // namespace
 
-size_t multittm_work(int N, const int64_t* I, int n, int R, int prec) {
-  Plan pl = make_plan(N, I, n, R, prec);
+size_t multittm_general_work(int N, const int64_t* I, unsigned cmask, int R, int prec) {
+  Plan pl = make_plan(N, I, cmask, R, prec);
   Carver cv(nullptr);
-  return carve(cv, pl, N, I, n, nullptr);
+  return carve(cv, pl, N, I, nullptr);
 }
 
-int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
-                     const double* const* Q, int prec, void* Y, void* work, hipStream_t st) {
-  PhaseTimer whole(PH_MULTITTM, st);
-  const Plan pl = make_plan(N, I, n, R, prec, reinterpret_cast<uintptr_t>(X) % 16 == 0);
+int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X, unsigned cmask, int n_unfold,
+                             int R, const double* const* Q, int prec, void* Y, void* work, hipStream_t st,
+                             bool streams_tensor) {
+  PhaseTimer whole(streams_tensor ? PH_MULTITTM : -1, st);
+  const Plan pl = make_plan(N, I, cmask, R, prec, reinterpret_cast<uintptr_t>(X) % 16 == 0);
   Bufs b;
   Carver cv(work);
-  carve(cv, pl, N, I, n, &b);
+  carve(cv, pl, N, I, &b);
   const int RP = pl.RP;
   const bool f64 = prec == CPQR_PREC_F64;
 
@@ -854,16 +880,18 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
     CPQR_TRY(check_launch("prep_u"));
   }
 
+  // the natural layout of the result is Y itself unless a later unfolding is asked for
+  const bool direct = n_unfold <= 0;
   const void* cur = X;
   int cur_dtype = xdtype;
-  int64_t Pn = 1, Sn = 1;
   for (int t = 0; t < pl.nsteps; ++t) {
     const Step& s = pl.st[t];
     const bool last = t + 1 == pl.nsteps;
-    void* dst = (last && n == 0) ? Y : b.buf[t % 2];
+    void* dst = (last && direct) ? Y : b.buf[t % 2];
     void* kout = s.splits > 1 ? b.part : dst;
     {
-      PhaseTimer first(t == 0 ? PH_TTM_FIRST : -1, st);
+      const bool first = t == 0 && streams_tensor;
+      PhaseTimer ph_first(first ? PH_TTM_FIRST : -1, st);
       if (f64) {
         CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
                                            static_cast<double*>(kout), s, R, RP, st)));
@@ -871,8 +899,8 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
         CPQR_TRY(launch_valu_f32(prec, cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
                                  static_cast<float*>(kout), s, R, RP, st));
       } else {
-        PhaseTimer stream_m(t == 0 && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
-        CPQR_TRY(launch_mfma(prec, t == 0, static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
+        PhaseTimer stream_m(first && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
+        CPQR_TRY(launch_mfma(prec, first, static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
                              static_cast<float*>(kout), s, R, RP, st));
       }
       if (s.splits > 1) {
@@ -891,20 +919,36 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
     cur = dst;
     cur_dtype = f64 ? CPQR_F64 : CPQR_F32;
   }
-  if (n != 0) {
-    for (int m = 0; m < n; ++m) Pn *= R;
-    for (int m = n + 1; m < N; ++m) Sn *= R;
-    const int64_t cnt = Pn * I[n] * Sn;
+  if (pl.nsteps == 0 && xdtype != (f64 ? CPQR_F64 : CPQR_F32))
+    return fail(CPQR_ERR_UNSUPPORTED, "multittm: nothing to contract and the output type differs from the input");
+  if (!direct || pl.nsteps == 0) {
+    // Y_(n): result dims D (contracted modes have size R), unfolded along n
+    int64_t D[CPQR_MAX_MODES];
+    for (int k = 0; k < N; ++k) D[k] = (cmask >> k & 1u) ? R : I[k];
+    const int n = n_unfold < 0 ? 0 : n_unfold;
+    int64_t Pn = 1, Sn = 1;
+    for (int m = 0; m < n; ++m) Pn *= D[m];
+    for (int m = n + 1; m < N; ++m) Sn *= D[m];
+    const int64_t cnt = Pn * D[n] * Sn;
     const dim3 grd(unsigned(ceil_div(cnt, 256)));
-    if (f64)
+    if (cur_dtype == CPQR_F64)
       hipLaunchKernelGGL(unfold_copy<double>, grd, dim3(256), 0, st, static_cast<const double*>(cur),
-                         Pn, I[n], Sn, static_cast<double*>(Y));
+                         Pn, D[n], Sn, static_cast<double*>(Y));
     else
       hipLaunchKernelGGL(unfold_copy<float>, grd, dim3(256), 0, st, static_cast<const float*>(cur),
-                         Pn, I[n], Sn, static_cast<float*>(Y));
+                         Pn, D[n], Sn, static_cast<float*>(Y));
     CPQR_TRY(check_launch("unfold_copy"));
   }
   return CPQR_OK;
+}
+
+size_t multittm_work(int N, const int64_t* I, int n, int R, int prec) {
+  return multittm_general_work(N, I, all_but(N, n), R, prec);
+}
+
+int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                     const double* const* Q, int prec, void* Y, void* work, hipStream_t st) {
+  return multittm_general_enqueue(N, I, xdtype, X, all_but(N, n), n, R, Q, prec, Y, work, st, true);
 }
 
 }  // namespace cpqr

@@ -1,5 +1,8 @@
 """GPU CP-ALS-QR sweeps (Alg. 2 end to end through cpqr_als_sweep) against the
-FP64 oracle from the same seeded data and the same initial factors.
+FP64 oracle from the same seeded data and the same initial factors.  The
+sweeps reuse partial Multi-TTMs across modes (dimension trees) unless a test
+says otherwise; the oracle always runs one Multi-TTM per mode, so every test
+also checks that the reuse leaves the iterates unchanged.
 
 Tolerances: the FP64 path must reproduce the oracle's relative-error history
 to 1e-10 and its Kruskal model to 1e-9 (relative, via the dense model); the
@@ -19,10 +22,10 @@ from helpers import relnorm, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(X, init, maxiters, prec, use_svd=False, error_mode=C.ERROR_EFFICIENT):
+def run_gpu(X, init, maxiters, prec, use_svd=False, error_mode=C.ERROR_EFFICIENT, dimtree=-1):
     tdt = torch.float32 if X.dtype == np.float32 else torch.float64
     st, hist = C.cp_als_qr(to_dev(X, tdt), init, maxiters=maxiters, prec=prec, use_svd=use_svd,
-                           error_mode=error_mode)
+                           error_mode=error_mode, dimtree=dimtree)
     torch.cuda.synchronize()
     lam = to_np(st.lam)
     A = [to_np(a) for a in st.A]
@@ -106,3 +109,37 @@ def test_deterministic():
     a = run_gpu(X, d["init"], 5, C.PREC_F32)
     b = run_gpu(X, d["init"], 5, C.PREC_F32)
     assert np.array_equal(a[0], b[0]) and all(np.array_equal(x, y) for x, y in zip(a[1], b[1]))
+
+
+@pytest.mark.parametrize("shape,R,split", [((12, 9, 10), 3, 0), ((12, 9, 10), 3, 1), ((12, 9, 10), 3, 2),
+                                           ((6, 5, 7, 4), 2, 0), ((6, 5, 7, 4), 2, 1), ((6, 5, 7, 4), 2, 2),
+                                           ((6, 5, 7, 4), 2, 3), ((5, 4, 3, 4, 3), 2, 2), ((5, 4, 3, 4, 3), 2, 3)])
+def test_dimension_tree_splits_fp64(shape, R, split):
+    """Every split point of the mode reuse (0 = one Multi-TTM per mode) gives
+    the oracle's iterates on the FP64 path."""
+    d = synth.cp_tensor(shape, R, 321, noise=1e-2, dtype=np.float64)
+    init = synth.init_factors(shape, R, 321)
+    lam, A, hist, status = run_gpu(d["X"], init, 8, C.PREC_F64, dimtree=split)
+    lo, Ao, ho = OQ.cp_als_qr(d["X"], init, maxiters=8)
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, A, lo, Ao) < 1e-9
+
+
+@pytest.mark.parametrize("split", [0, 1, 2, -1])
+def test_dimension_tree_fp32_matches_per_mode(split):
+    """FP32 Multi-TTM at several splits against the oracle (direct error)."""
+    shape, R = (40, 36, 44), 6
+    d = synth.cp_tensor(shape, R, 654, noise=1e-3, dtype=np.float32)
+    init = synth.init_factors(shape, R, 654)
+    lam, A, hist, status = run_gpu(d["X"], init, 10, C.PREC_F32, error_mode=C.ERROR_DIRECT, dimtree=split)
+    lo, Ao, ho = OQ.cp_als_qr(d["X"].astype(np.float64), init, maxiters=10, error="direct")
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-6)
+    assert model_diff(lam, A, lo, Ao) < 1e-5
+
+
+def test_dimension_tree_rejects_bad_split():
+    d = synth.workload_small()
+    with pytest.raises(C.CpqrError):
+        C.cp_als_qr(to_dev(d["X"], torch.float64), d["init"], maxiters=1, prec=C.PREC_F64, dimtree=3)
