@@ -111,3 +111,61 @@ def test_no_cpu_fallback():
     import torch
     with pytest.raises(TypeError):
         C.cpqr_factor_qr(torch.zeros(8, 2, dtype=torch.float64))
+
+
+def test_validation_batch_learned_dimtree(L):
+    P = 4096
+    # sweep: the dimension-tree split must be -1, 0 or in [1, N-1]
+    p = C.Problem()
+    p.N, p.R = 3, 4
+    for k in range(3):
+        p.I[k] = 10
+        p.A[k] = p.Q[k] = p.Rf[k] = P
+    p.X, p.lam, p.xdtype, p.prec, p.error_mode = P, P, 0, 1, 0
+    for ok in (-1, 0, 1, 2):
+        p.dimtree = ok
+        assert L.cpqr_als_work(ctypes.byref(p)) > 0, ok
+    for bad in (-2, 3, 7):
+        p.dimtree = bad
+        assert L.cpqr_als_work(ctypes.byref(p)) == 0, bad
+    # batch: rank and mode-size limits
+    items = (C.BatchItem * 1)()
+    items[0].I[0], items[0].I[1], items[0].I[2] = 20, 30, 40
+    items[0].R, items[0].X, items[0].lam = 4, P, P
+    for k in range(3):
+        items[0].A[k] = P
+    assert L.cpqr_als_batch_work(items, 1) > 0
+    items[0].R = 17
+    assert L.cpqr_als_batch_work(items, 1) == 0
+    assert L.cpqr_als_batch_prepare(items, 1, 0, P, 1 << 30, None) == -2
+    items[0].R, items[0].I[1] = 4, 300
+    assert L.cpqr_als_batch_prepare(items, 1, 0, P, 1 << 30, None) == -2
+    assert L.cpqr_als_batch_run(None, 1, 1, 0, 0, None) == -4
+    # sketch: sizes
+    I = C._i64_array([256, 256, 256])
+    J = (ctypes.c_int * 3)(64, 64, 64)
+    assert L.cpqr_sketch3_work(I, J) > 0
+    assert L.cpqr_sketch3_work(C._i64_array([100, 64, 64]), J) == 0
+    assert L.cpqr_sketch3_work(I, (ctypes.c_int * 3)(64, 48, 64)) == 0
+    Sp = (ctypes.c_void_p * 3)(P, P, P)
+    assert L.cpqr_sketch3(I, P, J, Sp, P, None, P, 16, None) == -4
+    assert L.cpqr_sketch3(I, None, J, Sp, P, None, P, 1 << 30, None) == -1
+    # MLP: widths and batch multiples of 64, non-null weights
+    net = C.Mlp(128, 64, 192, (ctypes.c_void_p * 3)(P, P, P), (ctypes.c_void_p * 3)(P, P, P))
+    assert L.cpqr_mlp_work(ctypes.byref(net), 64) > 0
+    assert L.cpqr_mlp_work(ctypes.byref(net), 32) == 0
+    bad = C.Mlp(100, 64, 192, (ctypes.c_void_p * 3)(P, P, P), (ctypes.c_void_p * 3)(P, P, P))
+    assert L.cpqr_mlp_work(ctypes.byref(bad), 64) == 0
+    assert L.cpqr_mlp_forward(ctypes.byref(net), 64, None, P, P, P, P, 1 << 30, None) == -1
+    assert L.cpqr_mlp_forward(ctypes.byref(bad), 64, P, P, P, P, P, 1 << 30, None) == -2
+    # Kruskal loss: mode sizes <= 256, ranks <= 16, known loss kind, leading dimensions
+    I3 = C._i64_array([32, 32, 32])
+    assert L.cpqr_kruskal_loss_grad(1, C._i64_array([300, 4, 4]), 2, 2, P, 10000, P, 10000, 0, P, P, P, 1.0, None) == -2
+    assert L.cpqr_kruskal_loss_grad(1, I3, 17, 2, P, 10000, P, 10000, 0, P, P, P, 1.0, None) == -2
+    assert L.cpqr_kruskal_loss_grad(1, I3, 2, 2, P, 10000, P, 10000, 5, P, P, P, 1.0, None) == -1
+    assert L.cpqr_kruskal_loss_grad(1, I3, 2, 2, P, 100, P, 10000, 0, P, P, P, 1.0, None) == -2
+    # Adam and the bfloat16 conversion
+    assert L.cpqr_adam(0, P, P, P, P, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.cpqr_adam(10, P, P, P, P, None, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.cpqr_to_bf16(None, 10, P, None) == -1
+    assert L.cpqr_to_bf16(P, 0, P, None) == 0
