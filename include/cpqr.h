@@ -328,10 +328,15 @@ int cpqr_to_bf16(const float* x, int64_t n, uint16_t* y, void* stream);
  * accumulated milliseconds and launch counts per phase since the last reset.
  * Phases: 0 Multi-TTM, 1 first (tensor-streaming) contraction, 2 factor QR,
  * 3 computing Q_0, 4 applying Q_0, 5 solve + normalize, 6 error, 7 the
- * subset of phase 1 that runs the row-tiled matrix-core kernel.
+ * subset of phase 1 that runs the row-tiled matrix-core kernel.  Phase 7 is
+ * timed by events attached to the kernel dispatch itself and adds no work
+ * to the stream; the others record events between phases, which costs some
+ * microseconds per event.  cpqr_timing_select limits recording to the
+ * phases whose bit is set in mask (all phases after load).
  */
 #define CPQR_NPHASES 8
 int cpqr_timing_enable(int on);
+int cpqr_timing_select(unsigned mask);
 int cpqr_timing_reset(void);
 int cpqr_timing_read(double* ms, int64_t* counts, int nphases);
 

@@ -116,6 +116,7 @@ _SIGS = {
     "cpqr_to_bf16": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "cpqr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "cpqr_timing_reset": (ctypes.c_int, []),
+    "cpqr_timing_select": (ctypes.c_int, [ctypes.c_uint]),
     "cpqr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.c_int]),
 }
 
@@ -446,6 +447,12 @@ class AlsBatch:
 
 def cpqr_timing_enable(on=True):
     _call("cpqr_timing_enable", int(bool(on)))
+
+
+def cpqr_timing_select(phases=None):
+    """Record only the named phases (all when None)."""
+    mask = 0xFFFFFFFF if phases is None else sum(1 << PHASES.index(p) for p in phases)
+    _call("cpqr_timing_select", ctypes.c_uint(mask))
 
 
 def cpqr_timing_reset():

@@ -20,6 +20,7 @@ thread_local std::string g_error;
 struct TimingState {
   std::mutex mu;
   bool on = false;
+  unsigned mask = ~0u;  // phases that record
   struct Pending {
     int phase;
     hipEvent_t a, b;
@@ -69,11 +70,37 @@ int check_work(void* work, size_t have, size_t need) {
   return CPQR_OK;
 }
 
+KernelEvents kernel_events(int phase, hipStream_t s) {
+  KernelEvents ke;
+  if (phase < 0) return ke;
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on || !((t.mask >> phase) & 1u)) return ke;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return ke;
+  ke.a = t.get();
+  ke.b = ke.a ? t.get() : nullptr;
+  if (!ke.b) {
+    if (ke.a) t.pool.push_back(ke.a);
+    ke.a = nullptr;
+    return ke;
+  }
+  ke.phase = phase;
+  return ke;
+}
+
+void kernel_events_done(const KernelEvents& ke) {
+  if (!ke.a) return;
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.pending.push_back({ke.phase, ke.a, ke.b});
+}
+
 PhaseTimer::PhaseTimer(int ph, hipStream_t s) : phase(ph), stream(s) {
   if (ph < 0) return;
   TimingState& t = timing();
   std::lock_guard<std::mutex> g(t.mu);
-  if (!t.on) return;
+  if (!t.on || !((t.mask >> ph) & 1u)) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   ev0 = t.get();
@@ -459,6 +486,13 @@ int cpqr_timing_enable(int on) {
   TimingState& t = timing();
   std::lock_guard<std::mutex> g(t.mu);
   t.on = on != 0;
+  return CPQR_OK;
+}
+
+int cpqr_timing_select(unsigned mask) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.mask = mask;
   return CPQR_OK;
 }
 

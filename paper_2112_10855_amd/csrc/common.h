@@ -62,6 +62,16 @@ inline int64_t ipow(int64_t b, int e) {
 // ---------------------------------------------------------------- timing
 enum Phase { PH_MULTITTM = 0, PH_TTM_FIRST = 1, PH_FACTOR_QR = 2, PH_Q0 = 3, PH_APPLY_Q0 = 4,
              PH_SOLVE = 5, PH_ERROR = 6, PH_TTM_STREAM_M = 7 };
+// Events attached to one kernel dispatch (hipExtLaunchKernelGGL), so that
+// timing a kernel adds no packets of its own to the stream; both null when
+// the phase is not being timed.
+struct KernelEvents {
+  int phase = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+};
+KernelEvents kernel_events(int phase, hipStream_t s);
+void kernel_events_done(const KernelEvents& ke);
+
 // Scoped phase timer: records an event pair on `stream` when timing is on.
 struct PhaseTimer {
   int phase;

@@ -26,11 +26,23 @@
 //  The last contraction lands in the tensor layout [P_n, I_n, S_n]; unless
 //  n is the first mode a permute kernel writes the unfolding Y_(n).
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "common.h"
 
 namespace cpqr {
+
+// Launch with the dispatch's own start/stop events when they are set.
+template <typename... Args, typename F = void (*)(Args...)>
+void launch_ev(const KernelEvents& ke, F kernel, const dim3& grid, const dim3& block, size_t lds, hipStream_t st,
+               Args... args) {
+  if (ke.a)
+    hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), st, ke.a, ke.b, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -772,7 +784,8 @@ int launch_valu_f32(int prec, const void* src, int src_dtype, const float* U, fl
 }
 
 template <bool SPLIT, bool STREAM>
-int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, int R, int RP, hipStream_t st) {
+int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, int R, int RP, hipStream_t st,
+                  const KernelEvents& ke) {
   const int NB = RP / 16;
   constexpr int NWV = 8;
   const size_t lds = LDS_FLOATS * sizeof(float);
@@ -780,11 +793,11 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
     constexpr int MG = 2;
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
     if (NB == 1)
-      hipLaunchKernelGGL((ttm_bf16_m<SPLIT, 1, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_bf16_m<SPLIT, 1, MG, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     else
-      hipLaunchKernelGGL((ttm_bf16_m<SPLIT, 2, MG, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_bf16_m<SPLIT, 2, MG, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     return check_launch("ttm_bf16_m");
   }
   constexpr int UN = 2;
@@ -800,7 +813,7 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
 
 template <bool STREAM>
 int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, int R, int RP,
-                  hipStream_t st) {
+                  hipStream_t st, const KernelEvents& ke) {
   const int NB = RP / 16;
   constexpr int NWV = 8;
   const size_t lds = LDS_FLOATS * sizeof(float);
@@ -809,17 +822,17 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
     const bool one = s.kchunk <= (LDS_FLOATS / RP) / (4 * UN) * (4 * UN);  // K range fits in LDS
     if (NB == 1 && one)
-      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM, true>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else if (NB == 1)
-      hipLaunchKernelGGL((ttm_mfma_m<1, UN, MG, NWV, STREAM, false>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else if (one)
-      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM, true>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else
-      hipLaunchKernelGGL((ttm_mfma_m<2, UN, MG, NWV, STREAM, false>), grd, dim3(NWV * 64), lds, st, src, U, dst,
-                         s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m");
   }
   constexpr int UN = 4;
@@ -834,14 +847,15 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
 }
 
 int launch_mfma(int prec, bool first, const float* src, const float* U, float* dst, const Step& s, int R,
-                int RP, hipStream_t st) {
+                int RP, hipStream_t st, const KernelEvents& ke) {
   if (prec == CPQR_PREC_BF16X2)
-    return first ? launch_bf16_t<true, true>(src, U, dst, s, R, RP, st)
-                 : launch_bf16_t<true, false>(src, U, dst, s, R, RP, st);
+    return first ? launch_bf16_t<true, true>(src, U, dst, s, R, RP, st, ke)
+                 : launch_bf16_t<true, false>(src, U, dst, s, R, RP, st, ke);
   if (prec == CPQR_PREC_BF16)
-    return first ? launch_bf16_t<false, true>(src, U, dst, s, R, RP, st)
-                 : launch_bf16_t<false, false>(src, U, dst, s, R, RP, st);
-  return first ? launch_mfma_t<true>(src, U, dst, s, R, RP, st) : launch_mfma_t<false>(src, U, dst, s, R, RP, st);
+    return first ? launch_bf16_t<false, true>(src, U, dst, s, R, RP, st, ke)
+                 : launch_bf16_t<false, false>(src, U, dst, s, R, RP, st, ke);
+  return first ? launch_mfma_t<true>(src, U, dst, s, R, RP, st, ke)
+               : launch_mfma_t<false>(src, U, dst, s, R, RP, st, ke);
 }
 
 }  // namespace
@@ -899,9 +913,10 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
         CPQR_TRY(launch_valu_f32(prec, cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
                                  static_cast<float*>(kout), s, R, RP, st));
       } else {
-        PhaseTimer stream_m(first && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
+        const KernelEvents ke = kernel_events(first && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
         CPQR_TRY(launch_mfma(prec, first, static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
-                             static_cast<float*>(kout), s, R, RP, st));
+                             static_cast<float*>(kout), s, R, RP, st, ke));
+        kernel_events_done(ke);
       }
       if (s.splits > 1) {
         const dim3 grd(unsigned(ceil_div(s.out_count, 256)));

@@ -3,55 +3,32 @@
 // V_n = Q_0 R_0 (paper section 3.1, Alg. 2), both with the orthonormal
 // factor formed explicitly.
 //
-// Design.  One workgroup of NT threads owns one block ("node") of at most NT
-// rows; thread t holds row t of the block in registers (R <= 32 doubles).
-// Column j of the Householder factorization needs two reductions over the
-// rows: the norm of the sub-column, and one batched reduction that returns at
-// once the trailing products w_c = v_j^T A(:,c) (c > j) and the reflector
-// Gram entries G(i,j) = v_i^T v_j (i < j).  Reductions are reduce-scatter
-// butterflies inside each wavefront followed by one LDS pass across
-// wavefronts; their order is fixed, so results are bitwise reproducible.
-// The orthonormal factor uses the compact WY form of the reflectors,
-// H_0 ... H_{R-1} = I - V T V^T with T upper triangular built from G, so
-// forming Q needs no further reductions: Q [C; 0] = [C; 0] - V (T V_1^T C),
-// V_1 being the top R x R block of V.
-//
-// Blocks larger than one workgroup are combined in a tree: the triangular
-// factors of up to NT/R children are stacked and factorized again, level by
-// level, until one block remains (its R is the answer).  Q is formed top
-// down: each node applies its reflectors to [C; 0], where C is the node's
-// R x R slice of its parent's Q, and hands R x R slices to its children.
-// Every step is a genuine Householder reflection of the real rows, so Q has
-// orthonormal columns even when the input is rank deficient.
+// Design: a reduction tree whose every node is one wavefront.  A leaf holds
+// up to 64 P rows of the input (P rows per lane); an inner node stacks the R
+// factors of up to 64 P / R children.  Each node is factorized by Householder
+// reflections held in registers, one in-wave reduction per column, and keeps
+// its reflectors in the compact WY form H_0 ... H_{R-1} = I - V T V^T.  The
+// up-sweep runs one launch per level (one single-wavefront workgroup per
+// node); the root's R is the answer.  The down-sweep forms Q top down: each
+// node applies its reflectors to [C; 0], C being its R x R slice of the
+// parent's Q (the identity at the root), and hands R x R slices to its
+// children.  Every step is a genuine Householder reflection of the real
+// rows, so Q has orthonormal columns even when the input is rank deficient.
 
 #include <algorithm>
 
 #include "common.h"
-#include "wgqr.h"
 
 namespace cpqr {
 namespace {
 
-enum Src { SRC_MATRIX = 0, SRC_KRP = 1, SRC_STACK = 2 };
+enum Src { SRC_MATRIX = 0, SRC_KRP = 1 };
 
 struct KrpSrc {
   const double* Rk[CPQR_MAX_MODES];
   int nm;  // the N-1 modes k != n, ascending (lowest varies fastest)
   int64_t ldr;
 };
-
-struct Level {
-  int nt;             // rows per node (threads per workgroup)
-  int64_t nodes;      // nodes at this level
-  int64_t rows;       // leaf level: rows of the input
-  int64_t prev_nodes; // internal levels: nodes of the level below
-  int g;              // internal levels: children per node
-  double* V;          // nodes x RMAX x nt reflectors (column c of node j at (j*RMAX + c)*nt)
-  double* T;          // nodes x RMAX x RMAX compact-WY factors
-  double* Rin;        // internal levels: prev_nodes blocks of RMAX x RMAX (stacked R's)
-};
-
-using namespace wgqr;
 
 // Balanced leaf partition: leaf b of nl covering `rows` rows.
 __device__ __host__ inline void leaf_range(int64_t rows, int64_t nl, int64_t b, int64_t& start,
@@ -61,140 +38,8 @@ __device__ __host__ inline void leaf_range(int64_t rows, int64_t nl, int64_t b, 
   start = b * base + (b < rem ? b : rem);
 }
 
-// Rows of the node's input block.
-template <int RMAX, int SRC>
-__device__ inline int load_rows(double (&a)[RMAX], const Level& L, int64_t node, int R, int tid,
-                                const double* A, int64_t lda, const KrpSrc& krp, int64_t& start) {
-  int m;
-  if (SRC == SRC_STACK) {
-    const int64_t c0 = node * L.g;
-    const int64_t nch = min<int64_t>(L.g, L.prev_nodes - c0);
-    m = int(nch) * R;
-    start = 0;
-    const int child = tid / R, i = tid % R;
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      a[c] = (tid < m && c < R) ? L.Rin[((c0 + child) * RMAX + c) * RMAX + i] : 0.0;
-  } else {
-    leaf_range(L.rows, L.nodes, node, start, m);
-    const int64_t g = start + tid;
-    if (SRC == SRC_MATRIX) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) a[c] = (tid < m && c < R) ? A[g + c * lda] : 0.0;
-    } else {
-      int digit[CPQR_MAX_MODES];
-      int64_t d = g;
-#pragma unroll
-      for (int t = 0; t < CPQR_MAX_MODES; ++t) {
-        digit[t] = int(d % R);
-        d /= R;
-      }
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        double p = (tid < m && c < R) ? 1.0 : 0.0;
-#pragma unroll
-        for (int t = 0; t < CPQR_MAX_MODES; ++t)
-          if (t < krp.nm && tid < m && c < R) p *= krp.Rk[t][digit[t] + c * krp.ldr];
-        a[c] = p;
-      }
-    }
-  }
-  return m;
-}
-
-template <int RMAX>
-__device__ inline void write_q(const double (&q)[RMAX], bool leaf, int64_t start, int m,
-                               double* Qout, int64_t ldq, double* Cchild, int64_t node, int g,
-                               int R, int tid) {
-  if (tid >= m) return;
-  if (leaf) {
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      if (c < R) Qout[start + tid + c * ldq] = q[c];
-  } else {
-    const int64_t child = node * g + tid / R;
-    const int i = tid % R;
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      if (c < R) Cchild[(child * RMAX + c) * RMAX + i] = q[c];
-  }
-}
-
-// Up-sweep of one level (factorize, store reflectors and T, pass R up).  At
-// the root (nodes == 1) also writes R to Rout and forms the root's Q from
-// C = I.
-template <int RMAX, int NT, int SRC>
-__global__ __launch_bounds__(NT) void tsqr_up(Level L, int R, const double* A, int64_t lda,
-                                              KrpSrc krp, double* Rnext, double* Rout,
-                                              int64_t ldr_out, double* Qout, int64_t ldq,
-                                              double* Cchild, int gchild) {
-  __shared__ Shared<RMAX, NT> sh;
-  const int tid = threadIdx.x;
-  const int64_t node = blockIdx.x;
-  double a[RMAX];
-  int64_t start;
-  const int m = load_rows<RMAX, SRC>(a, L, node, R, tid, A, lda, krp, start);
-  wg_factor<RMAX, NT>(a, tid, m, R, sh);
-  wg_build_t<RMAX, NT>(tid, R, sh);
-  if (L.nodes > 1) {
-    double* V = L.V + node * RMAX * NT;
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) V[c * NT + tid] = a[c];
-    for (int e = tid; e < RMAX * RMAX; e += NT)
-      L.T[node * RMAX * RMAX + e] = (e / RMAX < R && e % RMAX < R) ? sh.T[e / RMAX][e % RMAX] : 0.0;
-    if (tid < R) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) Rnext[(node * RMAX + c) * RMAX + tid] = (c >= tid) ? a[c] : 0.0;
-    }
-    return;
-  }
-  if (tid < R) {
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      if (c < R) Rout[tid + c * ldr_out] = (c >= tid) ? a[c] : 0.0;
-  }
-  for (int e = tid; e < RMAX * RMAX; e += NT) sh.C[e / RMAX][e % RMAX] = (e / RMAX == e % RMAX) ? 1.0 : 0.0;
-  __syncthreads();
-  double q[RMAX];
-  wg_form_q<RMAX, NT>(a, q, tid, m, R, sh);
-  write_q<RMAX>(q, SRC != SRC_STACK, start, m, Qout, ldq, Cchild, node, gchild, R, tid);
-}
-
-// Down-sweep of one non-root level: form each node's Q from its C block.
-template <int RMAX, int NT, bool LEAF>
-__global__ __launch_bounds__(NT) void tsqr_down(Level L, int R, const double* Cin, double* Qout,
-                                                int64_t ldq, double* Cchild, int gchild) {
-  __shared__ Shared<RMAX, NT> sh;
-  const int tid = threadIdx.x;
-  const int64_t node = blockIdx.x;
-  double a[RMAX], q[RMAX];
-  const double* V = L.V + node * RMAX * NT;
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) a[c] = V[c * NT + tid];
-  for (int e = tid; e < RMAX * RMAX; e += NT) {
-    sh.T[e / RMAX][e % RMAX] = L.T[node * RMAX * RMAX + e];
-    sh.C[e % RMAX][e / RMAX] = Cin[node * RMAX * RMAX + e];  // C blocks are column-major
-  }
-  int m;
-  int64_t start = 0;
-  if (LEAF) {
-    leaf_range(L.rows, L.nodes, node, start, m);
-  } else {
-    const int64_t c0 = node * L.g;
-    m = int(min<int64_t>(L.g, L.prev_nodes - c0)) * R;
-  }
-  __syncthreads();
-  wg_form_q<RMAX, NT>(a, q, tid, m, R, sh);
-  write_q<RMAX>(q, LEAF, start, m, Qout, ldq, Cchild, node, gchild, R, tid);
-}
-
-// ------------------------------------------------------------ one-workgroup wave tree
-// For up to some thousands of rows the kernels above are bound by latency:
-// each of the R columns costs two reductions across the whole workgroup, each
-// with two workgroup barriers.  Here every node of the tree is one wavefront
-// holding at most 64 P rows (P rows per lane, row 64 p + lane in slot p), and
-// the whole tree runs inside one workgroup of a few wavefronts, level by
-// level, with a workgroup barrier only between levels.
+// ------------------------------------------------------------ wavefront nodes
+// A node holds at most 64 P rows, row 64 p + lane in slot p of the lane.
 //
 // Column j of a wavefront node costs one in-wave reduction.  With x the
 // sub-column below the diagonal (rows r > j) it returns, in one batch of R
@@ -207,7 +52,7 @@ __global__ __launch_bounds__(NT) void tsqr_down(Level L, int R, const double* Ci
 namespace wt {
 
 constexpr int W = 64;
-constexpr int MAXLEV = 16;
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 // Workspace of the tree: per level l, the reflectors V_l ([node][p][c][lane]),
 // the compact-WY factors T_l ([node][row][c]) and, for l >= 1, S_l, which
@@ -442,14 +287,14 @@ __device__ __forceinline__ double vcomp(double ac, int c, int row) {
 // b.Z on entry; returns row `lane` of C (lanes < R, else zero) in crow[].
 // Every R x R operand is zero-padded to RMAX, so the products run over fixed
 // trip counts.
-template <int RMAX, int P>
-__device__ __forceinline__ void wave_m(const double (&a)[P][RMAX], const double (&t)[RMAX],
-                                       double (&crow)[RMAX], int lane, int R, Buf<RMAX>& b) {
+template <int RMAX>
+__device__ __forceinline__ void wave_m(const double* Vl, const double (&t)[RMAX], double (&crow)[RMAX],
+                                       int lane, int R, Buf<RMAX>& b) {
   constexpr int NE = (RMAX * RMAX + W - 1) / W;
   if (lane < RMAX) {
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
-      b.X[lane][c] = (lane < R && c < R) ? vcomp(a[0][c], c, lane) : 0.0;
+      b.X[lane][c] = (lane < R && c < R) ? vcomp(Vl[c * W + lane], c, lane) : 0.0;
       b.Y[lane][c] = lane < R ? t[c] : 0.0;
     }
   }
@@ -492,18 +337,17 @@ __device__ __forceinline__ void wave_m(const double (&a)[P][RMAX], const double 
   wave_sync();
 }
 
-// Row 64 s + lane of the node's Q: [C; 0](row) - v(row) M, M in b.Z.
-template <int RMAX, int P>
-__device__ __forceinline__ void wave_q_row(const double (&a)[P][RMAX], const double (&crow)[RMAX], int s,
-                                  double (&q)[RMAX], int lane, int R, const Buf<RMAX>& b) {
+// Row 64 s + lane of the node's Q: [C; 0](row) - v(row) M, with M in b.Z
+// and the node's reflectors in Vl ([p][c][lane]).
+template <int RMAX>
+__device__ __forceinline__ void wave_q_row(const double* Vl, const double (&crow)[RMAX], int s,
+                                           double (&q)[RMAX], int lane, int R, const Buf<RMAX>& b) {
   const int row = s * W + lane;
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) q[c] = s == 0 ? crow[c] : 0.0;
-#pragma unroll 2
-  for (int k = 0; k < RMAX; ++k) {
-    double vk = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < RMAX; ++kk) vk = (kk == k && k < R) ? vcomp(a[s][kk], kk, row) : vk;
+#pragma unroll 4
+  for (int k = 0; k < R; ++k) {
+    const double vk = vcomp(Vl[(s * RMAX + k) * W + lane], k, row);
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) q[c] -= vk * b.Z[k][c];
   }
@@ -555,13 +399,13 @@ __device__ __forceinline__ void load_stack(double (&a)[P][RMAX], int lane, int m
 
 // Writes the node's Q rows: to the output (leaf) or as the children's C blocks.
 template <int RMAX, int P>
-__device__ __forceinline__ void store_q(const double (&a)[P][RMAX], const double (&crow)[RMAX], int lane, int R,
+__device__ __forceinline__ void store_q(const double* Vl, const double (&crow)[RMAX], int lane, int R,
                                int m, bool leaf, int64_t start, double* Qout, int64_t ldq, double* S,
                                int64_t c0, const Buf<RMAX>& b) {
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     double q[RMAX];
-    wave_q_row<RMAX, P>(a, crow, s, q, lane, R, b);
+    wave_q_row<RMAX>(Vl, crow, s, q, lane, R, b);
     const int r = s * W + lane;
     if (r >= m) continue;
     if (leaf) {
@@ -576,242 +420,95 @@ __device__ __forceinline__ void store_q(const double (&a)[P][RMAX], const double
   }
 }
 
-// Up-sweep: factorize every node, save its reflectors and T, pass R up; the
-// root's R is the answer.
-template <int RMAX, int P, int NW, int SRC>
-__global__ __launch_bounds__(NW * W) void wave_tree_up(int64_t rows, int R, const double* A, int64_t lda,
-                                                      KrpSrc krp, double* Rout, int64_t ldr, double* work) {
-  __shared__ Buf<RMAX> bufs[NW];
-  const int lane = threadIdx.x % W, w = threadIdx.x / W;
-  Buf<RMAX>& b = bufs[w];
+// Up-sweep, one launch per level, one node per single-wavefront workgroup:
+// factorize the node, save its reflectors and T, pass its R up (the root's R
+// is the answer).
+template <int RMAX, int P, int SRC>
+__global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, const double* A, int64_t lda,
+                                                  KrpSrc krp, double* Rout, int64_t ldr, double* work) {
+  __shared__ Buf<RMAX> b;
+  const int lane = threadIdx.x, node = blockIdx.x;
   const int g = W * P / R;
   const int top = level_count(rows, R, P) - 1;
+  const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
   double a[P][RMAX], t[RMAX];
-#pragma unroll 1
-  for (int l = 0; l <= top; ++l) {
-    const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
+  if (l == 0) {
+    int m;
+    int64_t start;
+    leaf_range(rows, L.nodes, node, start, m);
+    load_leaf<RMAX, P, SRC>(a, lane, start, m, R, A, lda, krp);
+  } else {
+    const int64_t c0 = int64_t(node) * g;
+    const int m = int(min<int64_t>(g, L.prev - c0)) * R;
+    load_stack<RMAX, P>(a, lane, m, R, work + L.s, c0);
+  }
+  wave_factor<RMAX, P>(a, t, lane, R, b);
+  double* V = work + L.v + int64_t(node) * P * RMAX * W;
+#pragma unroll
+  for (int s = 0; s < P; ++s)
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) V[(s * RMAX + c) * W + lane] = a[s][c];
+  if (lane < R) {
+    double* T = work + L.t + int64_t(node) * RMAX * RMAX;
     double* Snext = l < top ? work + level_of(rows, R, P, RMAX, l + 1, nullptr).s : nullptr;
-#pragma unroll 1
-    for (int node = w; node < L.nodes; node += NW) {
-      if (l == 0) {
-        int m;
-        int64_t start;
-        leaf_range(rows, L.nodes, node, start, m);
-        load_leaf<RMAX, P, SRC>(a, lane, start, m, R, A, lda, krp);
-      } else {
-        const int64_t c0 = int64_t(node) * g;
-        const int m = int(min<int64_t>(g, L.prev - c0)) * R;
-        load_stack<RMAX, P>(a, lane, m, R, work + L.s, c0);
-      }
-      wave_factor<RMAX, P>(a, t, lane, R, b);
-      double* V = work + L.v + int64_t(node) * P * RMAX * W;
 #pragma unroll
-      for (int s = 0; s < P; ++s)
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c) V[(s * RMAX + c) * W + lane] = a[s][c];
-      if (lane < R) {
-        double* T = work + L.t + int64_t(node) * RMAX * RMAX;
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c) {
-          T[lane * RMAX + c] = t[c];
-          const double r = c >= lane ? a[0][c] : 0.0;
-          if (l < top)
-            Snext[(int64_t(node) * RMAX + lane) * RMAX + c] = r;
-          else if (c < R)
-            Rout[lane + c * ldr] = r;
-        }
-      }
+    for (int c = 0; c < RMAX; ++c) {
+      T[lane * RMAX + c] = t[c];
+      const double r = c >= lane ? a[0][c] : 0.0;
+      if (l < top)
+        Snext[(int64_t(node) * RMAX + lane) * RMAX + c] = r;
+      else if (c < R)
+        Rout[lane + c * ldr] = r;
     }
-    __syncthreads();
   }
 }
 
-// Down-sweep: each node applies its reflectors to its C block (the identity
-// at the root) and writes its Q rows: the output, or its children's C blocks.
-template <int RMAX, int P, int NW>
-__global__ __launch_bounds__(NW * W) void wave_tree_down(int64_t rows, int R, double* Qout, int64_t ldq,
-                                                        double* work) {
-  __shared__ Buf<RMAX> bufs[NW];
-  const int lane = threadIdx.x % W, w = threadIdx.x / W;
-  Buf<RMAX>& b = bufs[w];
+// Down-sweep, one launch per level: each node applies its reflectors to its
+// C block (the identity at the root) and writes its Q rows: the output, or
+// its children's C blocks.
+template <int RMAX, int P>
+__global__ __launch_bounds__(W) void wave_tree_down(int64_t rows, int R, int l, double* Qout, int64_t ldq,
+                                                    double* work) {
+  __shared__ Buf<RMAX> b;
+  __shared__ double Vl[P * RMAX * W];
+  const int lane = threadIdx.x, node = blockIdx.x;
   const int g = W * P / R;
   const int top = level_count(rows, R, P) - 1;
-  double a[P][RMAX], t[RMAX], crow[RMAX];
-#pragma unroll 1
-  for (int l = top; l >= 0; --l) {
-    const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
-    const double* Cin = l < top ? work + level_of(rows, R, P, RMAX, l + 1, nullptr).s : nullptr;
-#pragma unroll 1
-    for (int node = w; node < L.nodes; node += NW) {
-      const double* V = work + L.v + int64_t(node) * P * RMAX * W;
-      const double* T = work + L.t + int64_t(node) * RMAX * RMAX;
+  const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
+  const double* Cin = l < top ? work + level_of(rows, R, P, RMAX, l + 1, nullptr).s : nullptr;
+  double t[RMAX], crow[RMAX];
+  const double* V = work + L.v + int64_t(node) * P * RMAX * W;
+  const double* T = work + L.t + int64_t(node) * RMAX * RMAX;
+  for (int e = lane; e < P * RMAX * W; e += W) Vl[e] = V[e];
 #pragma unroll
-      for (int s = 0; s < P; ++s)
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c) a[s][c] = V[(s * RMAX + c) * W + lane];
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) t[c] = lane < R ? T[lane * RMAX + c] : 0.0;
-      for (int e = lane; e < RMAX * RMAX; e += W) {
-        const int i = e / RMAX, c = e % RMAX;
-        b.Z[i][c] = (i >= R || c >= R) ? 0.0
-                    : (l < top ? Cin[int64_t(node) * RMAX * RMAX + e] : (i == c ? 1.0 : 0.0));
-      }
-      wave_sync();
-      wave_m<RMAX, P>(a, t, crow, lane, R, b);
-      int m;
-      int64_t start = 0, c0 = 0;
-      if (l == 0) {
-        leaf_range(rows, L.nodes, node, start, m);
-      } else {
-        c0 = int64_t(node) * g;
-        m = int(min<int64_t>(g, L.prev - c0)) * R;
-      }
-      store_q<RMAX, P>(a, crow, lane, R, m, l == 0, start, Qout, ldq, work + L.s, c0, b);
-    }
-    __syncthreads();
+  for (int c = 0; c < RMAX; ++c) t[c] = lane < R ? T[lane * RMAX + c] : 0.0;
+  for (int e = lane; e < RMAX * RMAX; e += W) {
+    const int i = e / RMAX, c = e % RMAX;
+    b.Z[i][c] = (i >= R || c >= R) ? 0.0
+                : (l < top ? Cin[int64_t(node) * RMAX * RMAX + e] : (i == c ? 1.0 : 0.0));
   }
+  wave_sync();
+  wave_m<RMAX>(Vl, t, crow, lane, R, b);
+  int m;
+  int64_t start = 0, c0 = 0;
+  if (l == 0) {
+    leaf_range(rows, L.nodes, node, start, m);
+  } else {
+    c0 = int64_t(node) * g;
+    m = int(min<int64_t>(g, L.prev - c0)) * R;
+  }
+  store_q<RMAX, P>(Vl, crow, lane, R, m, l == 0, start, Qout, ldq, work + L.s, c0, b);
 }
 
 }  // namespace wt
 
 // ------------------------------------------------------------ host side
-constexpr int ntmax_for(int RM) { return RM <= 16 ? 1024 : 512; }
-
-int pick_nt(int64_t rows, int RM) {
-  if (rows <= 64) return 64;
-  if (rows <= 256) return 256;
-  return ntmax_for(RM);
-}
-
-struct Tree {
-  int nlev = 0;
-  Level lev[40];
-};
-
-Tree make_tree(int64_t rows, int R, int RM) {
-  Tree t;
-  const int ntm = ntmax_for(RM);
-  Level L{};
-  L.nodes = rows <= ntm ? 1 : ceil_div(rows, ntm);
-  L.rows = rows;
-  L.nt = L.nodes == 1 ? pick_nt(rows, RM) : ntm;
-  t.lev[t.nlev++] = L;
-  while (t.lev[t.nlev - 1].nodes > 1) {
-    const int64_t prev = t.lev[t.nlev - 1].nodes;
-    Level U{};
-    U.g = ntm / R;
-    U.prev_nodes = prev;
-    U.nodes = ceil_div(prev, U.g);
-    const int64_t rows_here = std::min<int64_t>(U.g, prev) * R;
-    U.nt = U.nodes == 1 ? pick_nt(rows_here, RM) : ntm;
-    t.lev[t.nlev++] = U;
-  }
-  return t;
-}
-
-size_t carve_tree(Carver& cv, Tree& t, int RM) {
-  for (int l = 0; l < t.nlev; ++l) {
-    Level& L = t.lev[l];
-    L.V = cv.take<double>(size_t(L.nodes) * RM * L.nt);
-    L.T = cv.take<double>(size_t(L.nodes) * RM * RM);
-    if (l > 0) L.Rin = cv.take<double>(size_t(L.prev_nodes) * RM * RM);
-  }
-  return cv.bytes();
-}
-
-template <int RMAX, int NT>
-int launch_up(int src, const Level& L, int R, const double* A, int64_t lda, const KrpSrc& krp,
-              double* Rnext, double* Rout, int64_t ldr_out, double* Q, int64_t ldq, double* Cchild,
-              int gchild, hipStream_t s) {
-  const dim3 grd(unsigned(L.nodes)), blk(NT);
-  if (src == SRC_MATRIX)
-    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_MATRIX>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
-                       ldr_out, Q, ldq, Cchild, gchild);
-  else if (src == SRC_KRP)
-    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_KRP>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
-                       ldr_out, Q, ldq, Cchild, gchild);
-  else
-    hipLaunchKernelGGL((tsqr_up<RMAX, NT, SRC_STACK>), grd, blk, 0, s, L, R, A, lda, krp, Rnext, Rout,
-                       ldr_out, Q, ldq, Cchild, gchild);
-  return check_launch("tsqr_up");
-}
-
-template <int RMAX, int NT>
-int launch_down(bool leaf, const Level& L, int R, const double* Cin, double* Q, int64_t ldq,
-                double* Cchild, int gchild, hipStream_t s) {
-  const dim3 grd(unsigned(L.nodes)), blk(NT);
-  if (leaf)
-    hipLaunchKernelGGL((tsqr_down<RMAX, NT, true>), grd, blk, 0, s, L, R, Cin, Q, ldq, Cchild, gchild);
-  else
-    hipLaunchKernelGGL((tsqr_down<RMAX, NT, false>), grd, blk, 0, s, L, R, Cin, Q, ldq, Cchild, gchild);
-  return check_launch("tsqr_down");
-}
-
-template <int RMAX>
-int dispatch_up(int nt, int src, const Level& L, int R, const double* A, int64_t lda,
-                const KrpSrc& krp, double* Rnext, double* Rout, int64_t ldr_out, double* Q,
-                int64_t ldq, double* Cchild, int gchild, hipStream_t s) {
-  constexpr int NTM = ntmax_for(RMAX);
-  if (nt == 64)
-    return launch_up<RMAX, 64>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
-  if (nt == 256)
-    return launch_up<RMAX, 256>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
-  return launch_up<RMAX, NTM>(src, L, R, A, lda, krp, Rnext, Rout, ldr_out, Q, ldq, Cchild, gchild, s);
-}
-
-template <int RMAX>
-int dispatch_down(int nt, bool leaf, const Level& L, int R, const double* Cin, double* Q,
-                  int64_t ldq, double* Cchild, int gchild, hipStream_t s) {
-  constexpr int NTM = ntmax_for(RMAX);
-  if (nt == 64) return launch_down<RMAX, 64>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
-  if (nt == 256) return launch_down<RMAX, 256>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
-  return launch_down<RMAX, NTM>(leaf, L, R, Cin, Q, ldq, Cchild, gchild, s);
-}
-
-template <int RMAX>
-int tsqr_run(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
-             double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
-  Tree t = make_tree(rows, R, RMAX);
-  Carver cv(work);
-  carve_tree(cv, t, RMAX);
-  for (int l = 0; l < t.nlev; ++l) {
-    const Level& L = t.lev[l];
-    double* Rnext = (l + 1 < t.nlev) ? t.lev[l + 1].Rin : nullptr;
-    double* Cchild = l > 0 ? L.Rin : nullptr;
-    const int gchild = l > 0 ? L.g : 0;
-    CPQR_TRY(dispatch_up<RMAX>(L.nt, l == 0 ? src : SRC_STACK, L, R, A, lda, krp, Rnext, Rout,
-                               ldr_out, Q, ldq, Cchild, gchild, s));
-  }
-  for (int l = t.nlev - 2; l >= 0; --l) {
-    const Level& L = t.lev[l];
-    const double* Cin = t.lev[l + 1].Rin;
-    CPQR_TRY(dispatch_down<RMAX>(L.nt, l == 0, L, R, Cin, Q, ldq, l > 0 ? L.Rin : nullptr,
-                                 l > 0 ? L.g : 0, s));
-  }
-  return CPQR_OK;
-}
-
-// One-workgroup wave tree: rows per lane P and wavefronts per workgroup NW
-// for a problem, or P = 0 where the multi-workgroup tree is faster (measured
-// on MI355X: the wave tree wins up to about 2k rows at R <= 16, up to about
-// 6k rows at R <= 8, and only for a single node at R > 16).
-struct WtShape {
-  int P, NW;
-};
-WtShape wt_shape(int64_t rows, int R) {
-  switch (round_rank(R)) {
-    case 8:
-      if (rows <= 128) return {2, 8};
-      if (rows <= 256) return {4, 8};
-      if (rows <= 1024) return {2, 8};
-      return rows <= 6144 ? WtShape{4, 8} : WtShape{0, 0};
-    case 16:
-      if (rows <= 128) return {2, 4};
-      if (rows <= 256) return {4, 4};
-      return rows <= 2048 ? WtShape{2, 8} : WtShape{0, 0};
-    default:
-      return rows <= 64 ? WtShape{1, 4} : WtShape{0, 0};
-  }
+// Rows per lane: 1 at R > 16 (registers); otherwise 2 or 4, whichever gives
+// fewer levels, 2 on a tie (measured on MI355X: fewer, fatter levels win,
+// and at equal depth the lighter nodes do).
+int wt_rows_per_lane(int64_t rows, int R) {
+  if (round_rank(R) > 16) return 1;
+  return wt::level_count(rows, R, 4) < wt::level_count(rows, R, 2) ? 4 : 2;
 }
 
 size_t wt_work(int64_t rows, int R, int P) {
@@ -820,54 +517,51 @@ size_t wt_work(int64_t rows, int R, int P) {
   return total * sizeof(double);
 }
 
-template <int RMAX, int P, int NW>
+template <int RMAX, int P>
 int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
               int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
   double* w = static_cast<double*>(work);
-  const dim3 grd(1), blk(NW * wt::W);
-  if (src == SRC_MATRIX)
-    hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, NW, SRC_MATRIX>), grd, blk, 0, s, rows, R, A, lda, krp,
-                       Rout, ldr_out, w);
-  else
-    hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, NW, SRC_KRP>), grd, blk, 0, s, rows, R, A, lda, krp,
-                       Rout, ldr_out, w);
-  CPQR_TRY(check_launch("wave_tree_up"));
-  hipLaunchKernelGGL((wt::wave_tree_down<RMAX, P, NW>), grd, blk, 0, s, rows, R, Q, ldq, w);
-  return check_launch("wave_tree_down");
+  const int nlev = wt::level_count(rows, R, P);
+  for (int l = 0; l < nlev; ++l) {
+    const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
+    if (src == SRC_MATRIX)
+      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_MATRIX>), grd, blk, 0, s, rows, R, l, A, lda, krp,
+                         Rout, ldr_out, w);
+    else
+      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_KRP>), grd, blk, 0, s, rows, R, l, A, lda, krp,
+                         Rout, ldr_out, w);
+    CPQR_TRY(check_launch("wave_tree_up"));
+  }
+  for (int l = nlev - 1; l >= 0; --l) {
+    const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
+    hipLaunchKernelGGL((wt::wave_tree_down<RMAX, P>), grd, blk, 0, s, rows, R, l, Q, ldq, w);
+    CPQR_TRY(check_launch("wave_tree_down"));
+  }
+  return CPQR_OK;
 }
 
-int wt_run(const WtShape& sh, int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
-           double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
-  const int RM = round_rank(R);
-  if (RM == 8 && sh.P == 2) return wt_launch<8, 2, 8>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  if (RM == 8) return wt_launch<8, 4, 8>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  if (RM == 16 && sh.NW == 8) return wt_launch<16, 2, 8>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  if (RM == 16 && sh.P == 2) return wt_launch<16, 2, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  if (RM == 16) return wt_launch<16, 4, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  return wt_launch<32, 1, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+int wt_run(int P, int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
+           int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
+  switch (round_rank(R)) {
+    case 8:
+      return P == 2 ? wt_launch<8, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s)
+                    : wt_launch<8, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+    case 16:
+      return P == 2 ? wt_launch<16, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s)
+                    : wt_launch<16, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+    default:
+      return wt_launch<32, 1>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+  }
 }
 
 int tsqr_dispatch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
                   double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
-  const WtShape sh = wt_shape(rows, R);
-  if (sh.P > 0) return wt_run(sh, src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  switch (round_rank(R)) {
-    case 8: return tsqr_run<8>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-    case 16: return tsqr_run<16>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-    default: return tsqr_run<32>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
-  }
+  return wt_run(wt_rows_per_lane(rows, R), src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
 }
 
 }  // namespace
 
-size_t tsqr_work(int64_t rows, int R) {
-  const int RM = round_rank(R);
-  Carver cv(nullptr);
-  const WtShape sh = wt_shape(rows, R);
-  if (sh.P > 0) return wt_work(rows, R, sh.P);
-  Tree t = make_tree(rows, R, RM);
-  return carve_tree(cv, t, RM);
-}
+size_t tsqr_work(int64_t rows, int R) { return wt_work(rows, R, wt_rows_per_lane(rows, R)); }
 
 int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
                       double* Rk, int64_t ldr, void* work, hipStream_t s) {

@@ -33,7 +33,8 @@ def rng(seed):
 
 @pytest.mark.parametrize("I,R", [(50, 5), (64, 16), (65, 16), (1000, 16), (200, 32), (256, 10), (130, 3),
                                  (5000, 7), (100, 1), (2000, 32), (32, 32), (4097, 12), (129, 16), (257, 16),
-                                 (2048, 16), (6000, 8), (1024, 8), (64, 32), (65, 32)])
+                                 (2048, 16), (6000, 8), (1024, 8), (64, 32), (65, 32), (20000, 16),
+                                 (100000, 3)])
 def test_factor_qr(I, R):
     A = rng(I * 100 + R).standard_normal((I, R))
     Q, Rk = C.cpqr_factor_qr(to_dev(A))
@@ -62,7 +63,8 @@ def test_factor_qr_rank_deficient():
 
 # ------------------------------------------------------------------ KRP QR
 
-@pytest.mark.parametrize("N,R", [(3, 5), (3, 16), (4, 7), (2, 8), (5, 3), (3, 1), (4, 32), (3, 32), (6, 4)])
+@pytest.mark.parametrize("N,R", [(3, 5), (3, 16), (4, 7), (2, 8), (5, 3), (3, 1), (4, 32), (3, 32), (6, 4),
+                                 (5, 12)])
 def test_krp_qr(N, R):
     g = rng(N * 1000 + R)
     Rs = [OQ.factor_qr(g.standard_normal((R + 3, R)))[1] for _ in range(N)]
