@@ -468,8 +468,14 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
     }
     double* out = relerr ? relerr + sw : w.relerr_tmp;
     if (p->error_mode == CPQR_ERROR_EFFICIENT) {
+      // on the side stream, overlapping the next sweep's first Multi-TTM: the
+      // next Khatri-Rao QR (which rewrites R_0) queues behind it there, and the
+      // caller's stream waits for that QR before it rewrites W and lambda
+      CPQR_HIP(hipEventRecord(side.ready, s));
+      CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       CPQR_TRY(error_efficient_enqueue(p->I[N - 1], R, w.W, p->A[N - 1], p->lambda, w.R0, p->Rf[N - 1],
-                                       w.xnorm2, out, s));
+                                       w.xnorm2, out, side.s));
+      CPQR_HIP(hipEventRecord(side.done, side.s));
     } else if (p->error_mode == CPQR_ERROR_DIRECT) {
       const double* Ap[CPQR_MAX_MODES];
       for (int k = 0; k < N; ++k) Ap[k] = p->A[k];
@@ -479,6 +485,9 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       CPQR_TRY(fill_enqueue(out, 1, std::nan(""), s));
     }
   }
+  // everything this call queued on the side stream completes before later
+  // work on the caller's stream
+  if (nsweeps > 0) CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
   return CPQR_OK;
 }
 

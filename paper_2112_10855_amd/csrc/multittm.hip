@@ -642,6 +642,7 @@ struct Step {
   int splits;
   int64_t kchunk;
   int64_t out_count;  // P * R * S
+  int mg;             // row-tiled matrix-core kernels: 64 * mg rows per wavefront
 };
 
 struct Plan {
@@ -703,7 +704,14 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
     const bool vec_ok = t > 0 || x_aligned;
     if (uses_mfma(prec) && vec_ok && s.P % 4 == 0) {
       s.kind = K_MFMA_M;
-      units = ceil_div(s.P * s.S, 64 * 4);
+      // wide row tiles; a step whose rows leave the GPU under-filled takes
+      // 64-row tiles before it splits K (small operands: no streaming hints)
+      s.mg = prec == CPQR_PREC_F32 ? 4 : 2;
+      units = ceil_div(s.P * s.S, 64 * s.mg);
+      if (units < MIN_WAVES) {
+        s.mg = 1;
+        units = ceil_div(s.P * s.S, 64);
+      }
     } else if (uses_mfma(prec) && vec_ok && s.P == 1 && s.K % 4 == 0) {
       s.kind = K_MFMA_K;
       units = ceil_div(s.S, 16);
@@ -714,8 +722,11 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
     // Split K only when the rows alone leave the GPU under-filled.
     const int64_t quantum = 16;
     int64_t splits = 1;
+    // (K splits write P R S partial sums each; at most K / (4 R) of them keeps
+    // that traffic under a quarter of the input's)
     if (units < MIN_WAVES)
-      splits = std::min<int64_t>(ceil_div(TARGET_WAVES, units), std::max<int64_t>(1, s.K / quantum));
+      splits = std::min<int64_t>({ceil_div(TARGET_WAVES, units), std::max<int64_t>(1, s.K / quantum),
+                                  std::max<int64_t>(1, s.K / (4 * R))});
     splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
     s.kchunk = ceil_div(ceil_div(s.K, splits), quantum) * quantum;
     s.splits = int(ceil_div(s.K, s.kchunk));
@@ -790,13 +801,22 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
   constexpr int NWV = 8;
   const size_t lds = LDS_FLOATS * sizeof(float);
   if (s.kind == K_MFMA_M) {
-    constexpr int MG = 2;
-    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
+    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
+    if (s.mg == 1) {
+      if (NB == 1)
+        launch_ev(ke, ttm_bf16_m<SPLIT, 1, 1, NWV, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+      else
+        launch_ev(ke, ttm_bf16_m<SPLIT, 2, 1, NWV, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+      return check_launch("ttm_bf16_m");
+    }
+    if (s.mg != 2) return fail(CPQR_ERR_UNSUPPORTED, "ttm_bf16_m: unsupported row tile");
     if (NB == 1)
-      launch_ev(ke, ttm_bf16_m<SPLIT, 1, MG, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+      launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     else
-      launch_ev(ke, ttm_bf16_m<SPLIT, 2, MG, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+      launch_ev(ke, ttm_bf16_m<SPLIT, 2, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     return check_launch("ttm_bf16_m");
   }
@@ -819,8 +839,24 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
   const size_t lds = LDS_FLOATS * sizeof(float);
   if (s.kind == K_MFMA_M) {
     constexpr int UN = 2, MG = 4;
-    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * MG), NWV)), unsigned(s.splits));
+    const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
     const bool one = s.kchunk <= (LDS_FLOATS / RP) / (4 * UN) * (4 * UN);  // K range fits in LDS
+    if (s.mg == 1) {
+      if (NB == 1 && one)
+        launch_ev(ke, ttm_mfma_m<1, UN, 1, NWV, false, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      else if (NB == 1)
+        launch_ev(ke, ttm_mfma_m<1, UN, 1, NWV, false, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      else if (one)
+        launch_ev(ke, ttm_mfma_m<2, UN, 1, NWV, false, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      else
+        launch_ev(ke, ttm_mfma_m<2, UN, 1, NWV, false, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      return check_launch("ttm_mfma_m");
+    }
+    if (s.mg != MG) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m: unsupported row tile");
     if (NB == 1 && one)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);

@@ -98,8 +98,6 @@ __host__ __device__ __forceinline__ int level_count(int64_t rows, int R, int P) 
 
 template <int RMAX>
 struct Buf {
-  double row[RMAX];           // row J of the node, broadcast during column J
-  double sum[RMAX];           // the column's reduction results s_c
   double X[RMAX][RMAX + 1];
   double Y[RMAX][RMAX + 1];
   double Z[RMAX][RMAX];
@@ -196,17 +194,12 @@ __device__ __forceinline__ double wave_sum(double (&x)[V], int lane) {
 }
 
 // Column J of the wavefront Householder QR (J < R).  A template per column
-// keeps every register-array index a compile-time constant.  alpha and s_J
-// are read from their lanes directly; the other entries of row J and the
-// other sums reach every lane through LDS while the reflector is formed.
+// keeps every register-array index a compile-time constant.  Row J and the
+// sums are read from the lanes that hold them (readlane), so they arrive in
+// scalar registers that every lane reads.
 template <int J, int RMAX, int P>
-__device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R,
-                                            Buf<RMAX>& b) {
+__device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
   constexpr int SH = 6 - ilog2(RMAX);
-  if (lane == J) {
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) b.row[c] = a[0][c];
-  }
   double x[P], p[RMAX];
 #pragma unroll
   for (int s = 0; s < P; ++s) x[s] = (s > 0 || lane > J) ? a[s][J] : 0.0;
@@ -218,9 +211,7 @@ __device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RM
     p[c] = acc;
   }
   const double red = wave_sum<RMAX>(p, lane);
-  if ((lane & ((1 << SH) - 1)) == 0) b.sum[lane >> SH] = red;
   const double alpha = rdlane(a[0][J], J), sub2 = rdlane(red, J << SH);
-  wave_sync();
   double tau = 0.0, beta = alpha, scal = 0.0;
   if (sub2 > 0.0) {
     const double nrm = sqrt(alpha * alpha + sub2);
@@ -234,13 +225,13 @@ __device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RM
   // T(0:J, J) = -tau T(0:J, 0:J) G(0:J, J), G(k, J) = v_k^T v_J = v_k(J) + scal s_k
   double tg = 0.0;
 #pragma unroll
-  for (int k = 0; k < J; ++k) tg += t[k] * (b.row[k] + scal * b.sum[k]);
+  for (int k = 0; k < J; ++k) tg += t[k] * (rdlane(a[0][k], J) + scal * rdlane(red, k << SH));
   t[J] = lane < J ? -tau * tg : (lane == J ? tau : 0.0);
   // trailing columns: A(:, c) -= tau v (v^T A(:, c)), v^T A(:, c) = A(J, c) + scal s_c
 #pragma unroll
   for (int c = J + 1; c < RMAX; ++c) {
     if (c < R) {
-      const double tw = tau * (b.row[c] + scal * b.sum[c]);
+      const double tw = tau * (rdlane(a[0][c], J) + scal * rdlane(red, c << SH));
 #pragma unroll
       for (int s = 0; s < P; ++s) a[s][c] -= tw * v[s];
     }
@@ -248,21 +239,19 @@ __device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RM
   a[0][J] = lane == J ? beta : (lane > J ? v[0] : a[0][J]);
 #pragma unroll
   for (int s = 1; s < P; ++s) a[s][J] = v[s];
-  wave_sync();
 }
 
 template <int J, int RMAX, int P>
 struct WaveColumns {
-  static __device__ __forceinline__ void run(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R,
-                                             Buf<RMAX>& b) {
+  static __device__ __forceinline__ void run(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
     if (J >= R) return;
-    wave_column<J, RMAX, P>(a, t, lane, R, b);
-    WaveColumns<J + 1, RMAX, P>::run(a, t, lane, R, b);
+    wave_column<J, RMAX, P>(a, t, lane, R);
+    WaveColumns<J + 1, RMAX, P>::run(a, t, lane, R);
   }
 };
 template <int RMAX, int P>
 struct WaveColumns<RMAX, RMAX, P> {
-  static __device__ __forceinline__ void run(double (&)[P][RMAX], double (&)[RMAX], int, int, Buf<RMAX>&) {}
+  static __device__ __forceinline__ void run(double (&)[P][RMAX], double (&)[RMAX], int, int) {}
 };
 
 // Householder QR of the node block (row 64 p + lane in a[p][.]; rows beyond
@@ -271,11 +260,10 @@ struct WaveColumns<RMAX, RMAX, P> {
 // reflector c's components (v_c(c) = 1 implicitly), and t[] holds row `lane`
 // of T (lanes < R).
 template <int RMAX, int P>
-__device__ __forceinline__ void wave_factor(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R,
-                                            Buf<RMAX>& b) {
+__device__ __forceinline__ void wave_factor(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) t[c] = 0.0;
-  WaveColumns<0, RMAX, P>::run(a, t, lane, R, b);
+  WaveColumns<0, RMAX, P>::run(a, t, lane, R);
 }
 
 // Component of reflector c in row `row` of the node (from a[slot][c]).
@@ -420,16 +408,14 @@ __device__ __forceinline__ void store_q(const double* Vl, const double (&crow)[R
   }
 }
 
-// Up-sweep, one launch per level, one node per single-wavefront workgroup:
-// factorize the node, save its reflectors and T, pass its R up (the root's R
-// is the answer).
+// Up-sweep below the root, one launch per level, one node per
+// single-wavefront workgroup: factorize the node, save its reflectors and T,
+// pass its R up.
 template <int RMAX, int P, int SRC>
 __global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, const double* A, int64_t lda,
-                                                  KrpSrc krp, double* Rout, int64_t ldr, double* work) {
-  __shared__ Buf<RMAX> b;
+                                                  KrpSrc krp, double* work) {
   const int lane = threadIdx.x, node = blockIdx.x;
   const int g = W * P / R;
-  const int top = level_count(rows, R, P) - 1;
   const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
   double a[P][RMAX], t[RMAX];
   if (l == 0) {
@@ -442,7 +428,7 @@ __global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, co
     const int m = int(min<int64_t>(g, L.prev - c0)) * R;
     load_stack<RMAX, P>(a, lane, m, R, work + L.s, c0);
   }
-  wave_factor<RMAX, P>(a, t, lane, R, b);
+  wave_factor<RMAX, P>(a, t, lane, R);
   double* V = work + L.v + int64_t(node) * P * RMAX * W;
 #pragma unroll
   for (int s = 0; s < P; ++s)
@@ -450,22 +436,62 @@ __global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, co
     for (int c = 0; c < RMAX; ++c) V[(s * RMAX + c) * W + lane] = a[s][c];
   if (lane < R) {
     double* T = work + L.t + int64_t(node) * RMAX * RMAX;
-    double* Snext = l < top ? work + level_of(rows, R, P, RMAX, l + 1, nullptr).s : nullptr;
+    double* Snext = work + level_of(rows, R, P, RMAX, l + 1, nullptr).s;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       T[lane * RMAX + c] = t[c];
-      const double r = c >= lane ? a[0][c] : 0.0;
-      if (l < top)
-        Snext[(int64_t(node) * RMAX + lane) * RMAX + c] = r;
-      else if (c < R)
-        Rout[lane + c * ldr] = r;
+      Snext[(int64_t(node) * RMAX + lane) * RMAX + c] = c >= lane ? a[0][c] : 0.0;
     }
   }
 }
 
-// Down-sweep, one launch per level: each node applies its reflectors to its
-// C block (the identity at the root) and writes its Q rows: the output, or
-// its children's C blocks.
+// The root (one workgroup): factorize, write R, and form the root's Q from
+// C = I straight away: the output itself when the root is the only leaf,
+// else the C blocks of its children.
+template <int RMAX, int P, int SRC>
+__global__ __launch_bounds__(W) void wave_tree_root(int64_t rows, int R, const double* A, int64_t lda,
+                                                    KrpSrc krp, double* Qout, int64_t ldq, double* Rout,
+                                                    int64_t ldr, double* work) {
+  __shared__ Buf<RMAX> b;
+  __shared__ double Vl[P * RMAX * W];
+  const int lane = threadIdx.x;
+  const int top = level_count(rows, R, P) - 1;
+  const NodeLevel L = level_of(rows, R, P, RMAX, top, nullptr);
+  double t[RMAX], crow[RMAX];
+  int m;
+  int64_t start = 0;
+  {
+    double a[P][RMAX];
+    if (top == 0) {
+      leaf_range(rows, 1, 0, start, m);
+      load_leaf<RMAX, P, SRC>(a, lane, start, m, R, A, lda, krp);
+    } else {
+      m = L.prev * R;
+      load_stack<RMAX, P>(a, lane, m, R, work + L.s, 0);
+    }
+    wave_factor<RMAX, P>(a, t, lane, R);
+    if (lane < R) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c)
+        if (c < R) Rout[lane + c * ldr] = c >= lane ? a[0][c] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) Vl[(s * RMAX + c) * W + lane] = a[s][c];
+  }
+  for (int e = lane; e < RMAX * RMAX; e += W) {
+    const int i = e / RMAX, c = e % RMAX;
+    b.Z[i][c] = (i < R && i == c) ? 1.0 : 0.0;
+  }
+  wave_sync();
+  wave_m<RMAX>(Vl, t, crow, lane, R, b);
+  store_q<RMAX, P>(Vl, crow, lane, R, m, top == 0, start, Qout, ldq, work + L.s, 0, b);
+}
+
+// Down-sweep below the root, one launch per level: each node applies its
+// reflectors to its C block and writes its Q rows: the output, or its
+// children's C blocks.
 template <int RMAX, int P>
 __global__ __launch_bounds__(W) void wave_tree_down(int64_t rows, int R, int l, double* Qout, int64_t ldq,
                                                     double* work) {
@@ -473,19 +499,18 @@ __global__ __launch_bounds__(W) void wave_tree_down(int64_t rows, int R, int l, 
   __shared__ double Vl[P * RMAX * W];
   const int lane = threadIdx.x, node = blockIdx.x;
   const int g = W * P / R;
-  const int top = level_count(rows, R, P) - 1;
   const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
-  const double* Cin = l < top ? work + level_of(rows, R, P, RMAX, l + 1, nullptr).s : nullptr;
+  const double* Cin = work + level_of(rows, R, P, RMAX, l + 1, nullptr).s;
   double t[RMAX], crow[RMAX];
   const double* V = work + L.v + int64_t(node) * P * RMAX * W;
   const double* T = work + L.t + int64_t(node) * RMAX * RMAX;
+#pragma unroll 8
   for (int e = lane; e < P * RMAX * W; e += W) Vl[e] = V[e];
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) t[c] = lane < R ? T[lane * RMAX + c] : 0.0;
   for (int e = lane; e < RMAX * RMAX; e += W) {
     const int i = e / RMAX, c = e % RMAX;
-    b.Z[i][c] = (i >= R || c >= R) ? 0.0
-                : (l < top ? Cin[int64_t(node) * RMAX * RMAX + e] : (i == c ? 1.0 : 0.0));
+    b.Z[i][c] = (i >= R || c >= R) ? 0.0 : Cin[int64_t(node) * RMAX * RMAX + e];
   }
   wave_sync();
   wave_m<RMAX>(Vl, t, crow, lane, R, b);
@@ -522,17 +547,22 @@ int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const 
               int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
   double* w = static_cast<double*>(work);
   const int nlev = wt::level_count(rows, R, P);
-  for (int l = 0; l < nlev; ++l) {
+  for (int l = 0; l + 1 < nlev; ++l) {
     const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
     if (src == SRC_MATRIX)
-      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_MATRIX>), grd, blk, 0, s, rows, R, l, A, lda, krp,
-                         Rout, ldr_out, w);
+      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_MATRIX>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
     else
-      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_KRP>), grd, blk, 0, s, rows, R, l, A, lda, krp,
-                         Rout, ldr_out, w);
+      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_KRP>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
     CPQR_TRY(check_launch("wave_tree_up"));
   }
-  for (int l = nlev - 1; l >= 0; --l) {
+  if (src == SRC_MATRIX)
+    hipLaunchKernelGGL((wt::wave_tree_root<RMAX, P, SRC_MATRIX>), dim3(1), dim3(wt::W), 0, s, rows, R, A, lda,
+                       krp, Q, ldq, Rout, ldr_out, w);
+  else
+    hipLaunchKernelGGL((wt::wave_tree_root<RMAX, P, SRC_KRP>), dim3(1), dim3(wt::W), 0, s, rows, R, A, lda,
+                       krp, Q, ldq, Rout, ldr_out, w);
+  CPQR_TRY(check_launch("wave_tree_root"));
+  for (int l = nlev - 2; l >= 0; --l) {
     const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
     hipLaunchKernelGGL((wt::wave_tree_down<RMAX, P>), grd, blk, 0, s, rows, R, l, Q, ldq, w);
     CPQR_TRY(check_launch("wave_tree_down"));
