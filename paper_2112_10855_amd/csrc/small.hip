@@ -30,39 +30,35 @@ __device__ inline T block_sum(T v, T* sh) {
 
 // ------------------------------------------------------------ apply Q_0
 // part[split][i + c*In] = sum over this split's rho of Y[i + rho*In] Q0[rho + c*K]
+// One thread per (row i, column c): a block covers 256 / RM rows, so that
+// even a few thousand rows spread over a few hundred workgroups.
 template <class TY, int RM>
 __global__ __launch_bounds__(BLK) void apply_q0_kernel(const TY* __restrict__ Y,
                                                        const double* __restrict__ Q0, double* part,
                                                        int64_t In, int64_t K, int R, int64_t kchunk) {
-  __shared__ double q0s[64][RM];
-  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  constexpr int RPB = BLK / RM;
+  __shared__ double q0s[64][RM + 1];
+  const int c = threadIdx.x % RM, ri = threadIdx.x / RM;
+  const int64_t i = int64_t(blockIdx.x) * RPB + ri;
   const int64_t k0 = int64_t(blockIdx.y) * kchunk;
   const int64_t k1 = min(K, k0 + kchunk);
-  double acc[RM];
-#pragma unroll
-  for (int c = 0; c < RM; ++c) acc[c] = 0.0;
+  const bool live = i < In && c < R;
+  double acc = 0.0;
   for (int64_t t0 = k0; t0 < k1; t0 += 64) {
     const int nt = int(min<int64_t>(64, k1 - t0));
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * RM; e += BLK) {
-      const int rr = e % 64, c = e / 64;
-      q0s[rr][c] = (rr < nt && c < R) ? Q0[t0 + rr + int64_t(c) * K] : 0.0;
+      const int rr = e % 64, cc = e / 64;
+      q0s[rr][cc] = (rr < nt && cc < R) ? Q0[t0 + rr + int64_t(cc) * K] : 0.0;
     }
     __syncthreads();
-    if (i < In) {
-      for (int rr = 0; rr < nt; ++rr) {
-        const double y = double(Y[i + (t0 + rr) * In]);
-#pragma unroll
-        for (int c = 0; c < RM; ++c) acc[c] += y * q0s[rr][c];
-      }
+    if (live) {
+      const TY* y = Y + i + t0 * In;
+#pragma unroll 8
+      for (int rr = 0; rr < nt; ++rr) acc += double(y[rr * In]) * q0s[rr][c];
     }
   }
-  if (i < In) {
-    double* o = part + int64_t(blockIdx.y) * In * R;
-#pragma unroll
-    for (int c = 0; c < RM; ++c)
-      if (c < R) o[i + c * In] = acc[c];
-  }
+  if (live) part[int64_t(blockIdx.y) * In * R + i + int64_t(c) * In] = acc;
 }
 
 __global__ void sum_parts(const double* __restrict__ part, int splits, int64_t count, double* dst) {
@@ -384,8 +380,8 @@ __global__ __launch_bounds__(BLK) void fit_direct_kernel(const TX* __restrict__ 
   }
 }
 
-int64_t apply_splits(int64_t In, int64_t K) {
-  const int64_t rb = ceil_div(In, BLK);
+int64_t apply_splits(int64_t In, int64_t K, int R) {
+  const int64_t rb = ceil_div(In, BLK / round_rank(R));
   int64_t sp = std::max<int64_t>(1, std::min<int64_t>(ceil_div(1024, rb), ceil_div(K, 64)));
   return std::min<int64_t>(sp, 512);
 }
@@ -396,20 +392,20 @@ constexpr int NORM_BLOCKS = 2048;
 
 size_t apply_q0_work(int64_t In, int64_t K, int R) {
   Carver cv(nullptr);
-  cv.take<double>(size_t(apply_splits(In, K)) * In * R);
+  cv.take<double>(size_t(apply_splits(In, K, R)) * In * R);
   return cv.bytes();
 }
 
 int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                      double* W, void* work, hipStream_t s) {
   PhaseTimer pt(PH_APPLY_Q0, s);
-  const int64_t sp = apply_splits(In, K);
+  const int64_t sp = apply_splits(In, K, R);
   const int64_t kchunk = ceil_div(ceil_div(K, sp), 64) * 64;
   const int64_t splits = ceil_div(K, kchunk);
   Carver cv(work);
   double* part = cv.take<double>(size_t(sp) * In * R);
-  const dim3 grd(unsigned(ceil_div(In, BLK)), unsigned(splits));
   const int RM = round_rank(R);
+  const dim3 grd(unsigned(ceil_div(In, BLK / RM)), unsigned(splits));
 #define APPLY(TY, RMV)                                                                             \
   hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, \
                      splits > 1 ? part : W, In, K, R, kchunk)
