@@ -437,11 +437,13 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   SideStream side;
   CPQR_TRY(side_stream(side));
   const int h = dt_split(p);
+  bool r_marked = false;  // side.ready marks the last factor QR's R
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
       // Khatri-Rao QR (reads R_k) on the side stream, Multi-TTM (reads Q_k)
-      // on the caller's stream; both start after the previous factor QR.
-      CPQR_HIP(hipEventRecord(side.ready, s));
+      // on the caller's stream: the QR starts as soon as the previous factor
+      // QR has its R (its Q is still being formed), the Multi-TTM after it.
+      if (!r_marked) CPQR_HIP(hipEventRecord(side.ready, s));
       CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
       CPQR_HIP(hipEventRecord(side.done, side.s));
@@ -464,14 +466,16 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       CPQR_TRY(apply_q0_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.W, w.sub, s));
       CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda,
                              p->status, w.sub, s));
-      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s));
+      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s,
+                                 side.ready));
+      r_marked = true;
     }
     double* out = relerr ? relerr + sw : w.relerr_tmp;
     if (p->error_mode == CPQR_ERROR_EFFICIENT) {
       // on the side stream, overlapping the next sweep's first Multi-TTM: the
       // next Khatri-Rao QR (which rewrites R_0) queues behind it there, and the
-      // caller's stream waits for that QR before it rewrites W and lambda
-      CPQR_HIP(hipEventRecord(side.ready, s));
+      // caller's stream waits for that QR before it rewrites W and lambda.  It
+      // reads W, A_N, lambda and R_N, all complete once the last R is.
       CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       CPQR_TRY(error_efficient_enqueue(p->I[N - 1], R, w.W, p->A[N - 1], p->lambda, w.R0, p->Rf[N - 1],
                                        w.xnorm2, out, side.s));

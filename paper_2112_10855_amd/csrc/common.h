@@ -87,7 +87,8 @@ struct PhaseTimer {
 // tsqr.hip
 size_t tsqr_work(int64_t rows, int R);
 int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
-                      double* Rk, int64_t ldr, void* work, hipStream_t s);
+                      double* Rk, int64_t ldr, void* work, hipStream_t s,
+                      hipEvent_t r_ready = nullptr);
 int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
                    double* R0, void* work, hipStream_t s);
 

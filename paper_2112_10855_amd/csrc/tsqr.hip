@@ -544,7 +544,7 @@ size_t wt_work(int64_t rows, int R, int P) {
 
 template <int RMAX, int P>
 int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
-              int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
+              int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s, hipEvent_t r_ready) {
   double* w = static_cast<double*>(work);
   const int nlev = wt::level_count(rows, R, P);
   for (int l = 0; l + 1 < nlev; ++l) {
@@ -562,6 +562,7 @@ int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const 
     hipLaunchKernelGGL((wt::wave_tree_root<RMAX, P, SRC_KRP>), dim3(1), dim3(wt::W), 0, s, rows, R, A, lda,
                        krp, Q, ldq, Rout, ldr_out, w);
   CPQR_TRY(check_launch("wave_tree_root"));
+  if (r_ready) CPQR_HIP(hipEventRecord(r_ready, s));  // R is complete; Q follows
   for (int l = nlev - 2; l >= 0; --l) {
     const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
     hipLaunchKernelGGL((wt::wave_tree_down<RMAX, P>), grd, blk, 0, s, rows, R, l, Q, ldq, w);
@@ -571,22 +572,23 @@ int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const 
 }
 
 int wt_run(int P, int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
-           int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
+           int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s, hipEvent_t r_ready) {
   switch (round_rank(R)) {
     case 8:
-      return P == 2 ? wt_launch<8, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s)
-                    : wt_launch<8, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+      return P == 2 ? wt_launch<8, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
+                    : wt_launch<8, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
     case 16:
-      return P == 2 ? wt_launch<16, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s)
-                    : wt_launch<16, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+      return P == 2 ? wt_launch<16, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
+                    : wt_launch<16, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
     default:
-      return wt_launch<32, 1>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+      return wt_launch<32, 1>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
   }
 }
 
 int tsqr_dispatch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
-                  double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s) {
-  return wt_run(wt_rows_per_lane(rows, R), src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s);
+                  double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s,
+                  hipEvent_t r_ready = nullptr) {
+  return wt_run(wt_rows_per_lane(rows, R), src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
 }
 
 }  // namespace
@@ -594,10 +596,10 @@ int tsqr_dispatch(int src, int64_t rows, int R, const double* A, int64_t lda, co
 size_t tsqr_work(int64_t rows, int R) { return wt_work(rows, R, wt_rows_per_lane(rows, R)); }
 
 int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
-                      double* Rk, int64_t ldr, void* work, hipStream_t s) {
+                      double* Rk, int64_t ldr, void* work, hipStream_t s, hipEvent_t r_ready) {
   PhaseTimer pt(PH_FACTOR_QR, s);
   KrpSrc none{};
-  return tsqr_dispatch(SRC_MATRIX, I, R, A, lda, none, Q, ldq, Rk, ldr, work, s);
+  return tsqr_dispatch(SRC_MATRIX, I, R, A, lda, none, Q, ldq, Rk, ldr, work, s, r_ready);
 }
 
 int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
