@@ -386,7 +386,8 @@ def main():
     mt_gbs = (xbytes + ybytes + qbytes) / (mt_ms / max(mt_cnt, 1) / 1e3) / 1e9
     src = open(os.path.join(ROOT, "paper_2112_10855_amd", "csrc", "multittm.hip"), "rb").read()
     sha = hashlib.sha256(src).hexdigest()
-    traffic = traffic_from_profiles(sha)
+    # the counters were taken on the FP32 kernel
+    traffic = traffic_from_profiles(sha) if args.prec == "f32" else None
 
     out = {
         "metric": METRIC,
