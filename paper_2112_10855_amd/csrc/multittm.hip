@@ -86,6 +86,42 @@ __global__ void prep_u_quads(const double* __restrict__ Q, int64_t K, int64_t ld
 // keeps them branch-free; the chunk tail is a separate masked step.
 constexpr int LDS_FLOATS = 16384;  // 64 KB
 
+// Output of the row-tiled kernels.  In the MFMA D layout, lane (l16, kq)
+// holds for tile g the 16 consecutive rows m0 = mt + 64 g + 16 kq, ... of
+// column l16 (row 4 v + j of the group in acc[g][j][v]).  When the 16 rows lie
+// in one slab of P they are 64 contiguous bytes of the output, written as
+// four float4 stores; otherwise (a slab boundary inside the group, the grid's
+// end, or an output not 16-byte aligned) element by element.
+template <int NB, int MG>
+__device__ __forceinline__ void store_tiles(const floatx4 (&acc)[NB][MG][4], float* __restrict__ o, int64_t mt,
+                                            int64_t M, int64_t P, int R, int l16, int kq) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int r = b * 16 + l16;
+    if (r >= R) continue;
+#pragma unroll
+    for (int g = 0; g < MG; ++g) {
+      const int64_t m0 = mt + 64 * g + 16 * kq;
+      const int64_t p0 = m0 % P, s0 = m0 / P;
+      float* d = o + p0 + r * P + s0 * P * R;
+      if (m0 + 16 <= M && p0 + 16 <= P && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<float4*>(d + 4 * q) =
+              make_float4(acc[b][g][0][q], acc[b][g][1][q], acc[b][g][2][q], acc[b][g][3][q]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t m = m0 + 4 * v + j;
+            if (m < M) o[m % P + r * P + (m / P) * P * R] = acc[b][g][j][v];
+          }
+      }
+    }
+  }
+}
+
 // ---------------- P % 4 == 0: rows m = p + P s on the MFMA M dimension
 // STREAM marks the instantiation used for a first contraction (it streams the
 // whole tensor); it is the same code under its own symbol so that profiles and
@@ -199,25 +235,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
     }
     if (!active) return;
   }
-  // D layout: lane holds rows 4*kq + v (v = 0..3) of column l16.
-  float* o = out + int64_t(blockIdx.y) * split_stride;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int r = b * 16 + l16;
-    if (r >= R) continue;
-#pragma unroll
-    for (int g = 0; g < MG; ++g)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t m = mt + 64 * g + 4 * (4 * kq + v) + j;
-          if (m < M) {
-            const int64_t pp = m % P, ss = m / P;
-            o[pp + r * P + ss * P * R] = acc[b][g][j][v];
-          }
-        }
-  }
+  store_tiles<NB, MG>(acc, out + int64_t(blockIdx.y) * split_stride, mt, M, P, R, l16, kq);
 }
 
 // ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
@@ -456,24 +474,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_bf16_m(const float* __restrict__
     }
   }
   if (!active) return;
-  float* o = out + int64_t(blockIdx.y) * split_stride;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int r = b * 16 + l16;
-    if (r >= R) continue;
-#pragma unroll
-    for (int g = 0; g < MG; ++g)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t m = mt + 64 * g + 4 * (4 * kq + v) + j;
-          if (m < M) {
-            const int64_t pp = m % P, ss = m / P;
-            o[pp + r * P + ss * P * R] = acc[b][g][j][v];
-          }
-        }
-  }
+  store_tiles<NB, MG>(acc, out + int64_t(blockIdx.y) * split_stride, mt, M, P, R, l16, kq);
 }
 
 // ---------------- P == 1 (columns on the MFMA N dimension)
