@@ -463,9 +463,8 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
                                           w.Y, w.sub, s, false));
       }
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
-      CPQR_TRY(apply_q0_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.W, w.sub, s));
-      CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda,
-                             p->status, w.sub, s));
+      CPQR_TRY(apply_solve_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.R0, p->use_svd, p->rtol, w.W, p->A[n],
+                                   p->lambda, p->status, w.sub, s));
       CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s,
                                  side.ready));
       r_marked = true;

@@ -110,6 +110,11 @@ int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, 
 size_t apply_q0_work(int64_t In, int64_t K, int R);
 int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                      double* W, void* work, hipStream_t s);
+// W = Y_(n) Q_0, then A = W R0^-T with columns normalized into lambda; the
+// triangular solve sums the split partials of W itself (work: apply_q0_work).
+int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                        const double* R0, int use_svd, double rtol, double* W, double* A, double* lambda,
+                        int* status, void* work, hipStream_t s);
 size_t solve_work(int64_t In, int R);
 int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
                   double* A, double* lambda, int* status, void* work, hipStream_t s);

@@ -110,6 +110,62 @@ __global__ __launch_bounds__(BLK) void solve_tri_kernel(const double* __restrict
   if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
 }
 
+// The same solve when the apply-Q_0 product was split over K: one thread per
+// (row, column) of W adds up that entry's partials (stride In R) and stores
+// W; each row's back substitution then reads its W row from LDS, and the
+// solved rows leave through LDS so that the stores of A stay coalesced.
+template <int RM>
+__global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict__ part, int splits,
+                                                        const double* __restrict__ R0, double* W,
+                                                        double* A, int64_t In, int R, int* status) {
+  constexpr int RPB = BLK / RM;
+  __shared__ double r0[RM][RM + 1];
+  __shared__ double ws[RM][RPB + 1];
+  for (int e = threadIdx.x; e < R * R; e += BLK) r0[e % R][e / R] = R0[e];
+  const int ri = threadIdx.x % RPB, c = threadIdx.x / RPB;
+  const int64_t i = int64_t(blockIdx.x) * RPB + ri;
+  const bool live = i < In && c < R;
+  double w = 0.0;
+  if (live) {
+    const int64_t e = i + int64_t(c) * In;
+    for (int t = 0; t < splits; ++t) w += part[int64_t(t) * In * R + e];
+    W[e] = w;
+  }
+  ws[c][ri] = w;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && status) {
+    int bad = 0;
+    for (int j = 0; j < R; ++j) {
+      const double d = r0[j][j];
+      if (d == 0.0 || !isfinite(d)) bad = 1;
+    }
+    if (bad) atomicOr(status, CPQR_STATUS_SINGULAR);
+  }
+  if (threadIdx.x < RPB && i < In) {
+    double a[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) a[k] = ws[k][ri];
+#pragma unroll
+    for (int j = RM - 1; j >= 0; --j) {
+      if (j >= R) continue;
+      double v = a[j];
+#pragma unroll
+      for (int k = j + 1; k < RM; ++k)
+        if (k < R) v -= r0[j][k] * a[k];
+      a[j] = v / r0[j][j];
+    }
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      ws[k][ri] = a[k];
+      if (k < R) nonfinite |= !isfinite(a[k]);
+    }
+    if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
+  }
+  __syncthreads();
+  if (live) A[i + int64_t(c) * In] = ws[c][ri];
+}
+
 // One-sided Jacobi SVD of R0 (R x R, R <= 32) in one workgroup, then
 // M = U S^+ V^T with singular values <= rtol * sigma_max dropped.
 // Thread layout: 16 pairs x 32 rows; a pair's dot products are reductions
@@ -423,6 +479,47 @@ int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, co
     CPQR_TRY(check_launch("apply_q0 sum"));
   }
   return CPQR_OK;
+}
+
+int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                        const double* R0, int use_svd, double rtol, double* W, double* A, double* lambda,
+                        int* status, void* work, hipStream_t s) {
+  const int64_t sp = apply_splits(In, K, R);
+  const int64_t kchunk = ceil_div(ceil_div(K, sp), 64) * 64;
+  const int64_t splits = ceil_div(K, kchunk);
+  if (use_svd || splits == 1) {
+    CPQR_TRY(apply_q0_enqueue(In, K, R, ydtype, Y, Q0, W, work, s));
+    return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, s);
+  }
+  // the solve adds up the partial W's itself (one kernel fewer)
+  Carver cv(work);
+  double* part = cv.take<double>(size_t(sp) * In * R);
+  const int RM = round_rank(R);
+  {
+    PhaseTimer pt(PH_APPLY_Q0, s);
+    const dim3 grd(unsigned(ceil_div(In, BLK / RM)), unsigned(splits));
+#define APPLY(TY, RMV)                                                                             \
+  hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, part, \
+                     In, K, R, kchunk)
+    if (ydtype == CPQR_F64) {
+      if (RM == 8) APPLY(double, 8); else if (RM == 16) APPLY(double, 16); else APPLY(double, 32);
+    } else {
+      if (RM == 8) APPLY(float, 8); else if (RM == 16) APPLY(float, 16); else APPLY(float, 32);
+    }
+#undef APPLY
+    CPQR_TRY(check_launch("apply_q0"));
+  }
+  PhaseTimer pt(PH_SOLVE, s);
+  const dim3 grd(unsigned(ceil_div(In, BLK / RM)));
+  if (RM == 8)
+    hipLaunchKernelGGL((sum_solve_kernel<8>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
+  else if (RM == 16)
+    hipLaunchKernelGGL((sum_solve_kernel<16>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
+  else
+    hipLaunchKernelGGL((sum_solve_kernel<32>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
+  CPQR_TRY(check_launch("sum_solve"));
+  hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
+  return check_launch("normalize");
 }
 
 size_t solve_work(int64_t In, int R) {

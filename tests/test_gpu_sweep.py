@@ -143,3 +143,19 @@ def test_dimension_tree_rejects_bad_split():
     d = synth.workload_small()
     with pytest.raises(C.CpqrError):
         C.cp_als_qr(to_dev(d["X"], torch.float64), d["init"], maxiters=1, prec=C.PREC_F64, dimtree=3)
+
+
+@pytest.mark.parametrize("shape,R", [((1500, 12, 10), 8), ((3000, 9, 8), 5), ((5000, 7, 6), 6), ((2048, 20, 18), 16),
+                                     ((2100, 14, 13), 12)])
+def test_tall_modes_fp64(shape, R):
+    """Modes of a few thousand rows against short ones: the apply-Q_0 product
+    splits its sum over the long dimension into partials that the triangular
+    solve adds up, and the factor QR takes a multi-level tree; all must
+    reproduce the oracle's sweeps."""
+    d = synth.cp_tensor(shape, R, 913, noise=1e-2, dtype=np.float64)
+    init = synth.init_factors(shape, R, 914)
+    lam, A, hist, status = run_gpu(d["X"], init, 4, C.PREC_F64)
+    lo, Ao, ho = OQ.cp_als_qr(d["X"], init, maxiters=4)
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, A, lo, Ao) < 1e-9
