@@ -24,8 +24,9 @@
  *    the device or allocates device memory.
  *  - Scratch memory is caller-provided: each entry point that needs it
  *    takes (work, work_bytes) and has a *_work query returning the bytes it
- *    needs.  work must be 256-byte aligned.  Calls that share one work
- *    buffer must be ordered on one stream.
+ *    needs.  work must be 256-byte aligned; it may be NULL when the query
+ *    returns 0.  Calls that share one work buffer must be ordered on one
+ *    stream.
  *  - Return value: CPQR_OK or a negative CPQR_ERR_* code.  On error nothing
  *    has been enqueued and cpqr_last_error() gives a thread-local message.
  *  - Numerical conditions found on the device are OR-ed into an optional
@@ -86,8 +87,9 @@ int cpqr_version(void);
 /*
  * Compact QR of one factor matrix, A = Q R (Alg. 2, the factor QR before
  * the loop and after each mode update).  Householder reflections on the
- * GPU: one workgroup per block of up to 1024 rows (512 at R > 16), blocks
- * combined in a tall-skinny tree; Q formed explicitly.
+ * GPU: one workgroup per block of up to 1024 rows, blocks combined in a
+ * tall-skinny tree; Q formed explicitly.  Up to 1024 rows take one
+ * workgroup and no work buffer.
  *   A   : device, I x R, column-major, lda >= I (read only)
  *   Q   : device, I x R, column-major, ldq >= I (written)
  *   Rk  : device, R x R upper triangular, column-major, ldr >= R (written,

@@ -3,16 +3,22 @@
 // V_n = Q_0 R_0 (paper section 3.1, Alg. 2), both with the orthonormal
 // factor formed explicitly.
 //
-// Design: a reduction tree whose every node is one wavefront.  A leaf holds
-// up to 64 P rows of the input (P rows per lane); an inner node stacks the R
-// factors of up to 64 P / R children.  Each node is factorized by Householder
-// reflections held in registers, one in-wave reduction per column, and keeps
-// its reflectors in the compact WY form H_0 ... H_{R-1} = I - V T V^T.  The
-// up-sweep runs one launch per level (one single-wavefront workgroup per
-// node); the root's R is the answer.  The down-sweep forms Q top down: each
-// node applies its reflectors to [C; 0], C being its R x R slice of the
-// parent's Q (the identity at the root), and hands R x R slices to its
-// children.  Every step is a genuine Householder reflection of the real
+// Design: a reduction tree whose every node is one workgroup.  A node holds
+// up to 1024 rows (16 per lane); each of its wavefronts owns four columns of
+// them, so the per-column work of the Householder sweep (the reflector's
+// products with the trailing columns, their update) is split over the SIMDs
+// and a column costs one barrier.  The owner of column J forms reflector J
+// (one in-wave norm) and publishes it in LDS; every wavefront then takes the
+// products v_J^T A(:, c) of its own columns in one batched in-wave
+// reduction, updates the columns right of J and records the Gram entries
+// v_c^T v_J (c < J) from which the compact WY factor T of
+// H_0 ... H_{R-1} = I - V T V^T follows.  A leaf holds rows of the input;
+// an inner node stacks the R factors of up to 1024 / R children (one level
+// for up to 1024 rows, two up to 1024 * 1024 / R).  The up-sweep runs one
+// launch per level; the root's R is the answer.  The down-sweep forms Q top
+// down: each node applies its reflectors to [C; 0], C being its R x R slice
+// of the parent's Q (the identity at the root), and hands R x R slices to
+// its children.  Every step is a genuine Householder reflection of the real
 // rows, so Q has orthonormal columns even when the input is rank deficient.
 
 #include <algorithm>
@@ -38,48 +44,45 @@ __device__ __host__ inline void leaf_range(int64_t rows, int64_t nl, int64_t b, 
   start = b * base + (b < rem ? b : rem);
 }
 
-// ------------------------------------------------------------ wavefront nodes
-// A node holds at most 64 P rows, row 64 p + lane in slot p of the lane.
-//
-// Column j of a wavefront node costs one in-wave reduction.  With x the
-// sub-column below the diagonal (rows r > j) it returns, in one batch of R
-// sums, s_c = sum_r x(r) A(r, c) for every column c: s_j = ||x||^2 gives the
-// reflector, s_c (c > j) the trailing products v_j^T A(:, c) = A(j, c) +
-// s_c / (alpha - beta), and s_c (c < j) the reflector Gram entries
-// v_c^T v_j = v_c(j) + s_c / (alpha - beta) for the compact WY factor T.
-// Row j itself (alpha, A(j, c), v_c(j)) lives in lane j, slot 0 (R <= 32),
-// and is broadcast from there.
-namespace wt {
+// ------------------------------------------------------------ block nodes
+// A node holds at most 64 P rows (P = 4 or 16 row slots per lane), row
+// 64 p + lane in slot p of every lane; wavefront w of the node holds columns
+// 4 w .. 4 w + 3.  Rows beyond the node's are zero and take part in every
+// step, so the code has no row-count branches.
+namespace bn {
 
-constexpr int W = 64;
+constexpr int W = 64;   // lanes per wavefront
+constexpr int CW = 4;   // columns per wavefront
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-// Workspace of the tree: per level l, the reflectors V_l ([node][p][c][lane]),
-// the compact-WY factors T_l ([node][row][c]) and, for l >= 1, S_l, which
-// holds the R factors of level l-1 going up and their C blocks coming down
-// ([child][row][c]).  Every piece is a multiple of 256 bytes, so the offsets
-// are plain prefix sums (shared by the host's size query and the kernel).
+// Workspace of the tree: per level l below the root, the reflectors V_l
+// ([node][p][c][lane]) and the compact-WY factors T_l ([node][row][c]); per
+// level l >= 1, S_l, which holds the R factors of level l-1 going up and
+// their C blocks coming down ([child][row][c]).  A one-node tree needs none.
+// Every piece is a multiple of 256 bytes, so the offsets are plain prefix
+// sums (shared by the host's size query and the kernels).
 struct NodeLevel {
-  int nodes, prev;        // nodes here and at the level below (0 at the leaves)
-  size_t v, t, s;         // offsets (doubles) of V_l, T_l, S_l
+  int nodes, prev;   // nodes here and at the level below (0 at the leaves)
+  size_t v, t, s;    // offsets (doubles) of V_l, T_l, S_l
 };
 
 __host__ __device__ __forceinline__ NodeLevel level_of(int64_t rows, int R, int P, int RM, int l, size_t* total) {
-  const int g = W * P / R;
-  NodeLevel L{int((rows + W * P - 1) / (W * P)), 0, 0, 0, 0};
+  const int node = W * P, g = node / R;
+  NodeLevel L{int((rows + node - 1) / node), 0, 0, 0, 0};
   size_t off = 0;
   for (int k = 0;; ++k) {
     if (k > 0) {
       L.prev = L.nodes;
       L.nodes = (L.nodes + g - 1) / g;
     }
+    const bool root = L.nodes == 1;
     L.v = off;
-    off += size_t(L.nodes) * P * RM * W;
+    if (!root) off += size_t(L.nodes) * P * RM * W;
     L.t = off;
-    off += size_t(L.nodes) * RM * RM;
+    if (!root) off += size_t(L.nodes) * RM * RM;
     L.s = off;
     if (k > 0) off += size_t(L.prev) * RM * RM;
-    if (k == l || L.nodes == 1) break;
+    if (k == l || root) break;
   }
   if (total) *total = off;
   return L;
@@ -87,26 +90,13 @@ __host__ __device__ __forceinline__ NodeLevel level_of(int64_t rows, int R, int 
 
 // Number of levels (the root level has one node).
 __host__ __device__ __forceinline__ int level_count(int64_t rows, int R, int P) {
-  const int g = W * P / R;
-  int n = int((rows + W * P - 1) / (W * P)), nlev = 1;
+  const int node = W * P, g = node / R;
+  int n = int((rows + node - 1) / node), nlev = 1;
   while (n > 1) {
     n = (n + g - 1) / g;
     ++nlev;
   }
   return nlev;
-}
-
-template <int RMAX>
-struct Buf {
-  double X[RMAX][RMAX + 1];
-  double Y[RMAX][RMAX + 1];
-  double Z[RMAX][RMAX];
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ double rdlane(double x, int l) {
@@ -193,165 +183,52 @@ __device__ __forceinline__ double wave_sum(double (&x)[V], int lane) {
   }
 }
 
-// Column J of the wavefront Householder QR (J < R).  A template per column
-// keeps every register-array index a compile-time constant.  Row J and the
-// sums are read from the lanes that hold them (readlane), so they arrive in
-// scalar registers that every lane reads.
-template <int J, int RMAX, int P>
-__device__ __forceinline__ void wave_column(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
-  constexpr int SH = 6 - ilog2(RMAX);
-  double x[P], p[RMAX];
-#pragma unroll
-  for (int s = 0; s < P; ++s) x[s] = (s > 0 || lane > J) ? a[s][J] : 0.0;
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) {
-    double acc = 0.0;
-#pragma unroll
-    for (int s = 0; s < P; ++s) acc += a[s][c] * x[s];
-    p[c] = acc;
-  }
-  const double red = wave_sum<RMAX>(p, lane);
-  const double alpha = rdlane(a[0][J], J), sub2 = rdlane(red, J << SH);
-  double tau = 0.0, beta = alpha, scal = 0.0;
-  if (sub2 > 0.0) {
-    const double nrm = sqrt(alpha * alpha + sub2);
-    beta = alpha >= 0.0 ? -nrm : nrm;
-    tau = (beta - alpha) / beta;
-    scal = 1.0 / (alpha - beta);
-  }
-  double v[P];
-#pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = (s == 0 && lane == J) ? 1.0 : x[s] * scal;
-  // T(0:J, J) = -tau T(0:J, 0:J) G(0:J, J), G(k, J) = v_k^T v_J = v_k(J) + scal s_k
-  double tg = 0.0;
-#pragma unroll
-  for (int k = 0; k < J; ++k) tg += t[k] * (rdlane(a[0][k], J) + scal * rdlane(red, k << SH));
-  t[J] = lane < J ? -tau * tg : (lane == J ? tau : 0.0);
-  // trailing columns: A(:, c) -= tau v (v^T A(:, c)), v^T A(:, c) = A(J, c) + scal s_c
-#pragma unroll
-  for (int c = J + 1; c < RMAX; ++c) {
-    if (c < R) {
-      const double tw = tau * (rdlane(a[0][c], J) + scal * rdlane(red, c << SH));
-#pragma unroll
-      for (int s = 0; s < P; ++s) a[s][c] -= tw * v[s];
-    }
-  }
-  a[0][J] = lane == J ? beta : (lane > J ? v[0] : a[0][J]);
-#pragma unroll
-  for (int s = 1; s < P; ++s) a[s][J] = v[s];
+// Sum over the 64 lanes, returned in every lane.
+__device__ __forceinline__ double wave_allsum(double x, int lane) {
+  x = bfly<5>(x, x, lane);
+  x = bfly<4>(x, x, lane);
+  x = bfly<3>(x, x, lane);
+  x = bfly<2>(x, x, lane);
+  x = bfly<1>(x, x, lane);
+  return bfly<0>(x, x, lane);
 }
 
-template <int J, int RMAX, int P>
-struct WaveColumns {
-  static __device__ __forceinline__ void run(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
-    if (J >= R) return;
-    wave_column<J, RMAX, P>(a, t, lane, R);
-    WaveColumns<J + 1, RMAX, P>::run(a, t, lane, R);
-  }
-};
 template <int RMAX, int P>
-struct WaveColumns<RMAX, RMAX, P> {
-  static __device__ __forceinline__ void run(double (&)[P][RMAX], double (&)[RMAX], int, int) {}
+struct Shared {
+  // the current reflector while factorizing (double buffered, [p][lane]),
+  // then rows of V while forming Q (double buffered, [c][lane])
+  double buf[2 * (P > RMAX ? P : RMAX) * W];
+  double G[RMAX][RMAX + 1];  // G(k, J) = v_k^T v_J, k < J
+  double T[RMAX][RMAX + 1];
+  double C[RMAX][RMAX + 1];
+  double B[RMAX][RMAX + 1];  // V1^T C
+  double M[RMAX][RMAX];      // T V1^T C
+  double V1[RMAX][RMAX + 1]; // the top R x R block of V
+  double tau[RMAX];
+  double scal[RMAX];  // 1 / (alpha - beta) of each reflector (0 if none)
+  double beta[RMAX];  // R(J, J)
 };
 
-// Householder QR of the node block (row 64 p + lane in a[p][.]; rows beyond
-// the block and columns >= R are zero).  On return lanes < R of slot 0 hold
-// R's rows (entries c >= lane), the rows below column c's diagonal hold
-// reflector c's components (v_c(c) = 1 implicitly), and t[] holds row `lane`
-// of T (lanes < R).
-template <int RMAX, int P>
-__device__ __forceinline__ void wave_factor(double (&a)[P][RMAX], double (&t)[RMAX], int lane, int R) {
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) t[c] = 0.0;
-  WaveColumns<0, RMAX, P>::run(a, t, lane, R);
-}
-
-// Component of reflector c in row `row` of the node (from a[slot][c]).
-__device__ __forceinline__ double vcomp(double ac, int c, int row) {
-  return row == c ? 1.0 : (row > c ? ac : 0.0);
-}
-
-// Compact-WY product M = T V1^T C into b.Z, with C (R x R, zero beyond) in
-// b.Z on entry; returns row `lane` of C (lanes < R, else zero) in crow[].
-// Every R x R operand is zero-padded to RMAX, so the products run over fixed
-// trip counts.
-template <int RMAX>
-__device__ __forceinline__ void wave_m(const double* Vl, const double (&t)[RMAX], double (&crow)[RMAX],
-                                       int lane, int R, Buf<RMAX>& b) {
-  constexpr int NE = (RMAX * RMAX + W - 1) / W;
-  if (lane < RMAX) {
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) {
-      b.X[lane][c] = (lane < R && c < R) ? vcomp(Vl[c * W + lane], c, lane) : 0.0;
-      b.Y[lane][c] = lane < R ? t[c] : 0.0;
-    }
-  }
-  wave_sync();
-  // lane's entries e = lane + 64 u: column c = lane % RMAX, rows k_u
-  const int cc = lane % RMAX, k0 = lane / RMAX;
-  constexpr int KS = W / RMAX < RMAX ? W / RMAX : RMAX;
-  double e1[NE];
-#pragma unroll
-  for (int u = 0; u < NE; ++u) e1[u] = 0.0;
-#pragma unroll 2
-  for (int i = 0; i < RMAX; ++i) {  // B = V1^T C
-    const double z = b.Z[i][cc];
-#pragma unroll
-    for (int u = 0; u < NE; ++u) e1[u] += b.X[i][(k0 + u * KS) % RMAX] * z;
-  }
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) crow[c] = lane < RMAX ? b.Z[lane % RMAX][c] : 0.0;
-  wave_sync();
-#pragma unroll
-  for (int u = 0; u < NE; ++u) {
-    const int e = lane + u * W;
-    if (e < RMAX * RMAX) b.X[e / RMAX][e % RMAX] = e1[u];
-  }
-  wave_sync();
-#pragma unroll
-  for (int u = 0; u < NE; ++u) e1[u] = 0.0;
-#pragma unroll 2
-  for (int i = 0; i < RMAX; ++i) {  // M = T B
-    const double x = b.X[i][cc];
-#pragma unroll
-    for (int u = 0; u < NE; ++u) e1[u] += b.Y[(k0 + u * KS) % RMAX][i] * x;
-  }
-  wave_sync();
-#pragma unroll
-  for (int u = 0; u < NE; ++u) {
-    const int e = lane + u * W;
-    if (e < RMAX * RMAX) b.Z[e / RMAX][e % RMAX] = e1[u];
-  }
-  wave_sync();
-}
-
-// Row 64 s + lane of the node's Q: [C; 0](row) - v(row) M, with M in b.Z
-// and the node's reflectors in Vl ([p][c][lane]).
-template <int RMAX>
-__device__ __forceinline__ void wave_q_row(const double* Vl, const double (&crow)[RMAX], int s,
-                                           double (&q)[RMAX], int lane, int R, const Buf<RMAX>& b) {
-  const int row = s * W + lane;
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) q[c] = s == 0 ? crow[c] : 0.0;
-#pragma unroll 4
-  for (int k = 0; k < R; ++k) {
-    const double vk = vcomp(Vl[(s * RMAX + k) * W + lane], k, row);
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) q[c] -= vk * b.Z[k][c];
-  }
+// Component of reflector c in row `row` of the node from the stored entry ac
+// of column c: v_c(row) = ac * sc below the diagonal, 1 on it, 0 above.
+__device__ __forceinline__ double vcomp(double ac, double sc, int c, int row) {
+  return row == c ? 1.0 : (row > c ? ac * sc : 0.0);
 }
 
 // Rows of a leaf (rows beyond it, and columns >= R, are zero).
 template <int RMAX, int P, int SRC>
-__device__ __forceinline__ void load_leaf(double (&a)[P][RMAX], int lane, int64_t start, int m, int R,
-                                 const double* A, int64_t lda, const KrpSrc& krp) {
+__device__ __forceinline__ void load_leaf(double (&a)[P][CW], int w, int lane, int64_t start, int m, int R,
+                                          const double* A, int64_t lda, const KrpSrc& krp) {
 #pragma unroll
-  for (int s = 0; s < P; ++s) {
-    const int r = s * W + lane;
+  for (int p = 0; p < P; ++p) {
+    const int r = p * W + lane;
     const int64_t g = start + r;
     if (SRC == SRC_MATRIX) {
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) a[s][c] = (r < m && c < R) ? A[g + c * lda] : 0.0;
+      for (int j = 0; j < CW; ++j) {
+        const int c = w * CW + j;
+        a[p][j] = (r < m && c < R) ? A[g + c * lda] : 0.0;
+      }
     } else {
       int digit[CPQR_MAX_MODES];
       int d = int(g);
@@ -361,12 +238,13 @@ __device__ __forceinline__ void load_leaf(double (&a)[P][RMAX], int lane, int64_
         d /= R;
       }
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        double p = (r < m && c < R) ? 1.0 : 0.0;
+      for (int j = 0; j < CW; ++j) {
+        const int c = w * CW + j;
+        double v = (r < m && c < R) ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < CPQR_MAX_MODES; ++k)
-          if (k < krp.nm && r < m && c < R) p *= krp.Rk[k][digit[k] + c * krp.ldr];
-        a[s][c] = p;
+          if (k < krp.nm && r < m && c < R) v *= krp.Rk[k][digit[k] + c * krp.ldr];
+        a[p][j] = v;
       }
     }
   }
@@ -374,73 +252,256 @@ __device__ __forceinline__ void load_leaf(double (&a)[P][RMAX], int lane, int64_
 
 // Node rows of a stacked level: row i of child k's block at node row k R + i.
 template <int RMAX, int P>
-__device__ __forceinline__ void load_stack(double (&a)[P][RMAX], int lane, int m, int R, const double* S,
-                                  int64_t c0) {
+__device__ __forceinline__ void load_stack(double (&a)[P][CW], int w, int lane, int m, int R, const double* S,
+                                           int64_t c0) {
 #pragma unroll
-  for (int s = 0; s < P; ++s) {
-    const int r = s * W + lane;
+  for (int p = 0; p < P; ++p) {
+    const int r = p * W + lane;
     const int child = r / R, i = r % R;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[s][c] = r < m ? S[((c0 + child) * RMAX + i) * RMAX + c] : 0.0;
+    for (int j = 0; j < CW; ++j)
+      a[p][j] = r < m ? S[((c0 + child) * RMAX + i) * RMAX + w * CW + j] : 0.0;
   }
 }
 
-// Writes the node's Q rows: to the output (leaf) or as the children's C blocks.
+// Reflector J from the wavefront's column slot JL (rows > J of it form x):
+// H_J = I - tau v v^T with v(J) = 1, v(r > J) = x(r) scal, scal =
+// 1 / (alpha - beta).  Writes v ([p][lane], zero above row J) to vb and
+// tau, scal and beta to the shared arrays; the column itself keeps x (its
+// reflector is x scal below the diagonal, R(J, J) is beta).
+template <int RMAX, int P, int JL>
+__device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lane, double* vb,
+                                        Shared<RMAX, P>& sh) {
+  double x[P];
+  double ss = 0.0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    x[p] = (p > 0 || lane > J) ? a[p][JL] : 0.0;
+    ss += x[p] * x[p];
+  }
+  const double sub2 = wave_allsum(ss, lane);
+  const double alpha = rdlane(a[0][JL], J);
+  double tau = 0.0, beta = alpha, scal = 0.0;
+  if (sub2 > 0.0) {
+    const double nrm = sqrt(alpha * alpha + sub2);
+    beta = alpha >= 0.0 ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) vb[p * W + lane] = (p == 0 && lane == J) ? 1.0 : x[p] * scal;
+  if (lane == 0) {
+    sh.tau[J] = tau;
+    sh.scal[J] = scal;
+    sh.beta[J] = beta;
+  }
+}
+
+// Householder QR of the node (rows beyond it zero).  On
+// return the wavefront's column slots hold, for its columns c, R(r, c) in
+// rows r < c and x_c below the diagonal (v_c = x_c scal_c there); sh.tau,
+// sh.scal, sh.beta (R's diagonal) and sh.G are set.
 template <int RMAX, int P>
-__device__ __forceinline__ void store_q(const double* Vl, const double (&crow)[RMAX], int lane, int R,
-                               int m, bool leaf, int64_t start, double* Qout, int64_t ldq, double* S,
-                               int64_t c0, const Buf<RMAX>& b) {
+__device__ __forceinline__ void node_factor(double (&a)[P][CW], int R, int w, int lane,
+                                            Shared<RMAX, P>& sh) {
+  for (int J = 0; J < R; ++J) {
+    double* vb = sh.buf + (J & 1) * P * W;
+    const int jl = J - w * CW;
+    switch (jl) {  // the owner of column J forms the reflector
+      case 0: reflect<RMAX, P, 0>(a, J, lane, vb, sh); break;
+      case 1: reflect<RMAX, P, 1>(a, J, lane, vb, sh); break;
+      case 2: reflect<RMAX, P, 2>(a, J, lane, vb, sh); break;
+      case 3: reflect<RMAX, P, 3>(a, J, lane, vb, sh); break;
+      default: break;
+    }
+    __syncthreads();
+    double v[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) {
-    double q[RMAX];
-    wave_q_row<RMAX>(Vl, crow, s, q, lane, R, b);
-    const int r = s * W + lane;
-    if (r >= m) continue;
-    if (leaf) {
+    for (int p = 0; p < P; ++p) v[p] = vb[p * W + lane];
+    const double tau = sh.tau[J];
+    // s_j = v^T A(:, c) for the wavefront's columns c (v is zero above row J)
+    double s[CW];
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        if (c < R) Qout[start + r + c * ldq] = q[c];
+    for (int j = 0; j < CW; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        acc += v[p] * a[p][j];
+      s[j] = acc;
+    }
+    const double red = wave_sum<CW>(s, lane);
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w * CW + j;
+      const double sj = rdlane(red, j << (6 - ilog2(CW)));
+      if (c > J && c < R) {
+        const double tw = tau * sj;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          a[p][j] -= tw * v[p];
+      } else if (c < J && lane == 0) {
+        sh.G[c][J] = sh.scal[c] * sj;  // rows >= J of column c hold x_c there
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Compact WY factor T from sh.tau and sh.G, lane i of wavefront 0 forming row
+// i: T(0:J, J) = -tau_J T(0:J, 0:J) G(0:J, J), T(J, J) = tau_J.  Writes it to
+// sh.T and, if Tg is set, to Tg ([row][c]).  Zero beyond R.
+template <int RMAX, int P>
+__device__ __forceinline__ void node_t(int R, int w, int lane, Shared<RMAX, P>& sh, double* Tg) {
+  if (w != 0 || lane >= RMAX) return;
+  double t[RMAX];
+#pragma unroll
+  for (int J = 0; J < RMAX; ++J) {
+    if (J < R) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < J; ++k) acc += t[k] * sh.G[k][J];
+      const double tj = sh.tau[J];
+      t[J] = lane < J ? -tj * acc : (lane == J ? tj : 0.0);
     } else {
-      const int child = r / R, i = r % R;
+      t[J] = 0.0;
+    }
+  }
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) S[((c0 + child) * RMAX + i) * RMAX + c] = q[c];
+  for (int c = 0; c < RMAX; ++c) {
+    sh.T[lane][c] = t[c];
+    if (Tg) Tg[lane * RMAX + c] = t[c];
+  }
+}
+
+// Scale of the stored reflector entries of column c: scal_c straight after
+// the factorization (SCALED), 1 for reflectors read back from memory.
+template <bool SCALED, int RMAX, int P>
+__device__ __forceinline__ double vscale(const Shared<RMAX, P>& sh, int c) {
+  return SCALED ? sh.scal[c] : 1.0;
+}
+
+// The top R x R block of V into sh.V1 (zero beyond R).
+template <bool SCALED, int RMAX, int P>
+__device__ __forceinline__ void node_v1(const double (&a)[P][CW], int R, int w, int lane, Shared<RMAX, P>& sh) {
+  if (lane < RMAX) {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w * CW + j;
+      sh.V1[lane][c] = (lane < R && c < R) ? vcomp(a[0][j], vscale<SCALED>(sh, c), c, lane) : 0.0;
     }
   }
 }
 
-// Up-sweep below the root, one launch per level, one node per
-// single-wavefront workgroup: factorize the node, save its reflectors and T,
-// pass its R up.
-template <int RMAX, int P, int SRC>
-__global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, const double* A, int64_t lda,
-                                                  KrpSrc krp, double* work) {
-  const int lane = threadIdx.x, node = blockIdx.x;
-  const int g = W * P / R;
-  const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
-  double a[P][RMAX], t[RMAX];
-  if (l == 0) {
-    int m;
-    int64_t start;
-    leaf_range(rows, L.nodes, node, start, m);
-    load_leaf<RMAX, P, SRC>(a, lane, start, m, R, A, lda, krp);
-  } else {
-    const int64_t c0 = int64_t(node) * g;
-    const int m = int(min<int64_t>(g, L.prev - c0)) * R;
-    load_stack<RMAX, P>(a, lane, m, R, work + L.s, c0);
+// Q rows of a node: [C; 0] - V M with M = T V1^T C (C in sh.C, T in sh.T,
+// V1 in sh.V1, all visible).  The rows go to the output (leaf: Qout at
+// `start`) or, as C blocks, to children c0 ... of the stacked level S.
+template <bool SCALED, int RMAX, int P>
+__device__ __forceinline__ void node_q(const double (&a)[P][CW], int R, int m, int w, int lane,
+                                       Shared<RMAX, P>& sh, bool leaf, int64_t start, double* Qout, int64_t ldq,
+                                       double* S, int64_t c0) {
+  constexpr int NT = RMAX / CW * W;
+  const int tid = w * W + lane;
+  for (int e = tid; e < RMAX * RMAX; e += NT) {  // B = V1^T C
+    const int k = e / RMAX, c = e % RMAX;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < RMAX; ++i) acc += sh.V1[i][k] * sh.C[i][c];
+    sh.B[k][c] = acc;
   }
-  wave_factor<RMAX, P>(a, t, lane, R);
-  double* V = work + L.v + int64_t(node) * P * RMAX * W;
+  __syncthreads();
+  for (int e = tid; e < RMAX * RMAX; e += NT) {  // M = T B
+    const int k = e / RMAX, c = e % RMAX;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < RMAX; ++i) acc += sh.T[k][i] * sh.B[i][c];
+    sh.M[k][c] = acc;
+  }
+  __syncthreads();
+  double sc[CW];
 #pragma unroll
-  for (int s = 0; s < P; ++s)
+  for (int j = 0; j < CW; ++j) sc[j] = w * CW + j < R ? vscale<SCALED>(sh, w * CW + j) : 0.0;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) V[(s * RMAX + c) * W + lane] = a[s][c];
-  if (lane < R) {
-    double* T = work + L.t + int64_t(node) * RMAX * RMAX;
+  for (int p = 0; p < P; ++p) {
+    double* vs = sh.buf + (p & 1) * RMAX * W;
+    const int r = p * W + lane;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int k = w * CW + j;
+      vs[k * W + lane] = k < R ? vcomp(a[p][j], sc[j], k, r) : 0.0;
+    }
+    __syncthreads();
+    double q[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) q[j] = r < RMAX ? sh.C[r][w * CW + j] : 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double vk = vs[k * W + lane];
+#pragma unroll
+      for (int j = 0; j < CW; ++j) q[j] -= vk * sh.M[k][w * CW + j];
+    }
+    if (r < m) {
+      if (leaf) {
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+          const int c = w * CW + j;
+          if (c < R) Qout[start + r + c * ldq] = q[j];
+        }
+      } else {
+        const int child = r / R, i = r % R;
+#pragma unroll
+        for (int j = 0; j < CW; ++j) S[((c0 + child) * RMAX + i) * RMAX + w * CW + j] = q[j];
+      }
+    }
+  }
+}
+
+// Rows and first row of node `node` at level l.
+__device__ __forceinline__ void node_rows(int64_t rows, int R, int P, int l, const NodeLevel& L, int node,
+                                          int64_t& start, int64_t& c0, int& m) {
+  start = 0;
+  c0 = 0;
+  if (l == 0) {
+    leaf_range(rows, L.nodes, node, start, m);
+  } else {
+    const int g = W * P / R;
+    c0 = int64_t(node) * g;
+    m = int(min<int64_t>(g, L.prev - c0)) * R;
+  }
+}
+
+// Up-sweep below the root, one launch per level, one workgroup per node:
+// factorize the node, save its reflectors and T, pass its R up.
+template <int RMAX, int P, int SRC>
+__global__ __launch_bounds__(RMAX / CW * W) void bn_up(int64_t rows, int R, int l, const double* A, int64_t lda,
+                                                       KrpSrc krp, double* work) {
+  __shared__ Shared<RMAX, P> sh;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W, node = blockIdx.x;
+  const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
+  int64_t start, c0;
+  int m;
+  node_rows(rows, R, P, l, L, node, start, c0, m);
+  double a[P][CW];
+  if (l == 0)
+    load_leaf<RMAX, P, SRC>(a, w, lane, start, m, R, A, lda, krp);
+  else
+    load_stack<RMAX, P>(a, w, lane, m, R, work + L.s, c0);
+  node_factor<RMAX>(a, R, w, lane, sh);
+  node_t<RMAX>(R, w, lane, sh, work + L.t + size_t(node) * RMAX * RMAX);
+  // reflector entries as v (scaled); rows on and above the diagonal as stored
+  double* V = work + L.v + size_t(node) * P * RMAX * W;
+  double sc[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) sc[j] = w * CW + j < R ? sh.scal[w * CW + j] : 0.0;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int j = 0; j < CW; ++j) V[(p * RMAX + w * CW + j) * W + lane] = a[p][j] * sc[j];
+  if (lane < RMAX) {
     double* Snext = work + level_of(rows, R, P, RMAX, l + 1, nullptr).s;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) {
-      T[lane * RMAX + c] = t[c];
-      Snext[(int64_t(node) * RMAX + lane) * RMAX + c] = c >= lane ? a[0][c] : 0.0;
+    for (int j = 0; j < CW; ++j) {
+      const int c = w * CW + j;
+      Snext[(size_t(node) * RMAX + lane) * RMAX + c] =
+          (lane < R && c < R && c >= lane) ? (c == lane ? sh.beta[c] : a[0][j]) : 0.0;
     }
   }
 }
@@ -449,151 +510,133 @@ __global__ __launch_bounds__(W) void wave_tree_up(int64_t rows, int R, int l, co
 // C = I straight away: the output itself when the root is the only leaf,
 // else the C blocks of its children.
 template <int RMAX, int P, int SRC>
-__global__ __launch_bounds__(W) void wave_tree_root(int64_t rows, int R, const double* A, int64_t lda,
-                                                    KrpSrc krp, double* Qout, int64_t ldq, double* Rout,
-                                                    int64_t ldr, double* work) {
-  __shared__ Buf<RMAX> b;
-  __shared__ double Vl[P * RMAX * W];
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, const double* A, int64_t lda,
+                                                         KrpSrc krp, double* Qout, int64_t ldq, double* Rout,
+                                                         int64_t ldr, double* work) {
+  __shared__ Shared<RMAX, P> sh;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W;
   const int top = level_count(rows, R, P) - 1;
   const NodeLevel L = level_of(rows, R, P, RMAX, top, nullptr);
-  double t[RMAX], crow[RMAX];
+  int64_t start, c0;
   int m;
-  int64_t start = 0;
-  {
-    double a[P][RMAX];
-    if (top == 0) {
-      leaf_range(rows, 1, 0, start, m);
-      load_leaf<RMAX, P, SRC>(a, lane, start, m, R, A, lda, krp);
-    } else {
-      m = L.prev * R;
-      load_stack<RMAX, P>(a, lane, m, R, work + L.s, 0);
+  node_rows(rows, R, P, top, L, 0, start, c0, m);
+  double a[P][CW];
+  if (top == 0)
+    load_leaf<RMAX, P, SRC>(a, w, lane, start, m, R, A, lda, krp);
+  else
+    load_stack<RMAX, P>(a, w, lane, m, R, work + L.s, 0);
+  node_factor<RMAX>(a, R, w, lane, sh);
+  node_t<RMAX>(R, w, lane, sh, nullptr);
+  node_v1<true, RMAX>(a, R, w, lane, sh);
+  if (lane < R) {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w * CW + j;
+      if (c < R) Rout[lane + c * ldr] = c > lane ? a[0][j] : (c == lane ? sh.beta[c] : 0.0);
     }
-    wave_factor<RMAX, P>(a, t, lane, R);
-    if (lane < R) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        if (c < R) Rout[lane + c * ldr] = c >= lane ? a[0][c] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < P; ++s)
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) Vl[(s * RMAX + c) * W + lane] = a[s][c];
   }
-  for (int e = lane; e < RMAX * RMAX; e += W) {
+  for (int e = threadIdx.x; e < RMAX * RMAX; e += RMAX / CW * W) {
     const int i = e / RMAX, c = e % RMAX;
-    b.Z[i][c] = (i < R && i == c) ? 1.0 : 0.0;
+    sh.C[i][c] = (i < R && i == c) ? 1.0 : 0.0;
   }
-  wave_sync();
-  wave_m<RMAX>(Vl, t, crow, lane, R, b);
-  store_q<RMAX, P>(Vl, crow, lane, R, m, top == 0, start, Qout, ldq, work + L.s, 0, b);
+  __syncthreads();
+  node_q<true, RMAX>(a, R, m, w, lane, sh, top == 0, start, Qout, ldq, work + L.s, 0);
 }
 
 // Down-sweep below the root, one launch per level: each node applies its
 // reflectors to its C block and writes its Q rows: the output, or its
 // children's C blocks.
 template <int RMAX, int P>
-__global__ __launch_bounds__(W) void wave_tree_down(int64_t rows, int R, int l, double* Qout, int64_t ldq,
-                                                    double* work) {
-  __shared__ Buf<RMAX> b;
-  __shared__ double Vl[P * RMAX * W];
-  const int lane = threadIdx.x, node = blockIdx.x;
-  const int g = W * P / R;
+__global__ __launch_bounds__(RMAX / CW * W) void bn_down(int64_t rows, int R, int l, double* Qout, int64_t ldq,
+                                                         double* work) {
+  __shared__ Shared<RMAX, P> sh;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W, node = blockIdx.x;
   const NodeLevel L = level_of(rows, R, P, RMAX, l, nullptr);
-  const double* Cin = work + level_of(rows, R, P, RMAX, l + 1, nullptr).s;
-  double t[RMAX], crow[RMAX];
-  const double* V = work + L.v + int64_t(node) * P * RMAX * W;
-  const double* T = work + L.t + int64_t(node) * RMAX * RMAX;
-#pragma unroll 8
-  for (int e = lane; e < P * RMAX * W; e += W) Vl[e] = V[e];
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) t[c] = lane < R ? T[lane * RMAX + c] : 0.0;
-  for (int e = lane; e < RMAX * RMAX; e += W) {
-    const int i = e / RMAX, c = e % RMAX;
-    b.Z[i][c] = (i >= R || c >= R) ? 0.0 : Cin[int64_t(node) * RMAX * RMAX + e];
-  }
-  wave_sync();
-  wave_m<RMAX>(Vl, t, crow, lane, R, b);
+  int64_t start, c0;
   int m;
-  int64_t start = 0, c0 = 0;
-  if (l == 0) {
-    leaf_range(rows, L.nodes, node, start, m);
-  } else {
-    c0 = int64_t(node) * g;
-    m = int(min<int64_t>(g, L.prev - c0)) * R;
+  node_rows(rows, R, P, l, L, node, start, c0, m);
+  const double* V = work + L.v + size_t(node) * P * RMAX * W;
+  const double* T = work + L.t + size_t(node) * RMAX * RMAX;
+  const double* Cin = work + level_of(rows, R, P, RMAX, l + 1, nullptr).s + size_t(node) * RMAX * RMAX;
+  double a[P][CW];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int j = 0; j < CW; ++j) a[p][j] = V[(p * RMAX + w * CW + j) * W + lane];
+  for (int e = threadIdx.x; e < RMAX * RMAX; e += RMAX / CW * W) {
+    const int i = e / RMAX, c = e % RMAX;
+    sh.T[i][c] = T[e];
+    sh.C[i][c] = (i < R && c < R) ? Cin[e] : 0.0;
   }
-  store_q<RMAX, P>(Vl, crow, lane, R, m, l == 0, start, Qout, ldq, work + L.s, c0, b);
+  node_v1<false, RMAX>(a, R, w, lane, sh);
+  __syncthreads();
+  node_q<false, RMAX>(a, R, m, w, lane, sh, l == 0, start, Qout, ldq, work + L.s, c0);
 }
 
-}  // namespace wt
+}  // namespace bn
 
 // ------------------------------------------------------------ host side
-// Rows per lane: 1 at R > 16 (registers); otherwise 2 or 4, whichever gives
-// fewer levels, 2 on a tie (measured on MI355X: fewer, fatter levels win,
-// and at equal depth the lighter nodes do).
-int wt_rows_per_lane(int64_t rows, int R) {
-  if (round_rank(R) > 16) return 1;
-  return wt::level_count(rows, R, 4) < wt::level_count(rows, R, 2) ? 4 : 2;
-}
+// Row slots per lane: 4 (256-row nodes) when that takes a single node, else
+// 16 (1024-row nodes, one level up to 1024 rows).
+int bn_slots(int64_t rows) { return rows <= 4 * bn::W ? 4 : 16; }
 
-size_t wt_work(int64_t rows, int R, int P) {
+size_t bn_work(int64_t rows, int R) {
+  const int P = bn_slots(rows);
   size_t total = 0;
-  wt::level_of(rows, R, P, round_rank(R), wt::level_count(rows, R, P) - 1, &total);
+  bn::level_of(rows, R, P, round_rank(R), bn::level_count(rows, R, P) - 1, &total);
   return total * sizeof(double);
 }
 
 template <int RMAX, int P>
-int wt_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
+int bn_launch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
               int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s, hipEvent_t r_ready) {
   double* w = static_cast<double*>(work);
-  const int nlev = wt::level_count(rows, R, P);
+  const int nlev = bn::level_count(rows, R, P);
+  const dim3 blk(RMAX / bn::CW * bn::W);
   for (int l = 0; l + 1 < nlev; ++l) {
-    const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
+    const dim3 grd(unsigned(bn::level_of(rows, R, P, RMAX, l, nullptr).nodes));
     if (src == SRC_MATRIX)
-      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_MATRIX>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
+      hipLaunchKernelGGL((bn::bn_up<RMAX, P, SRC_MATRIX>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
     else
-      hipLaunchKernelGGL((wt::wave_tree_up<RMAX, P, SRC_KRP>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
-    CPQR_TRY(check_launch("wave_tree_up"));
+      hipLaunchKernelGGL((bn::bn_up<RMAX, P, SRC_KRP>), grd, blk, 0, s, rows, R, l, A, lda, krp, w);
+    CPQR_TRY(check_launch("bn_up"));
   }
   if (src == SRC_MATRIX)
-    hipLaunchKernelGGL((wt::wave_tree_root<RMAX, P, SRC_MATRIX>), dim3(1), dim3(wt::W), 0, s, rows, R, A, lda,
-                       krp, Q, ldq, Rout, ldr_out, w);
+    hipLaunchKernelGGL((bn::bn_root<RMAX, P, SRC_MATRIX>), dim3(1), blk, 0, s, rows, R, A, lda, krp, Q, ldq, Rout,
+                       ldr_out, w);
   else
-    hipLaunchKernelGGL((wt::wave_tree_root<RMAX, P, SRC_KRP>), dim3(1), dim3(wt::W), 0, s, rows, R, A, lda,
-                       krp, Q, ldq, Rout, ldr_out, w);
-  CPQR_TRY(check_launch("wave_tree_root"));
-  if (r_ready) CPQR_HIP(hipEventRecord(r_ready, s));  // R is complete; Q follows
+    hipLaunchKernelGGL((bn::bn_root<RMAX, P, SRC_KRP>), dim3(1), blk, 0, s, rows, R, A, lda, krp, Q, ldq, Rout,
+                       ldr_out, w);
+  CPQR_TRY(check_launch("bn_root"));
+  if (r_ready) CPQR_HIP(hipEventRecord(r_ready, s));  // R is complete; Q may follow
   for (int l = nlev - 2; l >= 0; --l) {
-    const dim3 grd(unsigned(wt::level_of(rows, R, P, RMAX, l, nullptr).nodes)), blk(wt::W);
-    hipLaunchKernelGGL((wt::wave_tree_down<RMAX, P>), grd, blk, 0, s, rows, R, l, Q, ldq, w);
-    CPQR_TRY(check_launch("wave_tree_down"));
+    const dim3 grd(unsigned(bn::level_of(rows, R, P, RMAX, l, nullptr).nodes));
+    hipLaunchKernelGGL((bn::bn_down<RMAX, P>), grd, blk, 0, s, rows, R, l, Q, ldq, w);
+    CPQR_TRY(check_launch("bn_down"));
   }
   return CPQR_OK;
-}
-
-int wt_run(int P, int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp, double* Q,
-           int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s, hipEvent_t r_ready) {
-  switch (round_rank(R)) {
-    case 8:
-      return P == 2 ? wt_launch<8, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
-                    : wt_launch<8, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
-    case 16:
-      return P == 2 ? wt_launch<16, 2>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
-                    : wt_launch<16, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
-    default:
-      return wt_launch<32, 1>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
-  }
 }
 
 int tsqr_dispatch(int src, int64_t rows, int R, const double* A, int64_t lda, const KrpSrc& krp,
                   double* Q, int64_t ldq, double* Rout, int64_t ldr_out, void* work, hipStream_t s,
                   hipEvent_t r_ready = nullptr) {
-  return wt_run(wt_rows_per_lane(rows, R), src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
+  const bool small = bn_slots(rows) == 4;
+  switch (round_rank(R)) {
+    case 8:
+      return small ? bn_launch<8, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
+                   : bn_launch<8, 16>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
+    case 16:
+      return small ? bn_launch<16, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
+                   : bn_launch<16, 16>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
+    default:
+      return small ? bn_launch<32, 4>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready)
+                   : bn_launch<32, 16>(src, rows, R, A, lda, krp, Q, ldq, Rout, ldr_out, work, s, r_ready);
+  }
 }
 
 }  // namespace
 
-size_t tsqr_work(int64_t rows, int R) { return wt_work(rows, R, wt_rows_per_lane(rows, R)); }
+size_t tsqr_work(int64_t rows, int R) { return bn_work(rows, R); }
 
 int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
                       double* Rk, int64_t ldr, void* work, hipStream_t s, hipEvent_t r_ready) {

@@ -50,9 +50,12 @@ def test_validation_codes(L):
     assert L.cpqr_factor_qr(3, 4, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
     assert L.cpqr_factor_qr(10, 4, None, 10, P, 10, P, 10, P, 1 << 20, None) == -1
     assert L.cpqr_factor_qr(10, 4, P, 9, P, 10, P, 10, P, 1 << 20, None) == -2
-    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, None, 0, None) == -4
-    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, P + 8, 1 << 20, None) == -4
-    assert L.cpqr_factor_qr(10, 4, P, 10, P, 10, P, 10, P, 16, None) == -4
+    # 5000 rows take a two-level tree, which needs a work buffer
+    assert L.cpqr_factor_qr_work(1000, 4) == 0
+    assert L.cpqr_factor_qr_work(5000, 4) > 16
+    assert L.cpqr_factor_qr(5000, 4, P, 5000, P, 5000, P, 10, None, 0, None) == -4
+    assert L.cpqr_factor_qr(5000, 4, P, 5000, P, 5000, P, 10, P + 8, 1 << 20, None) == -4
+    assert L.cpqr_factor_qr(5000, 4, P, 5000, P, 5000, P, 10, P, 16, None) == -4
     assert b"too small" in L.cpqr_last_error()
 
     I = C._i64_array([10, 11, 12])
@@ -96,7 +99,11 @@ def test_validation_codes(L):
 
 
 def test_workspace_queries(L):
-    assert L.cpqr_factor_qr_work(1000, 16) > 0
+    # up to 1024 rows: one node, no work buffer; 5000 x 16: five 1024-row
+    # leaves (reflectors 1024 x 16 and T 16 x 16 each) under a root that
+    # stacks their five 16 x 16 R factors
+    assert L.cpqr_factor_qr_work(1000, 16) == 0
+    assert L.cpqr_factor_qr_work(5000, 16) == 8 * (5 * 1024 * 16 + 5 * 256 + 5 * 256)
     assert L.cpqr_factor_qr_work(1000, 0) == 0
     assert L.cpqr_krp_qr_work(4, 32) >= 32768 * 32 * 8
     for n in range(3):
