@@ -196,8 +196,9 @@ __device__ __forceinline__ double wave_allsum(double x, int lane) {
 template <int RMAX, int P>
 struct Shared {
   // the current reflector while factorizing (double buffered, [p][lane]),
-  // then rows of V while forming Q (double buffered, [c][lane])
-  double buf[2 * (P > RMAX ? P : RMAX) * W];
+  // then a chunk of QCHUNK slots of V while forming Q ([slot][c][lane])
+  static constexpr int QCHUNK = P < 128 / RMAX ? P : 128 / RMAX;
+  double buf[(2 * P > QCHUNK * RMAX ? 2 * P : QCHUNK * RMAX) * W];
   double G[RMAX][RMAX + 1];  // G(k, J) = v_k^T v_J, k < J
   double T[RMAX][RMAX + 1];
   double C[RMAX][RMAX + 1];
@@ -264,6 +265,16 @@ __device__ __forceinline__ void load_stack(double (&a)[P][CW], int w, int lane, 
   }
 }
 
+// 1 / x from the hardware estimate and two Newton steps (a few ulp at most
+// from the rounded quotient; x is never 0 here).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Reflector J from the wavefront's column slot JL (rows > J of it form x):
 // H_J = I - tau v v^T with v(J) = 1, v(r > J) = x(r) scal, scal =
 // 1 / (alpha - beta).  Writes v ([p][lane], zero above row J) to vb and
@@ -272,21 +283,25 @@ __device__ __forceinline__ void load_stack(double (&a)[P][CW], int w, int lane, 
 template <int RMAX, int P, int JL>
 __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lane, double* vb,
                                         Shared<RMAX, P>& sh) {
-  double x[P];
-  double ss = 0.0;
+  constexpr int NA = P < 4 ? P : 4;  // independent partial sums
+  double x[P], ss[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) ss[u] = 0.0;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     x[p] = (p > 0 || lane > J) ? a[p][JL] : 0.0;
-    ss += x[p] * x[p];
+    ss[p % NA] += x[p] * x[p];
   }
-  const double sub2 = wave_allsum(ss, lane);
+#pragma unroll
+  for (int u = 1; u < NA; ++u) ss[0] += ss[u];
+  const double sub2 = wave_allsum(ss[0], lane);
   const double alpha = rdlane(a[0][JL], J);
   double tau = 0.0, beta = alpha, scal = 0.0;
   if (sub2 > 0.0) {
     const double nrm = sqrt(alpha * alpha + sub2);
     beta = alpha >= 0.0 ? -nrm : nrm;
-    tau = (beta - alpha) / beta;
-    scal = 1.0 / (alpha - beta);
+    tau = (beta - alpha) * recip(beta);
+    scal = recip(alpha - beta);
   }
 #pragma unroll
   for (int p = 0; p < P; ++p) vb[p * W + lane] = (p == 0 && lane == J) ? 1.0 : x[p] * scal;
@@ -297,13 +312,33 @@ __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lan
   }
 }
 
-// Householder QR of the node (rows beyond it zero).  On
-// return the wavefront's column slots hold, for its columns c, R(r, c) in
-// rows r < c and x_c below the diagonal (v_c = x_c scal_c there); sh.tau,
-// sh.scal, sh.beta (R's diagonal) and sh.G are set.
+// Column J of the compact WY factor T, lane i of a wavefront forming T(i, J):
+// T(0:J, J) = -tau_J T(0:J, 0:J) G(0:J, J), T(J, J) = tau_J.  Needs G(:, J)
+// and the columns of T left of J; the entries of T and G not yet set are zero.
+template <int RMAX, int P>
+__device__ __forceinline__ void t_column(int J, int lane, Shared<RMAX, P>& sh) {
+  if (lane < RMAX) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) acc += sh.T[lane][k] * sh.G[k][J];
+    const double tj = sh.tau[J];
+    if (lane <= J) sh.T[lane][J] = lane < J ? -tj * acc : tj;
+  }
+}
+
+// Householder QR of the node (rows beyond it zero).  On return the
+// wavefront's column slots hold, for its columns c, R(r, c) in rows r < c
+// and x_c below the diagonal (v_c = x_c scal_c there); sh.tau, sh.scal,
+// sh.beta (R's diagonal), sh.G and sh.T (zero beyond R) are set and visible.
+// Wavefront 0, whose columns are the first to be finished, forms column
+// J - 1 of T during step J.
 template <int RMAX, int P>
 __device__ __forceinline__ void node_factor(double (&a)[P][CW], int R, int w, int lane,
                                             Shared<RMAX, P>& sh) {
+  for (int e = threadIdx.x; e < RMAX * (RMAX + 1); e += RMAX / CW * W) {
+    (&sh.G[0][0])[e] = 0.0;
+    (&sh.T[0][0])[e] = 0.0;
+  }
   for (int J = 0; J < R; ++J) {
     double* vb = sh.buf + (J & 1) * P * W;
     const int jl = J - w * CW;
@@ -343,34 +378,11 @@ __device__ __forceinline__ void node_factor(double (&a)[P][CW], int R, int w, in
         sh.G[c][J] = sh.scal[c] * sj;  // rows >= J of column c hold x_c there
       }
     }
+    if (w == 0 && J > 0) t_column<RMAX>(J - 1, lane, sh);
   }
   __syncthreads();
-}
-
-// Compact WY factor T from sh.tau and sh.G, lane i of wavefront 0 forming row
-// i: T(0:J, J) = -tau_J T(0:J, 0:J) G(0:J, J), T(J, J) = tau_J.  Writes it to
-// sh.T and, if Tg is set, to Tg ([row][c]).  Zero beyond R.
-template <int RMAX, int P>
-__device__ __forceinline__ void node_t(int R, int w, int lane, Shared<RMAX, P>& sh, double* Tg) {
-  if (w != 0 || lane >= RMAX) return;
-  double t[RMAX];
-#pragma unroll
-  for (int J = 0; J < RMAX; ++J) {
-    if (J < R) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < J; ++k) acc += t[k] * sh.G[k][J];
-      const double tj = sh.tau[J];
-      t[J] = lane < J ? -tj * acc : (lane == J ? tj : 0.0);
-    } else {
-      t[J] = 0.0;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) {
-    sh.T[lane][c] = t[c];
-    if (Tg) Tg[lane * RMAX + c] = t[c];
-  }
+  if (w == 0) t_column<RMAX>(R - 1, lane, sh);
+  __syncthreads();
 }
 
 // Scale of the stored reflector entries of column c: scal_c straight after
@@ -420,35 +432,59 @@ __device__ __forceinline__ void node_q(const double (&a)[P][CW], int R, int m, i
   double sc[CW];
 #pragma unroll
   for (int j = 0; j < CW; ++j) sc[j] = w * CW + j < R ? vscale<SCALED>(sh, w * CW + j) : 0.0;
+  // QCHUNK slots at a time: every wavefront stages its columns of V for
+  // those rows in LDS, then forms its columns of Q for them, k outermost so
+  // that each row of M is read once per chunk.
+  constexpr int QC = Shared<RMAX, P>::QCHUNK;
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    double* vs = sh.buf + (p & 1) * RMAX * W;
-    const int r = p * W + lane;
+  for (int p0 = 0; p0 < P; p0 += QC) {
+    if (p0 > 0) __syncthreads();  // the previous chunk has been read
 #pragma unroll
-    for (int j = 0; j < CW; ++j) {
-      const int k = w * CW + j;
-      vs[k * W + lane] = k < R ? vcomp(a[p][j], sc[j], k, r) : 0.0;
+    for (int u = 0; u < QC; ++u) {
+#pragma unroll
+      for (int j = 0; j < CW; ++j) {
+        // rows of slots >= 1 lie below every diagonal (R <= 32 < 64); sc is 0 beyond R
+        const int k = w * CW + j;
+        sh.buf[(u * RMAX + k) * W + lane] =
+            p0 + u > 0 ? a[p0 + u][j] * sc[j] : (k < R ? vcomp(a[0][j], sc[j], k, lane) : 0.0);
+      }
     }
     __syncthreads();
-    double q[CW];
+    double q[QC][CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) q[j] = r < RMAX ? sh.C[r][w * CW + j] : 0.0;
-    for (int k = 0; k < R; ++k) {
-      const double vk = vs[k * W + lane];
+    for (int u = 0; u < QC; ++u) {
+      const int r = (p0 + u) * W + lane;
 #pragma unroll
-      for (int j = 0; j < CW; ++j) q[j] -= vk * sh.M[k][w * CW + j];
+      for (int j = 0; j < CW; ++j) q[u][j] = (p0 + u == 0 && r < RMAX) ? sh.C[r][w * CW + j] : 0.0;
     }
-    if (r < m) {
-      if (leaf) {
+    // rows k >= R of M and of the staged V are zero: no branches on R
+#pragma unroll 4
+    for (int k = 0; k < RMAX; ++k) {
+      double mk[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-          const int c = w * CW + j;
-          if (c < R) Qout[start + r + c * ldq] = q[j];
+      for (int j = 0; j < CW; ++j) mk[j] = sh.M[k][w * CW + j];
+#pragma unroll
+      for (int u = 0; u < QC; ++u) {
+        const double vk = sh.buf[(u * RMAX + k) * W + lane];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) q[u][j] -= vk * mk[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int r = (p0 + u) * W + lane;
+      if (r < m) {
+        if (leaf) {
+#pragma unroll
+          for (int j = 0; j < CW; ++j) {
+            const int c = w * CW + j;
+            if (c < R) Qout[start + r + c * ldq] = q[u][j];
+          }
+        } else {
+          const int child = r / R, i = r % R;
+#pragma unroll
+          for (int j = 0; j < CW; ++j) S[((c0 + child) * RMAX + i) * RMAX + w * CW + j] = q[u][j];
         }
-      } else {
-        const int child = r / R, i = r % R;
-#pragma unroll
-        for (int j = 0; j < CW; ++j) S[((c0 + child) * RMAX + i) * RMAX + w * CW + j] = q[j];
       }
     }
   }
@@ -485,7 +521,8 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_up(int64_t rows, int R, int 
   else
     load_stack<RMAX, P>(a, w, lane, m, R, work + L.s, c0);
   node_factor<RMAX>(a, R, w, lane, sh);
-  node_t<RMAX>(R, w, lane, sh, work + L.t + size_t(node) * RMAX * RMAX);
+  double* Tg = work + L.t + size_t(node) * RMAX * RMAX;
+  for (int e = threadIdx.x; e < RMAX * RMAX; e += RMAX / CW * W) Tg[e] = sh.T[e / RMAX][e % RMAX];
   // reflector entries as v (scaled); rows on and above the diagonal as stored
   double* V = work + L.v + size_t(node) * P * RMAX * W;
   double sc[CW];
@@ -526,7 +563,6 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, co
   else
     load_stack<RMAX, P>(a, w, lane, m, R, work + L.s, 0);
   node_factor<RMAX>(a, R, w, lane, sh);
-  node_t<RMAX>(R, w, lane, sh, nullptr);
   node_v1<true, RMAX>(a, R, w, lane, sh);
   if (lane < R) {
 #pragma unroll
