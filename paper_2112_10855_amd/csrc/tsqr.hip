@@ -282,7 +282,7 @@ __device__ __forceinline__ double recip(double x) {
 // reflector is x scal below the diagonal, R(J, J) is beta).
 template <int RMAX, int P, int JL>
 __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lane, double* vb,
-                                        Shared<RMAX, P>& sh) {
+                                        Shared<RMAX, P>& sh, double (&own_scal)[CW]) {
   constexpr int NA = P < 4 ? P : 4;  // independent partial sums
   double x[P], ss[NA];
 #pragma unroll
@@ -305,6 +305,7 @@ __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lan
   }
 #pragma unroll
   for (int p = 0; p < P; ++p) vb[p * W + lane] = (p == 0 && lane == J) ? 1.0 : x[p] * scal;
+  own_scal[JL] = scal;
   if (lane == 0) {
     sh.tau[J] = tau;
     sh.scal[J] = scal;
@@ -312,41 +313,42 @@ __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lan
   }
 }
 
-// Column J of the compact WY factor T, lane i of a wavefront forming T(i, J):
-// T(0:J, J) = -tau_J T(0:J, 0:J) G(0:J, J), T(J, J) = tau_J.  Needs G(:, J)
-// and the columns of T left of J; the entries of T and G not yet set are zero.
+// Compact WY factor T from sh.tau and sh.G: lane i of wavefront 0 forms row
+// i, T(i, J) = -tau_J sum_k T(i, k) G(k, J) (i < J), T(J, J) = tau_J, so
+// the lanes need no exchange.  Zero beyond R.
 template <int RMAX, int P>
-__device__ __forceinline__ void t_column(int J, int lane, Shared<RMAX, P>& sh) {
-  if (lane < RMAX) {
-    double acc = 0.0;
+__device__ __forceinline__ void node_t(int R, int w, int lane, Shared<RMAX, P>& sh) {
+  if (w != 0 || lane >= RMAX) return;
+  double t[RMAX];
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) acc += sh.T[lane][k] * sh.G[k][J];
-    const double tj = sh.tau[J];
-    if (lane <= J) sh.T[lane][J] = lane < J ? -tj * acc : tj;
+  for (int J = 0; J < RMAX; ++J) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < J; ++k) acc[k % 4] += t[k] * sh.G[k][J];
+    const double tj = J < R ? sh.tau[J] : 0.0;
+    t[J] = lane < J ? -tj * ((acc[0] + acc[1]) + (acc[2] + acc[3])) : (lane == J ? tj : 0.0);
   }
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) sh.T[lane][c] = t[c];
 }
 
 // Householder QR of the node (rows beyond it zero).  On return the
 // wavefront's column slots hold, for its columns c, R(r, c) in rows r < c
 // and x_c below the diagonal (v_c = x_c scal_c there); sh.tau, sh.scal,
 // sh.beta (R's diagonal), sh.G and sh.T (zero beyond R) are set and visible.
-// Wavefront 0, whose columns are the first to be finished, forms column
-// J - 1 of T during step J.
 template <int RMAX, int P>
 __device__ __forceinline__ void node_factor(double (&a)[P][CW], int R, int w, int lane,
                                             Shared<RMAX, P>& sh) {
-  for (int e = threadIdx.x; e < RMAX * (RMAX + 1); e += RMAX / CW * W) {
-    (&sh.G[0][0])[e] = 0.0;
-    (&sh.T[0][0])[e] = 0.0;
-  }
+  for (int e = threadIdx.x; e < RMAX * (RMAX + 1); e += RMAX / CW * W) (&sh.G[0][0])[e] = 0.0;
+  double own_scal[CW] = {0.0, 0.0, 0.0, 0.0};
   for (int J = 0; J < R; ++J) {
     double* vb = sh.buf + (J & 1) * P * W;
     const int jl = J - w * CW;
     switch (jl) {  // the owner of column J forms the reflector
-      case 0: reflect<RMAX, P, 0>(a, J, lane, vb, sh); break;
-      case 1: reflect<RMAX, P, 1>(a, J, lane, vb, sh); break;
-      case 2: reflect<RMAX, P, 2>(a, J, lane, vb, sh); break;
-      case 3: reflect<RMAX, P, 3>(a, J, lane, vb, sh); break;
+      case 0: reflect<RMAX, P, 0>(a, J, lane, vb, sh, own_scal); break;
+      case 1: reflect<RMAX, P, 1>(a, J, lane, vb, sh, own_scal); break;
+      case 2: reflect<RMAX, P, 2>(a, J, lane, vb, sh, own_scal); break;
+      case 3: reflect<RMAX, P, 3>(a, J, lane, vb, sh, own_scal); break;
       default: break;
     }
     __syncthreads();
@@ -365,23 +367,24 @@ __device__ __forceinline__ void node_factor(double (&a)[P][CW], int R, int w, in
       s[j] = acc;
     }
     const double red = wave_sum<CW>(s, lane);
+    double sj[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) sj[j] = rdlane(red, j << (6 - ilog2(CW)));
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
       const int c = w * CW + j;
-      const double sj = rdlane(red, j << (6 - ilog2(CW)));
       if (c > J && c < R) {
-        const double tw = tau * sj;
+        const double tw = tau * sj[j];
 #pragma unroll
         for (int p = 0; p < P; ++p)
           a[p][j] -= tw * v[p];
       } else if (c < J && lane == 0) {
-        sh.G[c][J] = sh.scal[c] * sj;  // rows >= J of column c hold x_c there
+        sh.G[c][J] = own_scal[j] * sj[j];  // rows >= J of column c hold x_c there
       }
     }
-    if (w == 0 && J > 0) t_column<RMAX>(J - 1, lane, sh);
   }
   __syncthreads();
-  if (w == 0) t_column<RMAX>(R - 1, lane, sh);
+  node_t<RMAX>(R, w, lane, sh);
   __syncthreads();
 }
 
