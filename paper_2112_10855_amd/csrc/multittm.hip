@@ -47,8 +47,22 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Tensor loads of the row-tiled kernels; NT marks them non-temporal.  A
+// first contraction whose contracted-matrix rows are 128-byte multiples apart
+// (P % 32 == 0) shares no cache line between row tiles and streams faster so
+// (1000^3, mode-3 contraction: 0.70 -> 0.66 ms on MI355X); with unaligned
+// rows (P = 1000) neighbouring tiles share lines and the hint costs 7 %.
+template <bool NT>
+__device__ __forceinline__ float4 ldx(const float* p) {
+  if constexpr (NT) {
+    const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *reinterpret_cast<const float4*>(p);
+  }
+}
+
 constexpr int WAVE = 64;
-constexpr int WPB = 4;
 constexpr int TARGET_WAVES = 2048;  // wavefronts wanted when K is split (8 per CU)
 constexpr int MIN_WAVES = 1024;     // below this many wavefronts, split K
 
@@ -126,7 +140,7 @@ __device__ __forceinline__ void store_tiles(const floatx4 (&acc)[NB][MG][4], flo
 // STREAM marks the instantiation used for a first contraction (it streams the
 // whole tensor); it is the same code under its own symbol so that profiles and
 // phase timers can single it out.
-template <int NB, int UN, int MG, int NWV, bool STREAM, bool ONE>
+template <int NB, int UN, int MG, int NWV, bool STREAM, bool ONE, bool NT = false>
 __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__ X,
                                                        const float* __restrict__ U,
                                                        float* __restrict__ out, int64_t P,
@@ -172,7 +186,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
       for (int u = 0; u < UN; ++u)
 #pragma unroll
         for (int g = 0; g < MG; ++g)
-          dst[u][g] = *reinterpret_cast<const float4*>(bp[g] + int64_t(i0 + 4 * u) * P);
+          dst[u][g] = ldx<NT>(bp[g] + int64_t(i0 + 4 * u) * P);
     };
     auto compute = [&](const float4(&src)[UN][MG], int t) {
 #pragma unroll
@@ -236,6 +250,108 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
     if (!active) return;
   }
   store_tiles<NB, MG>(acc, out + int64_t(blockIdx.y) * split_stride, mt, M, P, R, l16, kq);
+}
+
+// ---------------- first contraction of a middle mode with short slabs
+// (P % 4 == 0, P % 32 != 0, P <= 64 MG NWV, R <= 16): one workgroup per slab
+// s, i.e. per contiguous P x K block X[:, :, s].  Rows of that block are
+// 4 P bytes apart, not a multiple of the 128-byte cache line, so row tiles
+// of several wavefronts would share lines at their edges (and fetch them
+// twice).  Here the workgroup copies KC whole rows of its block at a time
+// (one contiguous stretch of memory; NRS stretches in flight, staged in
+// registers) into LDS, then each wavefront runs the row-tiled MFMA steps on
+// its 64 MG rows of the block from LDS.  U rows come with each stretch.
+template <int MG, int NWV, int KC, int NRS, bool NT>
+__global__ __launch_bounds__(NWV * 64) void ttm_slab_m(const float* __restrict__ X, const float* __restrict__ U,
+                                                       float* __restrict__ out, int64_t P, int64_t K, int64_t S,
+                                                       int R) {
+  constexpr int NTH = NWV * 64, RP = 16;
+  constexpr int LPT = (KC * 64 * MG * NWV / 4 + NTH - 1) / NTH;  // float4 loads per thread per stretch
+  extern __shared__ float sm[];
+  const int Pi = int(P);
+  float* xb0 = sm;                        // [2][KC * P]
+  float* ub0 = sm + 2 * KC * Pi;          // [2][KC * RP]
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int l16 = lane % 16, kq = lane / 16;
+  const int64_t s = blockIdx.x;
+  const float* Xs = X + s * P * K;
+  const int nch = int((K + KC - 1) / KC);
+  floatx4 acc[MG][4];
+#pragma unroll
+  for (int g = 0; g < MG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float4 rs[NRS][LPT];
+  auto kcount = [&](int c) { return int(min<int64_t>(KC, K - int64_t(c) * KC)); };
+  auto load = [&](float4(&r)[LPT], int c) {
+    const float* src = Xs + int64_t(c) * KC * P;
+    const int n4 = kcount(c) * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      r[i] = e < n4 ? ldx<NT>(src + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](const float4(&r)[LPT], int c) {
+    float* xb = xb0 + (c & 1) * KC * Pi;
+    float* ub = ub0 + (c & 1) * KC * RP;
+    const int kc = kcount(c), n4 = kc * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      if (e < n4) *reinterpret_cast<float4*>(xb + 4 * e) = r[i];
+    }
+    for (int e = tid; e < kc * RP; e += NTH) ub[e] = U[int64_t(c) * KC * RP + e];
+  };
+  const int prow = w * 64 * MG + 4 * l16;  // first of the lane's four rows in group 0
+  auto compute = [&](int c) {
+    const float* xb = xb0 + (c & 1) * KC * Pi;
+    const float* ub = ub0 + (c & 1) * KC * RP;
+    const int kc = kcount(c);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int k = kk + kq;
+      const bool ok = k < kc;
+      const float bv = ok ? ub[k * RP + l16] : 0.f;
+#pragma unroll
+      for (int g = 0; g < MG; ++g) {
+        const int pr = prow + 64 * g;
+        const float4 xv = (ok && pr < Pi) ? *reinterpret_cast<const float4*>(xb + k * Pi + pr)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[g][0], 0, 0, 0);
+        acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[g][1], 0, 0, 0);
+        acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[g][2], 0, 0, 0);
+        acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[g][3], 0, 0, 0);
+      }
+    }
+  };
+  // register set j holds stretch c with c % NRS == j; at step c the set of
+  // stretch c (already in LDS) takes the loads of stretch c + NRS, stretch c
+  // is computed from LDS and stretch c + 1 goes to the other LDS buffer
+#pragma unroll
+  for (int j = 0; j < NRS; ++j)
+    if (j < nch) load(rs[j], j);
+  store(rs[0], 0);
+  __syncthreads();
+  for (int c0 = 0; c0 < nch; c0 += NRS) {
+#pragma unroll
+    for (int j = 0; j < NRS; ++j) {
+      const int c = c0 + j;
+      if (c < nch) {  // uniform over the workgroup
+        if (c + NRS < nch) load(rs[j], c + NRS);
+        compute(c);
+        if (c + 1 < nch) store(rs[(j + 1) % NRS], c + 1);
+        __syncthreads();
+      }
+    }
+  }
+  floatx4 acc1[1][MG][4];
+#pragma unroll
+  for (int g = 0; g < MG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc1[0][g][j] = acc[g][j];
+  // rows of this slab only: past P they would alias the next slab's rows
+  store_tiles<1, MG>(acc1, out, s * P + w * 64 * MG, (s + 1) * P, P, R, l16, kq);
 }
 
 // ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
@@ -385,7 +501,7 @@ __device__ inline void stage_u_bf16(const float* __restrict__ U, int64_t c0, int
 // A step covers 16 K rows: lane kq loads rows 4kq..4kq+3 (four float4 of four
 // consecutive p each); component j of the four loads forms the A operand of
 // the MFMA for rows m = mt + 4*l16 + j.
-template <bool SPLIT, int NB, int MG, int NWV, bool STREAM>
+template <bool SPLIT, int NB, int MG, int NWV, bool STREAM, bool NT = false>
 __global__ __launch_bounds__(NWV * 64) void ttm_bf16_m(const float* __restrict__ X,
                                                        const float* __restrict__ U,
                                                        float* __restrict__ out, int64_t P,
@@ -432,7 +548,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_bf16_m(const float* __restrict__
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int g = 0; g < MG; ++g) dst[r][g] = *reinterpret_cast<const float4*>(base[g] + (i0 + r) * P);
+        for (int g = 0; g < MG; ++g) dst[r][g] = ldx<NT>(base[g] + (i0 + r) * P);
     };
     auto compute = [&](const float4(&src)[4][MG], int64_t qoff) {
 #pragma unroll
@@ -813,8 +929,15 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_bf16_m");
     }
     if (s.mg != 2) return fail(CPQR_ERR_UNSUPPORTED, "ttm_bf16_m: unsupported row tile");
-    if (NB == 1)
+    const bool nt = STREAM && s.P % 32 == 0;  // see ldx
+    if (NB == 1 && nt)
+      launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+    else if (NB == 1)
       launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+    else if (nt)
+      launch_ev(ke, ttm_bf16_m<SPLIT, 2, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     else
       launch_ev(ke, ttm_bf16_m<SPLIT, 2, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
@@ -858,8 +981,29 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_mfma_m");
     }
     if (s.mg != MG) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m: unsupported row tile");
-    if (NB == 1 && one)
+    // short slabs whose rows are not line multiples apart: whole-slab workgroups
+    constexpr int SKC = 8, SNWV = 8, SMG = 2, SNRS = 3;
+    const size_t slab_lds = size_t(2) * SKC * (s.P + 16) * sizeof(float);
+    if (STREAM && NB == 1 && s.splits == 1 && s.P % 32 != 0 && s.P <= 64 * SMG * SNWV && slab_lds <= lds &&
+        s.S >= 256) {
+      const bool snt = (SKC * s.P) % 32 == 0 && (s.P * s.K) % 32 == 0;  // stretches start on line boundaries
+      if (snt)
+        launch_ev(ke, ttm_slab_m<SMG, SNWV, SKC, SNRS, true>, dim3(unsigned(s.S)), dim3(SNWV * 64), slab_lds, st,
+                  src, U, dst, s.P, s.K, s.S, R);
+      else
+        launch_ev(ke, ttm_slab_m<SMG, SNWV, SKC, SNRS, false>, dim3(unsigned(s.S)), dim3(SNWV * 64), slab_lds, st,
+                  src, U, dst, s.P, s.K, s.S, R);
+      return check_launch("ttm_slab_m");
+    }
+    const bool nt = STREAM && s.P % 32 == 0;  // see ldx
+    if (NB == 1 && one && nt)
+      launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (NB == 1 && one)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (NB == 2 && one && nt)
+      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else if (NB == 1)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,

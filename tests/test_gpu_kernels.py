@@ -116,6 +116,21 @@ def test_multittm_f64(shape, xdtype):
         assert relnorm(Y, Yo) < 1e-12
 
 
+@pytest.mark.parametrize("shape,R", [((600, 301, 257), 16), ((600, 304, 257), 16), ((60, 50, 300), 5),
+                                     ((100, 80, 260), 12)])
+def test_multittm_short_slabs(shape, R):
+    """Mode-3 update of tensors whose first contraction is over the middle
+    mode with short slabs (P = I_1 a multiple of 4 but not of 32, at least
+    256 slabs): whole-slab workgroups stage rows through LDS, with and without
+    a K tail and with line-aligned stretches (304 rows)."""
+    g = rng(sum(shape) + R)
+    X = g.standard_normal(shape).astype(np.float32)
+    Qs = [synth.orthonormal_columns(s, R, 10 * k + 3) for k, s in enumerate(shape)]
+    Y = to_np(C.cpqr_multittm(to_dev(X, torch.float32), [to_dev(Qs[0]), to_dev(Qs[1]), None], 2, C.PREC_F32))
+    Yo = OQ.multittm_unfolded(X.astype(np.float64), Qs, 2)
+    assert relnorm(Y, Yo) < 1e-5, relnorm(Y, Yo)
+
+
 def test_multittm_general_matrices_elementwise():
     """Non-orthonormal operands and an element-by-element check against the
     brute-force sum on a tiny tensor."""
