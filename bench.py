@@ -409,7 +409,7 @@ def main():
             "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
         },
         "roofline": {
-            "kernel": "ttm_mfma_m first contraction (streams X once; two per sweep with the mode reuse)",
+            "kernel": "first contraction of each Multi-TTM pass (streams X once; two per sweep with the mode reuse): ttm_mfma_m with non-temporal row tiles (mode-3 contraction) and ttm_slab_m with whole-slab LDS stretches (mode-2 contraction)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
