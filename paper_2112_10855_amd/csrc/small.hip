@@ -61,6 +61,84 @@ __global__ __launch_bounds__(BLK) void apply_q0_kernel(const TY* __restrict__ Y,
   if (live) part[int64_t(blockIdx.y) * In * R + i + int64_t(c) * In] = acc;
 }
 
+// The same product for a long K (many rows of Q_0 per row of W), as a tiled
+// matrix product: a workgroup forms a 64 x RM tile of W over its split of K,
+// each thread 2 rows x RM/8 columns; Y (widened to FP64) and Q_0 pass through
+// LDS 32 rows of Q_0 at a time, the next 32 prefetched in registers.
+template <class TY, int RM>
+__global__ __launch_bounds__(BLK) void apply_q0_tile(const TY* __restrict__ Y, const double* __restrict__ Q0,
+                                                     double* __restrict__ part, int64_t In, int64_t K, int R,
+                                                     int64_t kchunk) {
+  constexpr int KS = 32, TR = 64, CPT = RM / 8;
+  static_assert(BLK == 256, "thread mapping");
+  __shared__ double ys[KS][TR];
+  __shared__ double qs[KS][RM + 1];
+  const int t = threadIdx.x;
+  const int64_t i0 = int64_t(blockIdx.x) * TR;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t k1 = min(K, k0 + kchunk);
+  const int rp = t / 8, cq = t % 8;      // W rows i0 + 2 rp, + 1; columns cq CPT ...
+  const int lr = t % TR, lg = t / TR;    // Y loads: row lr, Q_0 rows 8 lg ... 8 lg + 7
+  const int qk = t % KS, qc = t / KS;    // Q_0 loads: row qk, columns qc CPT ...
+  double acc[2][CPT];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) acc[r][u] = 0.0;
+  TY yv[8];
+  double qv[CPT];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = kb + lg * 8 + u;
+      yv[u] = (i0 + lr < In && k < k1) ? Y[i0 + lr + k * In] : TY(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int c = qc * CPT + u;
+      const int64_t k = kb + qk;
+      qv[u] = (c < R && k < k1) ? Q0[k + int64_t(c) * K] : 0.0;
+    }
+  };
+  gload(k0);
+  for (int64_t kb = k0; kb < k1; kb += KS) {
+    __syncthreads();  // the previous rows are consumed
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ys[lg * 8 + u][lr] = double(yv[u]);
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) qs[qk][qc * CPT + u] = qv[u];
+    __syncthreads();
+    if (kb + KS < k1) gload(kb + KS);
+#pragma unroll 8
+    for (int k = 0; k < KS; ++k) {
+      const double a0 = ys[k][2 * rp], a1 = ys[k][2 * rp + 1];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const double b = qs[k][cq * CPT + u];
+        acc[0][u] += a0 * b;
+        acc[1][u] += a1 * b;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int64_t i = i0 + 2 * rp + r;
+    if (i >= In) continue;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int c = cq * CPT + u;
+      if (c < R) part[int64_t(blockIdx.y) * In * R + i + int64_t(c) * In] = acc[r][u];
+    }
+  }
+}
+
+// Kernel choice and split of the apply-Q_0 sum: the tiled product once K
+// exceeds 1024, with about 1024 workgroups and at most 128 splits.
+struct ApplyPlan {
+  bool tiled;
+  int64_t kchunk, splits;
+};
+
 __global__ void sum_parts(const double* __restrict__ part, int splits, int64_t count, double* dst) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
@@ -128,6 +206,7 @@ __global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict
   double w = 0.0;
   if (live) {
     const int64_t e = i + int64_t(c) * In;
+#pragma unroll 8
     for (int t = 0; t < splits; ++t) w += part[int64_t(t) * In * R + e];
     W[e] = w;
   }
@@ -442,40 +521,69 @@ int64_t apply_splits(int64_t In, int64_t K, int R) {
   return std::min<int64_t>(sp, 512);
 }
 
-constexpr int NORM_BLOCKS = 2048;
-
-}  // namespace
-
-size_t apply_q0_work(int64_t In, int64_t K, int R) {
-  Carver cv(nullptr);
-  cv.take<double>(size_t(apply_splits(In, K, R)) * In * R);
-  return cv.bytes();
+ApplyPlan apply_plan(int64_t In, int64_t K, int R) {
+  ApplyPlan ap{};
+  ap.tiled = K > 1024;
+  const int64_t sp = ap.tiled ? std::max<int64_t>(1, std::min<int64_t>({ceil_div(1024, ceil_div(In, 64)), 128,
+                                                                         ceil_div(K, 32)}))
+                              : apply_splits(In, K, R);
+  const int64_t q = ap.tiled ? 32 : 64;
+  ap.kchunk = ceil_div(ceil_div(K, sp), q) * q;
+  ap.splits = ceil_div(K, ap.kchunk);
+  return ap;
 }
 
-int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
-                     double* W, void* work, hipStream_t s) {
-  PhaseTimer pt(PH_APPLY_Q0, s);
-  const int64_t sp = apply_splits(In, K, R);
-  const int64_t kchunk = ceil_div(ceil_div(K, sp), 64) * 64;
-  const int64_t splits = ceil_div(K, kchunk);
-  Carver cv(work);
-  double* part = cv.take<double>(size_t(sp) * In * R);
+// Launches the apply-Q_0 kernel of the plan; out holds one In x R block per split.
+void launch_apply(const ApplyPlan& ap, int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                  double* out, hipStream_t s) {
   const int RM = round_rank(R);
-  const dim3 grd(unsigned(ceil_div(In, BLK / RM)), unsigned(splits));
-#define APPLY(TY, RMV)                                                                             \
-  hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, \
-                     splits > 1 ? part : W, In, K, R, kchunk)
+  if (ap.tiled) {
+    const dim3 grd(unsigned(ceil_div(In, 64)), unsigned(ap.splits));
+#define APPLYT(TY, RMV)                                                                                    \
+  hipLaunchKernelGGL((apply_q0_tile<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, out, In, K, \
+                     R, ap.kchunk)
+    if (ydtype == CPQR_F64) {
+      if (RM == 8) APPLYT(double, 8); else if (RM == 16) APPLYT(double, 16); else APPLYT(double, 32);
+    } else {
+      if (RM == 8) APPLYT(float, 8); else if (RM == 16) APPLYT(float, 16); else APPLYT(float, 32);
+    }
+#undef APPLYT
+    return;
+  }
+  const dim3 grd(unsigned(ceil_div(In, BLK / RM)), unsigned(ap.splits));
+#define APPLY(TY, RMV)                                                                                     \
+  hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, out, In, K, \
+                     R, ap.kchunk)
   if (ydtype == CPQR_F64) {
     if (RM == 8) APPLY(double, 8); else if (RM == 16) APPLY(double, 16); else APPLY(double, 32);
   } else {
     if (RM == 8) APPLY(float, 8); else if (RM == 16) APPLY(float, 16); else APPLY(float, 32);
   }
 #undef APPLY
+}
+
+constexpr int NORM_BLOCKS = 2048;
+
+}  // namespace
+
+size_t apply_q0_work(int64_t In, int64_t K, int R) {
+  Carver cv(nullptr);
+  cv.take<double>(size_t(apply_plan(In, K, R).splits) * In * R);
+  return cv.bytes();
+}
+
+int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
+                     double* W, void* work, hipStream_t s) {
+  PhaseTimer pt(PH_APPLY_Q0, s);
+  const ApplyPlan ap = apply_plan(In, K, R);
+  Carver cv(work);
+  double* part = cv.take<double>(size_t(ap.splits) * In * R);
+  launch_apply(ap, In, K, R, ydtype, Y, Q0, ap.splits > 1 ? part : W, s);
   CPQR_TRY(check_launch("apply_q0"));
-  if (splits > 1) {
+  if (ap.splits > 1) {
     const int64_t cnt = In * R;
     hipLaunchKernelGGL(sum_parts, dim3(unsigned(ceil_div(cnt, BLK))), dim3(BLK), 0, s, part,
-                       int(splits), cnt, W);
+                       int(ap.splits), cnt, W);
     CPQR_TRY(check_launch("apply_q0 sum"));
   }
   return CPQR_OK;
@@ -484,29 +592,19 @@ int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, co
 int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                         const double* R0, int use_svd, double rtol, double* W, double* A, double* lambda,
                         int* status, void* work, hipStream_t s) {
-  const int64_t sp = apply_splits(In, K, R);
-  const int64_t kchunk = ceil_div(ceil_div(K, sp), 64) * 64;
-  const int64_t splits = ceil_div(K, kchunk);
+  const ApplyPlan ap = apply_plan(In, K, R);
+  const int64_t splits = ap.splits;
   if (use_svd || splits == 1) {
     CPQR_TRY(apply_q0_enqueue(In, K, R, ydtype, Y, Q0, W, work, s));
     return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, s);
   }
   // the solve adds up the partial W's itself (one kernel fewer)
   Carver cv(work);
-  double* part = cv.take<double>(size_t(sp) * In * R);
+  double* part = cv.take<double>(size_t(splits) * In * R);
   const int RM = round_rank(R);
   {
     PhaseTimer pt(PH_APPLY_Q0, s);
-    const dim3 grd(unsigned(ceil_div(In, BLK / RM)), unsigned(splits));
-#define APPLY(TY, RMV)                                                                             \
-  hipLaunchKernelGGL((apply_q0_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), Q0, part, \
-                     In, K, R, kchunk)
-    if (ydtype == CPQR_F64) {
-      if (RM == 8) APPLY(double, 8); else if (RM == 16) APPLY(double, 16); else APPLY(double, 32);
-    } else {
-      if (RM == 8) APPLY(float, 8); else if (RM == 16) APPLY(float, 16); else APPLY(float, 32);
-    }
-#undef APPLY
+    launch_apply(ap, In, K, R, ydtype, Y, Q0, part, s);
     CPQR_TRY(check_launch("apply_q0"));
   }
   PhaseTimer pt(PH_SOLVE, s);

@@ -148,7 +148,8 @@ def test_multittm_general_matrices_elementwise():
 
 # ------------------------------------------------------------------ apply Q0
 
-@pytest.mark.parametrize("In,K,R", [(50, 25, 5), (1000, 256, 16), (200, 32768, 32), (37, 64, 8), (300, 1000, 10)])
+@pytest.mark.parametrize("In,K,R", [(50, 25, 5), (1000, 256, 16), (200, 32768, 32), (37, 64, 8), (300, 1000, 10),
+                                    (1000, 4096, 16), (50, 1331, 11), (130, 1025, 7)])
 @pytest.mark.parametrize("ydt", [np.float32, np.float64])
 def test_apply_q0(In, K, R, ydt):
     g = rng(In + K + R)

@@ -159,3 +159,24 @@ def test_tall_modes_fp64(shape, R):
     assert status == 0
     np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
     assert model_diff(lam, A, lo, Ao) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [C.PREC_F64, C.PREC_F32])
+def test_long_khatri_rao_fp64_small_steps(prec):
+    """4-way rank 11: Q_0 has 11^3 = 1331 rows, so W = Y_(n) Q_0 takes the
+    tiled product split over K, whose partial sums the solve adds up.  With
+    rank 11 on modes of 12..15 the fitted factors are ill-conditioned: the
+    FP32 Multi-TTM's 1e-7 relative error moves them by up to 1e-4 while the
+    fit agrees to 1e-5, so the FP32 case checks the error history only."""
+    shape, R = (14, 13, 12, 15), 11
+    dt = np.float64 if prec == C.PREC_F64 else np.float32
+    d = synth.cp_tensor(shape, R, 515, noise=1e-2, dtype=dt)
+    init = synth.init_factors(shape, R, 516)
+    lam, A, hist, status = run_gpu(d["X"], init, 4, prec, error_mode=C.ERROR_DIRECT)
+    lo, Ao, ho = OQ.cp_als_qr(d["X"].astype(np.float64), init, maxiters=4, error="direct")
+    tol = 1e-9 if prec == C.PREC_F64 else 1e-5
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=tol)
+    if prec == C.PREC_F64:
+        assert model_diff(lam, A, lo, Ao) < tol
+
