@@ -161,6 +161,7 @@ struct AlsWs {
   void* sub;
   void* krp_sub;  // scratch of the Khatri-Rao QR, which runs beside the Multi-TTM
   void* Wt;       // X contracted over one half of the modes (dimension-tree reuse)
+  double* err_part;  // partial sums of the efficient error (side stream)
 };
 
 // Split point of the dimension-tree reuse (0 = off).
@@ -233,6 +234,7 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
     if (N - h > 1) wt = std::max(wt, half_dims(p, h, N, D));
   }
   w.Wt = cv.take<double>(size_t(wt));  // sized for FP64
+  w.err_part = cv.take<double>(error_efficient_work(p->I[N - 1]) / sizeof(double));
   if (ws) *ws = w;
   return cv.bytes();
 }
@@ -477,7 +479,7 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       // reads W, A_N, lambda and R_N, all complete once the last R is.
       CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       CPQR_TRY(error_efficient_enqueue(p->I[N - 1], R, w.W, p->A[N - 1], p->lambda, w.R0, p->Rf[N - 1],
-                                       w.xnorm2, out, side.s));
+                                       w.xnorm2, out, w.err_part, side.s));
       CPQR_HIP(hipEventRecord(side.done, side.s));
     } else if (p->error_mode == CPQR_ERROR_DIRECT) {
       const double* Ap[CPQR_MAX_MODES];

@@ -126,9 +126,11 @@ int fit_direct_enqueue(int N, const int64_t* I, int xdtype, const void* X, int R
 size_t norm2_work(int64_t count);
 int norm2_enqueue(int64_t count, int xdtype, const void* X, double* out, void* work, hipStream_t s);
 // efficient relative error into *relerr (device): section 3.3.1
+// ip partial sums per 256 rows and nn go to part (error_efficient_work bytes).
+size_t error_efficient_work(int64_t In);
 int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
                             const double* lambda, const double* R0, const double* RN,
-                            const double* xnorm2, double* relerr, hipStream_t s);
+                            const double* xnorm2, double* relerr, double* part, hipStream_t s);
 // relerr = sqrt(max(out[0],0) / out[1]) from a fit_direct result
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s);
 int fill_enqueue(double* p, int64_t count, double v, hipStream_t s);

@@ -380,8 +380,8 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(double* A, double* lambd
 template <int RM>
 __global__ __launch_bounds__(BLK) void error_efficient_kernel(
     const double* __restrict__ W, const double* __restrict__ A, const double* __restrict__ lam,
-    const double* __restrict__ R0, const double* __restrict__ RN, int64_t In, int R,
-    const double* __restrict__ xnorm2, double* relerr) {
+    const double* __restrict__ R0, const double* __restrict__ RN, int64_t In, int R, double* __restrict__ part) {
+  // one row per thread: block b sums rows 256 b ... of ip; block 0 also forms nn
   __shared__ double r0[RM][RM + 1];
   __shared__ double l[RM];
   __shared__ double sh[BLK / 64];
@@ -389,7 +389,8 @@ __global__ __launch_bounds__(BLK) void error_efficient_kernel(
   for (int e = threadIdx.x; e < R; e += BLK) l[e] = lam[e];
   __syncthreads();
   double ip = 0.0;
-  for (int64_t i = threadIdx.x; i < In; i += BLK) {
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (i < In) {
     double ah[RM];
 #pragma unroll
     for (int k = 0; k < RM; ++k) ah[k] = k < R ? A[i + k * In] * l[k] : 0.0;
@@ -404,6 +405,8 @@ __global__ __launch_bounds__(BLK) void error_efficient_kernel(
     }
   }
   ip = block_sum(ip, sh);
+  if (threadIdx.x == 0) part[1 + blockIdx.x] = ip;
+  if (blockIdx.x != 0) return;
   double nn = 0.0;
   for (int e = threadIdx.x; e < R * R; e += BLK) {
     const int a = e % R, b = e / R;
@@ -415,11 +418,17 @@ __global__ __launch_bounds__(BLK) void error_efficient_kernel(
     nn += g0 * l[a] * l[b] * gn;
   }
   nn = block_sum(nn, sh);
-  if (threadIdx.x == 0) {
-    const double x2 = *xnorm2;
-    const double r2 = x2 - 2.0 * ip + nn;
-    *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
-  }
+  if (threadIdx.x == 0) part[0] = nn;
+}
+
+// relerr from the partial sums (block order fixed): nb partial ip's after nn
+__global__ void error_efficient_final(const double* __restrict__ part, int nb, const double* __restrict__ xnorm2,
+                                      double* relerr) {
+  double ip = 0.0;
+  for (int b = 0; b < nb; ++b) ip += part[1 + b];
+  const double x2 = *xnorm2;
+  const double r2 = x2 - 2.0 * ip + part[0];
+  *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
 }
 
 __global__ void error_from_fit_kernel(const double* fit, double* relerr) {
@@ -682,21 +691,23 @@ int norm2_enqueue(int64_t count, int xdtype, const void* X, double* out, void* w
   return check_launch("norm2 final");
 }
 
+size_t error_efficient_work(int64_t In) { return size_t(1 + ceil_div(In, BLK)) * sizeof(double); }
+
 int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
                             const double* lambda, const double* R0, const double* RN,
-                            const double* xnorm2, double* relerr, hipStream_t s) {
+                            const double* xnorm2, double* relerr, double* part, hipStream_t s) {
   PhaseTimer pt(PH_ERROR, s);
   const int RM = round_rank(R);
+  const unsigned nb = unsigned(ceil_div(In, BLK));
   if (RM == 8)
-    hipLaunchKernelGGL((error_efficient_kernel<8>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
-                       R, xnorm2, relerr);
+    hipLaunchKernelGGL((error_efficient_kernel<8>), dim3(nb), dim3(BLK), 0, s, W, A, lambda, R0, RN, In, R, part);
   else if (RM == 16)
-    hipLaunchKernelGGL((error_efficient_kernel<16>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
-                       R, xnorm2, relerr);
+    hipLaunchKernelGGL((error_efficient_kernel<16>), dim3(nb), dim3(BLK), 0, s, W, A, lambda, R0, RN, In, R, part);
   else
-    hipLaunchKernelGGL((error_efficient_kernel<32>), dim3(1), dim3(BLK), 0, s, W, A, lambda, R0, RN, In,
-                       R, xnorm2, relerr);
-  return check_launch("error_efficient");
+    hipLaunchKernelGGL((error_efficient_kernel<32>), dim3(nb), dim3(BLK), 0, s, W, A, lambda, R0, RN, In, R, part);
+  CPQR_TRY(check_launch("error_efficient"));
+  hipLaunchKernelGGL(error_efficient_final, dim3(1), dim3(1), 0, s, part, int(nb), xnorm2, relerr);
+  return check_launch("error_efficient_final");
 }
 
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s) {

@@ -231,19 +231,24 @@ __device__ __forceinline__ void load_leaf(double (&a)[P][CW], int w, int lane, i
         a[p][j] = (r < m && c < R) ? A[g + c * lda] : 0.0;
       }
     } else {
-      int digit[CPQR_MAX_MODES];
+      // base-R digits of the row index (lowest first) by a rounded
+      // reciprocal: (d + 1/2) / R sits at least 1/(2R) away from an integer,
+      // far more than the rounding error for d < 2^31
+      const double inv = 1.0 / double(R);
+      int digit[CPQR_MAX_MODES - 1];
       int d = int(g);
 #pragma unroll
-      for (int k = 0; k < CPQR_MAX_MODES; ++k) {
-        digit[k] = d % R;
-        d /= R;
+      for (int k = 0; k < CPQR_MAX_MODES - 1; ++k) {
+        const int q = int((double(d) + 0.5) * inv);
+        digit[k] = d - q * R;
+        d = q;
       }
 #pragma unroll
       for (int j = 0; j < CW; ++j) {
         const int c = w * CW + j;
         double v = (r < m && c < R) ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < CPQR_MAX_MODES; ++k)
+        for (int k = 0; k < CPQR_MAX_MODES - 1; ++k)
           if (k < krp.nm && r < m && c < R) v *= krp.Rk[k][digit[k] + c * krp.ldr];
         a[p][j] = v;
       }
