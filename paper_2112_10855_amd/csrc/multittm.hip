@@ -593,6 +593,94 @@ __global__ __launch_bounds__(NWV * 64) void ttm_bf16_m(const float* __restrict__
   store_tiles<NB, MG>(acc, out + int64_t(blockIdx.y) * split_stride, mt, M, P, R, l16, kq);
 }
 
+// ---------------- short slabs, bfloat16 forms: the whole-slab scheme of
+// ttm_slab_m with 16-row stretches (one bf16 MFMA step each), split in
+// registers as they leave LDS; slabs of at most SLAB_PMAX rows (static LDS).
+constexpr int SLAB_PMAX = 1008;
+template <bool SPLIT, int MG, int NWV, int NRS, bool NT>
+__global__ __launch_bounds__(NWV * 64) void ttm_slab_bf16(const float* __restrict__ X, const float* __restrict__ U,
+                                                          float* __restrict__ out, int64_t P, int64_t K, int64_t S,
+                                                          int R) {
+  constexpr int KC = 16, NTH = NWV * 64, RP = 16;
+  constexpr int LPT = (KC * SLAB_PMAX / 4 + NTH - 1) / NTH;
+  __shared__ float xs[2][KC * SLAB_PMAX];
+  __shared__ shortx4 uh[2][(KC / 4) * RP], ul[2][(KC / 4) * RP];
+  const int Pi = int(P);
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int l16 = lane % 16, kq = lane / 16;
+  const int64_t s = blockIdx.x;
+  const float* Xs = X + s * P * K;
+  const int nch = int((K + KC - 1) / KC);
+  floatx4 acc[1][MG][4];
+#pragma unroll
+  for (int g = 0; g < MG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[0][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float4 rs[NRS][LPT];
+  auto kcount = [&](int c) { return int(min<int64_t>(KC, K - int64_t(c) * KC)); };
+  auto load = [&](float4(&r)[LPT], int c) {
+    const float* src = Xs + int64_t(c) * KC * P;
+    const int n4 = kcount(c) * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      r[i] = e < n4 ? ldx<NT>(src + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](const float4(&r)[LPT], int c) {
+    float* xb = xs[c & 1];
+    const int kc = kcount(c), n4 = kc * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      if (e < n4) *reinterpret_cast<float4*>(xb + 4 * e) = r[i];
+    }
+    stage_u_bf16(U, int64_t(c) * KC, int64_t(c) * KC + kc, KC, RP, uh[c & 1], ul[c & 1], tid, NTH);
+  };
+  const int prow = w * 64 * MG + 4 * l16;
+  auto compute = [&](int c) {
+    const float* xb = xs[c & 1];
+    const int kc = kcount(c);
+    const shortx4 bh = uh[c & 1][kq * RP + l16], bl = ul[c & 1][kq * RP + l16];
+#pragma unroll
+    for (int g = 0; g < MG; ++g) {
+      const int pr = prow + 64 * g;
+      float4 v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 4 * kq + r;
+        v[r] = (k < kc && pr < Pi) ? *reinterpret_cast<const float4*>(xb + k * Pi + pr)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      shortx4 ah[4], al[4];
+      split4(v[0].x, v[1].x, v[2].x, v[3].x, ah[0], al[0]);
+      split4(v[0].y, v[1].y, v[2].y, v[3].y, ah[1], al[1]);
+      split4(v[0].z, v[1].z, v[2].z, v[3].z, ah[2], al[2]);
+      split4(v[0].w, v[1].w, v[2].w, v[3].w, ah[3], al[3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[0][g][j] = mfma_bf16<SPLIT>(ah[j], al[j], bh, bl, acc[0][g][j]);
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < NRS; ++j)
+    if (j < nch) load(rs[j], j);
+  store(rs[0], 0);
+  __syncthreads();
+  for (int c0 = 0; c0 < nch; c0 += NRS) {
+#pragma unroll
+    for (int j = 0; j < NRS; ++j) {
+      const int c = c0 + j;
+      if (c < nch) {  // uniform over the workgroup
+        if (c + NRS < nch) load(rs[j], c + NRS);
+        compute(c);
+        if (c + 1 < nch) store(rs[(j + 1) % NRS], c + 1);
+        __syncthreads();
+      }
+    }
+  }
+  store_tiles<1, MG>(acc, out, s * P + w * 64 * MG, (s + 1) * P, P, R, l16, kq);
+}
+
 // ---------------- P == 1 (columns on the MFMA N dimension)
 // The float4 a lane loads from one column (rows 4kq..4kq+3 of the step) is the
 // B operand of one MFMA; U quads are the A operand.  K % 4 == 0.
@@ -929,6 +1017,17 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_bf16_m");
     }
     if (s.mg != 2) return fail(CPQR_ERR_UNSUPPORTED, "ttm_bf16_m: unsupported row tile");
+    // short slabs whose rows are not line multiples apart: whole-slab workgroups
+    if (STREAM && NB == 1 && s.splits == 1 && s.P % 32 != 0 && s.P <= SLAB_PMAX && s.S >= 256) {
+      const bool snt = (16 * s.P) % 32 == 0 && (s.P * s.K) % 32 == 0;  // stretches start on line boundaries
+      if (snt)
+        launch_ev(ke, ttm_slab_bf16<SPLIT, 2, 8, 2, true>, dim3(unsigned(s.S)), dim3(8 * 64), 0, st, src, U, dst,
+                  s.P, s.K, s.S, R);
+      else
+        launch_ev(ke, ttm_slab_bf16<SPLIT, 2, 8, 2, false>, dim3(unsigned(s.S)), dim3(8 * 64), 0, st, src, U, dst,
+                  s.P, s.K, s.S, R);
+      return check_launch("ttm_slab_bf16");
+    }
     const bool nt = STREAM && s.P % 32 == 0;  // see ldx
     if (NB == 1 && nt)
       launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,

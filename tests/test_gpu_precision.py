@@ -18,8 +18,10 @@ from helpers import relnorm, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
+# the last two: the mode-3 update's first contraction is over the middle
+# mode of short slabs (whole-slab workgroups)
 SHAPES = [((64, 64, 64), 16), ((100, 37, 52), 5), ((40, 36, 33, 20), 12), ((130, 20, 24), 32), ((33, 47, 29), 8),
-          ((16, 200, 8), 16)]
+          ((16, 200, 8), 16), ((100, 80, 260), 12), ((60, 50, 300), 5)]
 
 
 @pytest.mark.parametrize("shape,R", SHAPES)
