@@ -409,7 +409,12 @@ def main():
             "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
         },
         "roofline": {
-            "kernel": "first contraction of each Multi-TTM pass (streams X once; two per sweep with the mode reuse): ttm_mfma_m with non-temporal row tiles (mode-3 contraction) and ttm_slab_m with whole-slab LDS stretches (mode-2 contraction)",
+            "kernel": "first contraction of each Multi-TTM pass (streams X once; two per sweep with the mode reuse): " + {
+                "f32": "ttm_mfma_m with non-temporal row tiles (mode-3 contraction) and ttm_slab_m with whole-slab "
+                       "LDS stretches (mode-2 contraction)",
+                "bf16x2": "ttm_bf16_m<split> (mode-3 contraction) and ttm_slab_bf16<split> (mode-2 contraction)",
+                "bf16": "ttm_bf16_m (mode-3 contraction) and ttm_slab_bf16 (mode-2 contraction)",
+                "f64": "ttm_valu (FP64, one thread per row)"}[args.prec],
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
