@@ -16,7 +16,15 @@ import scipy.linalg
 from . import tensor as T
 
 
-def mode_update(X, A, G, n, solver="chol"):
+def default_rtol(R):
+    """Relative cutoff of the pseudo-inverse: singular values of S_n at or
+    below R * 2^-52 times the largest are dropped, the reading of MATLAB's
+    pinv default (size times the spacing of doubles at the norm) that the
+    SVD solve of CP-ALS-QR also takes."""
+    return R * 2.0 ** -52
+
+
+def mode_update(X, A, G, n, solver="chol", rtol=None):
     """One Alg. 1 mode update; updates A[n], G[n] in place.
     Returns (Ahat, lam, M, S)."""
     N = X.ndim
@@ -26,7 +34,9 @@ def mode_update(X, A, G, n, solver="chol"):
         c = scipy.linalg.cho_factor(S, lower=False, check_finite=False)
         Ahat = scipy.linalg.cho_solve(c, M.T, check_finite=False).T
     elif solver == "pinv":
-        Ahat = M @ np.linalg.pinv(S)
+        if rtol is None or rtol < 0:
+            rtol = default_rtol(S.shape[0])
+        Ahat = M @ np.linalg.pinv(S, rcond=rtol)
     else:
         raise ValueError("solver must be 'chol' or 'pinv'")
     lam = np.sqrt(np.sum(Ahat * Ahat, axis=0))
@@ -36,7 +46,7 @@ def mode_update(X, A, G, n, solver="chol"):
     return Ahat, lam, M, S
 
 
-def cp_als(X, A_init, maxiters=25, tol=0.0, solver="chol", error="efficient"):
+def cp_als(X, A_init, maxiters=25, tol=0.0, solver="chol", error="efficient", rtol=None):
     """CP-ALS / CP-ALS-PINV (Alg. 1).  Returns (lam, A, relerr history)."""
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
@@ -47,7 +57,7 @@ def cp_als(X, A_init, maxiters=25, tol=0.0, solver="chol", error="efficient"):
     hist = []
     for s in range(maxiters):
         for n in range(N):
-            Ahat, lam, M, S = mode_update(X, A, G, n, solver=solver)
+            Ahat, lam, M, S = mode_update(X, A, G, n, solver=solver, rtol=rtol)
         if error == "efficient":
             ip = float(np.sum(M * Ahat))
             nn = float(np.sum(S * ((lam[:, None] * G[N - 1]) * lam[None, :])))

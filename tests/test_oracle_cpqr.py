@@ -67,6 +67,63 @@ def pin_mode_update_lstsq(shape, R, n, seed=0, solver="qr"):
     return err
 
 
+def lstsq_by_entries(X, A, n):
+    """min over B of sum over all entries of (X[i] - sum_r B[i_n, r] prod_{k != n}
+    A_k[i_k, r])^2, one small least-squares problem per i_n with one equation
+    per tensor entry: no unfolding and no Khatri-Rao ordering involved."""
+    import itertools
+    N = X.ndim
+    others = [k for k in range(N) if k != n]
+    B = np.zeros((X.shape[n], A[0].shape[1]))
+    for i_n in range(X.shape[n]):
+        rows, rhs = [], []
+        for rest in itertools.product(*[range(X.shape[k]) for k in others]):
+            idx = [0] * N
+            idx[n] = i_n
+            z = np.ones(A[0].shape[1])
+            for k, i_k in zip(others, rest):
+                idx[k] = i_k
+                z = z * A[k][i_k]
+            rows.append(z)
+            rhs.append(X[tuple(idx)])
+        B[i_n] = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0]
+    return B
+
+
+def pin_als_update_lstsq(shape, R, n, seed=0, solver="chol"):
+    """Alg. 1's mode update (normal equations by Cholesky, or the
+    pseudo-inverse of S_n) equals the least-squares solution of eq. (ls_n)
+    from LAPACK's SVD-based lstsq on the explicit Khatri-Rao matrix Z_n, and
+    leaves unit columns, lambda and the Gram matrix of the new factor."""
+    N = len(shape)
+    rng = np.random.default_rng(seed + 200)
+    X = rng.standard_normal(shape)
+    A = rand_factors(shape, R, seed)
+    G = [a.T @ a for a in A]
+    for k in range(n):  # give mode n updated neighbours
+        ALS.mode_update(X, A, G, k, solver=solver)
+    ref = lstsq_by_entries(X, A, n)
+    Ahat, lam, M, S = ALS.mode_update(X, A, G, n, solver=solver)
+    err = np.linalg.norm(Ahat - ref) / np.linalg.norm(ref)
+    err = max(err, np.linalg.norm(A[n] * lam[None, :] - ref) / np.linalg.norm(ref))
+    err = max(err, np.abs(np.sqrt(np.sum(A[n] ** 2, axis=0)) - 1).max())
+    err = max(err, np.abs(G[n] - A[n].T @ A[n]).max())
+    return err
+
+
+def pin_als_error_forms(seed=0, solver="chol"):
+    """Alg. 1's efficient error (||X||^2 - 2 <M_N, Ahat_N> + <S_N, diag(lam)
+    G_N diag(lam)>) against the residual of the dense model, on squares."""
+    d = synth.workload_small(noise=1e-2, seed_item=seed)
+    X = d["X"]
+    worst = 0.0
+    for its in (1, 2, 4):
+        lam, A, h = ALS.cp_als(X, d["init"], maxiters=its, solver=solver)
+        dire = T.norm(X - T.full(lam, A)) / T.norm(X)
+        worst = max(worst, abs(h[-1] ** 2 - dire ** 2))
+    return worst
+
+
 def pin_error_forms(seed=0):
     """section 3.3.1: the efficient and the direct relative error agree;
     compared on squared errors, where the identity holds exactly."""
@@ -155,6 +212,52 @@ def test_svd_variant_is_pinv_on_rank_deficient():
     assert out["kept"] == R - 1
     assert out["status"] & Q.RANK_TRUNCATED
     np.testing.assert_allclose(out["Ahat"], ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape,R", [((6, 5, 7), 3), ((4, 5, 3, 4), 3), ((3, 4, 3, 2, 3), 2), ((9, 8, 7), 5)])
+@pytest.mark.parametrize("solver", ["chol", "pinv"])
+def test_als_mode_update_is_least_squares(shape, R, solver):
+    for n in range(len(shape)):
+        assert pin_als_update_lstsq(shape, R, n, solver=solver) < 1e-10
+
+
+@pytest.mark.parametrize("solver", ["chol", "pinv"])
+def test_als_error_forms_agree(solver):
+    assert pin_als_error_forms(solver=solver) < 1e-13
+
+
+def test_als_pinv_is_min_norm_on_rank_deficient():
+    """CP-ALS-PINV: with Z_n rank deficient (a duplicated column in every
+    factor), M_n pinv(S_n) = X_(n) Z_n pinv(Z_n^T Z_n) = X_(n) pinv(Z_n^T),
+    the minimum-norm least-squares solution (section 2.3)."""
+    shape, R = (6, 5, 7), 4
+    rng = np.random.default_rng(12)
+    A = rand_factors(shape, R, 7)
+    for a in A:
+        a[:, 2] = a[:, 1]
+    X = rng.standard_normal(shape)
+    G = [a.T @ a for a in A]
+    n = 1
+    Z = T.khatri_rao_list([A[k] for k in reversed(range(3)) if k != n])
+    assert np.linalg.matrix_rank(Z) == R - 1
+    ref = T.unfold(X, n) @ np.linalg.pinv(Z.T)
+    Ahat, lam, M, S = ALS.mode_update(X, A, G, n, solver="pinv")
+    np.testing.assert_allclose(Ahat, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+def test_planted_gram_of_mode_n_in_hadamard_is_caught(monkeypatch):
+    """Taking every Gram matrix into S_n (mode n's own included) is caught."""
+    real = T.hadamard_list
+    monkeypatch.setattr(T, "hadamard_list", lambda mats: real(list(mats) + [np.eye(mats[0].shape[0]) * 1.5]))
+    assert pin_als_update_lstsq((6, 5, 7), 3, 1) > 1e-3
+
+
+def test_planted_mttkrp_order_is_caught(monkeypatch):
+    """A Khatri-Rao product taken from mode 1 up instead of mode N down."""
+    real = T.khatri_rao_list
+    monkeypatch.setattr(T, "khatri_rao_list", lambda mats: real(list(reversed(mats))))
+    monkeypatch.setattr(ALS, "T", T)
+    assert pin_als_update_lstsq((6, 5, 7), 3, 0) > 1e-3 or pin_als_update_lstsq((6, 5, 7), 3, 2) > 1e-3
 
 
 def test_qr_matches_normal_equations_trajectory():
