@@ -45,6 +45,9 @@ def parse():
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
+    ap.add_argument("--method", default="qr", choices=["qr", "als", "als-pinv"],
+                    help="dense3 only: qr = CP-ALS-QR (Alg. 2, default); als = CP-ALS with the normal equations "
+                         "(Alg. 1, Cholesky); als-pinv = CP-ALS-PINV (Alg. 1, pseudo-inverse)")
     ap.add_argument("--dimtree", type=int, default=-1,
                     help="Multi-TTM reuse across modes: -1 library choice, 0 one Multi-TTM per mode, h split point")
     ap.add_argument("--train", type=int, default=20000, help="training tensors for --workload learned")
@@ -329,7 +332,13 @@ def main():
     prec = C.PREC_NAMES[args.prec]
     if prec == C.PREC_F64:
         Xd = Xd.double()
-    st = C.AlsState(Xd, d["init"], prec=prec, dimtree=args.dimtree)
+    def make_state(dimtree):
+        if args.method == "qr":
+            return C.AlsState(Xd, d["init"], prec=prec, dimtree=dimtree)
+        return C.AlsNeState(Xd, d["init"], prec=prec, solver="chol" if args.method == "als" else "pinv",
+                            dimtree=dimtree)
+
+    st = make_state(args.dimtree)
     st.init()
     for _ in range(args.warmup):
         st.sweep(1)
@@ -387,7 +396,7 @@ def main():
     src = open(os.path.join(ROOT, "paper_2112_10855_amd", "csrc", "multittm.hip"), "rb").read()
     sha = hashlib.sha256(src).hexdigest()
     # the counters were taken on the FP32 kernel
-    traffic = traffic_from_profiles(sha) if args.prec == "f32" else None
+    traffic = traffic_from_profiles(sha) if args.prec == "f32" and args.method == "qr" else None
 
     out = {
         "metric": METRIC,
@@ -403,9 +412,11 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {
-            "workload": "cp_als_qr_dense3_%dcube_%s_r%d" % (n, args.prec, R),
+            "workload": "%s_dense3_%dcube_%s_r%d" % ({"qr": "cp_als_qr", "als": "cp_als", "als-pinv": "cp_als_pinv"}[
+                args.method], n, args.prec, R),
             "shape": list(shape), "rank": R, "multittm_precision": args.prec,
-            "small_steps_precision": "f64", "solver": "qr", "error": "efficient", "dimtree": args.dimtree,
+            "small_steps_precision": "f64", "solver": {"qr": "qr", "als": "cholesky", "als-pinv": "pinv"}[args.method],
+            "error": "efficient", "dimtree": args.dimtree,
             "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
         },
         "roofline": {
@@ -439,17 +450,26 @@ def main():
     if not args.no_cpu_baseline:
         import threadpoolctl
 
+        import oracle.cp_als as OA
         import oracle.cp_als_qr as OQ
         log("oracle timing sample (FP64 numpy on host cores)")
         X64 = X.astype(np.float64)
         xn2 = float(np.einsum("i,i->", X64.reshape(-1, order="F"), X64.reshape(-1, order="F")))
         ost = OQ.init_state(d["init"])
+        oA = [np.array(a, dtype=np.float64) for a in d["init"]]
+        oG = [a.T @ a for a in oA]
         info = threadpoolctl.threadpool_info()
         cores = max([i.get("num_threads", 1) for i in info] + [1])
         sweeps, t = 0, 0.0
         while sweeps < 1 or (t < args.cpu_seconds and sweeps < 5):
             a = time.perf_counter()
-            orel, _ = OQ.sweep(X64, ost, xnorm2=xn2)
+            if args.method == "qr":
+                orel, _ = OQ.sweep(X64, ost, xnorm2=xn2)
+            else:  # Alg. 1 sweep and its efficient error, as the oracle's cp_als takes them
+                for m in range(3):
+                    Ahat, lam, M, S = OA.mode_update(X64, oA, oG, m, solver="chol" if args.method == "als" else "pinv")
+                nn = float(np.sum(S * ((lam[:, None] * oG[2]) * lam[None, :])))
+                orel = float(np.sqrt(max(xn2 - 2.0 * float(np.sum(M * Ahat)) + nn, 0.0) / xn2))
             t += time.perf_counter() - a
             sweeps += 1
             log("oracle sweep %d: %.2f s, relerr %.6e" % (sweeps, t, orel))
@@ -462,7 +482,7 @@ def main():
                 sweeps, n, n, n),
         }
         # the GPU path after the same number of sweeps from the same start
-        st2 = C.AlsState(Xd, d["init"], prec=prec)
+        st2 = make_state(-1)
         st2.init()
         grel = st2.sweep(sweeps).cpu().numpy()
         out["cpu_baseline"]["gpu_vs_oracle_relerr_after_sample"] = [float(grel[-1]), float(orel)]

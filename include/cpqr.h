@@ -209,6 +209,33 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
                    void* stream);
 
 /*
+ * CP-ALS with the normal equations, the paper's comparison algorithm (Alg. 1,
+ * section 2.3), on the same problem description and the same Multi-TTM:
+ * the MTTKRP M_n = X_(n) Z_n is read off Y_(n) (the Multi-TTM with the
+ * factors A_k themselves in place of Q_k), whose column r (1 + R + ... +
+ * R^{N-2}) is column r of M_n.  S_n is the Hadamard product of the Gram
+ * matrices A_k^T A_k over k != n, and Ahat_n S_n = M_n is solved by Cholesky
+ * (use_svd = 0; a non-positive pivot sets CPQR_STATUS_SINGULAR) or with the
+ * pseudo-inverse of S_n (use_svd = 1, CP-ALS-PINV: singular values of S_n at
+ * or below rtol times the largest are dropped, rtol < 0 meaning R * 2^-52;
+ * dropping sets CPQR_STATUS_TRUNCATED).  Columns are normalized into lambda.
+ * The efficient error is ||X||^2 - 2 <M_N, Ahat_N> + <S_N, diag(lambda) G_N
+ * diag(lambda)> (section 3.3.1).  Q and Rf are not used and may be NULL;
+ * A[0..N-1] all hold the start on entry (A[0] enters only through its Gram
+ * matrix, which the first update does not read).  prec, dimtree and
+ * error_mode act as in cpqr_als_sweep.  The work buffer keeps ||X||^2 and
+ * the N Gram matrices between calls: pass the same buffer to
+ * cpqr_als_ne_init and every cpqr_als_ne_sweep of one problem.  Everything
+ * runs on `stream`; the Gram matrices, S_n and its factor are FP64.
+ */
+size_t cpqr_als_ne_work(const cpqr_problem* p);
+/* Gram matrices of the starting factors, lambda = 1 and ||X||^2. */
+int cpqr_als_ne_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream);
+/* nsweeps sweeps of Alg. 1; relerr as in cpqr_als_sweep. */
+int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, size_t work_bytes,
+                      void* stream);
+
+/*
  * Batched CP-ALS-QR for many small 3-way FP32 tensors (Alg. 2 per tensor,
  * substitution solve, efficient error of section 3.3.1) in one persistent
  * launch: one workgroup runs every sweep of one tensor, tensors taken

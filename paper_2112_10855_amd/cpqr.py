@@ -96,6 +96,9 @@ _SIGS = {
     "cpqr_als_work": (_sz, [ctypes.POINTER(Problem)]),
     "cpqr_als_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
     "cpqr_als_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_als_ne_work": (_sz, [ctypes.POINTER(Problem)]),
+    "cpqr_als_ne_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
+    "cpqr_als_ne_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
     "cpqr_als_batch_work": (_sz, [ctypes.POINTER(BatchItem), ctypes.c_int]),
     "cpqr_als_batch_prepare": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int, _vp, _sz, _vp]),
     "cpqr_als_batch_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
@@ -377,6 +380,71 @@ def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=
     """Alg. 2 driven from the host: sweeps until |relerr change| < tol or
     maxiters (reads the error back after each sweep only when tol > 0)."""
     st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode, dimtree=dimtree)
+    st.init()
+    if tol <= 0:
+        rel = st.sweep(maxiters)
+        return st, rel.cpu().tolist()
+    hist = []
+    for s in range(maxiters):
+        hist.append(float(st.sweep(1)[0].item()))
+        if s >= 1 and abs(hist[-2] - hist[-1]) < tol:
+            break
+    return st, hist
+
+
+class AlsNeState:
+    """Device buffers of one CP-ALS problem (Alg. 1, normal equations or
+    pseudo-inverse), wired into ``cpqr_problem`` for cpqr_als_ne_*; every
+    init[k] is the start of A_k (A_0 only through its Gram matrix)."""
+
+    def __init__(self, X, init, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1):
+        _dev(X, "X")
+        _check_colmajor(X, "X")
+        if solver not in ("chol", "pinv"):
+            raise ValueError("solver must be 'chol' or 'pinv'")
+        prec = PREC_NAMES.get(prec, prec)
+        dev = X.device
+        N = X.dim()
+        R = init[1].shape[1]
+        self.X, self.N, self.R = X, N, R
+        self.A = [colmajor(torch.as_tensor(init[k], dtype=torch.float64).to(dev)) for k in range(N)]
+        self.lam = torch.ones(R, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        p = Problem()
+        p.N, p.R = N, R
+        for k in range(N):
+            p.I[k] = X.shape[k]
+            p.A[k] = self.A[k].data_ptr()
+        p.xdtype = _dtype_code(X)
+        p.X = X.data_ptr()
+        p.lam = self.lam.data_ptr()
+        p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(solver == "pinv"), float(rtol), error_mode
+        p.dimtree = int(dimtree)
+        p.status = self.status.data_ptr()
+        self.p = p
+        nbytes = lib().cpqr_als_ne_work(ctypes.byref(p))
+        if nbytes == 0:
+            raise CpqrError("cpqr_als_ne_work", -1, lib().cpqr_last_error().decode())
+        self._wkeep, self._w = _work(nbytes, dev)
+        self._wbytes = nbytes
+
+    def init(self):
+        _call("cpqr_als_ne_init", ctypes.byref(self.p), self._w, self._wbytes, _stream())
+
+    def sweep(self, nsweeps=1, relerr=None):
+        """Run nsweeps sweeps; returns the device tensor of relative errors."""
+        if relerr is None:
+            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.X.device)
+        _call("cpqr_als_ne_sweep", ctypes.byref(self.p), int(nsweeps), relerr.data_ptr(), self._w, self._wbytes,
+              _stream())
+        return relerr
+
+
+def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT,
+           dimtree=-1):
+    """Alg. 1 (CP-ALS, or CP-ALS-PINV with solver='pinv') driven from the
+    host, with the same stopping rule as cp_als_qr."""
+    st = AlsNeState(X, init, prec=prec, solver=solver, rtol=rtol, error_mode=error_mode, dimtree=dimtree)
     st.init()
     if tol <= 0:
         rel = st.sweep(maxiters)

@@ -183,10 +183,9 @@ int64_t half_dims(const cpqr_problem* p, int lo, int hi, int64_t* D) {
   return c;
 }
 
-size_t als_sub_bytes(const cpqr_problem* p) {
+size_t ttm_sub_bytes(const cpqr_problem* p) {
   const int N = p->N, R = p->R;
-  size_t b = tsqr_work(ipow(R, N - 1), R);
-  const int64_t K = ipow(R, N - 1);
+  size_t b = 0;
   const int h = dt_split(p);
   if (h > 0) {
     for (int half = 0; half < 2; ++half) {
@@ -201,14 +200,91 @@ size_t als_sub_bytes(const cpqr_problem* p) {
   int64_t count = 1;
   for (int k = 0; k < N; ++k) {
     count *= p->I[k];
-    b = std::max(b, tsqr_work(p->I[k], R));
     b = std::max(b, multittm_work(N, p->I, k, R, p->prec));
-    b = std::max(b, apply_q0_work(p->I[k], K, R));
-    b = std::max(b, solve_work(p->I[k], R));
   }
   b = std::max(b, fit_direct_work(N, p->I, R));
   b = std::max(b, norm2_work(count));
   return b;
+}
+
+size_t als_sub_bytes(const cpqr_problem* p) {
+  const int N = p->N, R = p->R;
+  const int64_t K = ipow(R, N - 1);
+  size_t b = std::max(ttm_sub_bytes(p), tsqr_work(K, R));
+  for (int k = 0; k < N; ++k) {
+    b = std::max(b, tsqr_work(p->I[k], R));
+    b = std::max(b, apply_q0_work(p->I[k], K, R));
+    b = std::max(b, solve_work(p->I[k], R));
+  }
+  return b;
+}
+
+// Size of the dimension-tree intermediate (elements; 0 without the reuse).
+int64_t dt_elems(const cpqr_problem* p) {
+  const int N = p->N, h = dt_split(p);
+  int64_t wt = 0;
+  if (h > 0) {
+    int64_t D[CPQR_MAX_MODES];
+    if (h > 1) wt = std::max(wt, half_dims(p, 0, h, D));
+    if (N - h > 1) wt = std::max(wt, half_dims(p, h, N, D));
+  }
+  return wt;
+}
+
+// ------------------------------------------------------------ Alg. 1 scratch
+// The Gram matrices persist in the work buffer from cpqr_als_ne_init on.
+struct NeWs {
+  double* xnorm2;
+  double* G;  // N blocks of R x R
+  double* S;
+  double* F;
+  void* Y;
+  double* M;
+  double* relerr_tmp;
+  void* sub;
+  void* Wt;
+  double* err_part;
+};
+
+size_t ne_carve(Carver& cv, const cpqr_problem* p, NeWs* ws) {
+  const int N = p->N, R = p->R;
+  const int64_t K = ipow(R, N - 1);
+  int64_t imax = 0;
+  for (int k = 0; k < N; ++k) imax = std::max(imax, p->I[k]);
+  NeWs w{};
+  w.xnorm2 = cv.take<double>(1);
+  w.G = cv.take<double>(size_t(N) * R * R);
+  w.S = cv.take<double>(size_t(R) * R);
+  w.F = cv.take<double>(size_t(R) * R);
+  w.Y = cv.take<double>(size_t(imax) * K);  // sized for FP64 Y
+  w.M = cv.take<double>(size_t(imax) * R);
+  w.relerr_tmp = cv.take<double>(1);
+  w.sub = cv.take<char>(std::max(ttm_sub_bytes(p), ne_update_work(R)));
+  w.Wt = cv.take<double>(size_t(dt_elems(p)));
+  w.err_part = cv.take<double>(ne_error_work(p->I[N - 1]) / sizeof(double));
+  if (ws) *ws = w;
+  return cv.bytes();
+}
+
+// Y = X contracted with U_k^T over every mode but n, unfolded along n, with the
+// dimension-tree reuse of the mode split h (shared by both algorithms).
+int ttm_for_mode(const cpqr_problem* p, int h, int n, const double* const* U, void* Y, void* Wt, void* sub,
+                 hipStream_t s) {
+  const int N = p->N, R = p->R;
+  const int ydt = p->prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
+  const int lo = (h > 0 && n >= h) ? h : 0, hi = (h > 0 && n < h) ? h : N;
+  if (h == 0 || hi - lo == 1)
+    return multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, U, p->prec, Y, sub, s);
+  // X contracted over the modes outside [lo, hi) once (when the first mode of
+  // the half is updated; those factors do not change while the half is
+  // updated), then the remaining modes of the half for each n
+  if (n == lo)
+    CPQR_TRY(multittm_general_enqueue(N, p->I, p->xdtype, p->X, ~range_mask(lo, hi) & range_mask(0, N), -1, R, U,
+                                      p->prec, Wt, sub, s, true));
+  int64_t D[CPQR_MAX_MODES];
+  half_dims(p, lo, hi, D);
+  return multittm_general_enqueue(N, D, ydt, Wt, range_mask(lo, hi) & ~(1u << n), n, R, U, p->prec, Y, sub, s,
+                                  false);
 }
 
 size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
@@ -226,14 +302,7 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
   w.relerr_tmp = cv.take<double>(1);
   w.sub = cv.take<char>(als_sub_bytes(p));
   w.krp_sub = cv.take<char>(tsqr_work(K, R));
-  const int h = dt_split(p);
-  int64_t wt = 0;
-  if (h > 0) {
-    int64_t D[CPQR_MAX_MODES];
-    if (h > 1) wt = std::max(wt, half_dims(p, 0, h, D));
-    if (N - h > 1) wt = std::max(wt, half_dims(p, h, N, D));
-  }
-  w.Wt = cv.take<double>(size_t(wt));  // sized for FP64
+  w.Wt = cv.take<double>(size_t(dt_elems(p)));  // sized for FP64
   w.err_part = cv.take<double>(error_efficient_work(p->I[N - 1]) / sizeof(double));
   if (ws) *ws = w;
   return cv.bytes();
@@ -263,7 +332,7 @@ int side_stream(SideStream& out) {
   return CPQR_OK;
 }
 
-int check_problem(const cpqr_problem* p) {
+int check_problem(const cpqr_problem* p, bool need_qr = true) {
   if (!p) return fail(CPQR_ERR_ARG, "problem is NULL");
   CPQR_TRY(check_modes(p->N, p->I));
   CPQR_TRY(check_rank(p->R));
@@ -278,7 +347,7 @@ int check_problem(const cpqr_problem* p) {
     return fail(CPQR_ERR_ARG, "dimtree must be -1, 0 or a split point in [1, N-1]");
   if (!p->X || !p->lambda) return fail(CPQR_ERR_ARG, "X or lambda is NULL");
   for (int k = 0; k < p->N; ++k) {
-    if (!p->A[k] || !p->Q[k] || !p->Rf[k])
+    if (!p->A[k] || (need_qr && (!p->Q[k] || !p->Rf[k])))
       return fail(CPQR_ERR_ARG, "A/Q/Rf pointer of mode " + std::to_string(k) + " is NULL");
     if (p->I[k] < p->R)
       return fail(CPQR_ERR_SHAPE, "mode " + std::to_string(k) + " is smaller than the rank");
@@ -449,21 +518,7 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
       CPQR_HIP(hipEventRecord(side.done, side.s));
-      const int lo = (h > 0 && n >= h) ? h : 0, hi = (h > 0 && n < h) ? h : N;
-      if (h == 0 || hi - lo == 1) {  // one Multi-TTM of X for this mode
-        CPQR_TRY(multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, p->Q, p->prec, w.Y, w.sub, s));
-      } else {
-        // dimension tree: X contracted over the modes outside [lo, hi) once (when the
-        // first mode of the half is updated; those Q_k do not change while the half
-        // is updated), then the remaining modes of the half for each n
-        if (n == lo)
-          CPQR_TRY(multittm_general_enqueue(N, p->I, p->xdtype, p->X, ~range_mask(lo, hi) & range_mask(0, N), -1,
-                                            R, p->Q, p->prec, w.Wt, w.sub, s, true));
-        int64_t D[CPQR_MAX_MODES];
-        half_dims(p, lo, hi, D);
-        CPQR_TRY(multittm_general_enqueue(N, D, ydt, w.Wt, range_mask(lo, hi) & ~(1u << n), n, R, p->Q, p->prec,
-                                          w.Y, w.sub, s, false));
-      }
+      CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
       CPQR_TRY(apply_solve_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.R0, p->use_svd, p->rtol, w.W, p->A[n],
                                    p->lambda, p->status, w.sub, s));
@@ -493,6 +548,63 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   // everything this call queued on the side stream completes before later
   // work on the caller's stream
   if (nsweeps > 0) CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
+  return CPQR_OK;
+}
+
+size_t cpqr_als_ne_work(const cpqr_problem* p) {
+  if (check_problem(p, false) != CPQR_OK) return 0;
+  Carver cv(nullptr);
+  return ne_carve(cv, p, nullptr);
+}
+
+int cpqr_als_ne_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_problem(p, false));
+  Carver cv(nullptr);
+  CPQR_TRY(check_work(work, work_bytes, ne_carve(cv, p, nullptr)));
+  NeWs w;
+  Carver c2(work);
+  ne_carve(c2, p, &w);
+  hipStream_t s = as_stream(stream);
+  const int N = p->N, R = p->R;
+  for (int k = 0; k < N; ++k) CPQR_TRY(gram_enqueue(p->I[k], R, p->A[k], w.G + int64_t(k) * R * R, s));
+  CPQR_TRY(fill_enqueue(p->lambda, R, 1.0, s));
+  int64_t count = 1;
+  for (int k = 0; k < N; ++k) count *= p->I[k];
+  return norm2_enqueue(count, p->xdtype, p->X, w.xnorm2, w.sub, s);
+}
+
+int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, size_t work_bytes,
+                      void* stream) {
+  CPQR_TRY(check_problem(p, false));
+  if (nsweeps < 0) return fail(CPQR_ERR_ARG, "nsweeps < 0");
+  Carver cv(nullptr);
+  CPQR_TRY(check_work(work, work_bytes, ne_carve(cv, p, nullptr)));
+  NeWs w;
+  Carver c2(work);
+  ne_carve(c2, p, &w);
+  hipStream_t s = as_stream(stream);
+  const int N = p->N, R = p->R;
+  const int ydt = p->prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
+  const double* Ap[CPQR_MAX_MODES];
+  for (int k = 0; k < N; ++k) Ap[k] = p->A[k];
+  const int h = dt_split(p);
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int n = 0; n < N; ++n) {
+      CPQR_TRY(ttm_for_mode(p, h, n, Ap, w.Y, w.Wt, w.sub, s));
+      CPQR_TRY(ne_update_enqueue(p->I[n], N, n, R, ydt, w.Y, w.G, p->use_svd, p->rtol, w.S, w.F, w.M, p->A[n],
+                                 p->lambda, p->status, w.sub, s));
+    }
+    double* out = relerr ? relerr + sw : w.relerr_tmp;
+    if (p->error_mode == CPQR_ERROR_EFFICIENT) {
+      CPQR_TRY(ne_error_enqueue(p->I[N - 1], R, w.M, p->A[N - 1], p->lambda, w.S, w.G + int64_t(N - 1) * R * R,
+                                w.xnorm2, out, w.err_part, s));
+    } else if (p->error_mode == CPQR_ERROR_DIRECT) {
+      CPQR_TRY(fit_direct_enqueue(N, p->I, p->xdtype, p->X, R, p->lambda, Ap, w.M, w.sub, s));
+      CPQR_TRY(error_from_fit_enqueue(w.M, out, s));
+    } else {
+      CPQR_TRY(fill_enqueue(out, 1, std::nan(""), s));
+    }
+  }
   return CPQR_OK;
 }
 

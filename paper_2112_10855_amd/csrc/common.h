@@ -134,5 +134,18 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
 // relerr = sqrt(max(out[0],0) / out[1]) from a fit_direct result
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s);
 int fill_enqueue(double* p, int64_t count, double v, hipStream_t s);
+// Alg. 1 (CP-ALS, normal equations): G = A^T A; one mode update from the
+// unfolded Multi-TTM Y_(n) of the factors themselves (MTTKRP = its diagonal
+// columns), the Gram matrices G (N blocks of R x R; block n is rewritten),
+// S = their Hadamard product over k != n, F = its Cholesky factor or
+// pseudo-inverse, M = the MTTKRP (In x R), A and lambda the new factor.
+int gram_enqueue(int64_t In, int R, const double* A, double* G, hipStream_t s);
+size_t ne_update_work(int R);
+int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y, double* G, int pinv,
+                      double rtol, double* S, double* F, double* M, double* A, double* lambda, int* status,
+                      void* work, hipStream_t s);
+size_t ne_error_work(int64_t In);
+int ne_error_enqueue(int64_t In, int R, const double* M, const double* A, const double* lambda, const double* S,
+                     const double* GN, const double* xnorm2, double* relerr, double* part, hipStream_t s);
 
 }  // namespace cpqr

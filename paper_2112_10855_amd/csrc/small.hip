@@ -573,6 +573,153 @@ void launch_apply(const ApplyPlan& ap, int64_t In, int64_t K, int R, int ydtype,
 
 constexpr int NORM_BLOCKS = 2048;
 
+// ------------------------------------------------------------ Alg. 1 (normal equations)
+// S_n = Hadamard product of the Gram matrices G_k = A_k^T A_k over k != n
+// (section 2.3), multiplied in increasing k; for the Cholesky solve also the
+// upper factor U of S_n = U^T U (right-looking, one column per step).  One
+// workgroup; a non-positive or non-finite pivot sets CPQR_STATUS_SINGULAR.
+__global__ __launch_bounds__(BLK) void ne_factor_kernel(const double* __restrict__ G, int N, int n, int R,
+                                                        int chol, double* S, double* U, int* status) {
+  __shared__ double s[32][33];
+  __shared__ double u[32][33];
+  for (int e = threadIdx.x; e < R * R; e += BLK) {
+    const int a = e % R, b = e / R;
+    double v = 1.0;
+    for (int k = 0; k < N; ++k)
+      if (k != n) v *= G[int64_t(k) * R * R + e];
+    s[a][b] = v;
+    S[e] = v;
+  }
+  if (!chol) return;
+  bool bad = false;
+  for (int j = 0; j < R; ++j) {
+    __syncthreads();
+    const double piv = s[j][j];
+    bad |= !(piv > 0.0) || !isfinite(piv);
+    const double rj = sqrt(piv);
+    if (threadIdx.x < R) {
+      const int k = threadIdx.x;
+      u[j][k] = k < j ? 0.0 : (k == j ? rj : s[j][k] / rj);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * R; e += BLK) {
+      const int a = e % R, b = e / R;
+      if (a > j && b >= a) s[a][b] -= u[j][a] * u[j][b];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += BLK) U[e] = u[e % R][e / R];
+  if (threadIdx.x == 0 && bad && status) atomicOr(status, CPQR_STATUS_SINGULAR);
+}
+
+// Row i of the MTTKRP M_n = X_(n) Z_n is read off Y_(n) = X_(n) (A_N kron ..
+// kron A_1 without A_n): column r of Z_n is the Kronecker column whose every
+// index is r, at position r (1 + R + .. + R^{N-2}) = r * dstep.  Then Ahat(i,:)
+// solves Ahat S_n = M_n: S_n = U^T U by a forward and a back substitution
+// (chol), or Ahat = M_n P with P = pinv(S_n).  One thread per row.
+template <class TY, int RM>
+__global__ __launch_bounds__(BLK) void ne_rows_kernel(const TY* __restrict__ Y, int64_t In, int64_t dstep,
+                                                      const double* __restrict__ F, int chol, int R,
+                                                      double* __restrict__ M, double* __restrict__ A,
+                                                      int* status) {
+  __shared__ double f[RM][RM + 1];
+  for (int e = threadIdx.x; e < R * R; e += BLK) f[e % R][e / R] = F[e];
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (i >= In) return;
+  double m[RM], a[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) {
+    m[c] = c < R ? double(Y[i + int64_t(c) * dstep * In]) : 0.0;
+    if (c < R) M[i + int64_t(c) * In] = m[c];
+  }
+  if (chol) {
+    // U^T y = m (forward), then U a = y (back)
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j >= R) continue;
+      double v = m[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= f[k][j] * a[k];
+      a[j] = v / f[j][j];
+    }
+#pragma unroll
+    for (int j = RM - 1; j >= 0; --j) {
+      if (j >= R) continue;
+      double v = a[j];
+#pragma unroll
+      for (int k = j + 1; k < RM; ++k)
+        if (k < R) v -= f[j][k] * a[k];
+      a[j] = v / f[j][j];
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < RM; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < R && b < R) v += m[c] * f[c][b];
+      a[b] = v;
+    }
+  }
+  bool nonfinite = false;
+#pragma unroll
+  for (int b = 0; b < RM; ++b) {
+    if (b >= R) continue;
+    A[i + int64_t(b) * In] = a[b];
+    nonfinite |= !isfinite(a[b]);
+  }
+  if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
+}
+
+// G = A^T A for an In x R column-major factor; one workgroup per entry, so
+// the two halves of the symmetric matrix come out bit-identical.
+__global__ __launch_bounds__(BLK) void gram_kernel(const double* __restrict__ A, int64_t In, int R, double* G) {
+  __shared__ double sh[BLK / 64];
+  const int a = blockIdx.x % R, b = blockIdx.x / R;
+  const double* ca = A + int64_t(a) * In;
+  const double* cb = A + int64_t(b) * In;
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < In; i += BLK) v += ca[i] * cb[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) G[blockIdx.x] = v;
+}
+
+// Alg. 1's efficient error: ip = <M_N, Ahat_N> = sum M(i,r) A(i,r) lambda_r,
+// partial sums per 256 rows, then nn = <S_N, diag(lambda) G_N diag(lambda)>
+// and relerr = sqrt(max(x2 - 2 ip + nn, 0) / x2) in one workgroup.
+__global__ __launch_bounds__(BLK) void ne_err_partial(const double* __restrict__ M, const double* __restrict__ A,
+                                                      const double* __restrict__ lam, int64_t In, int R,
+                                                      double* part) {
+  __shared__ double sh[BLK / 64];
+  const int64_t i = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  double v = 0.0;
+  if (i < In)
+    for (int c = 0; c < R; ++c) v += M[i + int64_t(c) * In] * A[i + int64_t(c) * In] * lam[c];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(BLK) void ne_err_final(const double* __restrict__ part, int nb,
+                                                    const double* __restrict__ S, const double* __restrict__ GN,
+                                                    const double* __restrict__ lam, int R,
+                                                    const double* __restrict__ xnorm2, double* relerr) {
+  __shared__ double sh[BLK / 64];
+  double ip = 0.0, nn = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLK) ip += part[b];
+  for (int e = threadIdx.x; e < R * R; e += BLK) {
+    const int a = e % R, b = e / R;
+    nn += S[e] * (lam[a] * GN[e] * lam[b]);
+  }
+  ip = block_sum(ip, sh);
+  __syncthreads();
+  nn = block_sum(nn, sh);
+  if (threadIdx.x == 0) {
+    const double x2 = *xnorm2;
+    *relerr = sqrt(fmax(x2 - 2.0 * ip + nn, 0.0) / x2);
+  }
+}
+
 }  // namespace
 
 size_t apply_q0_work(int64_t In, int64_t K, int R) {
@@ -761,6 +908,66 @@ int fit_direct_enqueue(int N, const int64_t* I, int xdtype, const void* X, int R
   CPQR_TRY(check_launch("fit_direct"));
   hipLaunchKernelGGL(sum_final, dim3(1), dim3(BLK), 0, s, part, int(gx * gy), 2, out);
   return check_launch("fit_direct final");
+}
+
+// ------------------------------------------------------------ Alg. 1 host side
+int gram_enqueue(int64_t In, int R, const double* A, double* G, hipStream_t s) {
+  hipLaunchKernelGGL(gram_kernel, dim3(unsigned(R * R)), dim3(BLK), 0, s, A, In, R, G);
+  return check_launch("gram");
+}
+
+size_t ne_update_work(int R) {
+  Carver cv(nullptr);
+  cv.take<int>(4);
+  return cv.bytes();
+}
+
+int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y, double* G, int pinv,
+                      double rtol, double* S, double* F, double* M, double* A, double* lambda, int* status,
+                      void* work, hipStream_t s) {
+  PhaseTimer pt(PH_SOLVE, s);
+  Carver cv(work);
+  int* kept = cv.take<int>(4);
+  hipLaunchKernelGGL(ne_factor_kernel, dim3(1), dim3(BLK), 0, s, G, N, n, R, pinv ? 0 : 1, S, F, status);
+  CPQR_TRY(check_launch("ne_factor"));
+  if (pinv) {
+    if (rtol < 0) rtol = R * 2.220446049250313e-16;
+    // S_n is symmetric, so the transposed pseudo-inverse the kernel forms is pinv(S_n) itself
+    hipLaunchKernelGGL(svd_pinv_kernel, dim3(1), dim3(512), 0, s, S, R, rtol, F, kept, status);
+    CPQR_TRY(check_launch("svd_pinv"));
+  }
+  int64_t dstep = 0, pw = 1;
+  for (int k = 0; k + 1 < N; ++k) {
+    dstep += pw;
+    pw *= R;
+  }
+  const dim3 grd(unsigned(ceil_div(In, BLK)));
+  const int RM = round_rank(R);
+#define ROWS(TY, RMV)                                                                                          \
+  hipLaunchKernelGGL((ne_rows_kernel<TY, RMV>), grd, dim3(BLK), 0, s, static_cast<const TY*>(Y), In, dstep, F, \
+                     pinv ? 0 : 1, R, M, A, status)
+  if (ydtype == CPQR_F64) {
+    if (RM == 8) ROWS(double, 8); else if (RM == 16) ROWS(double, 16); else ROWS(double, 32);
+  } else {
+    if (RM == 8) ROWS(float, 8); else if (RM == 16) ROWS(float, 16); else ROWS(float, 32);
+  }
+#undef ROWS
+  CPQR_TRY(check_launch("ne_rows"));
+  hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
+  CPQR_TRY(check_launch("normalize"));
+  return gram_enqueue(In, R, A, G + int64_t(n) * R * R, s);
+}
+
+size_t ne_error_work(int64_t In) { return size_t(ceil_div(In, BLK)) * sizeof(double); }
+
+int ne_error_enqueue(int64_t In, int R, const double* M, const double* A, const double* lambda, const double* S,
+                     const double* GN, const double* xnorm2, double* relerr, double* part, hipStream_t s) {
+  PhaseTimer pt(PH_ERROR, s);
+  const int nb = int(ceil_div(In, BLK));
+  hipLaunchKernelGGL(ne_err_partial, dim3(unsigned(nb)), dim3(BLK), 0, s, M, A, lambda, In, R, part);
+  CPQR_TRY(check_launch("ne_err_partial"));
+  hipLaunchKernelGGL(ne_err_final, dim3(1), dim3(BLK), 0, s, part, nb, S, GN, lambda, R, xnorm2, relerr);
+  return check_launch("ne_err_final");
 }
 
 }  // namespace cpqr

@@ -98,6 +98,30 @@ def test_validation_codes(L):
     assert L.cpqr_als_sweep(None, 1, None, P, 16, None) == -1
 
 
+def test_validation_normal_equations(L):
+    """Alg. 1 entry points: Q and Rf may be NULL (CP-ALS-QR still needs
+    them); the rest of the problem is validated as for the QR sweep."""
+    P = 4096
+    p = C.Problem()
+    p.N, p.R = 3, 4
+    for k in range(3):
+        p.I[k] = 10
+        p.A[k] = P
+    p.X, p.lam, p.xdtype, p.prec, p.error_mode = P, P, 0, 1, 0
+    assert L.cpqr_als_work(ctypes.byref(p)) == 0
+    w = L.cpqr_als_ne_work(ctypes.byref(p))
+    # Gram matrices (3 x 16), S and its factor, Y (10 x 16), M (10 x 4) at least
+    assert w >= 8 * (48 + 32 + 160 + 40)
+    p.A[1] = None
+    assert L.cpqr_als_ne_work(ctypes.byref(p)) == 0
+    assert L.cpqr_als_ne_init(ctypes.byref(p), P, 1 << 30, None) == -1
+    p.A[1] = P
+    assert L.cpqr_als_ne_sweep(ctypes.byref(p), -1, None, P, 1 << 30, None) == -1
+    assert L.cpqr_als_ne_sweep(ctypes.byref(p), 1, None, P, 16, None) == -4
+    p.I[2] = 3
+    assert L.cpqr_als_ne_init(ctypes.byref(p), P, 1 << 30, None) == -2
+
+
 def test_workspace_queries(L):
     # up to 1024 rows: one node, no work buffer; 5000 x 16: five 1024-row
     # leaves (reflectors 1024 x 16 and T 16 x 16 each) under a root that

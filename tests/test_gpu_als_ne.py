@@ -1,0 +1,155 @@
+"""GPU CP-ALS with the normal equations and CP-ALS-PINV (Alg. 1 through
+cpqr_als_ne_sweep) against the FP64 oracle of Alg. 1 from the same seeded
+data and the same starting factors.  The GPU takes the MTTKRP off the
+Multi-TTM with the factors themselves and, unless a test says otherwise,
+reuses partial Multi-TTMs across modes; the oracle forms X_(n) Z_n with the
+explicit Khatri-Rao product.
+
+Tolerances as for CP-ALS-QR: FP64 error histories to 1e-10 and models to
+1e-9 (relative, via the dense model); the FP32 Multi-TTM path to 1e-5 on the
+direct error, on the same input bytes."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.cp_als as OA
+from oracle import tensor as OT
+from paper_2112_10855_amd import cpqr as C
+from paper_2112_10855_amd import synth
+from helpers import relnorm, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def full_init(shape, R, seed):
+    """Starting factors for every mode (Alg. 1 reads A_0's Gram matrix)."""
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((s, R)) for s in shape]
+
+
+def run_gpu(X, init, maxiters, prec, solver="chol", error_mode=C.ERROR_EFFICIENT, dimtree=-1):
+    tdt = torch.float32 if X.dtype == np.float32 else torch.float64
+    st, hist = C.cp_als(to_dev(X, tdt), init, maxiters=maxiters, prec=prec, solver=solver, error_mode=error_mode,
+                        dimtree=dimtree)
+    torch.cuda.synchronize()
+    return to_np(st.lam), [to_np(a) for a in st.A], np.array(hist), int(st.status.item())
+
+
+def model_diff(lam1, A1, lam2, A2):
+    return relnorm(OT.full(lam1, A1), OT.full(lam2, A2))
+
+
+@pytest.mark.parametrize("solver", ["chol", "pinv"])
+def test_small_fp64(solver):
+    d = synth.workload_small()
+    init = d["init"]
+    lam, A, hist, status = run_gpu(d["X"], init, 25, C.PREC_F64, solver=solver)
+    lo, Ao, ho = OA.cp_als(d["X"], init, maxiters=25, solver=solver)
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, A, lo, Ao) < 1e-9
+    assert hist[-1] < 2e-4
+
+
+@pytest.mark.parametrize("shape,R", [((20, 18, 16, 14), 4), ((8, 7, 6, 5, 6), 3), ((40, 33, 64), 12),
+                                     ((24, 70), 6), ((300, 20, 17), 16), ((40, 36, 34), 32)])
+@pytest.mark.parametrize("prec", [C.PREC_F64, C.PREC_F32])
+def test_nway(shape, R, prec):
+    dt = np.float32 if prec == C.PREC_F32 else np.float64
+    d = synth.cp_tensor(shape, R, 177, noise=1e-3, dtype=dt)
+    init = full_init(shape, R, 178)
+    lam, A, hist, status = run_gpu(d["X"], init, 6, prec, error_mode=C.ERROR_DIRECT)
+    lo, Ao, ho = OA.cp_als(d["X"].astype(np.float64), init, maxiters=6, error="direct")
+    tol = 1e-9 if prec == C.PREC_F64 else 1e-5
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=tol)
+    assert model_diff(lam, A, lo, Ao) < tol
+
+
+@pytest.mark.parametrize("shape,R,split", [((12, 9, 10), 3, 0), ((12, 9, 10), 3, 1), ((12, 9, 10), 3, 2),
+                                           ((6, 5, 7, 4), 2, 1), ((6, 5, 7, 4), 2, 3), ((5, 4, 3, 4, 3), 2, 2)])
+@pytest.mark.parametrize("solver", ["chol", "pinv"])
+def test_dimension_tree_splits_fp64(shape, R, split, solver):
+    d = synth.cp_tensor(shape, R, 421, noise=1e-2, dtype=np.float64)
+    init = full_init(shape, R, 421)
+    lam, A, hist, status = run_gpu(d["X"], init, 8, C.PREC_F64, solver=solver, dimtree=split)
+    lo, Ao, ho = OA.cp_als(d["X"], init, maxiters=8, solver=solver)
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, A, lo, Ao) < 1e-9
+
+
+def test_pinv_rank_deficient_fp64():
+    """Duplicated columns in every starting factor keep every S_n singular:
+    CP-ALS-PINV takes the minimum-norm solution each time, drops one
+    singular value (status TRUNCATED) and matches the oracle's iterates."""
+    shape, R = (14, 12, 13), 4
+    d = synth.cp_tensor(shape, 3, 515, noise=1e-2, dtype=np.float64)
+    init = full_init(shape, R, 516)
+    for a in init:
+        a[:, 2] = a[:, 1]
+    lam, A, hist, status = run_gpu(d["X"], init, 5, C.PREC_F64, solver="pinv")
+    lo, Ao, ho = OA.cp_als(d["X"], init, maxiters=5, solver="pinv")
+    assert status & C.STATUS_TRUNCATED
+    assert not status & C.STATUS_NONFINITE
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, A, lo, Ao) < 1e-9
+
+
+def test_cholesky_breakdown_is_flagged():
+    """A zero column in a starting factor makes S_n singular: the Cholesky
+    solve reports it instead of returning silently."""
+    shape, R = (10, 9, 8), 3
+    d = synth.cp_tensor(shape, R, 600, noise=1e-2, dtype=np.float64)
+    init = full_init(shape, R, 601)
+    init[1][:, 0] = 0.0
+    _, _, _, status = run_gpu(d["X"], init, 1, C.PREC_F64)
+    assert status & C.STATUS_SINGULAR
+
+
+def test_efficient_error_fp32_resolution():
+    """The efficient error of Alg. 1 resolves relerr^2 to the accuracy of
+    <M_N, Ahat_N>; with an FP32 Multi-TTM that is about 1e-6."""
+    d = synth.workload_small(noise=1e-3)
+    X = d["X"].astype(np.float32)
+    init = full_init(X.shape, 5, 33)
+    _, _, hist, _ = run_gpu(X, init, 10, C.PREC_F32)
+    _, _, ho = OA.cp_als(X.astype(np.float64), init, maxiters=10)
+    np.testing.assert_allclose(np.array(hist) ** 2, np.array(ho) ** 2, rtol=0, atol=2e-6)
+
+
+def test_matches_cp_als_qr_on_well_conditioned():
+    """CP-ALS and CP-ALS-QR compute the same iterates in exact arithmetic
+    (section 1); on the GPU, from the same start, their error histories agree."""
+    d = synth.workload_small()
+    X = d["X"]
+    init = full_init(X.shape, 5, 34)
+    _, _, hn, _ = run_gpu(X, init, 15, C.PREC_F64)
+    stq, hq = C.cp_als_qr(to_dev(X, torch.float64), init, maxiters=15, prec=C.PREC_F64)
+    np.testing.assert_allclose(hn, hq, rtol=0, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec,tol", [(C.PREC_BF16X2, 1e-4), (C.PREC_BF16, 1e-2)])
+def test_reduced_precision_multittm(prec, tol):
+    """The bfloat16 Multi-TTM forms feed Alg. 1 as they feed Alg. 2."""
+    shape, R = (64, 60, 56), 8
+    d = synth.cp_tensor(shape, R, 700, noise=1e-3, dtype=np.float32)
+    init = full_init(shape, R, 701)
+    _, _, hist, status = run_gpu(d["X"], init, 6, prec, error_mode=C.ERROR_DIRECT)
+    _, _, ho = OA.cp_als(d["X"].astype(np.float64), init, maxiters=6, error="direct")
+    assert status == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=tol)
+
+
+def test_repeated_calls_continue_the_iteration():
+    """The Gram matrices persist in the work buffer: 3 + 4 sweeps in two
+    calls give the 7-sweep history."""
+    d = synth.workload_small(noise=1e-2)
+    X = to_dev(d["X"], torch.float64)
+    init = full_init(d["X"].shape, 5, 35)
+    st = C.AlsNeState(X, init, prec=C.PREC_F64)
+    st.init()
+    h = torch.cat([st.sweep(3), st.sweep(4)]).cpu().numpy()
+    _, _, ho = OA.cp_als(d["X"], init, maxiters=7)
+    np.testing.assert_allclose(h, ho, rtol=0, atol=1e-10)
