@@ -245,82 +245,101 @@ __global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict
   if (live) A[i + int64_t(c) * In] = ws[c][ri];
 }
 
-// One-sided Jacobi SVD of R0 (R x R, R <= 32) in one workgroup, then
-// M = U S^+ V^T with singular values <= rtol * sigma_max dropped.
-// Thread layout: 16 pairs x 32 rows; a pair's dot products are reductions
-// over the 32 lanes of a half wavefront.
-__global__ __launch_bounds__(512) void svd_pinv_kernel(const double* __restrict__ R0, int R,
-                                                       double rtol, double* M, int* kept_out,
-                                                       int* status) {
-  __shared__ double G[32][33];  // columns of R0 V (rows x cols)
-  __shared__ double Vm[32][33];
-  __shared__ double sig[32];
-  __shared__ int rotated;
-  const int tid = threadIdx.x;
-  const int pr = tid / 32, row = tid % 32;
-  for (int e = tid; e < 32 * 32; e += 512) {
-    const int i = e % 32, j = e / 32;
-    G[i][j] = (i < R && j < R) ? R0[i + j * R] : 0.0;
+// One-sided Jacobi SVD of an R x R matrix B (R <= RM <= 32) in one wavefront,
+// then M = U S^+ V^T = sum over kept j of (B v_j) v_j^T / sigma_j^2, with
+// singular values <= rtol * sigma_max dropped (B = R_0: the transposed
+// pseudo-inverse of R_0; B = S_n symmetric: pinv(S_n)).  The RM/2 column
+// pairs of a round-robin round rotate at once, each on 64/(RM/2) lanes that
+// hold its rows; a pair's three dot products are butterfly sums over those
+// lanes, which leave the same bits on all of them, so every lane of a pair
+// takes the same rotation.  Columns live in LDS between rounds.
+template <int RM>
+__global__ __launch_bounds__(64) void svd_pinv_kernel(const double* __restrict__ B, int R, double rtol,
+                                                      double* M, int* kept_out, int* status) {
+  constexpr int NP = RM / 2;
+  constexpr int LPP = 64 / NP;
+  constexpr int RPL = (RM + LPP - 1) / LPP;
+  __shared__ double G[RM][RM + 1];  // columns of B V
+  __shared__ double Vm[RM][RM + 1];
+  __shared__ double sig[RM];
+  const int lane = threadIdx.x;
+  const int pr = lane / LPP, sub = lane % LPP;
+  for (int e = lane; e < RM * RM; e += 64) {
+    const int i = e % RM, j = e / RM;
+    G[i][j] = (i < R && j < R) ? B[i + j * R] : 0.0;
     Vm[i][j] = (i == j && i < R) ? 1.0 : 0.0;
   }
   const int Rp = R + (R & 1);  // even number of players for the round robin
   const double eps = 2.220446049250313e-16;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
+    bool rotated = false;
     for (int round = 0; round < Rp - 1; ++round) {
+      __syncthreads();
       int p = -1, q = -1;
       if (pr < Rp / 2) {
         auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (Rp - 1)) + 1; };
         p = pos(pr);
         q = pos(Rp - 1 - pr);
-        if (p > q) { int t = p; p = q; q = t; }
+        if (p > q) { const int t = p; p = q; q = t; }
       }
       const bool active = p >= 0 && q < R;
-      double gp = active ? G[row][p] : 0.0, gq = active ? G[row][q] : 0.0;
-      double al = gp * gp, be = gq * gq, ga = gp * gq;
+      double gp[RPL], gq[RPL];
+      double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-      for (int off = 16; off > 0; off >>= 1) {
-        al += __shfl_xor(al, off, 32);
-        be += __shfl_xor(be, off, 32);
-        ga += __shfl_xor(ga, off, 32);
+      for (int t = 0; t < RPL; ++t) {
+        const int row = sub + t * LPP;
+        const bool ok = active && row < R;
+        gp[t] = ok ? G[row][p] : 0.0;
+        gq[t] = ok ? G[row][q] : 0.0;
+        al += gp[t] * gp[t];
+        be += gq[t] * gq[t];
+        ga += gp[t] * gq[t];
       }
-      __syncthreads();
+#pragma unroll
+      for (int off = LPP / 2; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, LPP);
+        be += __shfl_xor(be, off, LPP);
+        ga += __shfl_xor(ga, off, LPP);
+      }
       if (active && fabs(ga) > eps * sqrt(al * be) && ga != 0.0) {
         const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        G[row][p] = c * gp - s * gq;
-        G[row][q] = s * gp + c * gq;
-        const double vp = Vm[row][p], vq = Vm[row][q];
-        Vm[row][p] = c * vp - s * vq;
-        Vm[row][q] = s * vp + c * vq;
-        if (row == 0) rotated = 1;
+        const double tn = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = sub + t * LPP;
+          if (row < R) {
+            G[row][p] = c * gp[t] - sn * gq[t];
+            G[row][q] = sn * gp[t] + c * gq[t];
+            const double vp = Vm[row][p], vq = Vm[row][q];
+            Vm[row][p] = c * vp - sn * vq;
+            Vm[row][q] = sn * vp + c * vq;
+          }
+        }
+        rotated = true;
       }
-      __syncthreads();
     }
-    if (!rotated) break;
     __syncthreads();
+    if (!__any(rotated)) break;
   }
-  __syncthreads();
-  if (tid < 32) {
+  if (lane < RM) {
     double s2 = 0.0;
-    for (int i = 0; i < R; ++i) s2 += G[i][tid] * G[i][tid];
-    sig[tid] = tid < R ? sqrt(s2) : 0.0;
+    for (int i = 0; i < R; ++i) s2 += G[i][lane] * G[i][lane];
+    sig[lane] = lane < R ? sqrt(s2) : 0.0;
   }
   __syncthreads();
   double smax = 0.0;
   for (int j = 0; j < R; ++j) smax = fmax(smax, sig[j]);
   const double tau = rtol * smax;
-  // M = sum over kept j of (G(:,j)/sigma_j^2) V(:,j)^T   (U_j = G(:,j)/sigma_j)
-  for (int e = tid; e < R * R; e += 512) {
+  // U_j = G(:,j) / sigma_j
+  for (int e = lane; e < R * R; e += 64) {
     const int a = e % R, b = e / R;
     double v = 0.0;
     for (int j = 0; j < R; ++j)
       if (sig[j] > tau && sig[j] > 0.0) v += G[a][j] * Vm[b][j] / (sig[j] * sig[j]);
     M[a + b * R] = v;
   }
-  if (tid == 0) {
+  if (lane == 0) {
     int kept = 0;
     for (int j = 0; j < R; ++j) kept += (sig[j] > tau && sig[j] > 0.0) ? 1 : 0;
     *kept_out = kept;
@@ -720,6 +739,17 @@ __global__ __launch_bounds__(BLK) void ne_err_final(const double* __restrict__ p
   }
 }
 
+int launch_svd_pinv(const double* B, int R, double rtol, double* M, int* kept, int* status, hipStream_t s) {
+  const int RM = round_rank(R);
+  if (RM == 8)
+    hipLaunchKernelGGL(svd_pinv_kernel<8>, dim3(1), dim3(64), 0, s, B, R, rtol, M, kept, status);
+  else if (RM == 16)
+    hipLaunchKernelGGL(svd_pinv_kernel<16>, dim3(1), dim3(64), 0, s, B, R, rtol, M, kept, status);
+  else
+    hipLaunchKernelGGL(svd_pinv_kernel<32>, dim3(1), dim3(64), 0, s, B, R, rtol, M, kept, status);
+  return check_launch("svd_pinv");
+}
+
 }  // namespace
 
 size_t apply_q0_work(int64_t In, int64_t K, int R) {
@@ -802,8 +832,7 @@ int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_
     CPQR_TRY(check_launch("solve_tri"));
   } else {
     if (rtol < 0) rtol = R * 2.220446049250313e-16;
-    hipLaunchKernelGGL(svd_pinv_kernel, dim3(1), dim3(512), 0, s, R0, R, rtol, M, kept, status);
-    CPQR_TRY(check_launch("svd_pinv"));
+    CPQR_TRY(launch_svd_pinv(R0, R, rtol, M, kept, status, s));
     if (RM == 8)
       hipLaunchKernelGGL((rowmul_kernel<8>), grd, dim3(BLK), 0, s, W, M, A, In, R, status);
     else if (RM == 16)
@@ -933,8 +962,7 @@ int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y
   if (pinv) {
     if (rtol < 0) rtol = R * 2.220446049250313e-16;
     // S_n is symmetric, so the transposed pseudo-inverse the kernel forms is pinv(S_n) itself
-    hipLaunchKernelGGL(svd_pinv_kernel, dim3(1), dim3(512), 0, s, S, R, rtol, F, kept, status);
-    CPQR_TRY(check_launch("svd_pinv"));
+    CPQR_TRY(launch_svd_pinv(S, R, rtol, F, kept, status, s));
   }
   int64_t dstep = 0, pw = 1;
   for (int k = 0; k + 1 < N; ++k) {
