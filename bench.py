@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1000, help="mode size of the cubic tensor")
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x2", "bf16"])
-    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned", "fit"],
+    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned", "fit", "sinsum"],
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
@@ -79,6 +79,60 @@ def traffic_from_profiles(kernel_src_sha):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def run_sinsum(args):
+    """Sine of sums (section 4.3): the four ALS algorithms fit the rank-N form
+    of sin(x_1 + ... + x_N) on the paper's lower-order grids (N = 4, n = 64
+    and 128; N = 5, n = 32 and 64), 40 sweeps from one shared random start,
+    FP64, relative error taken directly after every sweep."""
+    import torch
+
+    from paper_2112_10855_amd import cpqr as C
+    from paper_2112_10855_amd import synth
+
+    cases = [(4, 64), (4, 128), (5, 32), (5, 64)]
+    iters = 40
+    results = []
+    for N, n in cases:
+        t0 = time.time()
+        X = synth.sine_of_sums(N, n)
+        Xd = torch.from_numpy(X.reshape(-1, order="F")).to("cuda").view(*(n,) * N).permute(*reversed(range(N)))
+        del X
+        log("sine of sums N=%d n=%d: generated and uploaded in %.1f s" % (N, n, time.time() - t0))
+        init = synth.init_factors((n,) * N, N, 4400 + 10 * N + n)
+        row = {"N": N, "n": n, "rank": N}
+        for alg in ("als", "pinv", "qr", "qrsvd"):
+            kw = dict(prec=C.PREC_F64, error_mode=C.ERROR_DIRECT)
+            if alg in ("als", "pinv"):
+                st = C.AlsNeState(Xd, init, solver="chol" if alg == "als" else "pinv", **kw)
+            else:
+                st = C.AlsState(Xd, init, use_svd=alg == "qrsvd", **kw)
+            st.init()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rel = st.sweep(iters)
+            e1.record()
+            torch.cuda.synchronize()
+            h = rel.cpu().numpy()
+            row[alg] = {"relerr_final": float(h[-1]), "relerr_min": float(h.min()),
+                        "relerr_every_5": [float(v) for v in h[4::5]],
+                        "ms_per_sweep": round(e0.elapsed_time(e1) / iters, 4)}
+            log("  %-5s final relerr %.3e, %.3f ms/sweep" % (alg, h[-1], row[alg]["ms_per_sweep"]))
+        results.append(row)
+        del Xd
+        torch.cuda.empty_cache()
+    main_case = results[1]
+    out = {
+        "metric": "sine of sums: relative error after 40 sweeps (CP-ALS-QR)", "value": main_case["qr"]["relerr_final"],
+        "unit": "relative error", "n_gpus": 1, "steps": iters, "warmup": 0,
+        "ms_per_step": main_case["qr"]["ms_per_sweep"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (closed form)",
+        "config": {"workload": "sine_of_sums_4way_n128_rank4_f64", "iterations": iters, "error": "direct",
+                   "start": "iid N(0,1) factors shared by the four algorithms"},
+        "cases": results,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_dense4(args):
@@ -299,10 +353,11 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("dense4", "batch", "learned", "fit"):
+    if args.workload in ("dense4", "batch", "learned", "fit", "sinsum"):
         import torch
         torch.cuda.set_device(0)
-        return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned, "fit": run_fit}[args.workload](args)
+        return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned, "fit": run_fit,
+                "sinsum": run_sinsum}[args.workload](args)
 
     import hashlib
 

@@ -182,3 +182,59 @@ def batch_shapes(count=512, lo=20, hi=160, rlo=2, rhi=12, seed=4000):
     dims = g.integers(lo, hi + 1, size=(count, 3))
     ranks = g.integers(rlo, rhi + 1, size=count)
     return [(tuple(int(v) for v in dims[b]), int(ranks[b])) for b in range(count)]
+
+
+# ---------------------------------------------------------------- sine of sums
+# The function-approximation workload of section 4.3: sin(x_1 + ... + x_N)
+# on an n-point grid of [0, 2 pi) per variable, a tensor of exact CP rank at
+# most N with a known rank-2^{N-1} expansion.
+
+def sine_of_sums_grid(n):
+    """x_j: n points discretizing [0, 2 pi) (x_i = 2 pi i / n, i = 0..n-1)."""
+    return 2.0 * np.pi * np.arange(int(n), dtype=np.float64) / int(n)
+
+
+def sine_of_sums(N, n, dtype=np.float64):
+    """Dense X[i_1, ..., i_N] = sin(x_{i_1} + ... + x_{i_N}), Fortran order;
+    the sums and sines are taken in FP64, then cast to ``dtype``."""
+    x = sine_of_sums_grid(n)
+    S = np.zeros((int(n),) * N, dtype=np.float64, order="F")
+    for k in range(N):
+        sh = [1] * N
+        sh[k] = int(n)
+        S += x.reshape(sh)
+    np.sin(S, out=S)
+    return S if dtype == np.float64 else np.asfortranarray(S.astype(dtype))
+
+
+def sine_of_sums_expanded(N, n):
+    """The rank-2^{N-1} CP form from the sum identities of sine and cosine:
+    one term per set J of variables of odd size, sign (-1)^{(|J|-1)/2},
+    factor sin(x) in the modes of J and cos(x) elsewhere.  Returns (lam, A)."""
+    x = sine_of_sums_grid(n)
+    s, c = np.sin(x), np.cos(x)
+    cols = [[] for _ in range(N)]
+    lam = []
+    for mask in range(1 << N):
+        k = bin(mask).count("1")
+        if k % 2 == 0:
+            continue
+        lam.append(-1.0 if (k - 1) // 2 % 2 else 1.0)
+        for j in range(N):
+            cols[j].append(s if mask >> j & 1 else c)
+    return np.array(lam), [np.stack(cj, axis=1) for cj in cols]
+
+
+def sine_of_sums_rank_n(N, n, alpha):
+    """The rank-N CP form of eq. (sinsum_rkd): term j has sin(x) in mode j
+    and sin(x + alpha_k - alpha_j) / sin(alpha_k - alpha_j) in every other
+    mode k (the alpha_j pairwise distinct modulo pi).  Returns (lam, A)."""
+    x = sine_of_sums_grid(n)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    A = []
+    for k in range(N):
+        M = np.empty((int(n), N))
+        for j in range(N):
+            M[:, j] = np.sin(x) if k == j else np.sin(x + alpha[k] - alpha[j]) / np.sin(alpha[k] - alpha[j])
+        A.append(M)
+    return np.ones(N), A
