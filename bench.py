@@ -45,9 +45,10 @@ def parse():
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
-    ap.add_argument("--method", default="qr", choices=["qr", "als", "als-pinv"],
-                    help="dense3 only: qr = CP-ALS-QR (Alg. 2, default); als = CP-ALS with the normal equations "
-                         "(Alg. 1, Cholesky); als-pinv = CP-ALS-PINV (Alg. 1, pseudo-inverse)")
+    ap.add_argument("--method", default="qr", choices=["qr", "qr-svd", "als", "als-pinv"],
+                    help="dense3 only: qr = CP-ALS-QR (Alg. 2, default); qr-svd = CP-ALS-QR-SVD (Alg. 2 with the "
+                         "SVD solve); als = CP-ALS with the normal equations (Alg. 1, Cholesky); als-pinv = "
+                         "CP-ALS-PINV (Alg. 1, pseudo-inverse)")
     ap.add_argument("--dimtree", type=int, default=-1,
                     help="Multi-TTM reuse across modes: -1 library choice, 0 one Multi-TTM per mode, h split point")
     ap.add_argument("--train", type=int, default=20000, help="training tensors for --workload learned")
@@ -388,8 +389,8 @@ def main():
     if prec == C.PREC_F64:
         Xd = Xd.double()
     def make_state(dimtree):
-        if args.method == "qr":
-            return C.AlsState(Xd, d["init"], prec=prec, dimtree=dimtree)
+        if args.method in ("qr", "qr-svd"):
+            return C.AlsState(Xd, d["init"], prec=prec, dimtree=dimtree, use_svd=args.method == "qr-svd")
         return C.AlsNeState(Xd, d["init"], prec=prec, solver="chol" if args.method == "als" else "pinv",
                             dimtree=dimtree)
 
@@ -467,10 +468,10 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {
-            "workload": "%s_dense3_%dcube_%s_r%d" % ({"qr": "cp_als_qr", "als": "cp_als", "als-pinv": "cp_als_pinv"}[
+            "workload": "%s_dense3_%dcube_%s_r%d" % ({"qr": "cp_als_qr", "qr-svd": "cp_als_qr_svd", "als": "cp_als", "als-pinv": "cp_als_pinv"}[
                 args.method], n, args.prec, R),
             "shape": list(shape), "rank": R, "multittm_precision": args.prec,
-            "small_steps_precision": "f64", "solver": {"qr": "qr", "als": "cholesky", "als-pinv": "pinv"}[args.method],
+            "small_steps_precision": "f64", "solver": {"qr": "qr", "qr-svd": "svd", "als": "cholesky", "als-pinv": "pinv"}[args.method],
             "error": "efficient", "dimtree": args.dimtree,
             "ground_truth": "rank-16, column congruence 0.99, relative noise 1e-3",
         },
@@ -518,8 +519,8 @@ def main():
         sweeps, t = 0, 0.0
         while sweeps < 1 or (t < args.cpu_seconds and sweeps < 5):
             a = time.perf_counter()
-            if args.method == "qr":
-                orel, _ = OQ.sweep(X64, ost, xnorm2=xn2)
+            if args.method in ("qr", "qr-svd"):
+                orel, _ = OQ.sweep(X64, ost, xnorm2=xn2, solver="svd" if args.method == "qr-svd" else "qr")
             else:  # Alg. 1 sweep and its efficient error, as the oracle's cp_als takes them
                 for m in range(3):
                     Ahat, lam, M, S = OA.mode_update(X64, oA, oG, m, solver="chol" if args.method == "als" else "pinv")
