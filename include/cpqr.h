@@ -186,8 +186,9 @@ typedef struct cpqr_problem {
   double* Rf[CPQR_MAX_MODES];     /* device R x R triangular factors (leading dimension R) */
   double* lambda;                 /* device, R weights */
   int prec;                       /* CPQR_PREC_* of the Multi-TTM */
-  int use_svd;                    /* 0: substitution, 1: SVD solve */
-  double rtol;                    /* SVD cutoff (negative: default) */
+  int use_svd;                    /* CP-ALS-QR: 0 substitution, 1 SVD solve;
+                                     CP-ALS (cpqr_als_ne_*): 0 Cholesky, 1 pseudo-inverse */
+  double rtol;                    /* cutoff of the SVD or pseudo-inverse (negative: default) */
   int error_mode;                 /* CPQR_ERROR_* */
   int* status;                    /* device int or NULL */
   int dimtree;                    /* Multi-TTM reuse across modes: 0 off (one Multi-TTM of X
