@@ -72,6 +72,9 @@ extern "C" {
 #define CPQR_STATUS_NONFINITE 2  /* a solved factor holds Inf/NaN */
 #define CPQR_STATUS_TRUNCATED 4  /* the SVD solve dropped singular values */
 #define CPQR_STATUS_ZERO_COLUMN 8 /* a solved factor column has zero norm */
+#define CPQR_STATUS_ILL_CONDITIONED 16 /* CP-ALS (Cholesky): cond(S_n) is proven above 1e4 (so
+                                          cond(Z_n) > 100): max_j S_jj ||S_n^-1 x|| > 1e4 for a unit x
+                                          from four steps of inverse iteration */
 
 /* error forms of section 3.3.1 */
 #define CPQR_ERROR_EFFICIENT 0 /* from W_N, R_0, R_N and lambda; accurate to ~sqrt(eps) */
@@ -216,7 +219,9 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
  * factors A_k themselves in place of Q_k), whose column r (1 + R + ... +
  * R^{N-2}) is column r of M_n.  S_n is the Hadamard product of the Gram
  * matrices A_k^T A_k over k != n, and Ahat_n S_n = M_n is solved by Cholesky
- * (use_svd = 0; a non-positive pivot sets CPQR_STATUS_SINGULAR) or with the
+ * (use_svd = 0; a non-positive pivot sets CPQR_STATUS_SINGULAR, a proven
+ * cond(S_n) > 1e4 sets CPQR_STATUS_ILL_CONDITIONED, the signal a hybrid
+ * driver uses to switch to CP-ALS-QR) or with the
  * pseudo-inverse of S_n (use_svd = 1, CP-ALS-PINV: singular values of S_n at
  * or below rtol times the largest are dropped, rtol < 0 meaning R * 2^-52;
  * dropping sets CPQR_STATUS_TRUNCATED).  Columns are normalized into lambda.

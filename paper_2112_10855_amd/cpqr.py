@@ -27,6 +27,7 @@ MAX_RANK = 32
 F32, F64 = 0, 1
 PREC_F64, PREC_F32, PREC_BF16X2, PREC_BF16 = 0, 1, 2, 3
 STATUS_SINGULAR, STATUS_NONFINITE, STATUS_TRUNCATED, STATUS_ZERO_COLUMN = 1, 2, 4, 8
+STATUS_ILL_CONDITIONED = 16
 ERROR_EFFICIENT, ERROR_DIRECT, ERROR_NONE = 0, 1, 2
 NPHASES = 8
 PHASES = ["multittm", "ttm_first", "factor_qr", "q0", "apply_q0", "solve", "error", "ttm_stream_m"]
@@ -455,6 +456,29 @@ def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.
         if s >= 1 and abs(hist[-2] - hist[-1]) < tol:
             break
     return st, hist
+
+
+def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIENT, dimtree=-1):
+    """The robust solver the paper envisions (section 1, section 5): CP-ALS
+    with the normal equations while they are well conditioned, CP-ALS-QR from
+    the current factors once a Cholesky factorization proves cond(S_n) > 1e4
+    (cond(Z_n) > 100) or breaks down.  The status word is read after every sweep; the sweep
+    that raised the flag is kept, and the QR sweeps continue from its factors.
+    Returns (state, history, number of normal-equations sweeps)."""
+    st = AlsNeState(X, init, prec=prec, solver="chol", error_mode=error_mode, dimtree=dimtree)
+    st.init()
+    hist = []
+    for s in range(maxiters):
+        hist.append(float(st.sweep(1)[0].item()))
+        if int(st.status.item()) & (STATUS_ILL_CONDITIONED | STATUS_SINGULAR | STATUS_NONFINITE):
+            break
+    n_ne = len(hist)
+    if n_ne == maxiters:
+        return st, hist, n_ne
+    qst = AlsState(X, [a.clone() for a in st.A], prec=prec, error_mode=error_mode, dimtree=dimtree)
+    qst.init()
+    hist += qst.sweep(maxiters - n_ne).cpu().tolist()
+    return qst, hist, n_ne
 
 
 class AlsBatch:

@@ -628,7 +628,38 @@ __global__ __launch_bounds__(BLK) void ne_factor_kernel(const double* __restrict
   }
   __syncthreads();
   for (int e = threadIdx.x; e < R * R; e += BLK) U[e] = u[e % R][e / R];
-  if (threadIdx.x == 0 && bad && status) atomicOr(status, CPQR_STATUS_SINGULAR);
+  if (threadIdx.x == 0 && status) {
+    if (bad) {
+      atomicOr(status, CPQR_STATUS_SINGULAR);
+    } else {
+      // A lower bound on cond(S_n) by inverse iteration: for unit x,
+      // ||S_n^-1 x|| <= 1 / lambda_min, and max_j S_jj <= lambda_max.
+      // Four steps from the all-ones vector, each two substitutions with U.
+      double x[32], smax = 0.0, est = 0.0;
+      for (int j = 0; j < R; ++j) {
+        x[j] = 1.0 / sqrt(double(R));
+        smax = fmax(smax, S[j + j * R]);
+      }
+      for (int it = 0; it < 4; ++it) {
+        for (int j = 0; j < R; ++j) {  // U^T y = x
+          double v = x[j];
+          for (int k = 0; k < j; ++k) v -= u[k][j] * x[k];
+          x[j] = v / u[j][j];
+        }
+        double nrm = 0.0;
+        for (int j = R - 1; j >= 0; --j) {  // U z = y
+          double v = x[j];
+          for (int k = j + 1; k < R; ++k) v -= u[j][k] * x[k];
+          x[j] = v / u[j][j];
+          nrm += x[j] * x[j];
+        }
+        nrm = sqrt(nrm);
+        est = fmax(est, smax * nrm);
+        for (int j = 0; j < R; ++j) x[j] /= nrm;
+      }
+      if (est > 1e4) atomicOr(status, CPQR_STATUS_ILL_CONDITIONED);
+    }
+  }
 }
 
 // Row i of the MTTKRP M_n = X_(n) Z_n is read off Y_(n) = X_(n) (A_N kron ..

@@ -153,3 +153,26 @@ def test_repeated_calls_continue_the_iteration():
     h = torch.cat([st.sweep(3), st.sweep(4)]).cpu().numpy()
     _, _, ho = OA.cp_als(d["X"], init, maxiters=7)
     np.testing.assert_allclose(h, ho, rtol=0, atol=1e-10)
+
+
+def test_hybrid_stays_on_normal_equations_when_well_conditioned():
+    """cond(S_n) stays near 1 on this problem: the hybrid never switches and
+    its history is Alg. 1's."""
+    d = synth.workload_small()
+    st, hist, n_ne = C.cp_als_hybrid(to_dev(d["X"], torch.float64), d["init"], maxiters=12, prec=C.PREC_F64)
+    _, _, ho = OA.cp_als(d["X"], d["init"], maxiters=12)
+    assert n_ne == 12
+    assert int(st.status.item()) == 0
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+
+
+def test_ill_conditioning_is_flagged_at_full_collinearity():
+    """Nearly collinear factors (column congruence 0.99999, start near the
+    truth) make S_n ill conditioned: the bound evaluated on the oracle's
+    iterates is 1.8e4-1.7e5 in every update of the first two sweeps (cond(S_n)
+    7.7e4-6.8e5), and the Cholesky step reports it."""
+    shape, R = (30, 28, 26), 4
+    d = synth.cp_tensor(shape, R, 810, congruence=0.99999, noise=1e-4, dtype=np.float64)
+    init = [a + 1e-3 * b for a, b in zip(d["A"], full_init(shape, R, 811))]
+    _, _, _, status = run_gpu(d["X"], init, 2, C.PREC_F64)
+    assert status & C.STATUS_ILL_CONDITIONED

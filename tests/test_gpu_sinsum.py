@@ -66,3 +66,19 @@ def test_qr_reaches_lower_error_5way_n32():
     print({k: "%.2e" % v for k, v in final.items()})
     assert max(final["qr"], final["qrsvd"]) < 1e-13
     assert 10 * max(final["qr"], final["qrsvd"]) < min(final["als"], final["pinv"])
+
+
+def test_hybrid_switches_to_qr_and_reaches_its_accuracy():
+    """The hybrid solver on the same problem: CP-ALS until a Cholesky step
+    proves cond(S_n) > 1e4, then CP-ALS-QR from the current factors.  The same
+    inverse-iteration bound evaluated on the oracle's CP-ALS iterates first
+    exceeds 1e4 in sweep 6 (1.7e4, with cond(S_n) = 6.3e4); after the switch
+    the error reaches the QR level that CP-ALS alone does not."""
+    N, n = 5, 32
+    Xd = to_dev(synth.sine_of_sums(N, n), torch.float64)
+    init = synth.init_factors((n,) * N, N, 4400 + 10 * N + n)
+    st, hist, n_ne = C.cp_als_hybrid(Xd, init, maxiters=40, prec=C.PREC_F64, error_mode=C.ERROR_DIRECT)
+    print("hybrid: %d normal-equations sweeps, final %.2e" % (n_ne, hist[-1]))
+    assert n_ne == 6
+    assert len(hist) == 40
+    assert hist[-1] < 1e-13
