@@ -593,6 +593,14 @@ void launch_apply(const ApplyPlan& ap, int64_t In, int64_t K, int R, int ydtype,
 constexpr int NORM_BLOCKS = 2048;
 
 // ------------------------------------------------------------ Alg. 1 (normal equations)
+// The value of v on lane j (j uniform across the wavefront).
+__device__ inline double lane_value(double v, int j) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(b), j);
+  const unsigned hi = __builtin_amdgcn_readlane(int(b >> 32), j);
+  return __builtin_bit_cast(double, (long long)((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // S_n = Hadamard product of the Gram matrices G_k = A_k^T A_k over k != n
 // (section 2.3), multiplied in increasing k; for the Cholesky solve also the
 // upper factor U of S_n = U^T U (right-looking, one column per step).  One
@@ -601,6 +609,7 @@ __global__ __launch_bounds__(BLK) void ne_factor_kernel(const double* __restrict
                                                         int chol, double* S, double* U, int* status) {
   __shared__ double s[32][33];
   __shared__ double u[32][33];
+  __shared__ double sd[32];
   for (int e = threadIdx.x; e < R * R; e += BLK) {
     const int a = e % R, b = e / R;
     double v = 1.0;
@@ -608,6 +617,7 @@ __global__ __launch_bounds__(BLK) void ne_factor_kernel(const double* __restrict
       if (k != n) v *= G[int64_t(k) * R * R + e];
     s[a][b] = v;
     S[e] = v;
+    if (a == b) sd[a] = v;
   }
   if (!chol) return;
   bool bad = false;
@@ -628,38 +638,51 @@ __global__ __launch_bounds__(BLK) void ne_factor_kernel(const double* __restrict
   }
   __syncthreads();
   for (int e = threadIdx.x; e < R * R; e += BLK) U[e] = u[e % R][e / R];
-  if (threadIdx.x == 0 && status) {
-    if (bad) {
-      atomicOr(status, CPQR_STATUS_SINGULAR);
-    } else {
-      // A lower bound on cond(S_n) by inverse iteration: for unit x,
-      // ||S_n^-1 x|| <= 1 / lambda_min, and max_j S_jj <= lambda_max.
-      // Four steps from the all-ones vector, each two substitutions with U.
-      double x[32], smax = 0.0, est = 0.0;
-      for (int j = 0; j < R; ++j) {
-        x[j] = 1.0 / sqrt(double(R));
-        smax = fmax(smax, S[j + j * R]);
-      }
-      for (int it = 0; it < 4; ++it) {
-        for (int j = 0; j < R; ++j) {  // U^T y = x
-          double v = x[j];
-          for (int k = 0; k < j; ++k) v -= u[k][j] * x[k];
-          x[j] = v / u[j][j];
-        }
-        double nrm = 0.0;
-        for (int j = R - 1; j >= 0; --j) {  // U z = y
-          double v = x[j];
-          for (int k = j + 1; k < R; ++k) v -= u[j][k] * x[k];
-          x[j] = v / u[j][j];
-          nrm += x[j] * x[j];
-        }
-        nrm = sqrt(nrm);
-        est = fmax(est, smax * nrm);
-        for (int j = 0; j < R; ++j) x[j] /= nrm;
-      }
-      if (est > 1e4) atomicOr(status, CPQR_STATUS_ILL_CONDITIONED);
-    }
+  if (!status) return;
+  if (bad) {
+    if (threadIdx.x == 0) atomicOr(status, CPQR_STATUS_SINGULAR);
+    return;
   }
+  if (threadIdx.x >= 64) return;
+  // A lower bound on cond(S_n) by inverse iteration, in wavefront 0: for unit
+  // x, ||S_n^-1 x|| <= 1 / lambda_min and max_j S_jj <= lambda_max.  Four
+  // steps from the all-ones vector, each two substitutions with U done
+  // column by column: lane i holds x_i and column and row i of U.
+  const int lane = threadIdx.x;
+  double ucol[32], urow[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    ucol[j] = (lane < R && j < R) ? u[j][lane] : 0.0;
+    urow[j] = (lane < R && j < R) ? u[lane][j] : 0.0;
+  }
+  const double dinv = lane < R ? 1.0 / u[lane][lane] : 0.0;
+  double smax = lane < R ? sd[lane] : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  double x = lane < R ? 1.0 / sqrt(double(R)) : 0.0, est = 0.0;
+  for (int it = 0; it < 4; ++it) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {  // U^T y = x
+      if (j >= R) continue;
+      const double yj = lane_value(x * dinv, j);
+      if (lane == j) x = yj;
+      else if (lane > j) x -= ucol[j] * yj;
+    }
+#pragma unroll
+    for (int j = 31; j >= 0; --j) {  // U z = y
+      if (j >= R) continue;
+      const double zj = lane_value(x * dinv, j);
+      if (lane == j) x = zj;
+      else if (lane < j) x -= urow[j] * zj;
+    }
+    double n2 = x * x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n2 += __shfl_xor(n2, off, 64);
+    const double nrm = sqrt(n2);
+    est = fmax(est, smax * nrm);
+    x /= nrm;
+  }
+  if (lane == 0 && est > 1e4) atomicOr(status, CPQR_STATUS_ILL_CONDITIONED);
 }
 
 // Row i of the MTTKRP M_n = X_(n) Z_n is read off Y_(n) = X_(n) (A_N kron ..
