@@ -43,30 +43,3 @@ def ttm_cost_closed_form(shape, n, R):
 def krp_qr_flops(N, R):
     """eq. (QRcost): 4 R^{N+1}, leading order, Q_0 formed explicitly."""
     return 4 * R ** (N + 1)
-
-
-def krp_form_flops(N, R):
-    """Forming V_n pairwise without exploiting sparsity: R^N (leading order)."""
-    return R ** N
-
-
-def apply_q0_flops(In, N, R):
-    """W_n = Y_(n) Q_0 with a dense Q_0: 2 I_n R^N."""
-    return 2 * In * R ** N
-
-
-def factor_qr_flops(In, R):
-    """Thin QR of I_n x R with Q formed explicitly: 4 I_n R^2 (leading order)."""
-    return 4 * In * R * R
-
-
-def mode_update_flops(shape, n, R):
-    """Leading-order flops of one Alg. 2 mode update (section 3.2)."""
-    N = len(shape)
-    return (krp_form_flops(N, R) + krp_qr_flops(N, R) + ttm_sequence_flops(shape, n, R)
-            + apply_q0_flops(shape[n], N, R) + 2 * shape[n] * R * R
-            + factor_qr_flops(shape[n], R))
-
-
-def sweep_flops(shape, R):
-    return sum(mode_update_flops(shape, n, R) for n in range(len(shape)))

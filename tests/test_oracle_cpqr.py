@@ -341,7 +341,80 @@ def test_ttm_cost_model():
                 a = costs.ttm_sequence_flops(shape, n, R)
                 b = costs.ttm_cost_closed_form(shape, n, R)
                 assert abs(a - b) <= 1e-9 * b
-    assert costs.krp_qr_flops(3, 16) == 4 * 16 ** 4
+
+
+def counted_householder_qr(M):
+    """Textbook Householder QR of an m x n matrix with Q formed explicitly by
+    backward accumulation, run on the actual numbers and counting every
+    floating-point addition, multiplication, division and square root it
+    performs.  Returns (Q, R, flop count).  Independent of the cost formula:
+    the count is what the loops execute."""
+    A = np.array(M, dtype=np.float64)
+    m, n = A.shape
+    flops = 0
+    vs, taus = [], []
+    for j in range(n):
+        x = A[j:, j].copy()
+        nrm = np.sqrt(np.dot(x, x))
+        flops += 2 * len(x)                       # squares, sum, sqrt
+        alpha = -nrm if x[0] >= 0 else nrm
+        v = x.copy()
+        v[0] -= alpha
+        flops += 1
+        vv = np.dot(v, v)
+        flops += 2 * len(v)
+        tau = 0.0 if vv == 0 else 2.0 / vv
+        flops += 1
+        for c in range(j + 1, n):                # A(j:, c) -= tau v (v^T A(j:, c))
+            d = np.dot(v, A[j:, c])
+            A[j:, c] -= tau * d * v
+            flops += 2 * len(v) + 1 + 2 * len(v)
+        A[j, j] = alpha                          # H_j x = alpha e_1
+        A[j + 1:, j] = 0.0
+        vs.append(v)
+        taus.append(tau)
+    Qm = np.eye(m, n)
+    for j in reversed(range(n)):                 # Q = H_0 .. H_{n-1} [I; 0]
+        v, tau = vs[j], taus[j]
+        for c in range(j, n):
+            d = np.dot(v, Qm[j:, c])
+            Qm[j:, c] -= tau * d * v
+            flops += 2 * len(v) + 1 + 2 * len(v)
+    return Qm, np.triu(A[:n, :]), flops
+
+
+@pytest.mark.parametrize("N,R", [(3, 4), (3, 6), (4, 3), (4, 5), (5, 3), (6, 2)])
+def test_krp_qr_cost_against_counted_householder(N, R):
+    """eq. (QRcost): the QR of the R^{N-1} x R matrix V_n with Q_0 formed
+    costs 4 R^{N+1} flops to leading order.  A Householder QR that counts the
+    operations it performs on V_n agrees with that figure up to the terms of
+    order R^3 (the triangle: 4 R^3 / 3) and R^N (the reflector norms: about
+    4 m R), and the counted QR really factors V_n.  The bound is tight enough
+    that 2 R^{N+1} or 4 R^N would fail it."""
+    rng = np.random.default_rng(N * 10 + R)
+    Rs = [Q.factor_qr(rng.standard_normal((R + 2, R)))[1] for _ in range(N)]
+    V = Q.krp_of_r(Rs, 0)
+    m = R ** (N - 1)
+    assert V.shape == (m, R)
+    Qm, Rm, flops = counted_householder_qr(V)
+    assert np.linalg.norm(Qm @ Rm - V) <= 1e-13 * np.linalg.norm(V)
+    lead = costs.krp_qr_flops(N, R)
+    lower = 4.0 * m * R + 4.0 * R ** 3 / 3.0 + 8.0 * R * R
+    assert abs(flops - lead) <= lower, (flops, lead, lower)
+
+
+def test_krp_qr_cost_leading_term_dominates():
+    """The terms below eq. (QRcost)'s leading one are of relative size 1/R
+    (reflector norms) and R^{2-N} (the triangle): with N = 3 and growing R
+    the counted flops approach 4 R^{N+1} from above."""
+    ratios = []
+    for R in (4, 8, 16):
+        rng = np.random.default_rng(R)
+        Rs = [Q.factor_qr(rng.standard_normal((R + 2, R)))[1] for _ in range(3)]
+        flops = counted_householder_qr(Q.krp_of_r(Rs, 0))[2]
+        ratios.append(flops / costs.krp_qr_flops(3, R))
+    assert ratios[0] > ratios[1] > ratios[2] > 1.0
+    assert ratios[2] - 1.0 < 0.1, ratios
 
 
 # ---------------------------------------------------------- planted mistakes
