@@ -460,22 +460,38 @@ def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.
 
 def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIENT, dimtree=-1):
     """The robust solver the paper envisions (section 1, section 5): CP-ALS
-    with the normal equations while they are well conditioned, CP-ALS-QR from
-    the current factors once a Cholesky factorization proves cond(S_n) > 1e4
-    (cond(Z_n) > 100) or breaks down.  The status word is read after every sweep; the sweep
-    that raised the flag is kept, and the QR sweeps continue from its factors.
-    Returns (state, history, number of normal-equations sweeps)."""
+    with the normal equations while they are well conditioned, then CP-ALS-QR.
+    The status word is read after every sweep.
+
+    * A Cholesky step that proves cond(S_n) > 1e4 (cond(Z_n) > 100): the
+      sweep is kept and CP-ALS-QR continues from its factors.
+    * A breakdown (a non-positive Cholesky pivot, or a non-finite factor):
+      the sweep's factors are not usable, so it is discarded and
+      CP-ALS-QR-SVD redoes it from the factors the sweep started from (a
+      device copy taken before every normal-equations sweep); the
+      pseudo-inverse solve is defined also when Z_n is rank deficient
+      (section 3.1), which is what a breakdown signals.
+
+    Returns (state, history, number of normal-equations sweeps kept)."""
     st = AlsNeState(X, init, prec=prec, solver="chol", error_mode=error_mode, dimtree=dimtree)
     st.init()
     hist = []
+    start, use_svd = None, False
     for s in range(maxiters):
-        hist.append(float(st.sweep(1)[0].item()))
-        if int(st.status.item()) & (STATUS_ILL_CONDITIONED | STATUS_SINGULAR | STATUS_NONFINITE):
+        before = [a.clone() for a in st.A]
+        rel = float(st.sweep(1)[0].item())
+        flags = int(st.status.item())
+        if flags & (STATUS_SINGULAR | STATUS_NONFINITE):
+            start, use_svd = before, True
+            break
+        hist.append(rel)
+        if flags & STATUS_ILL_CONDITIONED:
+            start = [a.clone() for a in st.A]
             break
     n_ne = len(hist)
-    if n_ne == maxiters:
+    if start is None:
         return st, hist, n_ne
-    qst = AlsState(X, [a.clone() for a in st.A], prec=prec, error_mode=error_mode, dimtree=dimtree)
+    qst = AlsState(X, start, prec=prec, use_svd=use_svd, error_mode=error_mode, dimtree=dimtree)
     qst.init()
     hist += qst.sweep(maxiters - n_ne).cpu().tolist()
     return qst, hist, n_ne

@@ -391,7 +391,7 @@ __device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, in
     nn = wg_sum1(nn, sh, tid);
     if (tid == 0 && it.relerr) {
       const double r2 = x2 - 2.0 * ip + nn;
-      it.relerr[offset + sweep] = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
+      it.relerr[offset + sweep] = isnan(r2) ? r2 : sqrt((r2 > 0.0 ? r2 : 0.0) / x2);  // NaN stays NaN
     }
     __syncthreads();
   }

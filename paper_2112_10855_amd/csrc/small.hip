@@ -440,6 +440,12 @@ __global__ __launch_bounds__(BLK) void error_efficient_kernel(
   if (threadIdx.x == 0) part[0] = nn;
 }
 
+// sqrt(max(r2, 0) / x2); a NaN residual stays NaN (a non-finite model must
+// not read as a perfect fit)
+__device__ __forceinline__ double rel_from_r2(double r2, double x2) {
+  return isnan(r2) ? r2 : sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
+}
+
 // relerr from the partial sums (block order fixed): nb partial ip's after nn
 __global__ void error_efficient_final(const double* __restrict__ part, int nb, const double* __restrict__ xnorm2,
                                       double* relerr) {
@@ -447,12 +453,11 @@ __global__ void error_efficient_final(const double* __restrict__ part, int nb, c
   for (int b = 0; b < nb; ++b) ip += part[1 + b];
   const double x2 = *xnorm2;
   const double r2 = x2 - 2.0 * ip + part[0];
-  *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / x2);
+  *relerr = rel_from_r2(r2, x2);
 }
 
 __global__ void error_from_fit_kernel(const double* fit, double* relerr) {
-  const double r2 = fit[0];
-  *relerr = sqrt((r2 > 0.0 ? r2 : 0.0) / fit[1]);
+  *relerr = rel_from_r2(fit[0], fit[1]);
 }
 
 __global__ void fill_kernel(double* p, int64_t count, double v) {
@@ -504,10 +509,12 @@ __global__ __launch_bounds__(BLK) void fit_direct_kernel(const TX* __restrict__ 
   const int64_t i = int64_t(blockIdx.y) * BLK + threadIdx.x;
   const int64_t s0 = int64_t(blockIdx.x) * CS;
   const int ns = int(min<int64_t>(CS, S - s0));
-  for (int e = threadIdx.x; e < CS * R; e += BLK) {
+  // every slot up to RM is written (zero beyond R): the row loop below runs
+  // to RM, and 0 times stale LDS contents could be NaN
+  for (int e = threadIdx.x; e < CS * RM; e += BLK) {
     const int sl = e % CS, r = e / CS;
     double v = 0.0;
-    if (sl < ns) {
+    if (sl < ns && r < R) {
       v = lam[r];
       int64_t rest = s0 + sl;
       for (int k = 1; k < N; ++k) {
@@ -789,7 +796,7 @@ __global__ __launch_bounds__(BLK) void ne_err_final(const double* __restrict__ p
   nn = block_sum(nn, sh);
   if (threadIdx.x == 0) {
     const double x2 = *xnorm2;
-    *relerr = sqrt(fmax(x2 - 2.0 * ip + nn, 0.0) / x2);
+    *relerr = rel_from_r2(x2 - 2.0 * ip + nn, x2);
   }
 }
 

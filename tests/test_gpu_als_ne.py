@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import oracle.cp_als as OA
+import oracle.cp_als_qr as OQ
 from oracle import tensor as OT
 from paper_2112_10855_amd import cpqr as C
 from paper_2112_10855_amd import synth
@@ -176,3 +177,56 @@ def test_ill_conditioning_is_flagged_at_full_collinearity():
     init = [a + 1e-3 * b for a, b in zip(d["A"], full_init(shape, R, 811))]
     _, _, _, status = run_gpu(d["X"], init, 2, C.PREC_F64)
     assert status & C.STATUS_ILL_CONDITIONED
+
+
+def test_hybrid_breakdown_restarts_from_factors_before_the_sweep():
+    """A start whose A_2 has a zero column makes S_1 = G_2 * G_3 exactly
+    singular: the Cholesky pivot of that column is 0, the sweep sets
+    CPQR_STATUS_SINGULAR and its factors are not finite.  The hybrid discards
+    that sweep and runs CP-ALS-QR-SVD from the factors it started from, so its
+    history is finite and equals, bit for bit, CP-ALS-QR-SVD run from that
+    start directly (run twice: the GPU path is deterministic).  With the
+    pseudo-inverse solve the zero column stays exactly zero (its singular
+    value is 0 and is dropped), so the fit is the rank-(R-1) one: the history
+    matches the oracle's CP-ALS-QR at rank R-1 from the start without that
+    column."""
+    d = synth.workload_small()
+    init = [np.array(a) for a in d["init"]]
+    init[1][:, 2] = 0.0
+    Xd = to_dev(d["X"], torch.float64)
+    kw = dict(prec=C.PREC_F64, error_mode=C.ERROR_DIRECT)
+    ne = C.AlsNeState(Xd, init, **kw)
+    ne.init()
+    ne.sweep(1)
+    assert int(ne.status.item()) & C.STATUS_SINGULAR
+    st, hist, n_ne = C.cp_als_hybrid(Xd, init, maxiters=25, **kw)
+    assert n_ne == 0 and len(hist) == 25
+    assert np.all(np.isfinite(hist))
+    assert not int(st.status.item()) & (C.STATUS_SINGULAR | C.STATUS_NONFINITE)
+    for _ in range(2):
+        _, hsvd = C.cp_als_qr(Xd, init, maxiters=25, use_svd=True, **kw)
+        assert hist == hsvd
+    keep = [0, 1, 3, 4]
+    _, _, ho = OQ.cp_als_qr(d["X"], [a[:, keep] for a in init], maxiters=25, error="direct")
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert np.all(to_np(st.A[0])[:, 2] == 0.0) and to_np(st.lam)[2] == 0.0
+
+
+@pytest.mark.parametrize("alg", ["qr", "als"])
+def test_nonfinite_input_sets_status(alg):
+    """A NaN in X reaches every factor through the Multi-TTM: the sweep
+    reports CPQR_STATUS_NONFINITE instead of failing silently; an Inf
+    likewise."""
+    d = synth.workload_small()
+    for bad in (np.nan, np.inf):
+        X = np.array(d["X"])
+        X[3, 4, 5] = bad
+        Xd = to_dev(X, torch.float64)
+        if alg == "qr":
+            st = C.AlsState(Xd, d["init"], prec=C.PREC_F64)
+        else:
+            st = C.AlsNeState(Xd, d["init"], prec=C.PREC_F64)
+        st.init()
+        st.sweep(1)
+        torch.cuda.synchronize()
+        assert int(st.status.item()) & C.STATUS_NONFINITE, (alg, bad)
