@@ -3,7 +3,10 @@ three products, and plain bfloat16), FP32 accumulation, against the FP64
 oracle.  The GPU's relative error must be within a factor 3 of the error of
 the oracle's emulation of the same form (same operand rounding, exact sums,
 FP32 intermediates); accumulation order differs, so bitwise equality is not
-expected.  The FP32 form is checked against the 1e-5 contract for reference.
+expected.  Every entry of the GPU result (and of the emulation) is also
+checked against the exact Multi-TTM within the per-contraction error bound of
+its form, relative to the magnitude bound |X| x |Q| of that entry.  The FP32
+form is checked against the 1e-5 contract for reference.
 """
 
 import numpy as np
@@ -14,7 +17,7 @@ import oracle.cp_als_qr as OQ
 from oracle import precision as OP
 from paper_2112_10855_amd import cpqr as C
 from paper_2112_10855_amd import synth
-from helpers import relnorm, to_dev, to_np
+from helpers import abs_bound_multittm, assert_entrywise, multittm_tol_lowp, relnorm, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +42,10 @@ def test_multittm_lowp_error_matches_emulation(shape, R, mode):
         emul = OP.multittm_lowp(X, Qs, n, mode)
         e_gpu, e_emul = relnorm(Y, exact), relnorm(emul, exact)
         assert e_emul / 3 <= e_gpu <= 3 * e_emul, (n, e_gpu, e_emul)
+        bound = abs_bound_multittm(X, Qs, n)
+        tol = multittm_tol_lowp(shape, n, mode)
+        assert_entrywise(emul, exact, bound, tol, ("emulation", shape, n))
+        assert_entrywise(Y, exact, bound, tol, ("gpu", shape, n))
 
 
 def test_precision_ordering_on_one_tensor():
@@ -53,16 +60,23 @@ def test_precision_ordering_on_one_tensor():
     for name, prec in [("f32", C.PREC_F32), ("bf16x2", C.PREC_BF16X2), ("bf16", C.PREC_BF16)]:
         Y = to_np(C.cpqr_multittm(Xd, [None, to_dev(Qs[1]), to_dev(Qs[2])], 0, prec))
         errs[name] = relnorm(Y, OQ.multittm_unfolded(X.astype(np.float64), Qs, 0))
+    print("[precision] Multi-TTM errors:", {k: "%.2e" % v for k, v in errs.items()})
     assert errs["f32"] < 1e-5
     assert errs["bf16x2"] < 1e-4
     assert 1e-4 < errs["bf16"] < 1e-2
     assert errs["f32"] < errs["bf16x2"] < errs["bf16"]
 
 
-@pytest.mark.parametrize("prec,tol", [(C.PREC_BF16X2, 1e-4), (C.PREC_BF16, 3e-2)])
-def test_sweeps_in_reduced_precision(prec, tol):
+@pytest.mark.parametrize("prec,tol,tol_err", [(C.PREC_BF16X2, 1e-5, 1e-5), (C.PREC_BF16, 1e-3, 5e-4)])
+def test_sweeps_in_reduced_precision(prec, tol, tol_err):
     """CP-ALS-QR with the reduced-precision Multi-TTM still fits the small
-    noisy workload: the final model is within tol of the FP64 oracle's."""
+    noisy workload: the final model is within tol of the FP64 oracle's.
+    Measured (deterministic: fixed seeds, fixed-order reductions): split
+    bfloat16 1.9e-6 on the model and 2e-9 on the error; plain bfloat16 9.0e-4
+    on the model -- inside the 1e-3 plain-bfloat16 contract, which applies to
+    the fitted model -- and 3.5e-4 on the error (its raw Multi-TTM error,
+    3-5e-3, misses 1e-3).  The bounds are the contract (model) and the
+    measured value with margin (error)."""
     d = synth.workload_small(noise=1e-3)
     X = d["X"].astype(np.float32)
     st, hist = C.cp_als_qr(to_dev(X, torch.float32), d["init"], maxiters=15, prec=prec,
@@ -71,5 +85,7 @@ def test_sweeps_in_reduced_precision(prec, tol):
     from oracle import tensor as OT
     lam = to_np(st.lam)
     A = [to_np(a) for a in st.A]
-    assert relnorm(OT.full(lam, A), OT.full(lo, Ao)) < tol
-    assert abs(hist[-1] - ho[-1]) < tol
+    dist = relnorm(OT.full(lam, A), OT.full(lo, Ao))
+    print("[precision] prec %d: model distance %.2e, final relerr %.6e vs %.6e" % (prec, dist, hist[-1], ho[-1]))
+    assert dist < tol
+    assert abs(hist[-1] - ho[-1]) < tol_err
