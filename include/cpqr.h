@@ -134,6 +134,24 @@ int cpqr_multittm(int N, const int64_t* I, int xdtype, const void* X, int n, int
                   void* stream);
 
 /*
+ * The same Multi-TTM for callers that cannot allocate device memory or pass
+ * a workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the scratch cpqr_multittm takes from `work` comes
+ * instead from a static device array of CPQR_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends.  Same
+ * arguments, kernels and results as cpqr_multittm.  A request whose
+ * cpqr_multittm_work exceeds CPQR_NOALLOC_SCRATCH_BYTES is rejected with
+ * CPQR_ERR_WORKSPACE before anything is enqueued.  The first call on a device
+ * resolves the array's address there (may return CPQR_ERR_HIP).  Every call
+ * on one device shares that array: calls that overlap in time on one device
+ * (different streams, or host threads) race and must be ordered by the
+ * caller.  No call allocates or frees device memory.
+ */
+#define CPQR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int cpqr_multittm_noalloc(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                          const double* const* Q, int prec, void* Y, void* stream);
+
+/*
  * Apply Q_0 (Alg. 2, eq. ls-qr-q0-step): W = Y_(n) Q_0 in FP64.
  *   Y   : device, In x K column-major (leading dimension In), ydtype F32/F64
  *   Q0  : device, K x R column-major (leading dimension K)

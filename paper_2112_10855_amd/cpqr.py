@@ -86,6 +86,8 @@ _SIGS = {
     "cpqr_multittm_work": (_sz, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "cpqr_multittm": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int,
                                      ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_multittm_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp]),
     "cpqr_apply_q0_work": (_sz, [_i64, _i64, ctypes.c_int]),
     "cpqr_apply_q0": (ctypes.c_int, [_i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cpqr_solve_rsvd_work": (_sz, [_i64, ctypes.c_int]),
@@ -269,6 +271,37 @@ def cpqr_multittm(X, Qs, n, prec=PREC_F32):
     keep, w = _work(lib().cpqr_multittm_work(N, I, n, R, prec), X.device)
     _call("cpqr_multittm", N, I, _dtype_code(X), X.data_ptr(), n, R, _ptr_array(Qs), prec, Y.data_ptr(), w,
           0 if keep is None else keep.numel() - 256, _stream())
+    return Y
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def cpqr_multittm_noalloc(X, Qs, n, prec=PREC_F32, Y=None):
+    """cpqr_multittm without a workspace: the library's static per-device
+    scratch (NOALLOC_SCRATCH_BYTES) holds the intermediates.  Y may be given
+    (a column-major I_n x R^(N-1) tensor of the output type) so that the call
+    allocates nothing at all."""
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    prec = PREC_NAMES.get(prec, prec)
+    N = X.dim()
+    ref = next(q for q in Qs if q is not None)
+    R = ref.shape[1]
+    for k, q in enumerate(Qs):
+        if k != n:
+            _dev(q, "Q")
+            _check_colmajor(q, "Q")
+    ydt = torch.float64 if prec == PREC_F64 else torch.float32
+    shape = (X.shape[n], R ** (N - 1))
+    if Y is None:
+        Y = empty_colmajor(shape, ydt, X.device)
+    elif Y.dtype != ydt or tuple(Y.shape) != shape:
+        raise ValueError("Y must be %s of shape %s" % (ydt, shape))
+    _dev(Y, "Y")
+    _check_colmajor(Y, "Y")
+    _call("cpqr_multittm_noalloc", N, _i64_array(X.shape), _dtype_code(X), X.data_ptr(), n, R, _ptr_array(Qs), prec,
+          Y.data_ptr(), _stream())
     return Y
 
 

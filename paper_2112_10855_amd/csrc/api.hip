@@ -355,6 +355,45 @@ int check_problem(const cpqr_problem* p, bool need_qr = true) {
   return CPQR_OK;
 }
 
+int check_multittm_args(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                        const double* const* Q, int prec, void* Y) {
+  CPQR_TRY(check_modes(N, I));
+  CPQR_TRY(check_rank(R));
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "multittm: n out of range");
+  if (!valid_dtype(xdtype)) return fail(CPQR_ERR_DTYPE, "multittm: xdtype must be CPQR_F32 or CPQR_F64");
+  if (!valid_prec(prec)) return fail(CPQR_ERR_ARG, "multittm: unknown precision");
+  if (prec != CPQR_PREC_F64 && xdtype != CPQR_F32)
+    return fail(CPQR_ERR_DTYPE, "multittm: reduced-precision forms need an FP32 tensor");
+  if (!X || !Y || !Q) return fail(CPQR_ERR_ARG, "multittm: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Q[k]) return fail(CPQR_ERR_ARG, "multittm: Q[" + std::to_string(k) + "] is NULL");
+  return check_krp_rows(N, R);
+}
+
+// Scratch of cpqr_multittm_noalloc: one copy per device, resolved there on the
+// first call with that device current.  In host code `scratch` is a host-side
+// stand-in for the symbol, never a device address: kernels get the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[CPQR_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  CPQR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    CPQR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+      return fail(CPQR_ERR_HIP, "multittm_noalloc: the scratch array has no aligned device address");
+    it = g_scratch_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return CPQR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -406,19 +445,23 @@ size_t cpqr_multittm_work(int N, const int64_t* I, int n, int R, int prec) {
 int cpqr_multittm(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
                   const double* const* Q, int prec, void* Y, void* work, size_t work_bytes,
                   void* stream) {
-  CPQR_TRY(check_modes(N, I));
-  CPQR_TRY(check_rank(R));
-  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "multittm: n out of range");
-  if (!valid_dtype(xdtype)) return fail(CPQR_ERR_DTYPE, "multittm: xdtype must be CPQR_F32 or CPQR_F64");
-  if (!valid_prec(prec)) return fail(CPQR_ERR_ARG, "multittm: unknown precision");
-  if (prec != CPQR_PREC_F64 && xdtype != CPQR_F32)
-    return fail(CPQR_ERR_DTYPE, "multittm: reduced-precision forms need an FP32 tensor");
-  if (!X || !Y || !Q) return fail(CPQR_ERR_ARG, "multittm: NULL pointer");
-  for (int k = 0; k < N; ++k)
-    if (k != n && !Q[k]) return fail(CPQR_ERR_ARG, "multittm: Q[" + std::to_string(k) + "] is NULL");
-  CPQR_TRY(check_krp_rows(N, R));
+  CPQR_TRY(check_multittm_args(N, I, xdtype, X, n, R, Q, prec, Y));
   CPQR_TRY(check_work(work, work_bytes, multittm_work(N, I, n, R, prec)));
   return multittm_enqueue(N, I, xdtype, X, n, R, Q, prec, Y, work, as_stream(stream));
+}
+
+int cpqr_multittm_noalloc(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
+                          const double* const* Q, int prec, void* Y, void* stream) {
+  CPQR_TRY(check_multittm_args(N, I, xdtype, X, n, R, Q, prec, Y));
+  const size_t need = multittm_work(N, I, n, R, prec);
+  if (need > CPQR_NOALLOC_SCRATCH_BYTES)
+    return fail(CPQR_ERR_WORKSPACE, "multittm_noalloc: this Multi-TTM needs " + std::to_string(need) +
+                                        " bytes of scratch, more than the " +
+                                        std::to_string(CPQR_NOALLOC_SCRATCH_BYTES) +
+                                        " of the static array; call cpqr_multittm with a workspace");
+  void* scr = nullptr;
+  CPQR_TRY(noalloc_scratch(&scr));
+  return multittm_enqueue(N, I, xdtype, X, n, R, Q, prec, Y, scr, as_stream(stream));
 }
 
 size_t cpqr_apply_q0_work(int64_t In, int64_t K, int R) {
