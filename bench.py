@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1000, help="mode size of the cubic tensor")
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x2", "bf16"])
-    ap.add_argument("--workload", default="dense3", choices=["dense3", "dense4", "batch", "learned", "fit", "sinsum"],
+    ap.add_argument("--workload", default="dense3",
+                    choices=["dense3", "dense4", "batch", "learned", "fit", "sinsum", "calib"],
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--fit-heldout", type=int, default=32, help="held-out tensors timed to relerr 1e-6")
     ap.add_argument("--fit-n", type=int, default=200, help="mode size of the time-to-fit study (--workload fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="dense3 f32 qr only: skip the FP64 1000^3 and 200^4 rank-32 sub-records")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle timing sample")
     return ap.parse_args()
 
@@ -136,9 +139,44 @@ def run_sinsum(args):
     print(json.dumps(out), flush=True)
 
 
-def run_dense4(args):
-    """200^4 FP32 tensor, rank 32, weights 1..1e-6, no noise: sweeps/s and the
-    Multi-TTM error against the FP64 oracle on sampled rows, per precision."""
+def timed_sweeps(C, torch, st, steps, phase):
+    """Time `steps` sweeps of a set-up state with events on the launch
+    stream; the dominant kernel (`phase`) is timed by events attached to its
+    own dispatches.  Returns (ms per sweep, (kernel ms, launches), relerr)."""
+    rel = torch.empty(steps, dtype=torch.float64, device="cuda")
+    C.cpqr_timing_reset()
+    C.cpqr_timing_select([phase])
+    C.cpqr_timing_enable(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    st.sweep(steps, rel)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    C.cpqr_timing_enable(False)
+    timed = C.cpqr_timing_read()
+    return e0.elapsed_time(e1) / steps, timed[phase], rel.cpu().numpy()
+
+
+def phase_pass(C, torch, st, nb):
+    """Per-phase breakdown from a separate pass with events between phases."""
+    C.cpqr_timing_reset()
+    C.cpqr_timing_select(None)
+    C.cpqr_timing_enable(True)
+    st.sweep(nb)
+    torch.cuda.synchronize()
+    C.cpqr_timing_enable(False)
+    ph = C.cpqr_timing_read()
+    return {k: round(v[0] / nb, 4) for k, v in ph.items()}
+
+
+def dense4_record(prec_name, steps, warmup, data=None):
+    """CP-ALS-QR on the 200^4 FP32 rank-32 workload (weights 1e0..1e-6, no
+    noise) with the Multi-TTM in the given precision: sweeps/s, the first
+    contraction (streams the 6.4 GB tensor) timed by events on its own
+    dispatches against the HBM roofline, and the Multi-TTM error against the
+    FP64 oracle on sampled rows of Y_(n) for every mode."""
     import torch
 
     from paper_2112_10855_amd import cpqr as C
@@ -146,38 +184,23 @@ def run_dense4(args):
     import oracle.cp_als_qr as OQ
 
     n, R = 200, 32
-    t0 = time.time()
-    d = synth.workload_4way(n=n, R=R)
+    if data is None:
+        t0 = time.time()
+        d = synth.workload_4way(n=n, R=R)
+        log("generated 200^4 FP32 tensor in %.1f s" % (time.time() - t0))
+        Xd = torch.from_numpy(d["X"].reshape(-1, order="F")).to("cuda").view(n, n, n, n).permute(3, 2, 1, 0)
+    else:
+        d, Xd = data
     X = d["X"]
-    log("generated 200^4 FP32 tensor in %.1f s" % (time.time() - t0))
-    Xd = torch.from_numpy(X.reshape(-1, order="F")).to("cuda").view(n, n, n, n).permute(3, 2, 1, 0)
-    prec = C.PREC_NAMES[args.prec]
+    prec = C.PREC_NAMES[prec_name]
     st = C.AlsState(Xd, d["init"], prec=prec)
     st.init()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         st.sweep(1)
-    torch.cuda.synchronize()
-    C.cpqr_timing_reset()
-    C.cpqr_timing_select(["ttm_stream_m"])
-    C.cpqr_timing_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    rel = st.sweep(args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    C.cpqr_timing_enable(False)
-    timed = C.cpqr_timing_read()
-    ms = e0.elapsed_time(e1) / args.steps
-    nb = min(args.steps, 3)
-    C.cpqr_timing_reset()
-    C.cpqr_timing_select(None)
-    C.cpqr_timing_enable(True)
-    st.sweep(nb)
-    torch.cuda.synchronize()
-    C.cpqr_timing_enable(False)
-    phases = C.cpqr_timing_read()
-    first_ms, first_cnt = phases["ttm_first"]
+    ms, (dom_ms, dom_cnt), rel = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
+    phases = phase_pass(C, torch, st, min(steps, 3))
     xbytes = X.size * 4
+    dom_s = dom_ms / max(dom_cnt, 1) / 1e3
     # Multi-TTM error vs FP64 on sampled rows, with random orthonormal Q_k
     Qs = [synth.orthonormal_columns(n, R, 90 + k) for k in range(4)]
     Qd = [torch.from_numpy(q).to("cuda").t().contiguous().t() for q in Qs]
@@ -192,23 +215,69 @@ def run_dense4(args):
             num += float(np.sum((Y[i] - yo) ** 2))
             den += float(np.sum(yo ** 2))
         errs.append(float(np.sqrt(num / den)))
-    out = {
-        "metric": METRIC, "value": round(1000.0 / ms, 3), "unit": "sweeps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "cp_als_qr_dense4_200_%s_r32" % args.prec, "shape": [n] * 4, "rank": R,
-                   "ground_truth": "rank-32, unit Gaussian columns, weights 1e0..1e-6, no noise"},
-        "first_contraction": {"avg_launch_ms": round(first_ms / max(first_cnt, 1), 4),
-                              "gbps": round(xbytes / (first_ms / max(first_cnt, 1) / 1e3) / 1e9, 1),
-                              "frac_of_8TBs": round(xbytes / (first_ms / max(first_cnt, 1) / 1e3) / 8e12, 4)},
-        "dominant_kernel": {"avg_launch_ms": round(timed["ttm_stream_m"][0] / max(timed["ttm_stream_m"][1], 1), 4),
-                            "launches": timed["ttm_stream_m"][1]},
-        "phases_ms_per_sweep": {k: round(v[0] / nb, 4) for k, v in phases.items()},
-        "phases_note": "separate pass of %d sweeps with events between phases" % nb,
+    log("200^4 rank 32 %s: %.3f ms/sweep, first contraction %.3f ms, Multi-TTM error %.2e"
+        % (prec_name, ms, dom_s * 1e3, max(errs)))
+    return {
+        "workload": "cp_als_qr_dense4_200_%s_r32" % prec_name, "value": round(1000.0 / ms, 3),
+        "unit": "sweeps/s", "ms_per_step": round(ms, 4), "steps": steps, "dtype": prec_name,
+        "roofline": {"kernel": "first contraction of each Multi-TTM pass (streams X once), two 16-column "
+                               "blocks, wide row tiles", "bound": "hbm",
+                     "achieved": round(xbytes / dom_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(xbytes / dom_s / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": xbytes,
+                     "avg_launch_ms": round(dom_s * 1e3, 4), "launches": dom_cnt},
+        "phases_ms_per_sweep": phases,
         "multittm_relerr_vs_fp64_sampled_rows": errs,
-        "relerr_last": float(rel[-1].item()),
+        "relerr_last": float(rel[-1]),
+    }
+
+
+def run_dense4(args):
+    """200^4 FP32 tensor, rank 32, weights 1..1e-6, no noise: sweeps/s and the
+    Multi-TTM error against the FP64 oracle on sampled rows, per precision."""
+    rec = dense4_record(args.prec, args.steps, args.warmup)
+    out = {
+        "metric": METRIC, "value": rec["value"], "unit": "sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": rec["workload"], "shape": [200] * 4, "rank": 32,
+                   "ground_truth": "rank-32, unit Gaussian columns, weights 1e0..1e-6, no noise"},
+        "roofline": rec["roofline"], "phases_ms_per_sweep": rec["phases_ms_per_sweep"],
+        "multittm_relerr_vs_fp64_sampled_rows": rec["multittm_relerr_vs_fp64_sampled_rows"],
+        "relerr_last": rec["relerr_last"],
     }
     print(json.dumps(out), flush=True)
+
+
+def dense3_f64_record(d, Xd32, steps, warmup):
+    """The 1000^3 rank-16 workload in the paper's precision: the tensor's
+    values read in FP64 (8 GB) and the Multi-TTM in FP64 on the matrix cores."""
+    import torch
+
+    from paper_2112_10855_amd import cpqr as C
+
+    Xd = Xd32.double()
+    st = C.AlsState(Xd, d["init"], prec=C.PREC_F64)
+    st.init()
+    for _ in range(warmup):
+        st.sweep(1)
+    ms, (dom_ms, dom_cnt), rel = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
+    phases = phase_pass(C, torch, st, min(steps, 3))
+    xbytes = Xd.numel() * 8
+    dom_s = dom_ms / max(dom_cnt, 1) / 1e3
+    log("1000^3 rank 16 FP64: %.3f ms/sweep, first contraction %.3f ms" % (ms, dom_s * 1e3))
+    del st, Xd
+    torch.cuda.empty_cache()
+    return {
+        "workload": "cp_als_qr_dense3_1000cube_f64_r16", "value": round(1000.0 / ms, 3), "unit": "sweeps/s",
+        "ms_per_step": round(ms, 4), "steps": steps, "dtype": "f64",
+        "roofline": {"kernel": "first contraction of each Multi-TTM pass (streams the 8 GB FP64 tensor once): "
+                               "ttm_mfma_m_f64 (FP64 matrix cores, 128-row tiles)", "bound": "hbm",
+                     "achieved": round(xbytes / dom_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(xbytes / dom_s / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": xbytes,
+                     "avg_launch_ms": round(dom_s * 1e3, 4), "launches": dom_cnt},
+        "phases_ms_per_sweep": phases,
+        "relerr_last": float(rel[-1]),
+    }
 
 
 def run_batch(args):
@@ -348,17 +417,34 @@ def run_fit(args):
     print(json.dumps(out), flush=True)
 
 
+def run_calib(args):
+    """Calibration workload for the HBM traffic counters: a plain device copy
+    of a 1 GiB FP32 buffer (torch's copy kernel), three times.  Under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) its counters, against the
+    known 1 GiB read and written per dispatch, scale the counters of the
+    library's kernels."""
+    import torch
+
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "calib_copy_1GiB_f32", "dispatches": 3, "bytes_each_way": 4 * n}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("dense4", "batch", "learned", "fit", "sinsum"):
+    if args.workload in ("dense4", "batch", "learned", "fit", "sinsum", "calib"):
         import torch
         torch.cuda.set_device(0)
         return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned, "fit": run_fit,
-                "sinsum": run_sinsum}[args.workload](args)
+                "sinsum": run_sinsum, "calib": run_calib}[args.workload](args)
 
     import hashlib
 
@@ -403,10 +489,9 @@ def main():
 
     rel = torch.empty(args.steps, dtype=torch.float64, device="cuda")
     # Inside the timed region only the dominant kernel is timed, by events
-    # attached to its own dispatches (no extra packets in the stream); the
-    # FP64 path has no such kernel and times its first contraction instead.
+    # attached to its own dispatches (no extra packets in the stream).
     C.cpqr_timing_reset()
-    C.cpqr_timing_select(["ttm_stream_m"] if prec != C.PREC_F64 else ["ttm_first"])
+    C.cpqr_timing_select(["ttm_stream_m"])
     C.cpqr_timing_enable(True)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -436,12 +521,12 @@ def main():
     C.cpqr_timing_enable(False)
     phases = C.cpqr_timing_read()
 
-    xbytes = X.size * X.itemsize
+    xbytes = X.size * (8 if prec == C.PREC_F64 else 4)  # the tensor as the Multi-TTM reads it
     first_ms, first_cnt = phases["ttm_first"]
     first_avg_s = first_ms / max(first_cnt, 1) / 1e3
     # dominant kernel: the row-tiled matrix-core kernel streaming X
     dom_ms, dom_cnt = timed["ttm_stream_m"]
-    if dom_cnt == 0:  # FP64 path: the first contraction runs on the vector ALUs
+    if dom_cnt == 0:  # no row-tiled first contraction: time the whole first contraction
         dom_ms, dom_cnt = timed["ttm_first"]
     dom_avg_s = dom_ms / max(dom_cnt, 1) / 1e3
     achieved = xbytes / dom_avg_s / 1e9
@@ -481,7 +566,8 @@ def main():
                        "LDS stretches (mode-2 contraction)",
                 "bf16x2": "ttm_bf16_m<split> (mode-3 contraction) and ttm_slab_bf16<split> (mode-2 contraction)",
                 "bf16": "ttm_bf16_m (mode-3 contraction) and ttm_slab_bf16 (mode-2 contraction)",
-                "f64": "ttm_valu (FP64, one thread per row)"}[args.prec],
+                "f64": "ttm_mfma_m_f64 (FP64 matrix cores, 128-row tiles; mode-3 contraction non-temporal)"}[
+                    args.prec],
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -502,6 +588,11 @@ def main():
         "phases_note": "separate pass of %d sweeps with events between phases (slower than the timed sweeps)" % nb,
         "relerr_last": float(relerr[-1]),
     }
+
+    # the same workload in the paper's precision, and the 4-way rank-32 workload
+    subs = {}
+    if args.prec == "f32" and args.method == "qr" and n == 1000 and not args.no_sub_records:
+        subs["dense3_1000_r16_f64"] = dense3_f64_record(d, Xd, 10, 2)
 
     if not args.no_cpu_baseline:
         import threadpoolctl
@@ -542,6 +633,21 @@ def main():
         st2.init()
         grel = st2.sweep(sweeps).cpu().numpy()
         out["cpu_baseline"]["gpu_vs_oracle_relerr_after_sample"] = [float(grel[-1]), float(orel)]
+        del st2
+    if subs:
+        del st
+        Xd = None
+        torch.cuda.empty_cache()
+        data4 = None
+        for p4 in ("f32", "bf16x2"):
+            if data4 is None:
+                t0 = time.time()
+                d4 = synth.workload_4way(n=200, R=32)
+                log("generated 200^4 FP32 tensor in %.1f s" % (time.time() - t0))
+                data4 = (d4, torch.from_numpy(d4["X"].reshape(-1, order="F")).to("cuda")
+                         .view(200, 200, 200, 200).permute(3, 2, 1, 0))
+            subs["dense4_200_r32_" + p4] = dense4_record(p4, 20, 2, data4)
+        out["sub_records"] = subs
     print(json.dumps(out), flush=True)
 
 

@@ -252,6 +252,157 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
   store_tiles<NB, MG>(acc, out + int64_t(blockIdx.y) * split_stride, mt, M, P, R, l16, kq);
 }
 
+// ---------------- FP64: the same row tiles on v_mfma_f64_16x16x4f64
+// Each lane loads four consecutive doubles (rows 4 l16 .. 4 l16 + 3 of its
+// 64-row group, two 16-byte loads) of K-row kq of a step and feeds them to
+// four MFMAs sharing one B operand (16 columns of U, FP64 in LDS).  The f64
+// MFMA returns row kq + 4 v of its 16 x 16 result in value v of lane
+// (l16, kq), so the lane ends up with rows 16 v + 4 kq + j (j = MFMA index)
+// of column l16: four runs of four consecutive rows.
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ doublex2 ldx2(const double* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(reinterpret_cast<const doublex2*>(p));
+  else
+    return *reinterpret_cast<const doublex2*>(p);
+}
+
+constexpr int LDS_DOUBLES = 8192;  // 64 KB
+
+template <int NB, int UN, int MG, int NWV, bool STREAM, bool NT>
+__global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restrict__ X,
+                                                           const double* __restrict__ U,
+                                                           double* __restrict__ out, int64_t P, int64_t K,
+                                                           int64_t S, int R, int64_t kchunk,
+                                                           int64_t split_stride) {
+  constexpr int RP = 16 * NB;
+  extern __shared__ double usd[];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int64_t M = P * S;
+  const int64_t mt = (int64_t(blockIdx.x) * NWV + w) * 64 * MG;
+  const bool active = mt < M;
+  const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
+  const int64_t kb1 = min(K, kb0 + kchunk);
+  const int l16 = lane % 16, kq = lane / 16;
+  const double* base[MG];
+#pragma unroll
+  for (int g = 0; g < MG; ++g) {
+    int64_t mrow = mt + 64 * g + 4 * l16;
+    mrow = mrow < M ? mrow : M - 4;
+    const int64_t p = mrow % P, s = mrow / P;
+    base[g] = X + p + s * P * K + kq * P;
+  }
+  doublex4 acc[NB][MG][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[b][g][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  constexpr int STEP = 4 * UN;
+  auto chunk = [&](int64_t c0, int cn) {
+    const int nfull = cn / STEP;
+    const int last = nfull > 0 ? (nfull - 1) * STEP : 0;
+    const double* bp[MG];
+#pragma unroll
+    for (int g = 0; g < MG; ++g) bp[g] = base[g] + c0 * P;
+    doublex2 A[UN][MG][2], B[UN][MG][2];
+    auto load = [&](doublex2(&dst)[UN][MG][2], int t) {
+      const int i0 = min(t * STEP, last);
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int g = 0; g < MG; ++g) {
+          const double* q = bp[g] + int64_t(i0 + 4 * u) * P;
+          dst[u][g][0] = ldx2<NT>(q);
+          dst[u][g][1] = ldx2<NT>(q + 2);
+        }
+    };
+    auto compute = [&](const doublex2(&src)[UN][MG][2], int t) {
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double bv = usd[(t * STEP + 4 * u + kq) * RP + b * 16 + l16];
+#pragma unroll
+          for (int g = 0; g < MG; ++g) {
+            acc[b][g][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(src[u][g][0].x, bv, acc[b][g][0], 0, 0, 0);
+            acc[b][g][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(src[u][g][0].y, bv, acc[b][g][1], 0, 0, 0);
+            acc[b][g][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(src[u][g][1].x, bv, acc[b][g][2], 0, 0, 0);
+            acc[b][g][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(src[u][g][1].y, bv, acc[b][g][3], 0, 0, 0);
+          }
+        }
+    };
+    if (nfull > 0) {
+      load(A, 0);
+      for (int t = 0; t < nfull; t += 2) {
+        load(B, t + 1);
+        compute(A, t);
+        load(A, t + 2);
+        if (t + 1 < nfull) compute(B, t + 1);
+      }
+    }
+    for (int i = nfull * STEP; i < cn; i += 4) {  // chunk tail
+      const int ii = i + kq;
+      const bool ok = ii < cn;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double bv = ok ? usd[ii * RP + b * 16 + l16] : 0.0;
+#pragma unroll
+        for (int g = 0; g < MG; ++g) {
+          const double* q = bp[g] + int64_t(i) * P;
+          const doublex2 x0 = ok ? *reinterpret_cast<const doublex2*>(q) : doublex2{0.0, 0.0};
+          const doublex2 x1 = ok ? *reinterpret_cast<const doublex2*>(q + 2) : doublex2{0.0, 0.0};
+          acc[b][g][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, bv, acc[b][g][0], 0, 0, 0);
+          acc[b][g][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.y, bv, acc[b][g][1], 0, 0, 0);
+          acc[b][g][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.x, bv, acc[b][g][2], 0, 0, 0);
+          acc[b][g][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.y, bv, acc[b][g][3], 0, 0, 0);
+        }
+      }
+    }
+  };
+  constexpr int KC = (LDS_DOUBLES / RP) / STEP * STEP;
+  for (int64_t c0 = kb0; c0 < kb1; c0 += KC) {
+    const int cn = int(min<int64_t>(kb1 - c0, KC));
+    __syncthreads();
+    const double* Uc = U + c0 * RP;
+    for (int e = tid; e < cn * RP; e += NWV * 64) usd[e] = Uc[e];
+    __syncthreads();
+    if (active) chunk(c0, cn);
+  }
+  if (!active) return;
+  double* o = out + int64_t(blockIdx.y) * split_stride;
+  // lane (l16, kq) holds rows m0 + j (j = 0..3), m0 = mt + 64 g + 16 v + 4 kq,
+  // of column r = 16 b + l16 in acc[b][g][j][v]
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int r = b * 16 + l16;
+    if (r >= R) continue;
+#pragma unroll
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m0 = mt + 64 * g + 16 * v + 4 * kq;
+        const int64_t p0 = m0 % P, s0 = m0 / P;
+        double* d = o + p0 + r * P + s0 * P * R;
+        if (m0 + 4 <= M && p0 + 4 <= P && (reinterpret_cast<uintptr_t>(d) & 15) == 0) {
+          *reinterpret_cast<doublex2*>(d) = doublex2{acc[b][g][0][v], acc[b][g][1][v]};
+          *reinterpret_cast<doublex2*>(d + 2) = doublex2{acc[b][g][2][v], acc[b][g][3][v]};
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int64_t m = m0 + j;
+            if (m < M) o[m % P + r * P + (m / P) * P * R] = acc[b][g][j][v];
+          }
+        }
+      }
+  }
+}
+
 // ---------------- first contraction of a middle mode with short slabs
 // (P % 4 == 0, P % 32 != 0, P <= 64 MG NWV, R <= 16): one workgroup per slab
 // s, i.e. per contiguous P x K block X[:, :, s].  Rows of that block are
@@ -352,6 +503,148 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab_m(const float* __restrict__
     for (int j = 0; j < 4; ++j) acc1[0][g][j] = acc[g][j];
   // rows of this slab only: past P they would alias the next slab's rows
   store_tiles<1, MG>(acc1, out, s * P + w * 64 * MG, (s + 1) * P, P, R, l16, kq);
+}
+
+// ---------------- both leading modes of each slab in one pass (fused)
+// out[r1 + R r2 + R^2 s] = sum_{i1, i2} X[i1, i2, s] U1[i1, r1] U2[i2, r2],
+// i.e. the contraction of the middle mode of the [P = I_1, K = I_2, S]
+// tensor followed by that of the first mode, for P <= 64 MG NWV, one
+// workgroup per slab s.  The slab's rows stream through LDS as in
+// ttm_slab_m and T1 = X(:, :, s) U2 (P x R) stays in registers in the MFMA
+// D layout: lane (l16, kq) holds T1(16 kq + 4 v + j, 16 b + l16) of each
+// 64-row group in acc[b][g][j][v].  For fixed (v, j) those values are the B
+// operand of a 16 x 16 x 4 MFMA whose K index kq runs over rows
+// 16 kq + 4 v + j, so U1^T T1 needs no data movement: the A operand is
+// U1(row, 16 b1 + l16).  Each wavefront sums its rows into an R x R partial,
+// the partials are added in LDS in wavefront order, and the slab writes its
+// R x R block.  The P x R x S intermediate never leaves the workgroup.
+template <int NB, int MG, int NWV, int KC, int NRS, bool NT>
+__global__ __launch_bounds__(NWV * 64) void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
+                                                        const float* __restrict__ U1, float* __restrict__ out,
+                                                        int64_t P, int64_t K, int64_t S, int R) {
+  constexpr int NTH = NWV * 64, RP = 16 * NB;
+  constexpr int LPT = (KC * 64 * MG * NWV / 4 + NTH - 1) / NTH;  // float4 loads per thread per stretch
+  extern __shared__ float sm[];
+  const int Pi = int(P);
+  float* xb0 = sm;                    // [2][KC * P]
+  float* ub0 = sm + 2 * KC * Pi;      // [2][KC * RP]
+  float* red = ub0 + 2 * KC * RP;     // [NWV][RP * RP]
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int l16 = lane % 16, kq = lane / 16;
+  const int64_t s = blockIdx.x;
+  const float* Xs = X + s * P * K;
+  const int nch = int((K + KC - 1) / KC);
+  floatx4 acc[NB][MG][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int g = 0; g < MG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float4 rs[NRS][LPT];
+  auto kcount = [&](int c) { return int(min<int64_t>(KC, K - int64_t(c) * KC)); };
+  auto load = [&](float4(&r)[LPT], int c) {
+    const float* src = Xs + int64_t(c) * KC * P;
+    const int n4 = kcount(c) * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      r[i] = e < n4 ? ldx<NT>(src + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](const float4(&r)[LPT], int c) {
+    float* xb = xb0 + (c & 1) * KC * Pi;
+    float* ub = ub0 + (c & 1) * KC * RP;
+    const int kc = kcount(c), n4 = kc * Pi / 4;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      if (e < n4) *reinterpret_cast<float4*>(xb + 4 * e) = r[i];
+    }
+    for (int e = tid; e < kc * RP; e += NTH) ub[e] = U2[int64_t(c) * KC * RP + e];
+  };
+  const int prow = w * 64 * MG + 4 * l16;  // first of the lane's four rows in group 0
+  auto compute = [&](int c) {
+    const float* xb = xb0 + (c & 1) * KC * Pi;
+    const float* ub = ub0 + (c & 1) * KC * RP;
+    const int kc = kcount(c);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int k = kk + kq;
+      const bool ok = k < kc;
+      float bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = ok ? ub[k * RP + b * 16 + l16] : 0.f;
+#pragma unroll
+      for (int g = 0; g < MG; ++g) {
+        const int pr = prow + 64 * g;
+        const float4 xv = (ok && pr < Pi) ? *reinterpret_cast<const float4*>(xb + k * Pi + pr)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[b][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv[b], acc[b][g][0], 0, 0, 0);
+          acc[b][g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv[b], acc[b][g][1], 0, 0, 0);
+          acc[b][g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv[b], acc[b][g][2], 0, 0, 0);
+          acc[b][g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv[b], acc[b][g][3], 0, 0, 0);
+        }
+      }
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < NRS; ++j)
+    if (j < nch) load(rs[j], j);
+  store(rs[0], 0);
+  __syncthreads();
+  for (int c0 = 0; c0 < nch; c0 += NRS) {
+#pragma unroll
+    for (int j = 0; j < NRS; ++j) {
+      const int c = c0 + j;
+      if (c < nch) {  // uniform over the workgroup
+        if (c + NRS < nch) load(rs[j], c + NRS);
+        compute(c);
+        if (c + 1 < nch) store(rs[(j + 1) % NRS], c + 1);
+        __syncthreads();
+      }
+    }
+  }
+  // U1^T T1 over this wavefront's rows (rows past P hold zeros in T1)
+  floatx4 acc2[NB][NB];
+#pragma unroll
+  for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+    for (int b2 = 0; b2 < NB; ++b2) acc2[b1][b2] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int g = 0; g < MG; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = w * 64 * MG + 64 * g + 16 * kq + 4 * v + j;
+#pragma unroll
+        for (int b1 = 0; b1 < NB; ++b1) {
+          const float a = row < Pi ? U1[int64_t(row) * RP + b1 * 16 + l16] : 0.f;
+#pragma unroll
+          for (int b2 = 0; b2 < NB; ++b2)
+            acc2[b1][b2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, acc[b2][g][j][v], acc2[b1][b2], 0, 0, 0);
+        }
+      }
+  // lane (l16, kq) holds partial(16 b1 + 4 kq + vv, 16 b2 + l16)
+  float* rw = red + w * RP * RP;
+#pragma unroll
+  for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+    for (int b2 = 0; b2 < NB; ++b2)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) rw[(b1 * 16 + 4 * kq + vv) + RP * (b2 * 16 + l16)] = acc2[b1][b2][vv];
+  __syncthreads();
+  float* o = out + s * R * R;
+  for (int e = tid; e < R * R; e += NTH) {
+    const int r1 = e % R, r2 = e / R;
+    float t = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < NWV; ++ww) t += red[ww * RP * RP + r1 + RP * r2];
+    o[e] = t;
+  }
 }
 
 // ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
@@ -861,6 +1154,9 @@ struct Plan {
 };
 
 bool uses_mfma(int prec) { return prec != CPQR_PREC_F64; }
+// every precision has the row-tiled kernels (FP64: ttm_mfma_m_f64); only
+// the P = 1 form is FP32 / bfloat16 only
+bool row_tiled(int) { return true; }
 int valu_mode(int prec) { return prec == CPQR_PREC_BF16 ? 1 : (prec == CPQR_PREC_BF16X2 ? 2 : 0); }
 
 // Contract the modes in cmask (bit k = mode k) of a tensor of sizes I.
@@ -879,7 +1175,7 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
   // index stride is small (rows at most 256 KB apart), start with the largest
   // such mode; the flop count of the first contraction is the same and the
   // later ones change by a factor of at most two.
-  if (uses_mfma(prec) && no > 1 && order[0] == 0) {
+  if (row_tiled(prec) && no > 1 && order[0] == 0) {
     for (int t = 1; t < no; ++t) {
       int64_t stride = 1;  // elements between consecutive indices of that mode
       for (int m = 0; m < order[t]; ++m) stride *= I[m];
@@ -907,11 +1203,13 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
     int64_t units;  // independent work units without splitting K
     // float4 loads of the tensor need 16-byte alignment (carved buffers have it)
     const bool vec_ok = t > 0 || x_aligned;
-    if (uses_mfma(prec) && vec_ok && s.P % 4 == 0) {
+    if (row_tiled(prec) && vec_ok && s.P % 4 == 0) {
       s.kind = K_MFMA_M;
       // wide row tiles; a step whose rows leave the GPU under-filled takes
       // 64-row tiles before it splits K (small operands: no streaming hints)
-      s.mg = prec == CPQR_PREC_F32 ? 4 : 2;
+      // (two 16-column blocks, R > 16, halve the tile: at 4 x 64 rows the
+      // FP32 kernel needs 202 VGPRs and one workgroup per CU)
+      s.mg = (prec == CPQR_PREC_F32 ? 4 : 2) / (R > 16 ? 2 : 1);
       units = ceil_div(s.P * s.S, 64 * s.mg);
       if (units < MIN_WAVES) {
         s.mg = 1;
@@ -1008,15 +1306,20 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
   if (s.kind == K_MFMA_M) {
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
     if (s.mg == 1) {
+      // 64-row tiles: small operands, or two 16-column blocks streaming X
+      const bool nt1 = STREAM && s.P % 32 == 0;
       if (NB == 1)
         launch_ev(ke, ttm_bf16_m<SPLIT, 1, 1, NWV, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                   s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
+      else if (nt1)
+        launch_ev(ke, ttm_bf16_m<SPLIT, 2, 1, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
       else
-        launch_ev(ke, ttm_bf16_m<SPLIT, 2, 1, NWV, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+        launch_ev(ke, ttm_bf16_m<SPLIT, 2, 1, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                   s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
       return check_launch("ttm_bf16_m");
     }
-    if (s.mg != 2) return fail(CPQR_ERR_UNSUPPORTED, "ttm_bf16_m: unsupported row tile");
+    if (s.mg != 2 || NB != 1) return fail(CPQR_ERR_UNSUPPORTED, "ttm_bf16_m: unsupported row tile");
     // short slabs whose rows are not line multiples apart: whole-slab workgroups
     if (STREAM && NB == 1 && s.splits == 1 && s.P % 32 != 0 && s.P <= SLAB_PMAX && s.S >= 256) {
       const bool snt = (16 * s.P) % 32 == 0 && (s.P * s.K) % 32 == 0;  // stretches start on line boundaries
@@ -1029,17 +1332,11 @@ int launch_bf16_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_slab_bf16");
     }
     const bool nt = STREAM && s.P % 32 == 0;  // see ldx
-    if (NB == 1 && nt)
+    if (nt)
       launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
-    else if (NB == 1)
-      launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
-                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
-    else if (nt)
-      launch_ev(ke, ttm_bf16_m<SPLIT, 2, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
-                s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     else
-      launch_ev(ke, ttm_bf16_m<SPLIT, 2, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+      launch_ev(ke, ttm_bf16_m<SPLIT, 1, 2, NWV, STREAM>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, RP, s.kchunk, s.out_count);
     return check_launch("ttm_bf16_m");
   }
@@ -1079,7 +1376,20 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
                   s.P, s.K, s.S, R, s.kchunk, s.out_count);
       return check_launch("ttm_mfma_m");
     }
-    if (s.mg != MG) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m: unsupported row tile");
+    if (s.mg == 2 && NB == 2) {  // two 16-column blocks: 2 x 64-row tiles
+      const bool nt2 = STREAM && s.P % 32 == 0;
+      if (one && nt2)
+        launch_ev(ke, ttm_mfma_m<2, UN, 2, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      else if (one)
+        launch_ev(ke, ttm_mfma_m<2, UN, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      else
+        launch_ev(ke, ttm_mfma_m<2, UN, 2, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                  s.P, s.K, s.S, R, s.kchunk, s.out_count);
+      return check_launch("ttm_mfma_m");
+    }
+    if (s.mg != MG || NB != 1) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m: unsupported row tile");
     // short slabs whose rows are not line multiples apart: whole-slab workgroups
     constexpr int SKC = 8, SNWV = 8, SMG = 2, SNRS = 3;
     const size_t slab_lds = size_t(2) * SKC * (s.P + 16) * sizeof(float);
@@ -1095,23 +1405,14 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_slab_m");
     }
     const bool nt = STREAM && s.P % 32 == 0;  // see ldx
-    if (NB == 1 && one && nt)
+    if (one && nt)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);
-    else if (NB == 1 && one)
+    else if (one)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);
-    else if (NB == 2 && one && nt)
-      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
-                s.P, s.K, s.S, R, s.kchunk, s.out_count);
-    else if (NB == 1)
-      launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
-                s.P, s.K, s.S, R, s.kchunk, s.out_count);
-    else if (one)
-      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
-                s.P, s.K, s.S, R, s.kchunk, s.out_count);
     else
-      launch_ev(ke, ttm_mfma_m<2, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+      launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m");
   }
@@ -1124,6 +1425,94 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
     hipLaunchKernelGGL((ttm_mfma_k<2, UN, NWV, STREAM>), grd, dim3(NWV * 64), lds, st, src, U, dst, s.K, s.S,
                        R, RP, s.kchunk, s.out_count);
   return check_launch("ttm_mfma_k");
+}
+
+// The fused leading-pair contraction applies to an FP32 first contraction of
+// mode 2 over short slabs (P = I_1 <= 1024, P % 4 == 0, many slabs, no K
+// split) directly followed by mode 1.
+bool fused_pair(const Plan& pl, int prec, bool streams_tensor, bool x_aligned) {
+  if (prec != CPQR_PREC_F32 || !streams_tensor || !x_aligned || pl.nsteps < 2) return false;
+  const Step& a = pl.st[0];
+  const Step& b = pl.st[1];
+  return a.k == 1 && b.k == 0 && a.kind == K_MFMA_M && a.splits == 1 && a.P % 4 == 0 && a.P <= 1024 &&
+         a.S >= 256;
+}
+
+int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, const Step& a, int R, int RP,
+                 hipStream_t st, const KernelEvents& ke) {
+  constexpr int KC = 8, NRS = 3;
+  const int NB = RP / 16;
+  const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;  // stretches start on line boundaries
+  const dim3 grd(unsigned(a.S));
+  if (a.P <= 256) {
+    constexpr int MG = 1, NWV = 4;
+    const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
+    if (NB == 1 && nt)
+      launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
+                a.S, R);
+    else if (NB == 1)
+      launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
+                a.K, a.S, R);
+    else if (nt)
+      launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
+                a.S, R);
+    else
+      launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
+                a.K, a.S, R);
+  } else {
+    constexpr int MG = 2, NWV = 8;
+    const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
+    if (NB == 1 && nt)
+      launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
+                a.S, R);
+    else if (NB == 1)
+      launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
+                a.K, a.S, R);
+    else if (nt)
+      launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
+                a.S, R);
+    else
+      launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
+                a.K, a.S, R);
+  }
+  return check_launch("ttm_slab2_m");
+}
+
+template <bool STREAM>
+int launch_mfma_f64_t(const double* src, const double* U, double* dst, const Step& s, int R, int RP,
+                      hipStream_t st, const KernelEvents& ke) {
+  const int NB = RP / 16;
+  // one step (four K rows) in flight per buffer: 122 VGPRs, two workgroups per CU
+  constexpr int NWV = 8, UN = 1;
+  const size_t lds = LDS_DOUBLES * sizeof(double);
+  const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
+  const bool nt = STREAM && s.P % 16 == 0;  // rows 128-byte multiples apart: no line shared between tiles
+  if (s.mg == 1) {  // 64-row tiles: small operands, or two 16-column blocks
+    if (NB == 1)
+      launch_ev(ke, ttm_mfma_m_f64<1, UN, 1, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+                s.K, s.S, R, s.kchunk, s.out_count);
+    else if (nt)
+      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+                s.K, s.S, R, s.kchunk, s.out_count);
+    else
+      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+                s.K, s.S, R, s.kchunk, s.out_count);
+    return check_launch("ttm_mfma_m_f64");
+  }
+  if (s.mg != 2 || NB != 1) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m_f64: unsupported row tile");
+  if (nt)
+    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+              s.S, R, s.kchunk, s.out_count);
+  else
+    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+              s.S, R, s.kchunk, s.out_count);
+  return check_launch("ttm_mfma_m_f64");
+}
+
+int launch_mfma_f64(bool first, const double* src, const double* U, double* dst, const Step& s, int R, int RP,
+                    hipStream_t st, const KernelEvents& ke) {
+  return first ? launch_mfma_f64_t<true>(src, U, dst, s, R, RP, st, ke)
+               : launch_mfma_f64_t<false>(src, U, dst, s, R, RP, st, ke);
 }
 
 int launch_mfma(int prec, bool first, const float* src, const float* U, float* dst, const Step& s, int R,
@@ -1150,12 +1539,14 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
                              int R, const double* const* Q, int prec, void* Y, void* work, hipStream_t st,
                              bool streams_tensor) {
   PhaseTimer whole(streams_tensor ? PH_MULTITTM : -1, st);
-  const Plan pl = make_plan(N, I, cmask, R, prec, reinterpret_cast<uintptr_t>(X) % 16 == 0);
+  const bool x_aligned = reinterpret_cast<uintptr_t>(X) % 16 == 0;
+  const Plan pl = make_plan(N, I, cmask, R, prec, x_aligned);
   Bufs b;
   Carver cv(work);
   carve(cv, pl, N, I, &b);
   const int RP = pl.RP;
   const bool f64 = prec == CPQR_PREC_F64;
+  const bool fused = fused_pair(pl, prec, streams_tensor, x_aligned);
 
   // operand preparation
   for (int t = 0; t < pl.nsteps; ++t) {
@@ -1165,7 +1556,7 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     if (f64)
       hipLaunchKernelGGL(prep_u_rows<double>, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<double*>(b.U[s.k]));
-    else if (s.kind == K_MFMA_K && prec == CPQR_PREC_F32)
+    else if (s.kind == K_MFMA_K && prec == CPQR_PREC_F32 && !(fused && t == 1))
       hipLaunchKernelGGL(prep_u_quads, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<float*>(b.U[s.k]));
     else
@@ -1178,7 +1569,20 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
   const bool direct = n_unfold <= 0;
   const void* cur = X;
   int cur_dtype = xdtype;
-  for (int t = 0; t < pl.nsteps; ++t) {
+  int t0 = 0;
+  if (fused) {  // steps 0 and 1 in one pass over X: the result of step 1
+    void* dst = (pl.nsteps == 2 && direct) ? Y : b.buf[1];
+    PhaseTimer ph_first(PH_TTM_FIRST, st);
+    const KernelEvents ke = kernel_events(PH_TTM_STREAM_M, st);
+    CPQR_TRY(launch_slab2(static_cast<const float*>(X), static_cast<const float*>(b.U[pl.st[0].k]),
+                          static_cast<const float*>(b.U[pl.st[1].k]), static_cast<float*>(dst), pl.st[0], R, RP,
+                          st, ke));
+    kernel_events_done(ke);
+    cur = dst;
+    cur_dtype = CPQR_F32;
+    t0 = 2;
+  }
+  for (int t = t0; t < pl.nsteps; ++t) {
     const Step& s = pl.st[t];
     const bool last = t + 1 == pl.nsteps;
     void* dst = (last && direct) ? Y : b.buf[t % 2];
@@ -1186,7 +1590,12 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     {
       const bool first = t == 0 && streams_tensor;
       PhaseTimer ph_first(first ? PH_TTM_FIRST : -1, st);
-      if (f64) {
+      if (f64 && s.kind == K_MFMA_M && cur_dtype == CPQR_F64) {
+        const KernelEvents ke = kernel_events(first ? PH_TTM_STREAM_M : -1, st);
+        CPQR_TRY(launch_mfma_f64(first, static_cast<const double*>(cur), static_cast<const double*>(b.U[s.k]),
+                                 static_cast<double*>(kout), s, R, RP, st, ke));
+        kernel_events_done(ke);
+      } else if (f64) {
         CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
                                            static_cast<double*>(kout), s, R, RP, st)));
       } else if (s.kind == K_VALU) {

@@ -55,6 +55,30 @@ def test_multittm_sampled_rows(big):
             print("[fullsize] mode %d row %d: worst entry at %.3f of the tolerance" % (n, i, r), flush=True)
 
 
+def test_multittm_f64_sampled_rows(big):
+    """The same tensor read in FP64 (8 GB): the FP64 matrix-core first
+    contraction against the oracle, entry by entry to 1e-12 of the magnitude
+    bound."""
+    d, Xd = big
+    X = d["X"]
+    X64 = Xd.double()
+    Qs = [synth.orthonormal_columns(N1, R, 60 + k) for k in range(3)]
+    Qd = [torch.from_numpy(q).to("cuda").t().contiguous().t() for q in Qs]
+    for n in range(3):
+        print("[fullsize] FP64 multittm mode %d" % n, flush=True)
+        Y = to_np(C.cpqr_multittm(X64, [None if k == n else Qd[k] for k in range(3)], n, C.PREC_F64))
+        for i in (0, 1, 127, 128, 517, N1 - 1):
+            sl = [slice(None)] * 3
+            sl[n] = slice(i, i + 1)
+            sub = X[tuple(sl)].astype(np.float64)
+            yo = OQ.multittm_unfolded(sub, Qs, n)[0]
+            bound = abs_bound_multittm(sub, Qs, n)[0]
+            r = assert_entrywise(Y[i], yo, bound, 1e-12, (n, i))
+            print("[fullsize] FP64 mode %d row %d: worst entry at %.3f of the tolerance" % (n, i, r), flush=True)
+    del X64
+    torch.cuda.empty_cache()
+
+
 def test_one_sweep_against_oracle(big):
     d, Xd = big
     st = C.AlsState(Xd, d["init"], prec=C.PREC_F32)

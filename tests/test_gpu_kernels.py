@@ -103,10 +103,15 @@ def test_multittm_f32(shape, R):
         assert_entrywise(Y, Yo, abs_bound_multittm(X, Qs, n), multittm_tol_f32(shape, n), (shape, R, n))
 
 
-@pytest.mark.parametrize("shape", SHAPES[:6])
+@pytest.mark.parametrize("shape", SHAPES[:6] + [(130, 20, 24), (16, 200, 8), (96, 64, 300)])
 @pytest.mark.parametrize("xdtype", [np.float64, np.float32])
-def test_multittm_f64(shape, xdtype):
-    R = min(6, min(shape))
+@pytest.mark.parametrize("Rw", [6, 16, 32])
+def test_multittm_f64(shape, xdtype, Rw):
+    """FP64 Multi-TTM: FP64 tensors stream through the FP64 matrix-core row
+    tiles (one or two 16-column blocks, 64- or 128-row tiles, split K, with
+    and without non-temporal loads), FP32 tensors through the vector-ALU
+    kernel."""
+    R = min(Rw, min(shape))
     g = rng(17)
     X = g.standard_normal(shape).astype(xdtype)
     Qs = [synth.orthonormal_columns(s, R, 10 * k + 2) for k, s in enumerate(shape)]
@@ -118,18 +123,24 @@ def test_multittm_f64(shape, xdtype):
 
 
 @pytest.mark.parametrize("shape,R", [((600, 301, 257), 16), ((600, 304, 257), 16), ((60, 50, 300), 5),
-                                     ((100, 80, 260), 12)])
+                                     ((100, 80, 260), 12), ((120, 100, 300), 32), ((1000, 600, 256), 24),
+                                     ((200, 180, 256), 17), ((40, 36, 20, 16), 9), ((48, 40, 300), 32)])
 def test_multittm_short_slabs(shape, R):
-    """Mode-3 update of tensors whose first contraction is over the middle
-    mode with short slabs (P = I_1 a multiple of 4 but not of 32, at least
-    256 slabs): whole-slab workgroups stage rows through LDS, with and without
-    a K tail and with line-aligned stretches (304 rows)."""
+    """Every mode update of tensors whose first contraction is over mode 2
+    with short slabs (P = I_1 <= 1024 rows, a multiple of 4, at least 256
+    slabs).  For the updates of modes 3, 4, .. the first two contractions run
+    fused, one workgroup per slab (64- and 128-row tiles, one or two
+    16-column blocks, K tails, line-aligned and unaligned stretches, and a
+    4-way tensor whose third contraction follows the fused pair)."""
     g = rng(sum(shape) + R)
     X = g.standard_normal(shape).astype(np.float32)
     Qs = [synth.orthonormal_columns(s, R, 10 * k + 3) for k, s in enumerate(shape)]
-    Y = to_np(C.cpqr_multittm(to_dev(X, torch.float32), [to_dev(Qs[0]), to_dev(Qs[1]), None], 2, C.PREC_F32))
-    Yo = OQ.multittm_unfolded(X.astype(np.float64), Qs, 2)
-    assert_entrywise(Y, Yo, abs_bound_multittm(X, Qs, 2), multittm_tol_f32(shape, 2), shape)
+    Xd = to_dev(X, torch.float32)
+    for n in range(len(shape)):
+        Y = to_np(C.cpqr_multittm(Xd, [None if k == n else to_dev(Qs[k]) for k in range(len(shape))], n,
+                                  C.PREC_F32))
+        Yo = OQ.multittm_unfolded(X.astype(np.float64), Qs, n)
+        assert_entrywise(Y, Yo, abs_bound_multittm(X, Qs, n), multittm_tol_f32(shape, n), (shape, n))
 
 
 def test_multittm_general_matrices_elementwise():
