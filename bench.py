@@ -562,8 +562,8 @@ def main():
         },
         "roofline": {
             "kernel": "first contraction of each Multi-TTM pass (streams X once; two per sweep with the mode reuse): " + {
-                "f32": "ttm_mfma_m with non-temporal row tiles (mode-3 contraction) and ttm_slab_m with whole-slab "
-                       "LDS stretches (mode-2 contraction)",
+                "f32": "ttm_mfma_m with non-temporal row tiles (mode-3 contraction) and ttm_slab2_m, the fused "
+                       "mode-2 and mode-1 contraction of each slab with whole-slab LDS stretches",
                 "bf16x2": "ttm_bf16_m<split> (mode-3 contraction) and ttm_slab_bf16<split> (mode-2 contraction)",
                 "bf16": "ttm_bf16_m (mode-3 contraction) and ttm_slab_bf16 (mode-2 contraction)",
                 "f64": "ttm_mfma_m_f64 (FP64 matrix cores, 128-row tiles; mode-3 contraction non-temporal)"}[

@@ -19,7 +19,7 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libcpqr.so")
+LIBPATH = os.environ.get("CPQR_LIB") or os.path.join(HERE, "libcpqr.so")
 
 MAX_MODES = 10
 MAX_RANK = 32

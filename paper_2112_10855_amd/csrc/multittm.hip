@@ -1438,14 +1438,22 @@ bool fused_pair(const Plan& pl, int prec, bool streams_tensor, bool x_aligned) {
          a.S >= 256;
 }
 
+// Slab stretch depth (rows of the slab staged per step) and stretches in
+// flight for slabs of at most 256 rows; compile-time tuning parameters.
+#ifndef CPQR_SLAB2_SMALL_KC
+#define CPQR_SLAB2_SMALL_KC 8
+#endif
+#ifndef CPQR_SLAB2_SMALL_NRS
+#define CPQR_SLAB2_SMALL_NRS 3
+#endif
+
 int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, const Step& a, int R, int RP,
                  hipStream_t st, const KernelEvents& ke) {
-  constexpr int KC = 8, NRS = 3;
   const int NB = RP / 16;
-  const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;  // stretches start on line boundaries
   const dim3 grd(unsigned(a.S));
   if (a.P <= 256) {
-    constexpr int MG = 1, NWV = 4;
+    constexpr int MG = 1, NWV = 4, KC = CPQR_SLAB2_SMALL_KC, NRS = CPQR_SLAB2_SMALL_NRS;
+    const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;  // stretches start on line boundaries
     const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
@@ -1460,7 +1468,8 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
       launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
                 a.K, a.S, R);
   } else {
-    constexpr int MG = 2, NWV = 8;
+    constexpr int MG = 2, NWV = 8, KC = 8, NRS = 3;
+    const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;
     const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
