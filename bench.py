@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--heldout", type=int, default=256, help="held-out tensors (loss) for --workload learned")
     ap.add_argument("--fit-heldout", type=int, default=32, help="held-out tensors timed to relerr 1e-6")
     ap.add_argument("--fit-n", type=int, default=200, help="mode size of the time-to-fit study (--workload fit)")
+    ap.add_argument("--krp-chain", type=int, default=-1,
+                    help="QR of the Khatri-Rao product: 1 structured, 0 dense, -1 structured for N >= 4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sub-records", action="store_true",
                     help="dense3 f32 qr only: skip the FP64 1000^3 and 200^4 rank-32 sub-records")
@@ -171,7 +173,7 @@ def phase_pass(C, torch, st, nb):
     return {k: round(v[0] / nb, 4) for k, v in ph.items()}
 
 
-def dense4_record(prec_name, steps, warmup, data=None):
+def dense4_record(prec_name, steps, warmup, data=None, krp_chain=-1):
     """CP-ALS-QR on the 200^4 FP32 rank-32 workload (weights 1e0..1e-6, no
     noise) with the Multi-TTM in the given precision: sweeps/s, the first
     contraction (streams the 6.4 GB tensor) timed by events on its own
@@ -193,7 +195,7 @@ def dense4_record(prec_name, steps, warmup, data=None):
         d, Xd = data
     X = d["X"]
     prec = C.PREC_NAMES[prec_name]
-    st = C.AlsState(Xd, d["init"], prec=prec)
+    st = C.AlsState(Xd, d["init"], prec=prec, krp_chain=krp_chain)
     st.init()
     for _ in range(warmup):
         st.sweep(1)
@@ -234,12 +236,12 @@ def dense4_record(prec_name, steps, warmup, data=None):
 def run_dense4(args):
     """200^4 FP32 tensor, rank 32, weights 1..1e-6, no noise: sweeps/s and the
     Multi-TTM error against the FP64 oracle on sampled rows, per precision."""
-    rec = dense4_record(args.prec, args.steps, args.warmup)
+    rec = dense4_record(args.prec, args.steps, args.warmup, krp_chain=args.krp_chain)
     out = {
         "metric": METRIC, "value": rec["value"], "unit": "sweeps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": rec["workload"], "shape": [200] * 4, "rank": 32,
+        "config": {"workload": rec["workload"], "shape": [200] * 4, "rank": 32, "krp_chain": args.krp_chain,
                    "ground_truth": "rank-32, unit Gaussian columns, weights 1e0..1e-6, no noise"},
         "roofline": rec["roofline"], "phases_ms_per_sweep": rec["phases_ms_per_sweep"],
         "multittm_relerr_vs_fp64_sampled_rows": rec["multittm_relerr_vs_fp64_sampled_rows"],

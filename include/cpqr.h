@@ -152,6 +152,37 @@ int cpqr_multittm_noalloc(int N, const int64_t* I, int xdtype, const void* X, in
                           const double* const* Q, int prec, void* Y, void* stream);
 
 /*
+ * Structured QR of V_n (section 3.3.3): the Khatri-Rao product of triangular
+ * factors is factorized without forming it.  With a_1 < .. < a_{N-1} the
+ * modes other than n, T_1 = R_{a_1} and, for j = 2..N-1, the QR
+ * R_{a_j} (.) T_{j-1} = Q_j T_j of an R^2 x R Khatri-Rao product of two
+ * triangular matrices, eq. (kr-id) gives
+ *   V_n = (I kron Q_2)(I kron Q_3) .. (I kron Q_{N-2}) Q_{N-1} T_{N-1},
+ * so R_0 = T_{N-1} and Q_0 = the product of the Kronecker-structured factors
+ * (orthonormal columns), equal to the dense Q_0, R_0 up to column signs.
+ * N - 2 QRs of R^2 x R rows replace one of R^{N-1} x R; Q_0 is never formed.
+ * For N = 3 this is the QR of V_n itself.  Requires 3 <= N.
+ *   Rk : host array of N device pointers to R x R factors (leading dimension
+ *        ldr); Rk[n] is not read
+ *   Qc : device, (N-2) blocks of R^2 x R column-major (Q_2 first)
+ *   R0 : device, R x R upper triangular (leading dimension R)
+ */
+size_t cpqr_krp_qr_chain_work(int N, int R);
+int cpqr_krp_qr_chain(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
+                      void* work, size_t work_bytes, void* stream);
+
+/*
+ * W = Y_(n) Q_0 with Q_0 in the structured form of cpqr_krp_qr_chain: step
+ * j = 2..N-1 contracts the two fastest column digits of the current
+ * I_n x (R^2 x R^{N-1-j}) array with Q_j (the first of them is the result of
+ * the step before), FP64 results.  Y: device I_n x R^(N-1) column-major,
+ * FP32 or FP64 (ydtype); W: device I_n x R column-major FP64.
+ */
+size_t cpqr_apply_q0_chain_work(int64_t In, int N, int R);
+int cpqr_apply_q0_chain(int64_t In, int N, int R, int ydtype, const void* Y, const double* Qc, double* W,
+                        void* work, size_t work_bytes, void* stream);
+
+/*
  * Apply Q_0 (Alg. 2, eq. ls-qr-q0-step): W = Y_(n) Q_0 in FP64.
  *   Y   : device, In x K column-major (leading dimension In), ydtype F32/F64
  *   Q0  : device, K x R column-major (leading dimension K)
@@ -217,6 +248,10 @@ typedef struct cpqr_problem {
                                      X contracted over modes h+1..N and modes h+1..N share X
                                      contracted over modes 1..h (two passes over X per sweep),
                                      -1: the library picks h (off for N = 2) */
+  int krp_chain;                  /* structured QR of V_n (cpqr_krp_qr_chain, Q_0 then formed
+                                     from its factors) in place of the dense QR of the formed
+                                     V_n: 1 on (N >= 3), 0 off, -1 the library picks (on for
+                                     N >= 4 once V_n has more than 65536 rows) */
 } cpqr_problem;
 
 size_t cpqr_als_work(const cpqr_problem* p);

@@ -56,7 +56,7 @@ class Problem(ctypes.Structure):
         ("A", _vp * MAX_MODES), ("Q", _vp * MAX_MODES), ("Rf", _vp * MAX_MODES),
         ("lam", _vp),
         ("prec", ctypes.c_int), ("use_svd", ctypes.c_int), ("rtol", ctypes.c_double),
-        ("error_mode", ctypes.c_int), ("status", _vp), ("dimtree", ctypes.c_int),
+        ("error_mode", ctypes.c_int), ("status", _vp), ("dimtree", ctypes.c_int), ("krp_chain", ctypes.c_int),
     ]
 
 
@@ -88,6 +88,12 @@ _SIGS = {
                                      ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _sz, _vp]),
     "cpqr_multittm_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int,
                                              ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp]),
+    "cpqr_krp_qr_chain_work": (_sz, [ctypes.c_int, ctypes.c_int]),
+    "cpqr_krp_qr_chain": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), _i64,
+                                         _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_apply_q0_chain_work": (_sz, [_i64, ctypes.c_int, ctypes.c_int]),
+    "cpqr_apply_q0_chain": (ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz,
+                                           _vp]),
     "cpqr_apply_q0_work": (_sz, [_i64, _i64, ctypes.c_int]),
     "cpqr_apply_q0": (ctypes.c_int, [_i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "cpqr_solve_rsvd_work": (_sz, [_i64, ctypes.c_int]),
@@ -305,6 +311,38 @@ def cpqr_multittm_noalloc(X, Qs, n, prec=PREC_F32, Y=None):
     return Y
 
 
+def cpqr_krp_qr_chain(Rks, n):
+    """Structured QR of V_n: (Qc, R0) with Qc the (N-2) R^2 x R factors
+    Q_2..Q_{N-1} stacked along a leading axis (each column-major)."""
+    N = len(Rks)
+    ref = next(r for r in Rks if r is not None)
+    R = ref.shape[0]
+    for k, r in enumerate(Rks):
+        if k != n:
+            _dev(r, "Rk")
+            _check_colmajor(r, "Rk")
+    Qc = torch.empty((N - 2, R, R * R), dtype=torch.float64, device=ref.device).transpose(1, 2)
+    R0 = empty_colmajor((R, R), torch.float64, ref.device)
+    nbytes = lib().cpqr_krp_qr_chain_work(N, R)
+    keep, w = _work(nbytes, ref.device)
+    _call("cpqr_krp_qr_chain", N, n, R, _ptr_array(Rks), R, Qc.data_ptr(), R0.data_ptr(), w, nbytes, _stream())
+    return Qc, R0
+
+
+def cpqr_apply_q0_chain(Y, Qc, N):
+    """W = Y_(n) Q_0 with Q_0 given by cpqr_krp_qr_chain's factors."""
+    _dev(Y, "Y")
+    _check_colmajor(Y, "Y")
+    In = Y.shape[0]
+    R = Qc.shape[2]
+    W = empty_colmajor((In, R), torch.float64, Y.device)
+    nbytes = lib().cpqr_apply_q0_chain_work(In, N, R)
+    keep, w = _work(nbytes, Y.device)
+    _call("cpqr_apply_q0_chain", In, N, R, _dtype_code(Y), Y.data_ptr(), Qc.data_ptr(), W.data_ptr(), w, nbytes,
+          _stream())
+    return W
+
+
 def cpqr_apply_q0(Y, Q0):
     """W = Y_(n) Q_0 in FP64."""
     _dev(Y, "Y")
@@ -353,7 +391,8 @@ def cpqr_fit_direct(X, lam, As):
 class AlsState:
     """Device buffers of one CP-ALS-QR problem, wired into ``cpqr_problem``."""
 
-    def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1):
+    def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1,
+                 krp_chain=-1):
         _dev(X, "X")
         _check_colmajor(X, "X")
         prec = PREC_NAMES.get(prec, prec)
@@ -381,6 +420,7 @@ class AlsState:
         p.lam = self.lam.data_ptr()
         p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(bool(use_svd)), float(rtol), error_mode
         p.dimtree = int(dimtree)
+        p.krp_chain = int(krp_chain)
         p.status = self.status.data_ptr()
         self.p = p
         nbytes = lib().cpqr_als_work(ctypes.byref(p))
@@ -410,10 +450,11 @@ def cpqr_als_sweep(state, nsweeps=1, relerr=None):
 
 
 def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=-1.0,
-              error_mode=ERROR_EFFICIENT, dimtree=-1):
+              error_mode=ERROR_EFFICIENT, dimtree=-1, krp_chain=-1):
     """Alg. 2 driven from the host: sweeps until |relerr change| < tol or
     maxiters (reads the error back after each sweep only when tol > 0)."""
-    st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode, dimtree=dimtree)
+    st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode, dimtree=dimtree,
+                  krp_chain=krp_chain)
     st.init()
     if tol <= 0:
         rel = st.sweep(maxiters)

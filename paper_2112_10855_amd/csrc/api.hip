@@ -153,6 +153,8 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 struct AlsWs {
   double* xnorm2;
   double* Q0;
+  double* Qc;  // factors of the structured QR of V_n (N - 2 blocks of R^2 x R)
+  double* Qx;  // ping-pong buffers that expand them into Q0
   double* R0;
   void* Y;
   double* W;
@@ -205,6 +207,101 @@ size_t ttm_sub_bytes(const cpqr_problem* p) {
   b = std::max(b, fit_direct_work(N, p->I, R));
   b = std::max(b, norm2_work(count));
   return b;
+}
+
+// ---------------------------------------------- structured QR of V_n
+// V_n = R_{a_{N-1}} (.) ... (.) R_{a_1} (modes a_1 < a_2 < .. other than n,
+// a_1's index fastest) is factorized without forming it, by eq. (kr-id):
+// with T_1 = R_{a_1} and the QR R_{a_j} (.) T_{j-1} = Q_j T_j of an R^2 x R
+// Khatri-Rao product of two triangular factors (j = 2..N-1),
+//   R_{a_j} (.) (Q_{j-1} T_{j-1}) = (I_R kron Q_{j-1}) (R_{a_j} (.) T_{j-1}),
+// so V_n = (I kron Q_2)(I kron Q_3) .. Q_{N-1} T_{N-1}: R_0 = T_{N-1} and Q_0 is
+// the product of the Kronecker-structured factors, never formed.  N - 2 QRs
+// of R^2 x R (4 R^4 flops each) replace one of R^{N-1} x R (4 R^{N+1}); for
+// N = 3 it is the QR of V_n itself.  Qc holds Q_2 .. Q_{N-1} one after the
+// other, each R^2 x R column-major.
+size_t krp_chain_work(int R) {
+  Carver cv(nullptr);
+  for (int i = 0; i < 4; ++i) cv.take<double>(size_t(R) * R);
+  cv.take<char>(tsqr_work(int64_t(R) * R, R));
+  return cv.bytes();
+}
+
+int krp_chain_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
+                      void* work, hipStream_t s) {
+  Carver cv(work);
+  double* T[2] = {cv.take<double>(size_t(R) * R), cv.take<double>(size_t(R) * R)};
+  double* F[2] = {cv.take<double>(size_t(R) * R), cv.take<double>(size_t(R) * R)};
+  void* qw = cv.take<char>(tsqr_work(int64_t(R) * R, R));
+  int a[CPQR_MAX_MODES], na = 0;
+  for (int k = 0; k < N; ++k)
+    if (k != n) a[na++] = k;
+  // every factor of a step is read with leading dimension R
+  auto packed = [&](const double* src, double* buf, const double** out) -> int {
+    if (ldr == R) {
+      *out = src;
+      return CPQR_OK;
+    }
+    CPQR_HIP(hipMemcpy2DAsync(buf, sizeof(double) * R, src, sizeof(double) * ldr, sizeof(double) * R, R,
+                              hipMemcpyDeviceToDevice, s));
+    *out = buf;
+    return CPQR_OK;
+  };
+  const double* t = nullptr;
+  CPQR_TRY(packed(Rk[a[0]], F[0], &t));
+  for (int j = 1; j < na; ++j) {
+    const double* f = nullptr;
+    CPQR_TRY(packed(Rk[a[j]], F[1], &f));
+    double* tout = j == na - 1 ? R0 : T[j % 2];
+    const double* fac[3] = {t, f, nullptr};  // R_{a_j} (.) T_{j-1}, T's index fastest
+    CPQR_TRY(krp_qr_enqueue(3, 2, R, fac, R, Qc + size_t(j - 1) * R * R * R, tout, qw, s));
+    t = tout;
+  }
+  return CPQR_OK;
+}
+
+// W = Y_(n) Q_0 with Q_0 = (I kron Q_2) .. Q_{N-1}: step j contracts the two
+// fastest remaining column digits of Y (R^2 of them, the first being the
+// output of step j - 1) with Q_j, a Multi-TTM step on the [I_n, R^2, R^{N-2-j}]
+// view; FP64 results.
+size_t apply_chain_work(int64_t In, int N, int R) {
+  const int64_t rest = ipow(R, N - 3);
+  const int64_t dims[3] = {In, int64_t(R) * R, rest};
+  Carver cv(nullptr);
+  if (N > 3)
+    for (int i = 0; i < 2; ++i) cv.take<double>(size_t(In) * R * rest);
+  cv.take<char>(multittm_general_work(3, dims, 2u, R, CPQR_PREC_F64));
+  return cv.bytes();
+}
+
+int apply_chain_enqueue(int64_t In, int N, int R, int ydtype, const void* Y, const double* Qc, double* W,
+                        void* work, hipStream_t s) {
+  const int64_t rest = ipow(R, N - 3);
+  Carver cv(work);
+  double* buf[2] = {nullptr, nullptr};
+  if (N > 3)
+    for (int i = 0; i < 2; ++i) buf[i] = cv.take<double>(size_t(In) * R * rest);
+  void* mw = cv.take<char>(0);
+  const void* cur = Y;
+  int cur_dt = ydtype;
+  for (int j = 1; j <= N - 2; ++j) {
+    const int64_t dims[3] = {In, int64_t(R) * R, ipow(R, N - 2 - j)};
+    const double* Q[3] = {nullptr, Qc + size_t(j - 1) * R * R * R, nullptr};
+    double* out = j == N - 2 ? W : buf[j % 2];
+    CPQR_TRY(multittm_general_enqueue(3, dims, cur_dt, cur, 2u, -1, R, Q, CPQR_PREC_F64, out, mw, s, false));
+    cur = out;
+    cur_dt = CPQR_F64;
+  }
+  return CPQR_OK;
+}
+
+// The dense QR of the formed V_n overlaps the Multi-TTM on its own stream; it
+// stays the default while V_n is short (R^{N-1} <= 65536 rows: at 32^3 rows it
+// left the sweep about 2% faster than the structured form's longer chain of
+// small launches) and the structured form takes over beyond.
+bool use_chain(const cpqr_problem* p) {
+  if (p->krp_chain > 0) return p->N >= 3;
+  return p->krp_chain < 0 && p->N >= 4 && ipow(p->R, p->N - 1) > 65536;
 }
 
 size_t als_sub_bytes(const cpqr_problem* p) {
@@ -295,13 +392,16 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
   AlsWs w{};
   w.xnorm2 = cv.take<double>(1);
   w.Q0 = cv.take<double>(size_t(K) * R);
+  // factors of the structured QR of V_n and the buffers that expand them into Q_0
+  w.Qc = cv.take<double>(size_t(std::max(N - 2, 0)) * R * R * R);
+  w.Qx = cv.take<double>(N >= 5 ? 2 * size_t(K) * R : 0);
   w.R0 = cv.take<double>(size_t(R) * R);
   w.Y = cv.take<double>(size_t(imax) * K);  // sized for FP64 Y
   w.W = cv.take<double>(size_t(imax) * R);
   w.fit = cv.take<double>(2);
   w.relerr_tmp = cv.take<double>(1);
   w.sub = cv.take<char>(als_sub_bytes(p));
-  w.krp_sub = cv.take<char>(tsqr_work(K, R));
+  w.krp_sub = cv.take<char>(std::max(tsqr_work(K, R), krp_chain_work(R)));
   w.Wt = cv.take<double>(size_t(dt_elems(p)));  // sized for FP64
   w.err_part = cv.take<double>(error_efficient_work(p->I[N - 1]) / sizeof(double));
   if (ws) *ws = w;
@@ -464,6 +564,41 @@ int cpqr_multittm_noalloc(int N, const int64_t* I, int xdtype, const void* X, in
   return multittm_enqueue(N, I, xdtype, X, n, R, Q, prec, Y, scr, as_stream(stream));
 }
 
+size_t cpqr_krp_qr_chain_work(int N, int R) {
+  if (N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return krp_chain_work(R);
+}
+
+int cpqr_krp_qr_chain(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
+                      void* work, size_t work_bytes, void* stream) {
+  if (N < 3 || N > CPQR_MAX_MODES) return fail(CPQR_ERR_SHAPE, "krp_qr_chain: N out of range (3..10)");
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "krp_qr_chain: n out of range");
+  CPQR_TRY(check_rank(R));
+  if (!Rk || !Qc || !R0) return fail(CPQR_ERR_ARG, "krp_qr_chain: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Rk[k]) return fail(CPQR_ERR_ARG, "krp_qr_chain: Rk[" + std::to_string(k) + "] is NULL");
+  if (ldr < R) return fail(CPQR_ERR_SHAPE, "krp_qr_chain: ldr < R");
+  CPQR_TRY(check_work(work, work_bytes, krp_chain_work(R)));
+  return krp_chain_enqueue(N, n, R, Rk, ldr, Qc, R0, work, as_stream(stream));
+}
+
+size_t cpqr_apply_q0_chain_work(int64_t In, int N, int R) {
+  if (In < 1 || N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return apply_chain_work(In, N, R);
+}
+
+int cpqr_apply_q0_chain(int64_t In, int N, int R, int ydtype, const void* Y, const double* Qc, double* W,
+                        void* work, size_t work_bytes, void* stream) {
+  if (N < 3 || N > CPQR_MAX_MODES) return fail(CPQR_ERR_SHAPE, "apply_q0_chain: N out of range (3..10)");
+  CPQR_TRY(check_rank(R));
+  if (In < 1) return fail(CPQR_ERR_SHAPE, "apply_q0_chain: In < 1");
+  CPQR_TRY(check_krp_rows(N, R));
+  if (!valid_dtype(ydtype)) return fail(CPQR_ERR_DTYPE, "apply_q0_chain: ydtype must be CPQR_F32 or CPQR_F64");
+  if (!Y || !Qc || !W) return fail(CPQR_ERR_ARG, "apply_q0_chain: NULL pointer");
+  CPQR_TRY(check_work(work, work_bytes, apply_chain_work(In, N, R)));
+  return apply_chain_enqueue(In, N, R, ydtype, Y, Qc, W, work, as_stream(stream));
+}
+
 size_t cpqr_apply_q0_work(int64_t In, int64_t K, int R) {
   if (In < 1 || K < 1 || R < 1 || R > CPQR_MAX_RANK) return 0;
   return apply_q0_work(In, K, R);
@@ -551,6 +686,7 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   SideStream side;
   CPQR_TRY(side_stream(side));
   const int h = dt_split(p);
+  const bool chain = use_chain(p);
   bool r_marked = false;  // side.ready marks the last factor QR's R
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
@@ -559,7 +695,11 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       // QR has its R (its Q is still being formed), the Multi-TTM after it.
       if (!r_marked) CPQR_HIP(hipEventRecord(side.ready, s));
       CPQR_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
-      CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
+      if (chain) {  // structured QR, then Q_0 formed from its factors (both on the side stream)
+        CPQR_TRY(krp_chain_enqueue(N, n, R, p->Rf, R, w.Qc, w.R0, w.krp_sub, side.s));
+        CPQR_TRY(expand_q0_enqueue(N, R, w.Qc, w.Q0, w.Qx, side.s));
+      } else
+        CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
       CPQR_HIP(hipEventRecord(side.done, side.s));
       CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));

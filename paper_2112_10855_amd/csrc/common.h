@@ -131,6 +131,9 @@ size_t error_efficient_work(int64_t In);
 int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
                             const double* lambda, const double* R0, const double* RN,
                             const double* xnorm2, double* relerr, double* part, hipStream_t s);
+// Q_0 (R^{N-1} x R) formed from the factors of the structured QR of V_n
+// (Qc: Q_2 .. Q_{N-1}, each R^2 x R); buf holds 2 R^{N-1} R doubles (N >= 5)
+int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, hipStream_t s);
 // relerr = sqrt(max(out[0],0) / out[1]) from a fit_direct result
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s);
 int fill_enqueue(double* p, int64_t count, double v, hipStream_t s);

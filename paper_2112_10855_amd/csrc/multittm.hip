@@ -272,8 +272,21 @@ __device__ __forceinline__ doublex2 ldx2(const double* p) {
 
 constexpr int LDS_DOUBLES = 8192;  // 64 KB
 
-template <int NB, int UN, int MG, int NWV, bool STREAM, bool NT>
-__global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restrict__ X,
+// Four consecutive elements of X (FP64, or FP32 widened) as two pairs.
+template <bool NT>
+__device__ __forceinline__ void ldx4(const double* q, doublex2& a, doublex2& b) {
+  a = ldx2<NT>(q);
+  b = ldx2<NT>(q + 2);
+}
+template <bool NT>
+__device__ __forceinline__ void ldx4(const float* q, doublex2& a, doublex2& b) {
+  const float4 v = ldx<NT>(q);
+  a = doublex2{double(v.x), double(v.y)};
+  b = doublex2{double(v.z), double(v.w)};
+}
+
+template <int NB, int UN, int MG, int NWV, bool STREAM, bool NT, class TX = double>
+__global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict__ X,
                                                            const double* __restrict__ U,
                                                            double* __restrict__ out, int64_t P, int64_t K,
                                                            int64_t S, int R, int64_t kchunk,
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restr
   const int64_t kb0 = int64_t(blockIdx.y) * kchunk;
   const int64_t kb1 = min(K, kb0 + kchunk);
   const int l16 = lane % 16, kq = lane / 16;
-  const double* base[MG];
+  const TX* base[MG];
 #pragma unroll
   for (int g = 0; g < MG; ++g) {
     int64_t mrow = mt + 64 * g + 4 * l16;
@@ -307,7 +320,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restr
   auto chunk = [&](int64_t c0, int cn) {
     const int nfull = cn / STEP;
     const int last = nfull > 0 ? (nfull - 1) * STEP : 0;
-    const double* bp[MG];
+    const TX* bp[MG];
 #pragma unroll
     for (int g = 0; g < MG; ++g) bp[g] = base[g] + c0 * P;
     doublex2 A[UN][MG][2], B[UN][MG][2];
@@ -316,11 +329,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restr
 #pragma unroll
       for (int u = 0; u < UN; ++u)
 #pragma unroll
-        for (int g = 0; g < MG; ++g) {
-          const double* q = bp[g] + int64_t(i0 + 4 * u) * P;
-          dst[u][g][0] = ldx2<NT>(q);
-          dst[u][g][1] = ldx2<NT>(q + 2);
-        }
+        for (int g = 0; g < MG; ++g) ldx4<NT>(bp[g] + int64_t(i0 + 4 * u) * P, dst[u][g][0], dst[u][g][1]);
     };
     auto compute = [&](const doublex2(&src)[UN][MG][2], int t) {
 #pragma unroll
@@ -354,9 +363,8 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const double* __restr
         const double bv = ok ? usd[ii * RP + b * 16 + l16] : 0.0;
 #pragma unroll
         for (int g = 0; g < MG; ++g) {
-          const double* q = bp[g] + int64_t(i) * P;
-          const doublex2 x0 = ok ? *reinterpret_cast<const doublex2*>(q) : doublex2{0.0, 0.0};
-          const doublex2 x1 = ok ? *reinterpret_cast<const doublex2*>(q + 2) : doublex2{0.0, 0.0};
+          doublex2 x0{0.0, 0.0}, x1{0.0, 0.0};
+          if (ok) ldx4<false>(bp[g] + int64_t(i) * P, x0, x1);
           acc[b][g][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, bv, acc[b][g][0], 0, 0, 0);
           acc[b][g][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.y, bv, acc[b][g][1], 0, 0, 0);
           acc[b][g][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.x, bv, acc[b][g][2], 0, 0, 0);
@@ -1487,8 +1495,8 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
   return check_launch("ttm_slab2_m");
 }
 
-template <bool STREAM>
-int launch_mfma_f64_t(const double* src, const double* U, double* dst, const Step& s, int R, int RP,
+template <bool STREAM, class TX>
+int launch_mfma_f64_t(const TX* src, const double* U, double* dst, const Step& s, int R, int RP,
                       hipStream_t st, const KernelEvents& ke) {
   const int NB = RP / 16;
   // one step (four K rows) in flight per buffer: 122 VGPRs, two workgroups per CU
@@ -1498,30 +1506,31 @@ int launch_mfma_f64_t(const double* src, const double* U, double* dst, const Ste
   const bool nt = STREAM && s.P % 16 == 0;  // rows 128-byte multiples apart: no line shared between tiles
   if (s.mg == 1) {  // 64-row tiles: small operands, or two 16-column blocks
     if (NB == 1)
-      launch_ev(ke, ttm_mfma_m_f64<1, UN, 1, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+      launch_ev(ke, ttm_mfma_m_f64<1, UN, 1, NWV, STREAM, false, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
                 s.K, s.S, R, s.kchunk, s.out_count);
     else if (nt)
-      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, true, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
                 s.K, s.S, R, s.kchunk, s.out_count);
     else
-      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
+      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, false, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,
                 s.K, s.S, R, s.kchunk, s.out_count);
     return check_launch("ttm_mfma_m_f64");
   }
   if (s.mg != 2 || NB != 1) return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m_f64: unsupported row tile");
   if (nt)
-    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, true>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, true, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
               s.S, R, s.kchunk, s.out_count);
   else
-    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, false>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
+    launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, false, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P, s.K,
               s.S, R, s.kchunk, s.out_count);
   return check_launch("ttm_mfma_m_f64");
 }
 
-int launch_mfma_f64(bool first, const double* src, const double* U, double* dst, const Step& s, int R, int RP,
+template <class TX>
+int launch_mfma_f64(bool first, const TX* src, const double* U, double* dst, const Step& s, int R, int RP,
                     hipStream_t st, const KernelEvents& ke) {
-  return first ? launch_mfma_f64_t<true>(src, U, dst, s, R, RP, st, ke)
-               : launch_mfma_f64_t<false>(src, U, dst, s, R, RP, st, ke);
+  return first ? launch_mfma_f64_t<true, TX>(src, U, dst, s, R, RP, st, ke)
+               : launch_mfma_f64_t<false, TX>(src, U, dst, s, R, RP, st, ke);
 }
 
 int launch_mfma(int prec, bool first, const float* src, const float* U, float* dst, const Step& s, int R,
@@ -1599,10 +1608,16 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     {
       const bool first = t == 0 && streams_tensor;
       PhaseTimer ph_first(first ? PH_TTM_FIRST : -1, st);
-      if (f64 && s.kind == K_MFMA_M && cur_dtype == CPQR_F64) {
+      if (f64 && s.kind == K_MFMA_M && (cur_dtype == CPQR_F64 || !first)) {
+        // FP64 matrix cores; an FP32 operand that is not the streamed tensor
+        // (the unfolded Y of the structured Q_0 application) is widened as it loads
         const KernelEvents ke = kernel_events(first ? PH_TTM_STREAM_M : -1, st);
-        CPQR_TRY(launch_mfma_f64(first, static_cast<const double*>(cur), static_cast<const double*>(b.U[s.k]),
-                                 static_cast<double*>(kout), s, R, RP, st, ke));
+        if (cur_dtype == CPQR_F64)
+          CPQR_TRY(launch_mfma_f64(first, static_cast<const double*>(cur), static_cast<const double*>(b.U[s.k]),
+                                   static_cast<double*>(kout), s, R, RP, st, ke));
+        else
+          CPQR_TRY(launch_mfma_f64(first, static_cast<const float*>(cur), static_cast<const double*>(b.U[s.k]),
+                                   static_cast<double*>(kout), s, R, RP, st, ke));
         kernel_events_done(ke);
       } else if (f64) {
         CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),

@@ -393,6 +393,25 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(double* A, double* lambd
   }
 }
 
+// ------------------------------------------------------------ structured Q_0
+// One step of forming Q_0 = (I kron Q_2) .. (I kron Q_{N-2}) Q_{N-1} from the
+// right: out = (I_m kron Qj) G, i.e. out[k + R^2 s, c] = sum_j Qj[k, j] G[j + R s, c]
+// (Qj R^2 x R, G (R m) x R, out (R^2 m) x R, all column-major); one thread per
+// entry of out.
+__global__ __launch_bounds__(BLK) void expand_q0_kernel(const double* __restrict__ Qj, const double* __restrict__ G,
+                                                        int64_t m, int R, double* __restrict__ out) {
+  const int64_t rows = int64_t(R) * R * m;
+  const int64_t e = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (e >= rows * R) return;
+  const int64_t row = e % rows;
+  const int c = int(e / rows);
+  const int64_t k = row % (int64_t(R) * R), s = row / (int64_t(R) * R);
+  const double* g = G + int64_t(R) * s + int64_t(R) * m * c;
+  double v = 0.0;
+  for (int j = 0; j < R; ++j) v += Qj[k + int64_t(R) * R * j] * g[j];
+  out[e] = v;
+}
+
 // ------------------------------------------------------------ errors
 // relerr = sqrt(max(x2 - 2 ip + nn, 0) / x2) with
 // ip = <W, Ahat R0^T>, Ahat = A diag(lambda), nn = <R0^T R0, diag(l) RN^T RN diag(l)>
@@ -945,6 +964,27 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
   CPQR_TRY(check_launch("error_efficient"));
   hipLaunchKernelGGL(error_efficient_final, dim3(1), dim3(1), 0, s, part, int(nb), xnorm2, relerr);
   return check_launch("error_efficient_final");
+}
+
+int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, hipStream_t s) {
+  const size_t blk = size_t(R) * R * R;  // doubles per factor Q_j
+  if (N == 3) {
+    CPQR_HIP(hipMemcpyAsync(Q0, Qc, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+    return CPQR_OK;
+  }
+  // G = Q_{N-1}, then G <- (I kron Q_j) G for j = N-2 .. 2; the last step writes Q0
+  const double* G = Qc + size_t(N - 3) * blk;
+  int64_t m = R;
+  for (int j = N - 2; j >= 2; --j) {
+    double* out = j == 2 ? Q0 : buf + ((N - 2 - j) % 2) * (ipow(R, N - 1) * R);
+    const int64_t cnt = int64_t(R) * R * m * R;
+    hipLaunchKernelGGL(expand_q0_kernel, dim3(unsigned(ceil_div(cnt, BLK))), dim3(BLK), 0, s,
+                       Qc + size_t(j - 2) * blk, G, m, R, out);
+    CPQR_TRY(check_launch("expand_q0"));
+    G = out;
+    m *= R;
+  }
+  return CPQR_OK;
 }
 
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s) {

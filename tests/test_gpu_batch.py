@@ -110,3 +110,28 @@ def test_streaming_shapes_give_identical_results(batch):
             for k in range(3):
                 assert torch.equal(runs[0].A[b][k], B.A[b][k]), (b, k)
             assert torch.equal(runs[0].relerr[b], B.relerr[b])
+
+
+def test_batch_512_workload_sampled_against_oracle():
+    """The 512-tensor workload (sizes uniform in [20, 160], ranks in
+    [2, 12], 1e-3 noise) swept 5 times in one call; 32 tensors -- the
+    largest, the smallest and 30 spread over the batch -- against the
+    oracle's 5-sweep trajectories from the same bytes and starts."""
+    shapes = synth.batch_shapes(512)
+    sizes = [s[0] * s[1] * s[2] for s, _ in shapes]
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} | set(range(0, 512, 17)))[:32]
+    Xs, inits, Xh = [], [], {}
+    for b, (shape, R) in enumerate(shapes):
+        d = synth.cp_tensor(shape, R, 5000 + b, noise=1e-3, dtype=np.float32, threads=1)
+        Xs.append(to_dev(d["X"], torch.float32))
+        inits.append(synth.init_factors(shape, R, 6000 + b))
+        if b in pick:
+            Xh[b] = d["X"]
+    B = C.AlsBatch(Xs, inits, 5)
+    B.run(5, init=True, graph=True)
+    torch.cuda.synchronize()
+    assert len(pick) == 32
+    for b in pick:
+        _, _, ho = OQ.cp_als_qr(Xh[b].astype(np.float64), inits[b], maxiters=5)
+        rel = to_np(B.relerr[b])
+        np.testing.assert_allclose(rel ** 2, np.array(ho) ** 2, rtol=2e-3, atol=2e-6, err_msg="tensor %d %s" % (b, shapes[b]))

@@ -240,3 +240,53 @@ def test_fit_direct(shape, R, xdt):
     x2 = OT.norm(Xd) ** 2
     assert abs(out[1] - x2) <= 1e-12 * x2
     assert abs(out[0] - r2) <= 1e-10 * r2
+
+
+# ------------------------------------------------------------------ structured KRP QR
+
+def chain_q0(Qc, N):
+    """Q_0 = (I kron Q_2)(I kron Q_3) .. Q_{N-1} formed explicitly (test side)."""
+    R = Qc.shape[2]
+    Q0 = Qc[N - 3]
+    for j in range(N - 4, -1, -1):  # Q_0 = (I_{R^{N-3-j}} kron Q_{j+2}) .. ; build from the right
+        Q0 = np.kron(np.eye(R ** (N - 3 - j)), Qc[j]) @ Q0
+    return Q0
+
+
+@pytest.mark.parametrize("N,R", [(3, 5), (3, 16), (4, 7), (4, 32), (5, 3), (5, 12), (6, 4), (7, 3), (10, 2)])
+def test_krp_qr_chain(N, R):
+    """The structured QR (eq. kr-id applied step by step) against the oracle's
+    dense QR of the explicit V_n: R_0 and Q_0 equal after fixing the signs of
+    the columns, Q_0 orthonormal, Q_0 R_0 = V_n."""
+    g = rng(N * 100 + R)
+    Rs = [OQ.factor_qr(g.standard_normal((R + 3, R)))[1] for _ in range(N)]
+    for n in sorted({0, N - 1, N // 2}):
+        Qc, R0 = C.cpqr_krp_qr_chain([to_dev(r) for r in Rs], n)
+        Qc, R0 = to_np(Qc), to_np(R0)
+        assert Qc.shape == (N - 2, R * R, R)
+        Q0 = chain_q0(Qc, N)
+        Q0o, R0o = OQ.krp_qr(Rs, n)
+        V = OQ.krp_of_r(Rs, n)
+        assert np.abs(np.tril(R0, -1)).max() == 0.0
+        assert np.linalg.norm(Q0.T @ Q0 - np.eye(R)) < 1e-12
+        assert relnorm(Q0 @ R0, V) < 1e-13
+        a, b = sign_fix(Q0, R0)
+        ao, bo = sign_fix(Q0o, R0o)
+        assert relnorm(b, bo) < 1e-11, relnorm(b, bo)
+        assert relnorm(a, ao) < 1e-10, relnorm(a, ao)
+
+
+@pytest.mark.parametrize("In,N,R", [(50, 4, 5), (200, 4, 32), (37, 5, 6), (130, 3, 16), (64, 6, 3)])
+@pytest.mark.parametrize("ydt", [np.float32, np.float64])
+def test_apply_q0_chain(In, N, R, ydt):
+    """W = Y_(n) Q_0 through the structured factors equals the product with
+    the explicit Q_0, entry by entry (FP64, magnitude bound |Y| |Q_0|)."""
+    g = rng(In + N + R)
+    Rs = [OQ.factor_qr(g.standard_normal((R + 3, R)))[1] for _ in range(N)]
+    Qc, R0 = C.cpqr_krp_qr_chain([to_dev(r) for r in Rs], 0)
+    Qc_np = to_np(Qc)
+    Q0 = chain_q0(Qc_np, N)
+    Y = g.standard_normal((In, R ** (N - 1))).astype(ydt)
+    W = to_np(C.cpqr_apply_q0_chain(to_dev(Y, torch.float32 if ydt == np.float32 else torch.float64), Qc, N))
+    Y64 = Y.astype(np.float64)
+    assert_entrywise(W, Y64 @ Q0, np.abs(Y64) @ np.abs(Q0), 1e-12, (In, N, R))

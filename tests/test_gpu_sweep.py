@@ -22,10 +22,10 @@ from helpers import relnorm, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(X, init, maxiters, prec, use_svd=False, error_mode=C.ERROR_EFFICIENT, dimtree=-1):
+def run_gpu(X, init, maxiters, prec, use_svd=False, error_mode=C.ERROR_EFFICIENT, dimtree=-1, krp_chain=-1):
     tdt = torch.float32 if X.dtype == np.float32 else torch.float64
     st, hist = C.cp_als_qr(to_dev(X, tdt), init, maxiters=maxiters, prec=prec, use_svd=use_svd,
-                           error_mode=error_mode, dimtree=dimtree)
+                           error_mode=error_mode, dimtree=dimtree, krp_chain=krp_chain)
     torch.cuda.synchronize()
     lam = to_np(st.lam)
     A = [to_np(a) for a in st.A]
@@ -180,3 +180,20 @@ def test_long_khatri_rao_fp64_small_steps(prec):
     if prec == C.PREC_F64:
         assert model_diff(lam, A, lo, Ao) < tol
 
+
+
+@pytest.mark.parametrize("shape,R", [((9, 8, 7), 4), ((12, 10, 9, 8), 5), ((6, 7, 5, 6, 5), 3), ((5, 4, 5, 4, 5, 4), 3), ((20, 18, 16, 14), 11)])
+@pytest.mark.parametrize("chain", [0, 1])
+@pytest.mark.parametrize("use_svd", [False, True])
+def test_structured_krp_qr_in_sweeps(shape, R, chain, use_svd):
+    """Sweeps with the structured QR of V_n (chain = 1) and with the dense
+    QR with Q_0 formed (chain = 0) both reproduce the oracle (dense QR of the
+    explicit V_n) in FP64."""
+    g = np.random.default_rng(sum(shape) + R)
+    A = [g.standard_normal((s, R)) for s in shape]
+    X = OT.full(np.ones(R), A) + 1e-3 * g.standard_normal(shape)
+    init = [g.standard_normal((s, R)) for s in shape]
+    lam, Ag, hist, status = run_gpu(X, init, 8, C.PREC_F64, use_svd=use_svd, krp_chain=chain)
+    lo, Ao, ho = OQ.cp_als_qr(X, init, maxiters=8, solver="svd" if use_svd else "qr")
+    np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
+    assert model_diff(lam, Ag, lo, Ao) < 1e-9
