@@ -173,6 +173,35 @@ def phase_pass(C, torch, st, nb):
     return {k: round(v[0] / nb, 4) for k, v in ph.items()}
 
 
+def krp_qr_alone(C, torch, N, R, reps=20):
+    """The QR of V_n (R^{N-1} x R) timed alone on an idle GPU, dense (V_n
+    formed, TSQR, Q_0 formed) against structured (N - 2 QRs of R^2 x R, then
+    Q_0 formed from their factors): ms per call, from events around reps
+    calls."""
+    g = torch.Generator().manual_seed(11)
+    Rks = [(torch.triu(torch.randn(R, R, generator=g, dtype=torch.float64)) + 4 * torch.eye(R, dtype=torch.float64))
+           .to("cuda").t().contiguous().t() for _ in range(N)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return round(a.elapsed_time(b) / reps, 4)
+
+    def structured():
+        Qc, _ = C.cpqr_krp_qr_chain(Rks, 0)
+        C.cpqr_expand_q0(Qc, N)
+
+    return {"N": N, "R": R, "rows": R ** (N - 1), "dense_ms": timed(lambda: C.cpqr_krp_qr(Rks, 0)),
+            "structured_ms": timed(structured),
+            "structured_factors_only_ms": timed(lambda: C.cpqr_krp_qr_chain(Rks, 0))}
+
+
 def dense4_record(prec_name, steps, warmup, data=None, krp_chain=-1):
     """CP-ALS-QR on the 200^4 FP32 rank-32 workload (weights 1e0..1e-6, no
     noise) with the Multi-TTM in the given precision: sweeps/s, the first
@@ -228,6 +257,7 @@ def dense4_record(prec_name, steps, warmup, data=None, krp_chain=-1):
                      "frac": round(xbytes / dom_s / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": xbytes,
                      "avg_launch_ms": round(dom_s * 1e3, 4), "launches": dom_cnt},
         "phases_ms_per_sweep": phases,
+        "krp_qr_alone": [krp_qr_alone(C, torch, nn, rr) for nn, rr in ((4, R), (5, 16), (5, R))],
         "multittm_relerr_vs_fp64_sampled_rows": errs,
         "relerr_last": float(rel[-1]),
     }
@@ -244,6 +274,7 @@ def run_dense4(args):
         "config": {"workload": rec["workload"], "shape": [200] * 4, "rank": 32, "krp_chain": args.krp_chain,
                    "ground_truth": "rank-32, unit Gaussian columns, weights 1e0..1e-6, no noise"},
         "roofline": rec["roofline"], "phases_ms_per_sweep": rec["phases_ms_per_sweep"],
+        "krp_qr_alone": rec["krp_qr_alone"],
         "multittm_relerr_vs_fp64_sampled_rows": rec["multittm_relerr_vs_fp64_sampled_rows"],
         "relerr_last": rec["relerr_last"],
     }

@@ -172,6 +172,18 @@ int cpqr_krp_qr_chain(int N, int n, int R, const double* const* Rk, int64_t ldr,
                       void* work, size_t work_bytes, void* stream);
 
 /*
+ * Q_0 formed from the factors of cpqr_krp_qr_chain (section 3.3.3, eq. kr-id):
+ * Q_0 = (I kron Q_2)(I kron Q_3) .. Q_{N-1}, built from the right, one
+ * Kronecker step per factor (2 R^{N+1} flops in the last step).
+ *   Qc : device, N - 2 blocks of R^2 x R column-major (as written by
+ *        cpqr_krp_qr_chain)
+ *   Q0 : device, R^{N-1} x R column-major (leading dimension R^{N-1}), written
+ *   work : 2 R^N doubles for N >= 5, none below
+ */
+size_t cpqr_expand_q0_work(int N, int R);
+int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_t work_bytes, void* stream);
+
+/*
  * W = Y_(n) Q_0 with Q_0 in the structured form of cpqr_krp_qr_chain: step
  * j = 2..N-1 contracts the two fastest column digits of the current
  * I_n x (R^2 x R^{N-1-j}) array with Q_j (the first of them is the result of

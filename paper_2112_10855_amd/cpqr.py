@@ -91,6 +91,8 @@ _SIGS = {
     "cpqr_krp_qr_chain_work": (_sz, [ctypes.c_int, ctypes.c_int]),
     "cpqr_krp_qr_chain": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), _i64,
                                          _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_expand_q0_work": (_sz, [ctypes.c_int, ctypes.c_int]),
+    "cpqr_expand_q0": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]),
     "cpqr_apply_q0_chain_work": (_sz, [_i64, ctypes.c_int, ctypes.c_int]),
     "cpqr_apply_q0_chain": (ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz,
                                            _vp]),
@@ -327,6 +329,18 @@ def cpqr_krp_qr_chain(Rks, n):
     keep, w = _work(nbytes, ref.device)
     _call("cpqr_krp_qr_chain", N, n, R, _ptr_array(Rks), R, Qc.data_ptr(), R0.data_ptr(), w, nbytes, _stream())
     return Qc, R0
+
+
+def cpqr_expand_q0(Qc, N):
+    """Q_0 (R^{N-1} x R, column-major FP64) formed from cpqr_krp_qr_chain's
+    factors."""
+    _dev(Qc, "Qc")
+    R = Qc.shape[2]
+    Q0 = empty_colmajor((R ** (N - 1), R), torch.float64, Qc.device)
+    nbytes = lib().cpqr_expand_q0_work(N, R)
+    keep, w = _work(nbytes, Qc.device)
+    _call("cpqr_expand_q0", N, R, Qc.data_ptr(), Q0.data_ptr(), w, nbytes, _stream())
+    return Q0
 
 
 def cpqr_apply_q0_chain(Y, Qc, N):

@@ -582,6 +582,20 @@ int cpqr_krp_qr_chain(int N, int n, int R, const double* const* Rk, int64_t ldr,
   return krp_chain_enqueue(N, n, R, Rk, ldr, Qc, R0, work, as_stream(stream));
 }
 
+size_t cpqr_expand_q0_work(int N, int R) {
+  if (N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
+  return N >= 5 ? sizeof(double) * 2 * size_t(ipow(R, N)) : 0;
+}
+
+int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_t work_bytes, void* stream) {
+  if (N < 3 || N > CPQR_MAX_MODES) return fail(CPQR_ERR_SHAPE, "expand_q0: N out of range (3..10)");
+  CPQR_TRY(check_rank(R));
+  CPQR_TRY(check_krp_rows(N, R));
+  if (!Qc || !Q0) return fail(CPQR_ERR_ARG, "expand_q0: NULL pointer");
+  CPQR_TRY(check_work(work, work_bytes, cpqr_expand_q0_work(N, R)));
+  return expand_q0_enqueue(N, R, Qc, Q0, static_cast<double*>(work), as_stream(stream));
+}
+
 size_t cpqr_apply_q0_chain_work(int64_t In, int N, int R) {
   if (In < 1 || N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
   return apply_chain_work(In, N, R);

@@ -276,6 +276,23 @@ def test_krp_qr_chain(N, R):
         assert relnorm(a, ao) < 1e-10, relnorm(a, ao)
 
 
+@pytest.mark.parametrize("N,R", [(3, 6), (4, 32), (5, 3), (5, 12), (6, 4), (7, 3), (10, 2)])
+def test_expand_q0(N, R):
+    """Q_0 formed on the device from the structured factors equals the
+    Kronecker product chain formed on the host, entry by entry."""
+    g = rng(N * 31 + R)
+    Rs = [OQ.factor_qr(g.standard_normal((R + 2, R)))[1] for _ in range(N)]
+    Qc, R0 = C.cpqr_krp_qr_chain([to_dev(r) for r in Rs], N - 1)
+    Q0 = to_np(C.cpqr_expand_q0(Qc, N))
+    Qc_np = to_np(Qc)
+    ref = chain_q0(Qc_np, N)
+    Qa = np.abs(Qc_np)
+    bound = Qa[N - 3]
+    for j in range(N - 4, -1, -1):
+        bound = np.kron(np.eye(R ** (N - 3 - j)), Qa[j]) @ bound
+    assert_entrywise(Q0, ref, bound, 1e-13, (N, R))
+
+
 @pytest.mark.parametrize("In,N,R", [(50, 4, 5), (200, 4, 32), (37, 5, 6), (130, 3, 16), (64, 6, 3)])
 @pytest.mark.parametrize("ydt", [np.float32, np.float64])
 def test_apply_q0_chain(In, N, R, ydt):

@@ -49,8 +49,12 @@ def test_multittm_lowp_error_matches_emulation(shape, R, mode):
 
 
 def test_precision_ordering_on_one_tensor():
-    """FP32 < split bfloat16 < plain bfloat16 in error, each at its expected
-    magnitude (FP32 <= 1e-5, split ~1e-5, plain ~1e-3)."""
+    """FP32 < split bfloat16 < plain bfloat16 in error.  Measured on this
+    tensor: 2.3e-7, 6.3e-6 and 3.3e-3; the bounds are those values with a
+    factor 2-4 of margin.  FP32 and split bfloat16 meet the 1e-5 contract;
+    plain bfloat16 misses its 1e-3 contract on the raw Multi-TTM (about 2^-9
+    per product, summed over 16 x 16 terms), which is asserted as a miss so
+    that a change in it is noticed."""
     g = np.random.default_rng(11)
     shape = (96, 80, 72)
     X = g.standard_normal(shape).astype(np.float32)
@@ -61,9 +65,9 @@ def test_precision_ordering_on_one_tensor():
         Y = to_np(C.cpqr_multittm(Xd, [None, to_dev(Qs[1]), to_dev(Qs[2])], 0, prec))
         errs[name] = relnorm(Y, OQ.multittm_unfolded(X.astype(np.float64), Qs, 0))
     print("[precision] Multi-TTM errors:", {k: "%.2e" % v for k, v in errs.items()})
-    assert errs["f32"] < 1e-5
-    assert errs["bf16x2"] < 1e-4
-    assert 1e-4 < errs["bf16"] < 1e-2
+    assert errs["f32"] < 1e-6
+    assert errs["bf16x2"] < 2e-5
+    assert 1e-3 < errs["bf16"] < 6.6e-3
     assert errs["f32"] < errs["bf16x2"] < errs["bf16"]
 
 
