@@ -20,6 +20,9 @@ Modules
                 with both error forms (section 3.3.1)
   cp_als     -- Alg. 1 (CP-ALS and CP-ALS-PINV), the normal-equations
                 comparator (section 2.3)
+  kruskal    -- Alg. 2 and Alg. 1 on a Kruskal-form input (section 3.3.2) and
+                the structured QR of the Khatri-Rao product of triangular
+                factors (section 3.3.3, eq. kr-id)
   costs      -- the flop model of section 3.2 (eq. QRcost, eq. TTMcost)
   precision  -- bit-level bfloat16 rounding and split-bfloat16 products, the
                 reduced-precision Multi-TTM forms the GPU offers
