@@ -35,4 +35,4 @@ invariants, closed forms), never to itself.  Functions without such a pin say
 "parity unpinned" in their docstring.
 """
 
-from . import tensor, cp_als_qr, cp_als, costs, precision, learned  # noqa: F401
+from . import tensor, cp_als_qr, cp_als, costs, precision, learned, kruskal  # noqa: F401
