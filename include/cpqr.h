@@ -33,7 +33,8 @@
  *    device int (`status`, may be NULL) as CPQR_STATUS_* bits.
  *
  * Limits: 2 <= N <= CPQR_MAX_MODES, 1 <= R <= CPQR_MAX_RANK, I[k] >= R for
- * every factor that is QR-factorized (its thin QR needs I[k] >= R).
+ * every mode of a sweep on a dense tensor (sweeps on a Kruskal-form input and
+ * cpqr_factor_qr accept smaller modes).
  */
 #ifndef CPQR_H
 #define CPQR_H
@@ -47,6 +48,7 @@ extern "C" {
 
 #define CPQR_MAX_MODES 10
 #define CPQR_MAX_RANK 32
+#define CPQR_MAX_KRUSKAL_TERMS 65536 /* terms S of a Kruskal-form input tensor */
 
 /* return codes */
 #define CPQR_OK 0
@@ -97,7 +99,11 @@ int cpqr_version(void);
  *   Q   : device, I x R, column-major, ldq >= I (written)
  *   Rk  : device, R x R upper triangular, column-major, ldr >= R (written,
  *         including the zeros below the diagonal)
- * Requires I >= R.  Signs of the diagonal of Rk are not normalized.
+ * Signs of the diagonal of Rk are not normalized.  I < R is allowed: the
+ * result is the QR of A padded with R - I zero rows, so Q's columns I..R-1
+ * and Rk's rows I..R-1 are zero (A = Q Rk still holds, and the nonzero
+ * columns of Q are orthonormal); a sweep on a Kruskal input uses this for
+ * modes smaller than the rank (the 10-way sine of sums, n = 8 < R = 10).
  */
 size_t cpqr_factor_qr_work(int64_t I, int R);
 int cpqr_factor_qr(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
@@ -184,6 +190,47 @@ size_t cpqr_expand_q0_work(int N, int R);
 int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_t work_bytes, void* stream);
 
 /*
+ * Kruskal-form input X = [[mu; V_1 .. V_N]] (section 3.3.2).  mu: device, S
+ * weights; V: host array of N device pointers to I[k] x S column-major FP64
+ * factors (leading dimension I[k]); 1 <= S <= CPQR_MAX_KRUSKAL_TERMS.
+ *
+ * cpqr_kruskal_w: W = Y_(n) Q_0 for Y = X x_{k != n} Q_k^T, without forming Y
+ * or Q_0: with B_k = Q_k^T V_k, W = V_n diag(mu) [(B_{a_{N-1}} (.) .. (.)
+ * B_{a_1})^T Q_0], the bracket taken term by term through eq. (kr-id) on the
+ * structured factors Qc of cpqr_krp_qr_chain (N >= 3): c_1 = B_{a_1}(:, s),
+ * c_j = Q_j^T (B_{a_j}(:, s) (x) c_{j-1}), row s of the bracket = c_{N-1}^T.
+ * Q: host array of device I[k] x R orthonormal factors (Q[n] not read);
+ * W: device I[n] x R column-major FP64.  (N I R S + (N-2) R^3 S + I_n R S
+ * multiply-adds.)
+ */
+size_t cpqr_kruskal_w_work(int N, int R, int S);
+int cpqr_kruskal_w(int N, int n, int R, const int64_t* I, int S, const double* mu, const double* const* V,
+                   const double* const* Q, const double* Qc, double* W, void* work, size_t work_bytes,
+                   void* stream);
+
+/* MTTKRP of a Kruskal input (section 3.3.2, Alg. 1): M = X_(n) Z_n =
+ * V_n diag(mu) (Hadamard product over k != n of V_k^T A_k); A: host array of
+ * device I[k] x R factors (A[n] not read); M: device I[n] x R FP64. */
+size_t cpqr_kruskal_mttkrp_work(int N, int R, int S);
+int cpqr_kruskal_mttkrp(int N, int n, int R, const int64_t* I, int S, const double* mu, const double* const* V,
+                        const double* const* A, double* M, void* work, size_t work_bytes, void* stream);
+
+/* ||X||^2 of a Kruskal input: mu^T (Hadamard product of V_k^T V_k) mu, into
+ * out[0] (device double); fixed-order sums. */
+size_t cpqr_kruskal_norm2_work(int S);
+int cpqr_kruskal_norm2(int N, const int64_t* I, int S, const double* mu, const double* const* V, double* out,
+                       void* work, size_t work_bytes, void* stream);
+
+/* The dense tensor of a Kruskal input (eq. cp): X column-major (mode 1
+ * fastest) in xdtype (CPQR_F64 or CPQR_F32, summed in FP64), as the product
+ * of the scaled Khatri-Rao rows of the leading modes and those of the
+ * trailing modes.  CPQR_ERR_SHAPE when the trailing modes hold more than
+ * 65535 x 64 entries. */
+size_t cpqr_kruskal_full_work(int N, const int64_t* I, int S);
+int cpqr_kruskal_full(int N, const int64_t* I, int S, const double* mu, const double* const* V, int xdtype,
+                      void* X, void* work, size_t work_bytes, void* stream);
+
+/*
  * W = Y_(n) Q_0 with Q_0 in the structured form of cpqr_krp_qr_chain: step
  * j = 2..N-1 contracts the two fastest column digits of the current
  * I_n x (R^2 x R^{N-1-j}) array with Q_j (the first of them is the result of
@@ -264,6 +311,18 @@ typedef struct cpqr_problem {
                                      from its factors) in place of the dense QR of the formed
                                      V_n: 1 on (N >= 3), 0 off, -1 the library picks (on for
                                      N >= 4 once V_n has more than 65536 rows) */
+  int xS;                         /* 0: the input is the dense tensor X.  S > 0: the input is
+                                     the Kruskal tensor [[xmu; xV[0], .., xV[N-1]]] of S terms
+                                     (section 3.3.2): both algorithms work on its factors (the
+                                     Multi-TTM and the MTTKRP are never formed densely; Alg. 2
+                                     takes Q_0 in the structured form of cpqr_krp_qr_chain,
+                                     whatever krp_chain says, and needs no R^{N-1} x R buffer),
+                                     prec and dimtree are not used, and X may be NULL; when
+                                     given (the same tensor, dense, e.g. from
+                                     cpqr_kruskal_full) it is read only by the direct error */
+  const double* xmu;              /* device, S weights of the Kruskal input (any sign) */
+  const double* xV[CPQR_MAX_MODES]; /* device I[k] x S column-major factors of the Kruskal input
+                                     (leading dimension I[k]) */
 } cpqr_problem;
 
 size_t cpqr_als_work(const cpqr_problem* p);

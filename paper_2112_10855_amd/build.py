@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "cpqr")
 LIB = os.path.join(HERE, "libcpqr.so")
-SOURCES = ["api.hip", "tsqr.hip", "multittm.hip", "small.hip", "batch.hip", "learned.hip"]
+SOURCES = ["api.hip", "tsqr.hip", "multittm.hip", "small.hip", "batch.hip", "learned.hip", "kruskal.hip"]
 ARCH = os.environ.get("CPQR_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -57,6 +57,7 @@ class Problem(ctypes.Structure):
         ("lam", _vp),
         ("prec", ctypes.c_int), ("use_svd", ctypes.c_int), ("rtol", ctypes.c_double),
         ("error_mode", ctypes.c_int), ("status", _vp), ("dimtree", ctypes.c_int), ("krp_chain", ctypes.c_int),
+        ("xS", ctypes.c_int), ("xmu", _vp), ("xV", _vp * MAX_MODES),
     ]
 
 
@@ -93,6 +94,19 @@ _SIGS = {
                                          _vp, _vp, _vp, _sz, _vp]),
     "cpqr_expand_q0_work": (_sz, [ctypes.c_int, ctypes.c_int]),
     "cpqr_expand_q0": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_kruskal_w_work": (_sz, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "cpqr_kruskal_w": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int,
+                                      _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_kruskal_mttkrp_work": (_sz, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "cpqr_kruskal_mttkrp": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64),
+                                           ctypes.c_int, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
+                                           _sz, _vp]),
+    "cpqr_kruskal_norm2_work": (_sz, [ctypes.c_int]),
+    "cpqr_kruskal_norm2": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp,
+                                          ctypes.POINTER(_vp), _vp, _vp, _sz, _vp]),
+    "cpqr_kruskal_full_work": (_sz, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int]),
+    "cpqr_kruskal_full": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp,
+                                         ctypes.POINTER(_vp), ctypes.c_int, _vp, _vp, _sz, _vp]),
     "cpqr_apply_q0_chain_work": (_sz, [_i64, ctypes.c_int, ctypes.c_int]),
     "cpqr_apply_q0_chain": (ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _sz,
                                            _vp]),
@@ -343,6 +357,66 @@ def cpqr_expand_q0(Qc, N):
     return Q0
 
 
+def _kruskal_args(mu, V):
+    _dev(mu, "mu")
+    if mu.dtype != torch.float64 or mu.dim() != 1:
+        raise ValueError("mu must be a 1-D FP64 tensor")
+    S = mu.shape[0]
+    for k, v in enumerate(V):
+        _dev(v, "V[%d]" % k)
+        _check_colmajor(v, "V[%d]" % k)
+        if v.dtype != torch.float64 or v.dim() != 2 or v.shape[1] != S:
+            raise ValueError("V[%d] must be an I_k x S FP64 matrix" % k)
+    return len(V), S, _i64_array([v.shape[0] for v in V])
+
+
+def cpqr_kruskal_w(mu, V, Qs, Qc, n):
+    """W = Y_(n) Q_0 for the Kruskal input [[mu; V]] and Y = X x_{k != n} Q_k^T,
+    with Q_0 given by cpqr_krp_qr_chain's factors."""
+    N, S, I = _kruskal_args(mu, V)
+    _dev(Qc, "Qc")
+    R = Qc.shape[2]
+    W = empty_colmajor((V[n].shape[0], R), torch.float64, mu.device)
+    nbytes = lib().cpqr_kruskal_w_work(N, R, S)
+    keep, w = _work(nbytes, mu.device)
+    _call("cpqr_kruskal_w", N, n, R, I, S, mu.data_ptr(), _ptr_array(V), _ptr_array(Qs), Qc.data_ptr(),
+          W.data_ptr(), w, nbytes, _stream())
+    return W
+
+
+def cpqr_kruskal_mttkrp(mu, V, As, n):
+    """M = X_(n) Z_n for the Kruskal input [[mu; V]] (As[n] not read)."""
+    N, S, I = _kruskal_args(mu, V)
+    R = next(a for a in As if a is not None).shape[1]
+    M = empty_colmajor((V[n].shape[0], R), torch.float64, mu.device)
+    nbytes = lib().cpqr_kruskal_mttkrp_work(N, R, S)
+    keep, w = _work(nbytes, mu.device)
+    _call("cpqr_kruskal_mttkrp", N, n, R, I, S, mu.data_ptr(), _ptr_array(V), _ptr_array(As), M.data_ptr(), w,
+          nbytes, _stream())
+    return M
+
+
+def cpqr_kruskal_norm2(mu, V):
+    """||[[mu; V]]||^2 as a one-element device tensor."""
+    N, S, I = _kruskal_args(mu, V)
+    out = torch.empty(1, dtype=torch.float64, device=mu.device)
+    nbytes = lib().cpqr_kruskal_norm2_work(S)
+    keep, w = _work(nbytes, mu.device)
+    _call("cpqr_kruskal_norm2", N, I, S, mu.data_ptr(), _ptr_array(V), out.data_ptr(), w, nbytes, _stream())
+    return out
+
+
+def cpqr_kruskal_full(mu, V, dtype=torch.float64):
+    """The dense tensor of [[mu; V]] (column-major) in FP64 or FP32."""
+    N, S, I = _kruskal_args(mu, V)
+    X = empty_colmajor(tuple(v.shape[0] for v in V), dtype, mu.device)
+    nbytes = lib().cpqr_kruskal_full_work(N, I, S)
+    keep, w = _work(nbytes, mu.device)
+    _call("cpqr_kruskal_full", N, I, S, mu.data_ptr(), _ptr_array(V), _dtype_code(X), X.data_ptr(), w, nbytes,
+          _stream())
+    return X
+
+
 def cpqr_apply_q0_chain(Y, Qc, N):
     """W = Y_(n) Q_0 with Q_0 given by cpqr_krp_qr_chain's factors."""
     _dev(Y, "Y")
@@ -402,35 +476,68 @@ def cpqr_fit_direct(X, lam, As):
     return out
 
 
+def _input_shape(X, kruskal):
+    """(shape, device) of the input: the dense X, or the Kruskal factors."""
+    if kruskal is not None:
+        mu, V = kruskal
+        _kruskal_args(mu, V)
+        shape = tuple(v.shape[0] for v in V)
+        if X is not None:
+            _dev(X, "X")
+            _check_colmajor(X, "X")
+            if tuple(X.shape) != shape:
+                raise ValueError("X and the Kruskal factors disagree on the shape")
+        return shape, mu.device
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    return tuple(X.shape), X.device
+
+
+def _set_input(p, X, kruskal):
+    """Fill the input fields of a Problem; returns what must stay alive."""
+    if X is not None:
+        p.xdtype = _dtype_code(X)
+        p.X = X.data_ptr()
+    if kruskal is None:
+        return None
+    mu, V = kruskal
+    p.xS = mu.shape[0]
+    p.xmu = mu.data_ptr()
+    for k, v in enumerate(V):
+        p.xV[k] = v.data_ptr()
+    return (mu, list(V))
+
+
 class AlsState:
     """Device buffers of one CP-ALS-QR problem, wired into ``cpqr_problem``."""
 
     def __init__(self, X, init, prec=PREC_F32, use_svd=False, rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1,
-                 krp_chain=-1):
-        _dev(X, "X")
-        _check_colmajor(X, "X")
+                 krp_chain=-1, kruskal=None):
+        """kruskal=(mu, V): the input is the Kruskal tensor [[mu; V]] (section
+        3.3.2); X is then optional, the same tensor in dense form, read only
+        by the direct error."""
+        shape, dev = _input_shape(X, kruskal)
         prec = PREC_NAMES.get(prec, prec)
-        dev = X.device
-        N = X.dim()
+        N = len(shape)
         R = init[1].shape[1]
         self.X, self.N, self.R = X, N, R
+        self.dev = dev
         self.A = [colmajor(torch.as_tensor(init[k], dtype=torch.float64).to(dev)) if k > 0 else
-                  empty_colmajor((X.shape[0], R), torch.float64, dev) for k in range(N)]
+                  empty_colmajor((shape[0], R), torch.float64, dev) for k in range(N)]
         if N > 0:
             self.A[0].zero_()
-        self.Q = [empty_colmajor((X.shape[k], R), torch.float64, dev) for k in range(N)]
+        self.Q = [empty_colmajor((shape[k], R), torch.float64, dev) for k in range(N)]
         self.Rf = [empty_colmajor((R, R), torch.float64, dev) for k in range(N)]
         self.lam = torch.ones(R, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         p = Problem()
         p.N, p.R = N, R
         for k in range(N):
-            p.I[k] = X.shape[k]
+            p.I[k] = shape[k]
             p.A[k] = self.A[k].data_ptr()
             p.Q[k] = self.Q[k].data_ptr()
             p.Rf[k] = self.Rf[k].data_ptr()
-        p.xdtype = _dtype_code(X)
-        p.X = X.data_ptr()
+        self.kruskal = _set_input(p, X, kruskal)
         p.lam = self.lam.data_ptr()
         p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(bool(use_svd)), float(rtol), error_mode
         p.dimtree = int(dimtree)
@@ -449,7 +556,7 @@ class AlsState:
     def sweep(self, nsweeps=1, relerr=None):
         """Run nsweeps sweeps; returns the device tensor of relative errors."""
         if relerr is None:
-            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.X.device)
+            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.dev)
         _call("cpqr_als_sweep", ctypes.byref(self.p), int(nsweeps), relerr.data_ptr(), self._w, self._wbytes,
               _stream())
         return relerr
@@ -464,11 +571,11 @@ def cpqr_als_sweep(state, nsweeps=1, relerr=None):
 
 
 def cp_als_qr(X, init, maxiters=25, tol=0.0, prec=PREC_F32, use_svd=False, rtol=-1.0,
-              error_mode=ERROR_EFFICIENT, dimtree=-1, krp_chain=-1):
+              error_mode=ERROR_EFFICIENT, dimtree=-1, krp_chain=-1, kruskal=None):
     """Alg. 2 driven from the host: sweeps until |relerr change| < tol or
     maxiters (reads the error back after each sweep only when tol > 0)."""
     st = AlsState(X, init, prec=prec, use_svd=use_svd, rtol=rtol, error_mode=error_mode, dimtree=dimtree,
-                  krp_chain=krp_chain)
+                  krp_chain=krp_chain, kruskal=kruskal)
     st.init()
     if tol <= 0:
         rel = st.sweep(maxiters)
@@ -486,26 +593,25 @@ class AlsNeState:
     pseudo-inverse), wired into ``cpqr_problem`` for cpqr_als_ne_*; every
     init[k] is the start of A_k (A_0 only through its Gram matrix)."""
 
-    def __init__(self, X, init, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1):
-        _dev(X, "X")
-        _check_colmajor(X, "X")
+    def __init__(self, X, init, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT, dimtree=-1,
+                 kruskal=None):
+        shape, dev = _input_shape(X, kruskal)
         if solver not in ("chol", "pinv"):
             raise ValueError("solver must be 'chol' or 'pinv'")
         prec = PREC_NAMES.get(prec, prec)
-        dev = X.device
-        N = X.dim()
+        N = len(shape)
         R = init[1].shape[1]
         self.X, self.N, self.R = X, N, R
+        self.dev = dev
         self.A = [colmajor(torch.as_tensor(init[k], dtype=torch.float64).to(dev)) for k in range(N)]
         self.lam = torch.ones(R, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         p = Problem()
         p.N, p.R = N, R
         for k in range(N):
-            p.I[k] = X.shape[k]
+            p.I[k] = shape[k]
             p.A[k] = self.A[k].data_ptr()
-        p.xdtype = _dtype_code(X)
-        p.X = X.data_ptr()
+        self.kruskal = _set_input(p, X, kruskal)
         p.lam = self.lam.data_ptr()
         p.prec, p.use_svd, p.rtol, p.error_mode = prec, int(solver == "pinv"), float(rtol), error_mode
         p.dimtree = int(dimtree)
@@ -523,17 +629,18 @@ class AlsNeState:
     def sweep(self, nsweeps=1, relerr=None):
         """Run nsweeps sweeps; returns the device tensor of relative errors."""
         if relerr is None:
-            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.X.device)
+            relerr = torch.empty(nsweeps, dtype=torch.float64, device=self.dev)
         _call("cpqr_als_ne_sweep", ctypes.byref(self.p), int(nsweeps), relerr.data_ptr(), self._w, self._wbytes,
               _stream())
         return relerr
 
 
 def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT,
-           dimtree=-1):
+           dimtree=-1, kruskal=None):
     """Alg. 1 (CP-ALS, or CP-ALS-PINV with solver='pinv') driven from the
     host, with the same stopping rule as cp_als_qr."""
-    st = AlsNeState(X, init, prec=prec, solver=solver, rtol=rtol, error_mode=error_mode, dimtree=dimtree)
+    st = AlsNeState(X, init, prec=prec, solver=solver, rtol=rtol, error_mode=error_mode, dimtree=dimtree,
+                    kruskal=kruskal)
     st.init()
     if tol <= 0:
         rel = st.sweep(maxiters)
@@ -546,7 +653,7 @@ def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.
     return st, hist
 
 
-def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIENT, dimtree=-1):
+def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIENT, dimtree=-1, kruskal=None):
     """The robust solver the paper envisions (section 1, section 5): CP-ALS
     with the normal equations while they are well conditioned, then CP-ALS-QR.
     The status word is read after every sweep.
@@ -561,7 +668,7 @@ def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIEN
       (section 3.1), which is what a breakdown signals.
 
     Returns (state, history, number of normal-equations sweeps kept)."""
-    st = AlsNeState(X, init, prec=prec, solver="chol", error_mode=error_mode, dimtree=dimtree)
+    st = AlsNeState(X, init, prec=prec, solver="chol", error_mode=error_mode, dimtree=dimtree, kruskal=kruskal)
     st.init()
     hist = []
     start, use_svd = None, False
@@ -579,7 +686,7 @@ def cp_als_hybrid(X, init, maxiters=25, prec=PREC_F32, error_mode=ERROR_EFFICIEN
     n_ne = len(hist)
     if start is None:
         return st, hist, n_ne
-    qst = AlsState(X, start, prec=prec, use_svd=use_svd, error_mode=error_mode, dimtree=dimtree)
+    qst = AlsState(X, start, prec=prec, use_svd=use_svd, error_mode=error_mode, dimtree=dimtree, kruskal=kruskal)
     qst.init()
     hist += qst.sweep(maxiters - n_ne).cpu().tolist()
     return qst, hist, n_ne

@@ -432,10 +432,31 @@ int side_stream(SideStream& out) {
   return CPQR_OK;
 }
 
+bool kruskal_input(const cpqr_problem* p) { return p->xS > 0; }
+
 int check_problem(const cpqr_problem* p, bool need_qr = true) {
   if (!p) return fail(CPQR_ERR_ARG, "problem is NULL");
   CPQR_TRY(check_modes(p->N, p->I));
   CPQR_TRY(check_rank(p->R));
+  if (p->xS < 0 || p->xS > CPQR_MAX_KRUSKAL_TERMS)
+    return fail(CPQR_ERR_SHAPE, "xS must be in [0, " + std::to_string(CPQR_MAX_KRUSKAL_TERMS) + "]");
+  if (kruskal_input(p)) {
+    if (!p->xmu) return fail(CPQR_ERR_ARG, "Kruskal input: xmu is NULL");
+    for (int k = 0; k < p->N; ++k)
+      if (!p->xV[k]) return fail(CPQR_ERR_ARG, "Kruskal input: xV[" + std::to_string(k) + "] is NULL");
+    if (p->error_mode == CPQR_ERROR_DIRECT && !p->X)
+      return fail(CPQR_ERR_ARG, "the direct error of a Kruskal input needs its dense tensor X");
+    if (p->X && !valid_dtype(p->xdtype)) return fail(CPQR_ERR_DTYPE, "xdtype must be CPQR_F32 or CPQR_F64");
+    if (p->error_mode < CPQR_ERROR_EFFICIENT || p->error_mode > CPQR_ERROR_NONE)
+      return fail(CPQR_ERR_ARG, "unknown error_mode");
+    if (!p->lambda) return fail(CPQR_ERR_ARG, "lambda is NULL");
+    // modes smaller than the rank are allowed here: their factor QR is that of
+    // the factor padded with zero rows (cpqr_factor_qr)
+    for (int k = 0; k < p->N; ++k)
+      if (!p->A[k] || (need_qr && (!p->Q[k] || !p->Rf[k])))
+        return fail(CPQR_ERR_ARG, "A/Q/Rf pointer of mode " + std::to_string(k) + " is NULL");
+    return CPQR_OK;
+  }
   CPQR_TRY(check_krp_rows(p->N, p->R));
   if (!valid_dtype(p->xdtype)) return fail(CPQR_ERR_DTYPE, "xdtype must be CPQR_F32 or CPQR_F64");
   if (!valid_prec(p->prec)) return fail(CPQR_ERR_ARG, "unknown precision");
@@ -510,7 +531,7 @@ size_t cpqr_factor_qr_work(int64_t I, int R) {
 int cpqr_factor_qr(int64_t I, int R, const double* A, int64_t lda, double* Q, int64_t ldq,
                    double* Rk, int64_t ldr, void* work, size_t work_bytes, void* stream) {
   CPQR_TRY(check_rank(R));
-  if (I < R) return fail(CPQR_ERR_SHAPE, "factor_qr needs I >= R");
+  if (I < 1) return fail(CPQR_ERR_SHAPE, "factor_qr needs I >= 1");
   if (!A || !Q || !Rk) return fail(CPQR_ERR_ARG, "factor_qr: NULL pointer");
   if (lda < I || ldq < I || ldr < R) return fail(CPQR_ERR_SHAPE, "factor_qr: leading dimension too small");
   CPQR_TRY(check_work(work, work_bytes, tsqr_work(I, R)));
@@ -596,6 +617,115 @@ int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_
   return expand_q0_enqueue(N, R, Qc, Q0, static_cast<double*>(work), as_stream(stream));
 }
 
+int check_kruskal(int N, const int64_t* I, int S, const double* mu, const double* const* V) {
+  CPQR_TRY(check_modes(N, I));
+  if (S < 1 || S > CPQR_MAX_KRUSKAL_TERMS)
+    return fail(CPQR_ERR_SHAPE, "S must be in [1, " + std::to_string(CPQR_MAX_KRUSKAL_TERMS) + "]");
+  if (!mu || !V) return fail(CPQR_ERR_ARG, "Kruskal input: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (!V[k]) return fail(CPQR_ERR_ARG, "Kruskal input: V[" + std::to_string(k) + "] is NULL");
+  return CPQR_OK;
+}
+
+size_t cpqr_kruskal_w_work(int N, int R, int S) {
+  if (N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK || S < 1 || S > CPQR_MAX_KRUSKAL_TERMS) return 0;
+  Carver cv(nullptr);
+  cv.take<double>(size_t(N) * R * S);
+  cv.take<double>(size_t(S) * R);
+  return cv.bytes();
+}
+
+int cpqr_kruskal_w(int N, int n, int R, const int64_t* I, int S, const double* mu, const double* const* V,
+                   const double* const* Q, const double* Qc, double* W, void* work, size_t work_bytes,
+                   void* stream) {
+  CPQR_TRY(check_kruskal(N, I, S, mu, V));
+  if (N < 3) return fail(CPQR_ERR_SHAPE, "kruskal_w: N must be at least 3 (Q_0 in structured form)");
+  CPQR_TRY(check_rank(R));
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "kruskal_w: n out of range");
+  if (!Q || !Qc || !W) return fail(CPQR_ERR_ARG, "kruskal_w: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Q[k]) return fail(CPQR_ERR_ARG, "kruskal_w: Q[" + std::to_string(k) + "] is NULL");
+  CPQR_TRY(check_work(work, work_bytes, cpqr_kruskal_w_work(N, R, S)));
+  hipStream_t s = as_stream(stream);
+  Carver cv(work);
+  double* P = cv.take<double>(size_t(N) * R * S);
+  double* M = cv.take<double>(size_t(S) * R);
+  const double* Pa[CPQR_MAX_MODES];
+  int na = 0;
+  for (int k = 0; k < N; ++k) {
+    if (k == n) continue;
+    double* Pk = P + size_t(k) * R * S;
+    CPQR_TRY(kr_cross_enqueue(I[k], R, S, Q[k], I[k], V[k], I[k], Pk, s));
+    Pa[na++] = Pk;
+  }
+  CPQR_TRY(kr_chain_enqueue(na, Pa, Qc, R, S, M, s));
+  return kr_w_enqueue(I[n], S, R, V[n], I[n], mu, M, W, s);
+}
+
+size_t cpqr_kruskal_mttkrp_work(int N, int R, int S) {
+  if (N < 2 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK || S < 1 || S > CPQR_MAX_KRUSKAL_TERMS) return 0;
+  Carver cv(nullptr);
+  cv.take<double>(size_t(N) * R * S);
+  cv.take<double>(size_t(S) * R);
+  return cv.bytes();
+}
+
+int cpqr_kruskal_mttkrp(int N, int n, int R, const int64_t* I, int S, const double* mu, const double* const* V,
+                        const double* const* A, double* M, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_kruskal(N, I, S, mu, V));
+  CPQR_TRY(check_rank(R));
+  if (n < 0 || n >= N) return fail(CPQR_ERR_ARG, "kruskal_mttkrp: n out of range");
+  if (!A || !M) return fail(CPQR_ERR_ARG, "kruskal_mttkrp: NULL pointer");
+  for (int k = 0; k < N; ++k)
+    if (k != n && !A[k]) return fail(CPQR_ERR_ARG, "kruskal_mttkrp: A[" + std::to_string(k) + "] is NULL");
+  CPQR_TRY(check_work(work, work_bytes, cpqr_kruskal_mttkrp_work(N, R, S)));
+  hipStream_t s = as_stream(stream);
+  Carver cv(work);
+  double* P = cv.take<double>(size_t(N) * R * S);
+  double* H = cv.take<double>(size_t(S) * R);
+  const double* Pa[CPQR_MAX_MODES];
+  int na = 0;
+  for (int k = 0; k < N; ++k) {
+    if (k == n) continue;
+    double* Pk = P + size_t(k) * R * S;
+    CPQR_TRY(kr_cross_enqueue(I[k], R, S, A[k], I[k], V[k], I[k], Pk, s));
+    Pa[na++] = Pk;
+  }
+  CPQR_TRY(kr_hadamard_enqueue(na, Pa, R, S, H, s));
+  return kr_w_enqueue(I[n], S, R, V[n], I[n], mu, H, M, s);
+}
+
+size_t cpqr_kruskal_norm2_work(int S) {
+  if (S < 1 || S > CPQR_MAX_KRUSKAL_TERMS) return 0;
+  return kr_norm2_work(S);
+}
+
+int cpqr_kruskal_norm2(int N, const int64_t* I, int S, const double* mu, const double* const* V, double* out,
+                       void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_kruskal(N, I, S, mu, V));
+  if (!out) return fail(CPQR_ERR_ARG, "kruskal_norm2: out is NULL");
+  CPQR_TRY(check_work(work, work_bytes, kr_norm2_work(S)));
+  return kr_norm2_enqueue(N, I, S, mu, V, out, work, as_stream(stream));
+}
+
+size_t cpqr_kruskal_full_work(int N, const int64_t* I, int S) {
+  if (!I || N < 2 || N > CPQR_MAX_MODES || S < 1 || S > CPQR_MAX_KRUSKAL_TERMS) return 0;
+  for (int k = 0; k < N; ++k)
+    if (I[k] < 1) return 0;
+  return kr_full_work(N, I, S);
+}
+
+int cpqr_kruskal_full(int N, const int64_t* I, int S, const double* mu, const double* const* V, int xdtype,
+                      void* X, void* work, size_t work_bytes, void* stream) {
+  CPQR_TRY(check_kruskal(N, I, S, mu, V));
+  if (!valid_dtype(xdtype)) return fail(CPQR_ERR_DTYPE, "kruskal_full: xdtype must be CPQR_F32 or CPQR_F64");
+  if (!X) return fail(CPQR_ERR_ARG, "kruskal_full: X is NULL");
+  if (kr_full_grid_y(N, I) > 65535)
+    return fail(CPQR_ERR_SHAPE, "kruskal_full: the trailing modes hold more than 65535 x 64 entries");
+  CPQR_TRY(check_work(work, work_bytes, kr_full_work(N, I, S)));
+  return kr_full_enqueue(N, I, S, mu, V, xdtype, X, work, as_stream(stream));
+}
+
 size_t cpqr_apply_q0_chain_work(int64_t In, int N, int R) {
   if (In < 1 || N < 3 || N > CPQR_MAX_MODES || R < 1 || R > CPQR_MAX_RANK) return 0;
   return apply_chain_work(In, N, R);
@@ -661,14 +791,184 @@ int cpqr_fit_direct(int N, const int64_t* I, int xdtype, const void* X, int R, c
   return fit_direct_enqueue(N, I, xdtype, X, R, lambda, A, out, work, as_stream(stream));
 }
 
+// ------------------------------------------------------------ Kruskal input
+// Section 3.3.2: the sweeps of both algorithms on X = [[xmu; xV]] work on its
+// factors.  P holds, per mode k, the R x S cross products with the factor
+// the method contracts X with (Q_k^T V_k for Alg. 2, A_k^T V_k for Alg. 1);
+// only P_n changes when mode n is updated.  Everything runs on the caller's
+// stream (every step is small).
+struct KrWs {
+  double* xnorm2;
+  double* G;  // Alg. 1: N blocks of R x R
+  double* Sm;
+  double* F;
+  double* P;  // N blocks of R x S
+  double* M;  // S x R: the chain's rows (Alg. 2) or the Hadamard product (Alg. 1)
+  double* W;  // Imax x R: W_n (Alg. 2) or M_n (Alg. 1)
+  double* Mn;  // Alg. 1: the MTTKRP as kept by the update (for the error)
+  double* Qc;
+  double* R0;
+  double* fit;
+  double* relerr_tmp;
+  void* sub;
+  double* err_part;
+};
+
+size_t kr_carve(Carver& cv, const cpqr_problem* p, bool ne, KrWs* ws) {
+  const int N = p->N, R = p->R, S = p->xS;
+  int64_t imax = 0;
+  for (int k = 0; k < N; ++k) imax = std::max(imax, p->I[k]);
+  KrWs w{};
+  w.xnorm2 = cv.take<double>(1);
+  w.G = cv.take<double>(ne ? size_t(N) * R * R : 0);
+  w.Sm = cv.take<double>(ne ? size_t(R) * R : 0);
+  w.F = cv.take<double>(ne ? size_t(R) * R : 0);
+  w.P = cv.take<double>(size_t(N) * R * S);
+  w.M = cv.take<double>(size_t(S) * R);
+  w.W = cv.take<double>(size_t(imax) * R);
+  w.Mn = cv.take<double>(ne ? size_t(imax) * R : 0);
+  w.Qc = cv.take<double>(ne ? 0 : size_t(std::max(N - 2, 0)) * R * R * R);
+  w.R0 = cv.take<double>(ne ? 0 : size_t(R) * R);
+  w.fit = cv.take<double>(2);
+  w.relerr_tmp = cv.take<double>(1);
+  size_t sub = std::max(kr_norm2_work(S), ne ? ne_update_work(R) : krp_chain_work(R));
+  for (int k = 0; k < N; ++k) {
+    if (!ne) sub = std::max(sub, std::max(tsqr_work(p->I[k], R), solve_work(p->I[k], R)));
+  }
+  if (p->X) sub = std::max(sub, fit_direct_work(N, p->I, R));
+  w.sub = cv.take<char>(sub);
+  w.err_part = cv.take<double>(std::max(error_efficient_work(p->I[N - 1]), ne_error_work(p->I[N - 1])) /
+                               sizeof(double));
+  if (ws) *ws = w;
+  return cv.bytes();
+}
+
+int kr_error_direct(const cpqr_problem* p, KrWs& w, double* out, hipStream_t s) {
+  const double* Ap[CPQR_MAX_MODES];
+  for (int k = 0; k < p->N; ++k) Ap[k] = p->A[k];
+  CPQR_TRY(fit_direct_enqueue(p->N, p->I, p->xdtype, p->X, p->R, p->lambda, Ap, w.fit, w.sub, s));
+  return error_from_fit_enqueue(w.fit, out, s);
+}
+
+int kr_als_init(const cpqr_problem* p, void* work, hipStream_t s) {
+  KrWs w;
+  Carver c2(work);
+  kr_carve(c2, p, false, &w);
+  const int N = p->N, R = p->R;
+  for (int k = 1; k < N; ++k)
+    CPQR_TRY(factor_qr_enqueue(p->I[k], R, p->A[k], p->I[k], p->Q[k], p->I[k], p->Rf[k], R, w.sub, s));
+  CPQR_TRY(fill_enqueue(p->lambda, R, 1.0, s));
+  return kr_norm2_enqueue(N, p->I, p->xS, p->xmu, p->xV, w.xnorm2, w.sub, s);
+}
+
+int kr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, hipStream_t s) {
+  KrWs w;
+  Carver c2(work);
+  kr_carve(c2, p, false, &w);
+  const int N = p->N, R = p->R, S = p->xS;
+  auto Pk = [&](int k) { return w.P + size_t(k) * R * S; };
+  for (int k = 1; k < N; ++k)
+    CPQR_TRY(kr_cross_enqueue(p->I[k], R, S, p->Q[k], p->I[k], p->xV[k], p->I[k], Pk(k), s));
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int n = 0; n < N; ++n) {
+      const double* Pa[CPQR_MAX_MODES];
+      int na = 0;
+      for (int k = 0; k < N; ++k)
+        if (k != n) Pa[na++] = Pk(k);
+      {
+        PhaseTimer pt(PH_Q0, s);
+        if (N >= 3) {
+          CPQR_TRY(krp_chain_enqueue(N, n, R, p->Rf, R, w.Qc, w.R0, w.sub, s));
+        } else {  // V_n = R_{a_1} is already triangular: Q_0 = I, R_0 = R_{a_1}
+          CPQR_HIP(hipMemcpyAsync(w.R0, p->Rf[1 - n], sizeof(double) * R * R, hipMemcpyDeviceToDevice, s));
+        }
+      }
+      {
+        PhaseTimer pt(PH_APPLY_Q0, s);
+        CPQR_TRY(kr_chain_enqueue(na, Pa, w.Qc, R, S, w.M, s));
+        CPQR_TRY(kr_w_enqueue(p->I[n], S, R, p->xV[n], p->I[n], p->xmu, w.M, w.W, s));
+      }
+      CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda, p->status, w.sub,
+                             s));
+      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s));
+      CPQR_TRY(kr_cross_enqueue(p->I[n], R, S, p->Q[n], p->I[n], p->xV[n], p->I[n], Pk(n), s));
+    }
+    double* out = relerr ? relerr + sw : w.relerr_tmp;
+    if (p->error_mode == CPQR_ERROR_EFFICIENT) {
+      CPQR_TRY(error_efficient_enqueue(p->I[N - 1], R, w.W, p->A[N - 1], p->lambda, w.R0, p->Rf[N - 1], w.xnorm2,
+                                       out, w.err_part, s));
+    } else if (p->error_mode == CPQR_ERROR_DIRECT) {
+      CPQR_TRY(kr_error_direct(p, w, out, s));
+    } else {
+      CPQR_TRY(fill_enqueue(out, 1, std::nan(""), s));
+    }
+  }
+  return CPQR_OK;
+}
+
+int kr_ne_init(const cpqr_problem* p, void* work, hipStream_t s) {
+  KrWs w;
+  Carver c2(work);
+  kr_carve(c2, p, true, &w);
+  const int N = p->N, R = p->R;
+  for (int k = 0; k < N; ++k) CPQR_TRY(gram_enqueue(p->I[k], R, p->A[k], w.G + int64_t(k) * R * R, s));
+  CPQR_TRY(fill_enqueue(p->lambda, R, 1.0, s));
+  return kr_norm2_enqueue(N, p->I, p->xS, p->xmu, p->xV, w.xnorm2, w.sub, s);
+}
+
+int kr_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work, hipStream_t s) {
+  KrWs w;
+  Carver c2(work);
+  kr_carve(c2, p, true, &w);
+  const int N = p->N, R = p->R, S = p->xS;
+  auto Pk = [&](int k) { return w.P + size_t(k) * R * S; };
+  for (int k = 0; k < N; ++k)
+    CPQR_TRY(kr_cross_enqueue(p->I[k], R, S, p->A[k], p->I[k], p->xV[k], p->I[k], Pk(k), s));
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int n = 0; n < N; ++n) {
+      const double* Pa[CPQR_MAX_MODES];
+      int na = 0;
+      for (int k = 0; k < N; ++k)
+        if (k != n) Pa[na++] = Pk(k);
+      {
+        PhaseTimer pt(PH_MULTITTM, s);
+        CPQR_TRY(kr_hadamard_enqueue(na, Pa, R, S, w.M, s));
+        CPQR_TRY(kr_w_enqueue(p->I[n], S, R, p->xV[n], p->I[n], p->xmu, w.M, w.W, s));
+      }
+      CPQR_TRY(ne_update_from_m_enqueue(p->I[n], N, n, R, w.W, w.G, p->use_svd, p->rtol, w.Sm, w.F, w.Mn, p->A[n],
+                                        p->lambda, p->status, w.sub, s));
+      CPQR_TRY(kr_cross_enqueue(p->I[n], R, S, p->A[n], p->I[n], p->xV[n], p->I[n], Pk(n), s));
+    }
+    double* out = relerr ? relerr + sw : w.relerr_tmp;
+    if (p->error_mode == CPQR_ERROR_EFFICIENT) {
+      CPQR_TRY(ne_error_enqueue(p->I[N - 1], R, w.Mn, p->A[N - 1], p->lambda, w.Sm, w.G + int64_t(N - 1) * R * R,
+                                w.xnorm2, out, w.err_part, s));
+    } else if (p->error_mode == CPQR_ERROR_DIRECT) {
+      CPQR_TRY(kr_error_direct(p, w, out, s));
+    } else {
+      CPQR_TRY(fill_enqueue(out, 1, std::nan(""), s));
+    }
+  }
+  return CPQR_OK;
+}
+
 size_t cpqr_als_work(const cpqr_problem* p) {
   if (check_problem(p) != CPQR_OK) return 0;
+  if (kruskal_input(p)) {
+    Carver cv(nullptr);
+    return kr_carve(cv, p, false, nullptr);
+  }
   Carver cv(nullptr);
   return als_carve(cv, p, nullptr);
 }
 
 int cpqr_als_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream) {
   CPQR_TRY(check_problem(p));
+  if (kruskal_input(p)) {
+    Carver cv(nullptr);
+    CPQR_TRY(check_work(work, work_bytes, kr_carve(cv, p, false, nullptr)));
+    return kr_als_init(p, work, as_stream(stream));
+  }
   Carver cv(nullptr);
   CPQR_TRY(check_work(work, work_bytes, als_carve(cv, p, nullptr)));
   AlsWs w;
@@ -688,6 +988,11 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
                    void* stream) {
   CPQR_TRY(check_problem(p));
   if (nsweeps < 0) return fail(CPQR_ERR_ARG, "nsweeps < 0");
+  if (kruskal_input(p)) {
+    Carver cv(nullptr);
+    CPQR_TRY(check_work(work, work_bytes, kr_carve(cv, p, false, nullptr)));
+    return kr_als_sweep(p, nsweeps, relerr, work, as_stream(stream));
+  }
   Carver cv(nullptr);
   CPQR_TRY(check_work(work, work_bytes, als_carve(cv, p, nullptr)));
   AlsWs w;
@@ -751,11 +1056,16 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
 size_t cpqr_als_ne_work(const cpqr_problem* p) {
   if (check_problem(p, false) != CPQR_OK) return 0;
   Carver cv(nullptr);
-  return ne_carve(cv, p, nullptr);
+  return kruskal_input(p) ? kr_carve(cv, p, true, nullptr) : ne_carve(cv, p, nullptr);
 }
 
 int cpqr_als_ne_init(const cpqr_problem* p, void* work, size_t work_bytes, void* stream) {
   CPQR_TRY(check_problem(p, false));
+  if (kruskal_input(p)) {
+    Carver cv(nullptr);
+    CPQR_TRY(check_work(work, work_bytes, kr_carve(cv, p, true, nullptr)));
+    return kr_ne_init(p, work, as_stream(stream));
+  }
   Carver cv(nullptr);
   CPQR_TRY(check_work(work, work_bytes, ne_carve(cv, p, nullptr)));
   NeWs w;
@@ -774,6 +1084,11 @@ int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* 
                       void* stream) {
   CPQR_TRY(check_problem(p, false));
   if (nsweeps < 0) return fail(CPQR_ERR_ARG, "nsweeps < 0");
+  if (kruskal_input(p)) {
+    Carver cv(nullptr);
+    CPQR_TRY(check_work(work, work_bytes, kr_carve(cv, p, true, nullptr)));
+    return kr_ne_sweep(p, nsweeps, relerr, work, as_stream(stream));
+  }
   Carver cv(nullptr);
   CPQR_TRY(check_work(work, work_bytes, ne_carve(cv, p, nullptr)));
   NeWs w;

@@ -151,4 +151,29 @@ size_t ne_error_work(int64_t In);
 int ne_error_enqueue(int64_t In, int R, const double* M, const double* A, const double* lambda, const double* S,
                      const double* GN, const double* xnorm2, double* relerr, double* part, hipStream_t s);
 
+// kruskal.hip: Kruskal-form input (section 3.3.2)
+// P = U^T V (R x S) for U: I x R (ldu), V: I x S (ldv)
+int kr_cross_enqueue(int64_t I, int R, int S, const double* U, int64_t ldu, const double* V, int64_t ldv,
+                     double* P, hipStream_t s);
+// M (S x R) = rows c_{nP-1}(s)^T of the chain c_1 = P[0](:, s),
+// c_j = Q_j^T (P[j-1](:, s) (x) c_{j-1}); Qc as written by krp_chain_enqueue
+int kr_chain_enqueue(int nP, const double* const* P, const double* Qc, int R, int S, double* M, hipStream_t s);
+// H (S x R) = Hadamard product of the P's (each R x S), transposed
+int kr_hadamard_enqueue(int nP, const double* const* P, int R, int S, double* H, hipStream_t s);
+// W (I x R) = V diag(mu) M, V: I x S (ldv), M: S x R
+int kr_w_enqueue(int64_t I, int S, int R, const double* V, int64_t ldv, const double* mu, const double* M,
+                 double* W, hipStream_t s);
+size_t kr_norm2_work(int S);
+int kr_norm2_enqueue(int N, const int64_t* I, int S, const double* mu, const double* const* V, double* out,
+                     void* work, hipStream_t s);
+size_t kr_full_work(int N, const int64_t* I, int S);
+// grid rows of the dense product (must stay <= 65535 for a launch)
+int64_t kr_full_grid_y(int N, const int64_t* I);
+int kr_full_enqueue(int N, const int64_t* I, int S, const double* mu, const double* const* V, int xdtype,
+                    void* X, void* work, hipStream_t s);
+// Alg. 1 update from a formed MTTKRP Mn (In x R, FP64)
+int ne_update_from_m_enqueue(int64_t In, int N, int n, int R, const double* Mn, double* G, int pinv, double rtol,
+                             double* S, double* F, double* M, double* A, double* lambda, int* status, void* work,
+                             hipStream_t s);
+
 }  // namespace cpqr

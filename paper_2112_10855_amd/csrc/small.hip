@@ -1052,9 +1052,11 @@ size_t ne_update_work(int R) {
   return cv.bytes();
 }
 
-int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y, double* G, int pinv,
-                      double rtol, double* S, double* F, double* M, double* A, double* lambda, int* status,
-                      void* work, hipStream_t s) {
+namespace {
+// The MTTKRP is column dstep * c of Y (dstep = 1 for a formed In x R matrix).
+int ne_update_core(int64_t In, int N, int n, int R, int ydtype, const void* Y, int64_t dstep, double* G, int pinv,
+                   double rtol, double* S, double* F, double* M, double* A, double* lambda, int* status,
+                   void* work, hipStream_t s) {
   PhaseTimer pt(PH_SOLVE, s);
   Carver cv(work);
   int* kept = cv.take<int>(4);
@@ -1064,11 +1066,6 @@ int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y
     if (rtol < 0) rtol = R * 2.220446049250313e-16;
     // S_n is symmetric, so the transposed pseudo-inverse the kernel forms is pinv(S_n) itself
     CPQR_TRY(launch_svd_pinv(S, R, rtol, F, kept, status, s));
-  }
-  int64_t dstep = 0, pw = 1;
-  for (int k = 0; k + 1 < N; ++k) {
-    dstep += pw;
-    pw *= R;
   }
   const dim3 grd(unsigned(ceil_div(In, BLK)));
   const int RM = round_rank(R);
@@ -1085,6 +1082,26 @@ int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y
   hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
   CPQR_TRY(check_launch("normalize"));
   return gram_enqueue(In, R, A, G + int64_t(n) * R * R, s);
+}
+}  // namespace
+
+int ne_update_enqueue(int64_t In, int N, int n, int R, int ydtype, const void* Y, double* G, int pinv,
+                      double rtol, double* S, double* F, double* M, double* A, double* lambda, int* status,
+                      void* work, hipStream_t s) {
+  // column r of M_n is the column of Y_(n) whose every Kronecker index is r:
+  // r (1 + R + .. + R^{N-2})
+  int64_t dstep = 0, pw = 1;
+  for (int k = 0; k + 1 < N; ++k) {
+    dstep += pw;
+    pw *= R;
+  }
+  return ne_update_core(In, N, n, R, ydtype, Y, dstep, G, pinv, rtol, S, F, M, A, lambda, status, work, s);
+}
+
+int ne_update_from_m_enqueue(int64_t In, int N, int n, int R, const double* Mn, double* G, int pinv, double rtol,
+                             double* S, double* F, double* M, double* A, double* lambda, int* status, void* work,
+                             hipStream_t s) {
+  return ne_update_core(In, N, n, R, CPQR_F64, Mn, 1, G, pinv, rtol, S, F, M, A, lambda, status, work, s);
 }
 
 size_t ne_error_work(int64_t In) { return size_t(ceil_div(In, BLK)) * sizeof(double); }

@@ -83,7 +83,10 @@ def multittm_tol_lowp(shape, n, mode):
 
 def kruskal_distance(l1, A1, l2, A2):
     """||[[l1; A1]] - [[l2; A2]]|| / ||[[l2; A2]]|| through Gram matrices:
-    <[[a]], [[b]]> = a^T (Hadamard product of A_k^T B_k) b."""
+    <[[a]], [[b]]> = a^T (Hadamard product of A_k^T B_k) b.  The squared
+    distance is a difference of terms of size ||[[l2; A2]]||^2, so distances
+    below about 1e-8 (the square root of the FP64 spacing) are not resolved;
+    compare dense models or the factors themselves below that."""
     def ip(la, A, lb, B):
         H = np.ones((len(la), len(lb)))
         for a, b in zip(A, B):

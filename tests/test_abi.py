@@ -47,7 +47,7 @@ def test_validation_codes(L):
     P = 4096  # fake, never dereferenced: validation fails first
     assert L.cpqr_factor_qr(10, 0, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
     assert L.cpqr_factor_qr(10, 33, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
-    assert L.cpqr_factor_qr(3, 4, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
+    assert L.cpqr_factor_qr(0, 4, P, 10, P, 10, P, 10, P, 1 << 20, None) == -2
     assert L.cpqr_factor_qr(10, 4, None, 10, P, 10, P, 10, P, 1 << 20, None) == -1
     assert L.cpqr_factor_qr(10, 4, P, 9, P, 10, P, 10, P, 1 << 20, None) == -2
     # 5000 rows take a two-level tree, which needs a work buffer
@@ -200,3 +200,39 @@ def test_validation_batch_learned_dimtree(L):
     assert L.cpqr_adam(10, P, P, P, P, None, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     assert L.cpqr_to_bf16(None, 10, P, None) == -1
     assert L.cpqr_to_bf16(P, 0, P, None) == 0
+
+
+def test_kruskal_validation_codes(L):
+    """Kruskal-input entries (section 3.3.2): argument errors are caught
+    before anything is enqueued."""
+    P = 4096
+    I = (C._i64 * 3)(5, 6, 7)
+    V = (C._vp * 3)(P, P, P)
+    Vnull = (C._vp * 3)(P, None, P)
+    assert L.cpqr_kruskal_w_work(2, 4, 5) == 0
+    assert L.cpqr_kruskal_w_work(3, 4, 5) > 0
+    assert L.cpqr_kruskal_w(2, 0, 4, I, 5, P, V, V, P, P, P, 1 << 20, None) == -2
+    assert L.cpqr_kruskal_w(3, 0, 4, I, 0, P, V, V, P, P, P, 1 << 20, None) == -2
+    assert L.cpqr_kruskal_w(3, 0, 4, I, 5, None, V, V, P, P, P, 1 << 20, None) == -1
+    assert L.cpqr_kruskal_w(3, 3, 4, I, 5, P, V, V, P, P, P, 1 << 20, None) == -1
+    assert L.cpqr_kruskal_w(3, 0, 4, I, 5, P, Vnull, V, P, P, P, 1 << 20, None) == -1
+    assert L.cpqr_kruskal_w(3, 0, 4, I, 5, P, V, V, P, P, None, 0, None) == -4
+    assert L.cpqr_kruskal_mttkrp(3, 0, 33, I, 5, P, V, V, P, P, 1 << 20, None) == -2
+    assert L.cpqr_kruskal_norm2(3, I, 5, P, V, None, P, 1 << 20, None) == -1
+    assert L.cpqr_kruskal_full(3, I, 5, P, V, 7, P, P, 1 << 20, None) == -3
+    big = (C._i64 * 2)(2, 5000000)
+    assert L.cpqr_kruskal_full(2, big, 5, P, V, C.F64, P, P, 1 << 40, None) == -2
+    p = C.Problem()
+    p.N, p.R = 3, 4
+    for k in range(3):
+        p.I[k] = (5, 6, 7)[k]
+        p.A[k] = p.Q[k] = p.Rf[k] = P
+    p.lam = P
+    p.xS = -1
+    assert L.cpqr_als_work(ctypes.byref(p)) == 0
+    p.xS, p.xmu = 5, P
+    for k in range(3):
+        p.xV[k] = P
+    assert L.cpqr_als_work(ctypes.byref(p)) > 0  # no dense X needed
+    p.error_mode = C.ERROR_DIRECT
+    assert L.cpqr_als_work(ctypes.byref(p)) == 0  # the direct error needs X
