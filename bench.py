@@ -91,7 +91,8 @@ def run_sinsum(args):
     """Sine of sums (section 4.3): the four ALS algorithms fit the rank-N form
     of sin(x_1 + ... + x_N) on the paper's lower-order grids (N = 4, n = 64
     and 128; N = 5, n = 32 and 64), 40 sweeps from one shared random start,
-    FP64, relative error taken directly after every sweep."""
+    FP64, relative error taken directly after every sweep; then the 10-way
+    case at n = 8 on the Kruskal-form input from five starts."""
     import torch
 
     from paper_2112_10855_amd import cpqr as C
@@ -128,6 +129,7 @@ def run_sinsum(args):
         results.append(row)
         del Xd
         torch.cuda.empty_cache()
+    results.append(sinsum10_case(C, torch, synth, iters))
     main_case = results[1]
     out = {
         "metric": "sine of sums: relative error after 40 sweeps (CP-ALS-QR)", "value": main_case["qr"]["relerr_final"],
@@ -139,6 +141,52 @@ def run_sinsum(args):
         "cases": results,
     }
     print(json.dumps(out), flush=True)
+
+
+def sinsum10_case(C, torch, synth, iters, trials=5):
+    """Section 4.3.3: N = 10, n = 8, rank 10 (wider than the modes), the input
+    in its rank-512 Kruskal form (never formed for the method); the dense
+    8^10 FP64 tensor (8.6 GB) is formed on the device only for the direct
+    error.  Five seeded starts, 40 sweeps of each algorithm from each."""
+    N, n = 10, 8
+    mu, V = synth.sine_of_sums_expanded(N, n)
+    mud = torch.from_numpy(mu).cuda()
+    Vd = [C.colmajor(torch.from_numpy(v).cuda()) for v in V]
+    t0 = time.time()
+    Xd = C.cpqr_kruskal_full(mud, Vd)
+    torch.cuda.synchronize()
+    log("sine of sums N=10 n=8: dense tensor for the direct error formed in %.2f s" % (time.time() - t0))
+    row = {"N": N, "n": n, "rank": N, "input": "Kruskal form, 512 terms (sum identities)", "starts": []}
+    for trial in range(trials):
+        init = synth.init_factors((n,) * N, N, 5400 + trial)
+        res = {"seed": 5400 + trial}
+        for alg in ("als", "pinv", "qr", "qrsvd"):
+            def make(mode):
+                kw = dict(prec=C.PREC_F64, error_mode=mode, kruskal=(mud, Vd))
+                if alg in ("als", "pinv"):
+                    return C.AlsNeState(Xd, init, solver="chol" if alg == "als" else "pinv", **kw)
+                return C.AlsState(Xd, init, use_svd=alg == "qrsvd", **kw)
+            st = make(C.ERROR_DIRECT)
+            st.init()
+            rel = st.sweep(iters)
+            h = rel.cpu().numpy()
+            res[alg] = {"relerr_final": float(h[-1]), "relerr_min": float(np.nanmin(h)),
+                        "relerr_every_5": [float(v) for v in h[4::5]]}
+            if trial == 0:  # sweep time without the error (it reads the 8.6 GB dense tensor)
+                st = make(C.ERROR_NONE)
+                st.init()
+                st.sweep(2)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                st.sweep(iters)
+                e1.record()
+                torch.cuda.synchronize()
+                res[alg]["ms_per_sweep_no_error"] = round(e0.elapsed_time(e1) / iters, 4)
+            log("  N=10 start %d %-5s final relerr %.3e" % (trial, alg, h[-1]))
+        row["starts"].append(res)
+    del Xd
+    torch.cuda.empty_cache()
+    return row
 
 
 def timed_sweeps(C, torch, st, steps, phase):
