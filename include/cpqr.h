@@ -337,6 +337,22 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
                    void* stream);
 
 /*
+ * nsweeps whole sweeps captured once into a HIP graph (the Alg. 2 or Alg. 1
+ * loop body, algo 0 = cpqr_als_sweep, 1 = cpqr_als_ne_sweep, including the
+ * side-stream fork and join) and replayed by cpqr_graph_launch on any
+ * stream, one launch for all of them.  The graph keeps the device pointers of
+ * *p, relerr (nsweeps doubles, written by every launch) and work: they must
+ * stay valid and the problem unchanged while the graph is used; every launch
+ * continues from the state the previous one left.  Capture runs nothing.
+ * cpqr_graph_destroy releases it (NULL is accepted).
+ */
+typedef struct cpqr_graph_t* cpqr_graph;
+int cpqr_als_graph_create(const cpqr_problem* p, int algo, int nsweeps, double* relerr, void* work,
+                          size_t work_bytes, cpqr_graph* out);
+int cpqr_graph_launch(cpqr_graph g, void* stream);
+int cpqr_graph_destroy(cpqr_graph g);
+
+/*
  * CP-ALS with the normal equations, the paper's comparison algorithm (Alg. 1,
  * section 2.3), on the same problem description and the same Multi-TTM:
  * the MTTKRP M_n = X_(n) Z_n is read off Y_(n) (the Multi-TTM with the

@@ -121,6 +121,10 @@ _SIGS = {
     "cpqr_als_work": (_sz, [ctypes.POINTER(Problem)]),
     "cpqr_als_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
     "cpqr_als_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "cpqr_als_graph_create": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, _vp, _vp, _sz,
+                                             ctypes.POINTER(_vp)]),
+    "cpqr_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "cpqr_graph_destroy": (ctypes.c_int, [_vp]),
     "cpqr_als_ne_work": (_sz, [ctypes.POINTER(Problem)]),
     "cpqr_als_ne_init": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, _sz, _vp]),
     "cpqr_als_ne_sweep": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, _vp, _vp, _sz, _vp]),
@@ -561,6 +565,34 @@ class AlsState:
               _stream())
         return relerr
 
+    def graph(self, nsweeps):
+        """nsweeps sweeps captured into a HIP graph (SweepGraph)."""
+        return SweepGraph(self, 0, nsweeps)
+
+
+class SweepGraph:
+    """nsweeps sweeps of a state captured into one HIP graph
+    (cpqr_als_graph_create); launch() replays them on the current stream and
+    leaves the relative errors in ``relerr``.  The state must stay alive."""
+
+    def __init__(self, state, algo, nsweeps):
+        self.state = state
+        self.relerr = torch.empty(int(nsweeps), dtype=torch.float64, device=state.dev)
+        h = _vp()
+        _call("cpqr_als_graph_create", ctypes.byref(state.p), int(algo), int(nsweeps), self.relerr.data_ptr(),
+              state._w, state._wbytes, ctypes.byref(h))
+        self.h = h
+
+    def launch(self):
+        _call("cpqr_graph_launch", self.h, _stream())
+        return self.relerr
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.cpqr_graph_destroy(h)
+            self.h = None
+
 
 def cpqr_als_init(state):
     state.init()
@@ -633,6 +665,10 @@ class AlsNeState:
         _call("cpqr_als_ne_sweep", ctypes.byref(self.p), int(nsweeps), relerr.data_ptr(), self._w, self._wbytes,
               _stream())
         return relerr
+
+    def graph(self, nsweeps):
+        """nsweeps sweeps captured into a HIP graph (SweepGraph)."""
+        return SweepGraph(self, 1, nsweeps)
 
 
 def cp_als(X, init, maxiters=25, tol=0.0, prec=PREC_F32, solver="chol", rtol=-1.0, error_mode=ERROR_EFFICIENT,

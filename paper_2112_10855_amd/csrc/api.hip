@@ -1120,6 +1120,78 @@ int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* 
   return CPQR_OK;
 }
 
+// ------------------------------------------------------------ HIP graphs
+// Whole sweeps captured once into a HIP graph: one launch replays every
+// kernel, copy and cross-stream dependency of the captured calls, without the
+// host-side launch work and with the side-stream fork/join as graph edges.
+struct cpqr_graph_t {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int cpqr_als_graph_create(const cpqr_problem* p, int algo, int nsweeps, double* relerr, void* work,
+                          size_t work_bytes, cpqr_graph* out) {
+  if (!out) return fail(CPQR_ERR_ARG, "als_graph_create: out is NULL");
+  *out = nullptr;
+  if (algo != 0 && algo != 1) return fail(CPQR_ERR_ARG, "als_graph_create: algo must be 0 (Alg. 2) or 1 (Alg. 1)");
+  if (nsweeps < 1) return fail(CPQR_ERR_ARG, "als_graph_create: nsweeps < 1");
+  // the same checks as the sweep itself, before anything is captured
+  CPQR_TRY(check_problem(p, algo == 0));
+  {
+    Carver cv(nullptr);
+    const size_t need = kruskal_input(p) ? kr_carve(cv, p, algo == 1, nullptr)
+                                         : (algo == 0 ? als_carve(cv, p, nullptr) : ne_carve(cv, p, nullptr));
+    CPQR_TRY(check_work(work, work_bytes, need));
+  }
+  SideStream side;
+  CPQR_TRY(side_stream(side));  // created outside the capture
+  hipStream_t cap = nullptr;
+  CPQR_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return fail(CPQR_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  const int rc = algo == 0 ? cpqr_als_sweep(p, nsweeps, relerr, work, work_bytes, cap)
+                           : cpqr_als_ne_sweep(p, nsweeps, relerr, work, work_bytes, cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (rc != CPQR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(CPQR_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(CPQR_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  cpqr_graph h = new cpqr_graph_t;
+  h->graph = g;
+  h->exec = ex;
+  *out = h;
+  return CPQR_OK;
+}
+
+int cpqr_graph_launch(cpqr_graph g, void* stream) {
+  if (!g || !g->exec) return fail(CPQR_ERR_ARG, "graph_launch: NULL graph");
+  CPQR_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+  return CPQR_OK;
+}
+
+int cpqr_graph_destroy(cpqr_graph g) {
+  if (!g) return CPQR_OK;
+  if (g->exec) CPQR_HIP(hipGraphExecDestroy(g->exec));
+  if (g->graph) CPQR_HIP(hipGraphDestroy(g->graph));
+  delete g;
+  return CPQR_OK;
+}
+
 int cpqr_timing_enable(int on) {
   TimingState& t = timing();
   std::lock_guard<std::mutex> g(t.mu);

@@ -236,3 +236,21 @@ def test_kruskal_validation_codes(L):
     assert L.cpqr_als_work(ctypes.byref(p)) > 0  # no dense X needed
     p.error_mode = C.ERROR_DIRECT
     assert L.cpqr_als_work(ctypes.byref(p)) == 0  # the direct error needs X
+
+
+def test_graph_validation_codes(L):
+    P = 4096
+    p = C.Problem()
+    p.N, p.R = 3, 4
+    for k in range(3):
+        p.I[k] = 10
+        p.A[k] = p.Q[k] = p.Rf[k] = P
+    p.lam = p.X = P
+    h = C._vp()
+    assert L.cpqr_als_graph_create(ctypes.byref(p), 0, 1, P, P, 1 << 30, None) == -1
+    assert L.cpqr_als_graph_create(ctypes.byref(p), 2, 1, P, P, 1 << 30, ctypes.byref(h)) == -1
+    assert L.cpqr_als_graph_create(ctypes.byref(p), 0, 0, P, P, 1 << 30, ctypes.byref(h)) == -1
+    assert L.cpqr_als_graph_create(ctypes.byref(p), 0, 1, P, None, 0, ctypes.byref(h)) == -4
+    assert h.value is None
+    assert L.cpqr_graph_launch(None, None) == -1
+    assert L.cpqr_graph_destroy(None) == 0
