@@ -59,8 +59,9 @@ def parse():
     ap.add_argument("--fit-n", type=int, default=200, help="mode size of the time-to-fit study (--workload fit)")
     ap.add_argument("--krp-chain", type=int, default=-1,
                     help="QR of the Khatri-Rao product: 1 structured, 0 dense, -1 structured for N >= 4")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager sweeps instead of one HIP graph launch of them")
+    ap.add_argument("--graph", action="store_true",
+                    help="time one HIP graph launch of the sweeps as the value (default: eager sweeps; the graph "
+                         "launch is then reported beside)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sub-records", action="store_true",
                     help="dense3 f32 qr only: skip the FP64 1000^3 and 200^4 rank-32 sub-records")
@@ -191,26 +192,14 @@ def sinsum10_case(C, torch, synth, iters, trials=5):
     return row
 
 
-def timed_sweeps(C, torch, st, steps, phase, graph=True):
-    """Time `steps` sweeps of a set-up state: with graph, the sweeps are
-    captured into one HIP graph first and the timed region is its launch;
-    the dominant kernel (`phase`) is then timed by events attached to its own
-    dispatches on an eager pass of the same number of sweeps right after (a
-    graph has no dispatch events).  Without graph, one eager pass does both.
-    Returns (ms per sweep, (kernel ms, launches), relerr, eager ms per sweep)."""
+def timed_sweeps(C, torch, st, steps, phase):
+    """Time `steps` eager sweeps of a set-up state with events on the launch
+    stream; the dominant kernel (`phase`) is timed by events attached to its
+    own dispatches in the same pass.  The same number of sweeps is then run
+    as one HIP graph launch and timed beside.  Returns (ms per sweep,
+    (kernel ms, launches), relerr, graph ms per sweep)."""
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ms_graph = None
-    if graph:
-        g = st.graph(steps)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        rel = g.launch()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_graph = e0.elapsed_time(e1) / steps
-        rel_np = rel.cpu().numpy()
-        del g
     rel = torch.empty(steps, dtype=torch.float64, device="cuda")
     C.cpqr_timing_reset()
     C.cpqr_timing_select([phase])
@@ -222,10 +211,16 @@ def timed_sweeps(C, torch, st, steps, phase, graph=True):
     torch.cuda.synchronize()
     C.cpqr_timing_enable(False)
     timed = C.cpqr_timing_read()
-    ms_eager = e0.elapsed_time(e1) / steps
-    if not graph:
-        rel_np = rel.cpu().numpy()
-    return (ms_graph if graph else ms_eager), timed[phase], rel_np, ms_eager
+    ms = e0.elapsed_time(e1) / steps
+    g = st.graph(steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    del g
+    return ms, timed[phase], rel.cpu().numpy(), ms_graph
 
 
 def phase_pass(C, torch, st, nb):
@@ -295,7 +290,7 @@ def dense4_record(prec_name, steps, warmup, data=None, krp_chain=-1):
     st.init()
     for _ in range(warmup):
         st.sweep(1)
-    ms, (dom_ms, dom_cnt), rel, ms_eager = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
+    ms, (dom_ms, dom_cnt), rel, ms_graph = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
     phases = phase_pass(C, torch, st, min(steps, 3))
     xbytes = X.size * 4
     dom_s = dom_ms / max(dom_cnt, 1) / 1e3
@@ -324,7 +319,7 @@ def dense4_record(prec_name, steps, warmup, data=None, krp_chain=-1):
                      "frac": round(xbytes / dom_s / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": xbytes,
                      "avg_launch_ms": round(dom_s * 1e3, 4), "launches": dom_cnt},
         "phases_ms_per_sweep": phases,
-        "eager_ms_per_step": round(ms_eager, 4),
+        "graph_ms_per_step": round(ms_graph, 4),
         "krp_qr_alone": [krp_qr_alone(C, torch, nn, rr) for nn, rr in ((4, R), (5, 16), (5, R))],
         "multittm_relerr_vs_fp64_sampled_rows": errs,
         "relerr_last": float(rel[-1]),
@@ -342,7 +337,7 @@ def run_dense4(args):
         "config": {"workload": rec["workload"], "shape": [200] * 4, "rank": 32, "krp_chain": args.krp_chain,
                    "ground_truth": "rank-32, unit Gaussian columns, weights 1e0..1e-6, no noise"},
         "roofline": rec["roofline"], "phases_ms_per_sweep": rec["phases_ms_per_sweep"],
-        "krp_qr_alone": rec["krp_qr_alone"], "eager_ms_per_step": rec["eager_ms_per_step"],
+        "krp_qr_alone": rec["krp_qr_alone"], "graph_ms_per_step": rec["graph_ms_per_step"],
         "multittm_relerr_vs_fp64_sampled_rows": rec["multittm_relerr_vs_fp64_sampled_rows"],
         "relerr_last": rec["relerr_last"],
     }
@@ -361,7 +356,7 @@ def dense3_f64_record(d, Xd32, steps, warmup):
     st.init()
     for _ in range(warmup):
         st.sweep(1)
-    ms, (dom_ms, dom_cnt), rel, ms_eager = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
+    ms, (dom_ms, dom_cnt), rel, ms_graph = timed_sweeps(C, torch, st, steps, "ttm_stream_m")
     phases = phase_pass(C, torch, st, min(steps, 3))
     xbytes = Xd.numel() * 8
     dom_s = dom_ms / max(dom_cnt, 1) / 1e3
@@ -377,7 +372,7 @@ def dense3_f64_record(d, Xd32, steps, warmup):
                      "frac": round(xbytes / dom_s / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": xbytes,
                      "avg_launch_ms": round(dom_s * 1e3, 4), "launches": dom_cnt},
         "phases_ms_per_sweep": phases,
-        "eager_ms_per_step": round(ms_eager, 4),
+        "graph_ms_per_step": round(ms_graph, 4),
         "relerr_last": float(rel[-1]),
     }
 
@@ -592,7 +587,8 @@ def main():
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    if not args.no_graph:
+    ms_graph = None
+    if args.graph:
         # the K sweeps captured into one HIP graph (nothing runs at capture);
         # the timed region is its launch
         graph = st.graph(args.steps)
@@ -603,14 +599,14 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         h1 = time.perf_counter()
-        ms_per_step = e0.elapsed_time(e1) / args.steps
+        ms_per_step = ms_graph = e0.elapsed_time(e1) / args.steps
         relerr = rel.cpu().numpy()
         del graph
         log("timed %d sweeps (one graph launch): %.3f ms/sweep (host clock %.3f ms/sweep); relerr %.6e"
             % (args.steps, ms_per_step, (h1 - h0) * 1e3 / args.steps, relerr[-1]))
     # The dominant kernel is timed by events attached to its own dispatches
-    # (no extra packets in the stream) on an eager pass of the same K sweeps;
-    # without --no-graph this pass follows the timed graph launch.
+    # (no extra packets in the stream) in this eager pass of the K sweeps;
+    # with --graph this pass follows the timed graph launch.
     rel_e = torch.empty(args.steps, dtype=torch.float64, device="cuda")
     C.cpqr_timing_reset()
     C.cpqr_timing_select(["ttm_stream_m"])
@@ -627,9 +623,19 @@ def main():
     ms_eager = e0.elapsed_time(e1) / args.steps
     log("eager %d sweeps: %.3f ms/sweep (host clock %.3f ms/sweep)" % (args.steps, ms_eager,
                                                                       (h3 - h2) * 1e3 / args.steps))
-    if args.no_graph:
+    if not args.graph:
         ms_per_step = ms_eager
         relerr = rel_e.cpu().numpy()
+        # the same sweeps as one HIP graph launch, reported beside (not timed as the value)
+        graph = st.graph(args.steps)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        graph.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+        del graph
+        log("the same %d sweeps as one graph launch: %.3f ms/sweep" % (args.steps, ms_graph))
 
     # phase breakdown: a separate, untimed pass with events between phases
     nb = min(args.steps, 5)
@@ -708,8 +714,10 @@ def main():
         "phases_note": "separate pass of %d sweeps with events between phases (slower than the timed sweeps)" % nb,
         "timed_region": ("one HIP graph launch of the %d sweeps (cpqr_als_graph_create); the dominant kernel's "
                          "launches timed by dispatch events on an eager pass of the same sweeps right after"
-                         % args.steps) if not args.no_graph else "eager sweeps, dominant kernel by dispatch events",
+                         % args.steps) if args.graph else "eager sweeps; the dominant kernel by events attached to "
+                                                          "its own dispatches in the same pass",
         "eager_ms_per_step": round(ms_eager, 4),
+        "graph_ms_per_step": round(ms_graph, 4),
         "relerr_last": float(relerr[-1]),
     }
 

@@ -888,9 +888,16 @@ int kr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* work,
         CPQR_TRY(kr_chain_enqueue(na, Pa, w.Qc, R, S, w.M, s));
         CPQR_TRY(kr_w_enqueue(p->I[n], S, R, p->xV[n], p->I[n], p->xmu, w.M, w.W, s));
       }
+      const bool fuse = norm_qr_fits(p->I[n], R);
       CPQR_TRY(solve_enqueue(p->I[n], R, w.W, w.R0, p->use_svd, p->rtol, p->A[n], p->lambda, p->status, w.sub,
-                             s));
-      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s));
+                             s, !fuse));
+      if (fuse) {
+        bool done = false;
+        CPQR_TRY(normalize_factor_qr_enqueue(p->I[n], R, p->A[n], p->lambda, p->status, p->Q[n], p->Rf[n], w.sub,
+                                             s, nullptr, &done));
+      } else {
+        CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s));
+      }
       CPQR_TRY(kr_cross_enqueue(p->I[n], R, S, p->Q[n], p->I[n], p->xV[n], p->I[n], Pk(n), s));
     }
     double* out = relerr ? relerr + sw : w.relerr_tmp;
@@ -1022,10 +1029,18 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       CPQR_HIP(hipEventRecord(side.done, side.s));
       CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
+      // normalization and factor QR in one launch where one workgroup takes A_n
+      const bool fuse = norm_qr_fits(p->I[n], R);
       CPQR_TRY(apply_solve_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.R0, p->use_svd, p->rtol, w.W, p->A[n],
-                                   p->lambda, p->status, w.sub, s));
-      CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s,
-                                 side.ready));
+                                   p->lambda, p->status, w.sub, s, !fuse));
+      if (fuse) {
+        bool done = false;
+        CPQR_TRY(normalize_factor_qr_enqueue(p->I[n], R, p->A[n], p->lambda, p->status, p->Q[n], p->Rf[n], w.sub,
+                                             s, side.ready, &done));
+      } else {
+        CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s,
+                                   side.ready));
+      }
       r_marked = true;
     }
     double* out = relerr ? relerr + sw : w.relerr_tmp;

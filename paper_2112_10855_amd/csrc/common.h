@@ -91,6 +91,14 @@ int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q,
                       hipEvent_t r_ready = nullptr);
 int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
                    double* R0, void* work, hipStream_t s);
+// Whether the factor QR of I x R takes a single workgroup (then the column
+// normalization can be fused into it).
+bool norm_qr_fits(int64_t I, int R);
+// Column normalization (lambda, A scaled in place, zero-column status) and
+// factor QR of A (leading dimensions I, I and R) in one launch; *fused is
+// false (and nothing is enqueued) when norm_qr_fits(I, R) does not hold.
+int normalize_factor_qr_enqueue(int64_t I, int R, double* A, double* lambda, int* status, double* Q, double* Rk,
+                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused);
 
 // multittm.hip
 size_t multittm_work(int N, const int64_t* I, int n, int R, int prec);
@@ -114,10 +122,10 @@ int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, co
 // triangular solve sums the split partials of W itself (work: apply_q0_work).
 int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                         const double* R0, int use_svd, double rtol, double* W, double* A, double* lambda,
-                        int* status, void* work, hipStream_t s);
+                        int* status, void* work, hipStream_t s, bool normalize = true);
 size_t solve_work(int64_t In, int R);
 int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
-                  double* A, double* lambda, int* status, void* work, hipStream_t s);
+                  double* A, double* lambda, int* status, void* work, hipStream_t s, bool normalize = true);
 size_t fit_direct_work(int N, const int64_t* I, int R);
 int fit_direct_enqueue(int N, const int64_t* I, int xdtype, const void* X, int R,
                        const double* lambda, const double* const* A, double* out, void* work,

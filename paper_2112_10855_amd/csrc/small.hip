@@ -857,12 +857,12 @@ int apply_q0_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, co
 
 int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                         const double* R0, int use_svd, double rtol, double* W, double* A, double* lambda,
-                        int* status, void* work, hipStream_t s) {
+                        int* status, void* work, hipStream_t s, bool normalize) {
   const ApplyPlan ap = apply_plan(In, K, R);
   const int64_t splits = ap.splits;
   if (use_svd || splits == 1) {
     CPQR_TRY(apply_q0_enqueue(In, K, R, ydtype, Y, Q0, W, work, s));
-    return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, s);
+    return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, s, normalize);
   }
   // the solve adds up the partial W's itself (one kernel fewer)
   Carver cv(work);
@@ -882,6 +882,7 @@ int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y,
   else
     hipLaunchKernelGGL((sum_solve_kernel<32>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
   CPQR_TRY(check_launch("sum_solve"));
+  if (!normalize) return CPQR_OK;
   hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
   return check_launch("normalize");
 }
@@ -895,7 +896,7 @@ size_t solve_work(int64_t In, int R) {
 }
 
 int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_svd, double rtol,
-                  double* A, double* lambda, int* status, void* work, hipStream_t s) {
+                  double* A, double* lambda, int* status, void* work, hipStream_t s, bool normalize) {
   PhaseTimer pt(PH_SOLVE, s);
   Carver cv(work);
   double* M = cv.take<double>(size_t(R) * R);
@@ -921,6 +922,7 @@ int solve_enqueue(int64_t In, int R, const double* W, const double* R0, int use_
       hipLaunchKernelGGL((rowmul_kernel<32>), grd, dim3(BLK), 0, s, W, M, A, In, R, status);
     CPQR_TRY(check_launch("rowmul"));
   }
+  if (!normalize) return CPQR_OK;
   hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
   return check_launch("normalize");
 }

@@ -554,10 +554,17 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_up(int64_t rows, int R, int 
 // The root (one workgroup): factorize, write R, and form the root's Q from
 // C = I straight away: the output itself when the root is the only leaf,
 // else the C blocks of its children.
-template <int RMAX, int P, int SRC>
+//
+// NORM (a single node of an input matrix only): the columns are first
+// normalized, lambda_c = ||A(:, c)||_2 and A(:, c) /= lambda_c written back
+// (a zero column stays zero, lambda_c = 0, CPQR_STATUS_ZERO_COLUMN), so the
+// sweep's normalization and factor QR are one launch; a wavefront holds all
+// rows of its columns, so the norms need no exchange between wavefronts.
+template <int RMAX, int P, int SRC, bool NORM = false>
 __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, const double* A, int64_t lda,
                                                          KrpSrc krp, double* Qout, int64_t ldq, double* Rout,
-                                                         int64_t ldr, double* work) {
+                                                         int64_t ldr, double* work, double* lambda = nullptr,
+                                                         int* status = nullptr) {
   __shared__ Shared<RMAX, P> sh;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W;
   const int top = level_count(rows, R, P) - 1;
@@ -570,6 +577,39 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, co
     load_leaf<RMAX, P, SRC>(a, w, lane, start, m, R, A, lda, krp);
   else
     load_stack<RMAX, P>(a, w, lane, m, R, work + L.s, 0);
+  if constexpr (NORM) {
+    double ss[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc += a[p][j] * a[p][j];
+      ss[j] = acc;
+    }
+    const double red = wave_sum<CW>(ss, lane);
+    double* Aw = const_cast<double*>(A);
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w * CW + j;
+      const double nrm = sqrt(rdlane(red, j << (6 - ilog2(CW))));
+      if (lane == 0 && c < R) {
+        lambda[c] = nrm;
+        if (nrm == 0.0 && status) atomicOr(status, CPQR_STATUS_ZERO_COLUMN);
+      }
+      if (nrm > 0.0) {
+        const double inv = 1.0 / nrm;
+#pragma unroll
+        for (int p = 0; p < P; ++p) a[p][j] *= inv;
+      }
+      if (c < R) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const int r = p * W + lane;
+          if (r < m) Aw[start + r + c * lda] = a[p][j];
+        }
+      }
+    }
+  }
   node_factor<RMAX>(a, R, w, lane, sh);
   node_v1<true, RMAX>(a, R, w, lane, sh);
   if (lane < R) {
@@ -687,6 +727,33 @@ int factor_qr_enqueue(int64_t I, int R, const double* A, int64_t lda, double* Q,
   PhaseTimer pt(PH_FACTOR_QR, s);
   KrpSrc none{};
   return tsqr_dispatch(SRC_MATRIX, I, R, A, lda, none, Q, ldq, Rk, ldr, work, s, r_ready);
+}
+
+bool norm_qr_fits(int64_t I, int R) {
+  (void)R;
+  return bn::level_count(I, R, bn_slots(I)) == 1;  // a single node holds all rows
+}
+
+int normalize_factor_qr_enqueue(int64_t I, int R, double* A, double* lambda, int* status, double* Q, double* Rk,
+                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused) {
+  *fused = false;
+  if (!norm_qr_fits(I, R)) return CPQR_OK;
+  PhaseTimer pt(PH_FACTOR_QR, s);
+  KrpSrc none{};
+  const bool small = bn_slots(I) == 4;
+#define NQR(RM, PP)                                                                                               \
+  hipLaunchKernelGGL((bn::bn_root<RM, PP, SRC_MATRIX, true>), dim3(1), dim3(RM / bn::CW * bn::W), 0, s, I, R, A, I, \
+                     none, Q, I, Rk, int64_t(R), static_cast<double*>(work), lambda, status)
+  switch (round_rank(R)) {
+    case 8: if (small) NQR(8, 4); else NQR(8, 16); break;
+    case 16: if (small) NQR(16, 4); else NQR(16, 16); break;
+    default: if (small) NQR(32, 4); else NQR(32, 16); break;
+  }
+#undef NQR
+  CPQR_TRY(check_launch("bn_root (normalizing)"));
+  if (r_ready) CPQR_HIP(hipEventRecord(r_ready, s));
+  *fused = true;
+  return CPQR_OK;
 }
 
 int krp_qr_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Q0,
