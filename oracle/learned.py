@@ -23,6 +23,13 @@ What the GPU side computes, and what this module defines:
                        not depend on the scale of its start).
            The loss of a batch is the mean of the per-sample losses.
   Adam     the update of Kingma and Ba with bias correction.
+  HOSVD    the fallback start: for each mode k, an orthonormal basis of the
+           range of X_(k) taken from its product with a Khatri-Rao test
+           matrix of Gaussian factors, W_k = X_(k) (Omega_N (.) .. (.)
+           Omega_{k+1} (.) Omega_{k-1} (.) .. (.) Omega_1) (the MTTKRP of
+           section 2.3 with random factors), then the thin QR of W_k
+           (``hosvd_start``): the randomized form of the leading-R mode-k
+           singular subspace of the HOSVD (equal to it when X_(k) has rank R).
 
 The paper does not describe this component; it is the project's learned
 initializer, and the gain it brings is measured, not pinned to a published
@@ -191,3 +198,18 @@ def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def hosvd_start(X, Omegas, R, modes=None):
+    """Randomized HOSVD start: A_k = Q of the thin QR of X_(k) (Khatri-Rao of
+    Omega_j, j != k) for each k in ``modes`` (default: all); the other
+    entries are None.  Library primitives: the oracle's MTTKRP and LAPACK QR."""
+    from . import tensor as T
+    N = np.asarray(X).ndim
+    modes = range(N) if modes is None else modes
+    out = [None] * N
+    for k in modes:
+        W = T.mttkrp(np.asarray(X, dtype=np.float64), [np.asarray(o, dtype=np.float64) for o in Omegas], k)
+        Q, _ = np.linalg.qr(W, mode="reduced")
+        out[k] = Q[:, :R]
+    return out

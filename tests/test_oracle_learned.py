@@ -185,3 +185,46 @@ def test_planted_gradient_sign_is_caught():
     M[0][0, 0] -= h
     fd = (L.kruskal_loss(P, A) - L.kruskal_loss(M, A)) / (2 * h)
     assert abs(fd - wrong[0, 0]) > 1e-4
+
+
+def test_hosvd_start_spans_the_factor_subspace():
+    """For an exact rank-R tensor the randomized HOSVD start spans the mode-k
+    column space of the ground-truth factor, which is also the leading-R left
+    singular subspace of X_(k) (projectors compared)."""
+    import oracle.learned as OLm
+    from oracle import tensor as T
+    g = np.random.default_rng(4)
+    shape, R = (12, 10, 9), 3
+    A = [g.standard_normal((s, R)) for s in shape]
+    X = T.full(np.ones(R), A)
+    Om = [g.standard_normal((s, R)) for s in shape]
+    Qs = OLm.hosvd_start(X, Om, R)
+    for k in range(3):
+        P = Qs[k] @ Qs[k].T
+        Qa, _ = np.linalg.qr(A[k])
+        np.testing.assert_allclose(P, Qa @ Qa.T, rtol=0, atol=1e-12)
+        U, _, _ = np.linalg.svd(T.unfold(X, k), full_matrices=False)
+        np.testing.assert_allclose(P, U[:, :R] @ U[:, :R].T, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(Qs[k].T @ Qs[k], np.eye(R), rtol=0, atol=1e-13)
+
+
+def test_hosvd_start_is_the_qr_of_the_random_mttkrp():
+    """W_k written out by index loops (sum over i_j, i_l of X times products
+    of Omega entries), then its QR: equal to the oracle's start."""
+    import itertools
+    import oracle.learned as OLm
+    g = np.random.default_rng(5)
+    shape, R = (4, 3, 5), 2
+    X = g.standard_normal(shape)
+    Om = [g.standard_normal((s, R)) for s in shape]
+    for k in range(3):
+        W = np.zeros((shape[k], R))
+        for idx in itertools.product(*[range(s) for s in shape]):
+            for r in range(R):
+                v = X[idx]
+                for j in range(3):
+                    if j != k:
+                        v *= Om[j][idx[j], r]
+                W[idx[k], r] += v
+        Q, _ = np.linalg.qr(W)
+        np.testing.assert_allclose(OLm.hosvd_start(X, Om, R, modes=[k])[k], Q, rtol=0, atol=1e-13)
