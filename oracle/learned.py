@@ -204,7 +204,6 @@ def hosvd_start(X, Omegas, R, modes=None):
     """Randomized HOSVD start: A_k = Q of the thin QR of X_(k) (Khatri-Rao of
     Omega_j, j != k) for each k in ``modes`` (default: all); the other
     entries are None.  Library primitives: the oracle's MTTKRP and LAPACK QR."""
-    from . import tensor as T
     N = np.asarray(X).ndim
     modes = range(N) if modes is None else modes
     out = [None] * N
