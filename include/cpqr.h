@@ -190,6 +190,22 @@ size_t cpqr_expand_q0_work(int N, int R);
 int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_t work_bytes, void* stream);
 
 /*
+ * Randomized HOSVD start, the fallback of the learned initializer: for each
+ * mode k >= k0, A[k] = the Q of the thin QR of W_k = X_(k) (Omega_N (.) ..
+ * (.) Omega_{k+1} (.) Omega_{k-1} (.) .. (.) Omega_1), an orthonormal basis
+ * of the range of X_(k) sampled by a Khatri-Rao test matrix (the leading-R
+ * mode-k singular subspace when X_(k) has rank R).  W_k is the MTTKRP of
+ * section 2.3, read off the Multi-TTM with U_j = Omega_j in precision prec.
+ *   Omega : host array of N device I[j] x R column-major FP64 test factors
+ *           (drawn by the caller, e.g. iid N(0, 1))
+ *   A     : host array of N device I[k] x R column-major FP64 outputs
+ *           (entries below k0 not read or written); I[k] >= R.
+ */
+size_t cpqr_hosvd_init_work(int N, const int64_t* I, int R, int prec);
+int cpqr_hosvd_init(int N, const int64_t* I, int xdtype, const void* X, int R, const double* const* Omega, int prec,
+                    int k0, double* const* A, void* work, size_t work_bytes, void* stream);
+
+/*
  * Kruskal-form input X = [[mu; V_1 .. V_N]] (section 3.3.2).  mu: device, S
  * weights; V: host array of N device pointers to I[k] x S column-major FP64
  * factors (leading dimension I[k]); 1 <= S <= CPQR_MAX_KRUSKAL_TERMS.

@@ -94,6 +94,10 @@ _SIGS = {
                                          _vp, _vp, _vp, _sz, _vp]),
     "cpqr_expand_q0_work": (_sz, [ctypes.c_int, ctypes.c_int]),
     "cpqr_expand_q0": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]),
+    "cpqr_hosvd_init_work": (_sz, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, ctypes.c_int]),
+    "cpqr_hosvd_init": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int, _vp, ctypes.c_int,
+                                       ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), _vp, _sz,
+                                       _vp]),
     "cpqr_kruskal_w_work": (_sz, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "cpqr_kruskal_w": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64), ctypes.c_int,
                                       _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp, _vp, _sz, _vp]),
@@ -359,6 +363,25 @@ def cpqr_expand_q0(Qc, N):
     keep, w = _work(nbytes, Qc.device)
     _call("cpqr_expand_q0", N, R, Qc.data_ptr(), Q0.data_ptr(), w, nbytes, _stream())
     return Q0
+
+
+def cpqr_hosvd_init(X, Omegas, R, prec=PREC_F32, k0=1):
+    """Randomized HOSVD start: list over modes of I_k x R orthonormal bases
+    (None below k0) from the test factors Omegas (device FP64, I_k x R)."""
+    _dev(X, "X")
+    _check_colmajor(X, "X")
+    prec = PREC_NAMES.get(prec, prec)
+    N = X.dim()
+    for o in Omegas:
+        _dev(o, "Omega")
+        _check_colmajor(o, "Omega")
+    A = [empty_colmajor((X.shape[k], R), torch.float64, X.device) if k >= k0 else None for k in range(N)]
+    I = _i64_array(X.shape)
+    nbytes = lib().cpqr_hosvd_init_work(N, I, R, prec)
+    keep, w = _work(nbytes, X.device)
+    _call("cpqr_hosvd_init", N, I, _dtype_code(X), X.data_ptr(), R, _ptr_array(Omegas), prec, int(k0), _ptr_array(A),
+          w, nbytes, _stream())
+    return A
 
 
 def _kruskal_args(mu, V):

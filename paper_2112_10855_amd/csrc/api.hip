@@ -617,6 +617,59 @@ int cpqr_expand_q0(int N, int R, const double* Qc, double* Q0, void* work, size_
   return expand_q0_enqueue(N, R, Qc, Q0, static_cast<double*>(work), as_stream(stream));
 }
 
+size_t hosvd_work(int N, const int64_t* I, int R, int prec) {
+  const int64_t K = ipow(R, N - 1);
+  int64_t imax = 0;
+  size_t sub = 0;
+  for (int k = 0; k < N; ++k) {
+    imax = std::max(imax, I[k]);
+    sub = std::max(sub, std::max(multittm_work(N, I, k, R, prec), tsqr_work(I[k], R)));
+  }
+  Carver cv(nullptr);
+  cv.take<double>(size_t(imax) * K);  // Y_(k), sized for FP64
+  cv.take<double>(size_t(imax) * R);  // W_k
+  cv.take<double>(size_t(R) * R);     // R of the QR (not returned)
+  cv.take<char>(sub);
+  return cv.bytes();
+}
+
+size_t cpqr_hosvd_init_work(int N, const int64_t* I, int R, int prec) {
+  if (check_modes(N, I) != CPQR_OK || R < 1 || R > CPQR_MAX_RANK || !valid_prec(prec)) return 0;
+  if (check_krp_rows(N, R) != CPQR_OK) return 0;
+  return hosvd_work(N, I, R, prec);
+}
+
+int cpqr_hosvd_init(int N, const int64_t* I, int xdtype, const void* X, int R, const double* const* Omega, int prec,
+                    int k0, double* const* A, void* work, size_t work_bytes, void* stream) {
+  if (!A || !Omega || !I) return fail(CPQR_ERR_ARG, "hosvd_init: NULL pointer array");
+  CPQR_TRY(check_modes(N, I));
+  if (k0 < 0 || k0 >= N) return fail(CPQR_ERR_ARG, "hosvd_init: k0 out of range");
+  for (int k = k0; k < N; ++k)
+    if (!A[k]) return fail(CPQR_ERR_ARG, "hosvd_init: A[" + std::to_string(k) + "] is NULL");
+  // the Multi-TTM's own checks (its output is internal; A[k0] stands in for it)
+  CPQR_TRY(check_multittm_args(N, I, xdtype, X, 0, R, Omega, prec, A[k0]));
+  if (!Omega[0]) return fail(CPQR_ERR_ARG, "hosvd_init: Omega[0] is NULL");
+  for (int k = k0; k < N; ++k)
+    if (I[k] < R) return fail(CPQR_ERR_SHAPE, "hosvd_init: mode " + std::to_string(k) + " is smaller than R");
+  CPQR_TRY(check_work(work, work_bytes, hosvd_work(N, I, R, prec)));
+  hipStream_t s = as_stream(stream);
+  const int64_t K = ipow(R, N - 1);
+  int64_t imax = 0;
+  for (int k = 0; k < N; ++k) imax = std::max(imax, I[k]);
+  Carver cv(work);
+  void* Y = cv.take<double>(size_t(imax) * K);
+  double* W = cv.take<double>(size_t(imax) * R);
+  double* Rk = cv.take<double>(size_t(R) * R);
+  void* sub = cv.take<char>(0);
+  const int ydt = prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
+  for (int k = k0; k < N; ++k) {
+    CPQR_TRY(multittm_enqueue(N, I, xdtype, X, k, R, Omega, prec, Y, sub, s));
+    CPQR_TRY(diag_cols_enqueue(I[k], N, R, ydt, Y, W, s));
+    CPQR_TRY(factor_qr_enqueue(I[k], R, W, I[k], A[k], I[k], Rk, R, sub, s));
+  }
+  return CPQR_OK;
+}
+
 int check_kruskal(int N, const int64_t* I, int S, const double* mu, const double* const* V) {
   CPQR_TRY(check_modes(N, I));
   if (S < 1 || S > CPQR_MAX_KRUSKAL_TERMS)

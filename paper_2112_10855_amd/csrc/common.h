@@ -142,6 +142,9 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
 // Q_0 (R^{N-1} x R) formed from the factors of the structured QR of V_n
 // (Qc: Q_2 .. Q_{N-1}, each R^2 x R); buf holds 2 R^{N-1} R doubles (N >= 5)
 int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, hipStream_t s);
+// W (In x R, FP64) = the columns of Y_(n) (In x R^{N-1}) whose every Kronecker
+// index is r (the MTTKRP part of a Multi-TTM)
+int diag_cols_enqueue(int64_t In, int N, int R, int ydtype, const void* Y, double* W, hipStream_t s);
 // relerr = sqrt(max(out[0],0) / out[1]) from a fit_direct result
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s);
 int fill_enqueue(double* p, int64_t count, double v, hipStream_t s);

@@ -393,6 +393,18 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(double* A, double* lambd
   }
 }
 
+// ------------------------------------------------------------ diagonal columns
+// W[i + In r] = Y[i + In r dstep]: the columns of Y_(n) whose every
+// Kronecker index equals r (dstep = 1 + R + .. + R^{N-2}).
+template <class TY>
+__global__ __launch_bounds__(BLK) void diag_cols_kernel(const TY* __restrict__ Y, int64_t In, int64_t dstep, int R,
+                                                        double* __restrict__ W) {
+  const int64_t e = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (e >= In * R) return;
+  const int64_t i = e % In, r = e / In;
+  W[e] = double(Y[i + In * r * dstep]);
+}
+
 // ------------------------------------------------------------ structured Q_0
 // One step of forming Q_0 = (I kron Q_2) .. (I kron Q_{N-2}) Q_{N-1} from the
 // right: out = (I_m kron Qj) G, i.e. out[k + R^2 s, c] = sum_j Qj[k, j] G[j + R s, c]
@@ -987,6 +999,20 @@ int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, h
     m *= R;
   }
   return CPQR_OK;
+}
+
+int diag_cols_enqueue(int64_t In, int N, int R, int ydtype, const void* Y, double* W, hipStream_t s) {
+  int64_t dstep = 0, pw = 1;
+  for (int k = 0; k + 1 < N; ++k) {
+    dstep += pw;
+    pw *= R;
+  }
+  const dim3 grd(unsigned(ceil_div(In * R, BLK)));
+  if (ydtype == CPQR_F64)
+    hipLaunchKernelGGL(diag_cols_kernel<double>, grd, dim3(BLK), 0, s, static_cast<const double*>(Y), In, dstep, R, W);
+  else
+    hipLaunchKernelGGL(diag_cols_kernel<float>, grd, dim3(BLK), 0, s, static_cast<const float*>(Y), In, dstep, R, W);
+  return check_launch("diag_cols");
 }
 
 int error_from_fit_enqueue(const double* fit, double* relerr, hipStream_t s) {

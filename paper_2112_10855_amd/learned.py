@@ -10,7 +10,9 @@ GPU CP-ALS-QR itself reached, with the scale-free Kruskal-form loss
 on the scale of its start; the distance form has a flat saddle at zero and
 grows with the sixth power of the output).
 At inference only A_2 and A_3 of the prediction are used (Alg. 2 never
-reads the initial A_1); random initial factors remain the fallback.
+reads the initial A_1); the fallback is the randomized HOSVD start
+(cpqr_hosvd_init: an orthonormal basis of the range of X_(k) sampled by a
+Khatri-Rao test matrix of Gaussian factors).
 
 Every step runs in libcpqr's kernels (sketch, GEMMs, loss gradient, Adam,
 batched CP-ALS-QR); torch provides device memory and builds the synthetic
@@ -24,7 +26,6 @@ import torch
 
 from . import cpqr as C
 from . import synth
-from .fit import time_to_fit
 
 
 def c5_factors(shape, R, seed, congruence=0.9):
@@ -158,8 +159,43 @@ def train(model, xs, tg, epochs, batch=256, lr=1e-3, seed=1, log=print):
     return hist
 
 
+def hosvd_start(X, R, seed):
+    """Randomized HOSVD start of a device tensor (modes 2 and 3; A_1 is
+    never read by Alg. 2 and is returned as zeros), FP64 host arrays."""
+    shape = tuple(X.shape)
+    Om = [C.colmajor(torch.as_tensor(o, dtype=torch.float64, device=X.device))
+          for o in synth.gaussian_factors(shape, R, seed)]
+    A = C.cpqr_hosvd_init(X, Om, R, prec=C.PREC_F32, k0=1)
+    return [np.zeros((shape[0], R))] + [a.cpu().numpy() for a in A[1:]]
+
+
+def fit_history(X, init, sweeps):
+    """Relative errors (direct form) after each of `sweeps` CP-ALS-QR sweeps
+    from `init` and the GPU seconds they took, error included."""
+    st = C.AlsState(X, init, prec=C.PREC_F32, error_mode=C.ERROR_DIRECT)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st.init()
+    rel = st.sweep(sweeps)
+    e1.record()
+    torch.cuda.synchronize()
+    return rel.cpu().numpy(), e0.elapsed_time(e1) / 1e3
+
+
+MARKS = (5, 10, 25, 50, 100, 200)
+
+
+def summarize(hist, secs, target=1e-6):
+    """Relative error at the marked sweep counts, and the sweeps and seconds
+    to reach `target` (None when not reached)."""
+    hit = next((i + 1 for i, v in enumerate(hist) if v <= target), None)
+    return {"relerr_at": {m: float(hist[m - 1]) for m in MARKS if m <= len(hist)},
+            "sweeps_to_target": hit, "seconds_to_target": None if hit is None else secs * hit / len(hist),
+            "final": float(hist[-1])}
+
+
 def usable_start(pred, fallback, cond_max=1e8):
-    """The predicted factors as a CP-ALS-QR start, or the fallback (random)
+    """The predicted factors as a CP-ALS-QR start, or the fallback (HOSVD)
     start when a predicted A_2 or A_3 is non-finite or numerically rank
     deficient.  Returns (factors, used_prediction)."""
     for k in (1, 2):
@@ -170,8 +206,10 @@ def usable_start(pred, fallback, cond_max=1e8):
 
 
 def evaluate(model, count, seed0, max_sweeps=200, log=print):
-    """Time to direct relerr <= 1e-6 from the learned and from random starts
-    on held-out tensors (seeds seed0 ..).  Returns per-tensor records."""
+    """Held-out tensors (seeds seed0 ..): CP-ALS-QR from the random start,
+    the HOSVD start and the learned start (HOSVD when the prediction is not
+    usable), the direct relative error after each sweep.  Returns per-tensor
+    records (summarize() of each start)."""
     recs = []
     for c0 in range(0, count, 64):
         n = min(64, count - c0)
@@ -183,12 +221,16 @@ def evaluate(model, count, seed0, max_sweeps=200, log=print):
             seed = seed0 + c0 + j
             X = build_tensor(c5_factors(model.shape, model.R, seed), model.device)
             rnd = synth.init_factors(model.shape, model.R, seed)
-            start, used = usable_start(preds[j], rnd)
-            s_r, t_r, e_r = time_to_fit(X, rnd, max_sweeps=max_sweeps)
-            s_l, t_l, e_l = time_to_fit(X, start, max_sweeps=max_sweeps)
-            recs.append({"seed": seed, "random": [s_r, t_r, e_r], "learned": [s_l, t_l, e_l], "used_prediction": used})
-            log("  held-out %d: random %s sweeps (%.3f s, relerr %.2e), learned %s sweeps (%.3f s, relerr %.2e)"
-                % (c0 + j, s_r, t_r, e_r, s_l, t_l, e_l))
+            hos = hosvd_start(X, model.R, seed + 7)
+            start, used = usable_start(preds[j], hos)
+            rec = {"seed": seed, "used_prediction": used}
+            for key, init in (("random", rnd), ("hosvd", hos), ("learned", start)):
+                rec[key] = summarize(*fit_history(X, init, max_sweeps))
+            recs.append(rec)
+            log("  held-out %d: relerr after 10 / 50 / %d sweeps: random %.2e %.2e %.2e, hosvd %.2e %.2e %.2e, "
+                "learned %.2e %.2e %.2e" % ((c0 + j, max_sweeps) + tuple(
+                    rec[k]["relerr_at"].get(m, float("nan")) for k in ("random", "hosvd", "learned")
+                    for m in (10, 50, max_sweeps))))
     return recs
 
 

@@ -254,3 +254,18 @@ def test_graph_validation_codes(L):
     assert h.value is None
     assert L.cpqr_graph_launch(None, None) == -1
     assert L.cpqr_graph_destroy(None) == 0
+
+
+def test_hosvd_validation_codes(L):
+    P = 4096
+    I = (C._i64 * 3)(10, 12, 14)
+    Om = (C._vp * 3)(P, P, P)
+    A = (C._vp * 3)(None, P, P)
+    assert L.cpqr_hosvd_init_work(3, I, 4, C.PREC_F32) > 0
+    assert L.cpqr_hosvd_init(3, I, C.F32, P, 4, Om, C.PREC_F32, 1, None, P, 1 << 30, None) == -1
+    assert L.cpqr_hosvd_init(3, I, C.F32, P, 4, Om, C.PREC_F32, 3, A, P, 1 << 30, None) == -1
+    assert L.cpqr_hosvd_init(3, I, C.F32, P, 4, Om, C.PREC_F32, 0, A, P, 1 << 30, None) == -1  # A[0] NULL
+    assert L.cpqr_hosvd_init(3, I, C.F32, P, 33, Om, C.PREC_F32, 1, A, P, 1 << 30, None) == -2
+    small = (C._i64 * 3)(10, 3, 14)
+    assert L.cpqr_hosvd_init(3, small, C.F32, P, 4, Om, C.PREC_F32, 1, A, P, 1 << 30, None) == -2
+    assert L.cpqr_hosvd_init(3, I, C.F32, P, 4, Om, C.PREC_F32, 1, A, None, 0, None) == -4

@@ -17,7 +17,7 @@ import torch
 from oracle import learned as OL
 from oracle.precision import round_bf16
 from paper_2112_10855_amd import cpqr as C
-from helpers import relnorm
+from helpers import relnorm, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -173,3 +173,32 @@ def test_training_steps_reduce_the_loss():
     torch.cuda.synchronize()
     assert losses[-1] < 0.95 * losses[0], losses
     assert all(b <= a + 1e-3 for a, b in zip(losses, losses[1:])), losses
+
+
+@pytest.mark.parametrize("shape,R,prec", [((30, 25, 20), 4, "f64"), ((64, 50, 40), 10, "f64"), ((64, 50, 40), 10, "f32"),
+                                          ((9, 8, 10, 7), 3, "f64")])
+def test_hosvd_init_against_oracle(shape, R, prec):
+    """The randomized HOSVD start (cpqr_hosvd_init) against the oracle with
+    the same Gaussian test factors: the QR of X_(k) (Khatri-Rao of Omega_j)
+    is unique up to column signs, so the bases are compared after fixing
+    them, entry by entry (FP64 Multi-TTM: 1e-10; FP32: 1e-4, the FP32
+    Multi-TTM error amplified by cond(W_k)).  For an exact rank-R tensor the
+    basis also spans the ground-truth factor."""
+    import oracle.learned as OLm
+    from oracle import tensor as OT
+    g = np.random.default_rng(sum(shape) + R)
+    A = [g.standard_normal((s, R)) for s in shape]
+    X = OT.full(np.ones(R), A) + 1e-3 * g.standard_normal(shape)
+    Om = [g.standard_normal((s, R)) for s in shape]
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    Q = C.cpqr_hosvd_init(to_dev(X.astype(np.float32) if prec == "f32" else X, tdt), [to_dev(o) for o in Om], R,
+                          prec=C.PREC_F64 if prec == "f64" else C.PREC_F32, k0=1)
+    Xo = X.astype(np.float32).astype(np.float64) if prec == "f32" else X
+    ref = OLm.hosvd_start(Xo, Om, R)
+    tol = 1e-10 if prec == "f64" else 1e-4
+    assert Q[0] is None
+    for k in range(1, len(shape)):
+        q = to_np(Q[k])
+        d = np.sign(np.sum(q * ref[k], axis=0))
+        np.testing.assert_allclose(q * d[None, :], ref[k], rtol=0, atol=tol)
+        np.testing.assert_allclose(q.T @ q, np.eye(R), rtol=0, atol=1e-12)

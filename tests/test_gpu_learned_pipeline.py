@@ -1,8 +1,9 @@
 """The learned-initialization pipeline end to end at a small size: method
 targets from the batched CP-ALS-QR, training on the GPU kernels, and the
-prediction used as a CP-ALS-QR start.  What the trained network gains over
-the untrained one on held-out tensors is measured and printed; training is
-required to lower the training loss (the kernels and Adam work together)."""
+prediction used as a CP-ALS-QR start, with the randomized HOSVD start as the
+fallback.  Training is required to lower the training loss (the kernels and
+Adam work together); the three starts are run on held-out tensors and their
+relative errors after each sweep are compared."""
 
 import numpy as np
 import pytest
@@ -13,16 +14,41 @@ from paper_2112_10855_amd import learned as LI
 pytestmark = pytest.mark.gpu
 
 
-def test_pipeline_trains_and_initializes():
+@pytest.fixture(scope="module")
+def trained():
     model = LI.LearnedInit(shape=(64, 64, 64), R=4, J=64, hidden=64, seed=3)
     xs, tg = LI.make_dataset(model, 256, seed0=500, sweeps=30, chunk=128, log=lambda *a: None)
     assert torch.isfinite(tg).all()
     before = LI.heldout_loss(model, 64, 9000)
     hist = LI.train(model, xs, tg, epochs=15, batch=64, lr=1e-3, log=lambda *a: None)
     after = LI.heldout_loss(model, 64, 9000)
+    recs = LI.evaluate(model, 8, 9000, max_sweeps=60, log=lambda *a: None)
+    return model, hist, before, after, recs
+
+
+def geomean(recs, key, m):
+    return float(np.exp(np.mean([np.log(max(r[key]["relerr_at"][m], 1e-300)) for r in recs])))
+
+
+def test_pipeline_trains_and_initializes(trained):
+    model, hist, before, after, recs = trained
     print("train loss %.4f -> %.4f, held-out %.4f -> %.4f" % (hist[0], hist[-1], before, after))
+    for m in (10, 25, 50):
+        print("after %d sweeps: random %.3e, hosvd %.3e, learned %.3e"
+              % (m, geomean(recs, "random", m), geomean(recs, "hosvd", m), geomean(recs, "learned", m)))
     assert hist[-1] < hist[0]
     assert np.isfinite(after)
-    recs = LI.evaluate(model, 2, 9000, max_sweeps=60, log=lambda *a: None)
     for r in recs:
-        assert r["learned"][2] == r["learned"][2]  # a finite relative error came back
+        for key in ("random", "hosvd", "learned"):
+            assert np.isfinite(r[key]["final"])
+
+
+@pytest.mark.skip(reason="the trained network does not beat the random start on held-out tensors of the "
+                         "congruence-0.9 workloads: its held-out Kruskal loss stays near 1 and the CP-ALS-QR "
+                         "errors from its start match those from random starts (measured numbers in the design "
+                         "notes); the assertion is kept for when a network does")
+def test_learned_start_gains_over_random(trained):
+    model, hist, before, after, recs = trained
+    assert after < 0.9 * before
+    for m in (10, 25):
+        assert geomean(recs, "learned", m) < 0.8 * geomean(recs, "random", m)
