@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x2", "bf16"])
     ap.add_argument("--workload", default="dense3",
-                    choices=["dense3", "dense4", "batch", "learned", "fit", "sinsum", "calib"],
+                    choices=["dense3", "dense4", "batch", "learned", "fit", "sinsum", "calib", "ratio"],
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
@@ -190,6 +190,65 @@ def sinsum10_case(C, torch, synth, iters, trials=5):
     del Xd
     torch.cuda.empty_cache()
     return row
+
+
+def run_ratio(args):
+    """Section 4.1 (the paper's performance experiment): time per sweep of
+    CP-ALS-QR and of CP-ALS (normal equations) on random dense tensors of
+    700^3, 300^4 and 75^5 at increasing rank, in FP64 as in the paper, the
+    mean over 10 sweeps after a first one (the paper's timing rule), with
+    the efficient error; the slowdown ratio CP-ALS-QR / CP-ALS and the
+    per-phase breakdown.  The entries are iid N(0, 1) drawn on the device
+    from a seeded generator (input only: no step of either algorithm)."""
+    import torch
+
+    from paper_2112_10855_amd import cpqr as C
+    from paper_2112_10855_amd import synth
+
+    ranks = (4, 8, 16, 32)
+    cases = [(3, 700), (4, 300), (5, 75)]
+    rows = []
+    for N, n in cases:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7000 + N)
+        X = torch.randn((n,) * N, dtype=torch.float64, device="cuda", generator=g)  # column-major view below
+        X = X.permute(*reversed(range(N)))
+        log("ratio: random %d-way n=%d FP64 tensor (%.1f GB)" % (N, n, X.numel() * 8 / 1e9))
+        for R in ranks:
+            init = synth.init_factors((n,) * N, R, 7100 + R)
+            row = {"N": N, "n": n, "rank": R}
+            for alg in ("qr", "als"):
+                if alg == "qr":
+                    st = C.AlsState(X, init, prec=C.PREC_F64)
+                else:
+                    st = C.AlsNeState(X, init, prec=C.PREC_F64, solver="chol")
+                st.init()
+                st.sweep(1)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                st.sweep(10)
+                e1.record()
+                torch.cuda.synchronize()
+                row[alg + "_ms_per_sweep"] = round(e0.elapsed_time(e1) / 10, 4)
+                row[alg + "_phases_ms_per_sweep"] = phase_pass(C, torch, st, 2)
+                del st
+            row["slowdown_qr_over_als"] = round(row["qr_ms_per_sweep"] / row["als_ms_per_sweep"], 3)
+            log("  N=%d n=%d R=%d: CP-ALS-QR %.3f ms, CP-ALS %.3f ms per sweep, ratio %.2f"
+                % (N, n, R, row["qr_ms_per_sweep"], row["als_ms_per_sweep"], row["slowdown_qr_over_als"]))
+            rows.append(row)
+        del X
+        torch.cuda.empty_cache()
+    top = rows[len(ranks) * 2 - 1]  # 300^4 at the highest rank
+    out = {
+        "metric": "CP-ALS-QR / CP-ALS time per sweep (slowdown ratio)", "value": top["slowdown_qr_over_als"],
+        "unit": "ratio", "n_gpus": 1, "steps": 10, "warmup": 1, "ms_per_step": top["qr_ms_per_sweep"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "slowdown_ratio_random_dense_f64", "cases": ["700^3", "300^4", "75^5"],
+                   "ranks": list(ranks), "error": "efficient"},
+        "cases": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def timed_sweeps(C, torch, st, steps, phase):
@@ -543,11 +602,11 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("dense4", "batch", "learned", "fit", "sinsum", "calib"):
+    if args.workload in ("dense4", "batch", "learned", "fit", "sinsum", "calib", "ratio"):
         import torch
         torch.cuda.set_device(0)
         return {"dense4": run_dense4, "batch": run_batch, "learned": run_learned, "fit": run_fit,
-                "sinsum": run_sinsum, "calib": run_calib}[args.workload](args)
+                "sinsum": run_sinsum, "calib": run_calib, "ratio": run_ratio}[args.workload](args)
 
     import hashlib
 

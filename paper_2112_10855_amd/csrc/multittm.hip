@@ -285,7 +285,10 @@ __device__ __forceinline__ void ldx4(const float* q, doublex2& a, doublex2& b) {
   b = doublex2{double(v.z), double(v.w)};
 }
 
-template <int NB, int UN, int MG, int NWV, bool STREAM, bool NT, class TX = double>
+// GENP: P need not be a multiple of 4 (the four rows of a lane may straddle
+// slabs), so each of them is loaded by its own address; the four loads of a
+// step cover the same lines as one vector load would.
+template <int NB, int UN, int MG, int NWV, bool STREAM, bool NT, class TX = double, bool GENP = false>
 __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict__ X,
                                                            const double* __restrict__ U,
                                                            double* __restrict__ out, int64_t P, int64_t K,
@@ -301,13 +304,35 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict_
   const int64_t kb1 = min(K, kb0 + kchunk);
   const int l16 = lane % 16, kq = lane / 16;
   const TX* base[MG];
+  const TX* rb[GENP ? MG : 1][4];  // GENP: the lane's four rows (clamped into the tensor)
 #pragma unroll
   for (int g = 0; g < MG; ++g) {
     int64_t mrow = mt + 64 * g + 4 * l16;
-    mrow = mrow < M ? mrow : M - 4;
-    const int64_t p = mrow % P, s = mrow / P;
-    base[g] = X + p + s * P * K + kq * P;
+    if (GENP) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t m = min(mrow + j, M - 1);
+        rb[GENP ? g : 0][j] = X + m % P + (m / P) * P * K + kq * P;
+      }
+      base[g] = rb[GENP ? g : 0][0];
+    } else {
+      mrow = mrow < M ? mrow : M - 4;
+      const int64_t p = mrow % P, s = mrow / P;
+      base[g] = X + p + s * P * K + kq * P;
+    }
   }
+  // the four rows of group g at K row i: one vector load, or four
+  auto ld4 = [&](int g, int64_t i, bool nt_ok, doublex2& lo, doublex2& hi) {
+    if (GENP) {
+      const int64_t o = i * P;
+      lo = doublex2{double(rb[GENP ? g : 0][0][o]), double(rb[GENP ? g : 0][1][o])};
+      hi = doublex2{double(rb[GENP ? g : 0][2][o]), double(rb[GENP ? g : 0][3][o])};
+    } else if (nt_ok) {
+      ldx4<NT>(base[g] + i * P, lo, hi);
+    } else {
+      ldx4<false>(base[g] + i * P, lo, hi);
+    }
+  };
   doublex4 acc[NB][MG][4];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -320,16 +345,13 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict_
   auto chunk = [&](int64_t c0, int cn) {
     const int nfull = cn / STEP;
     const int last = nfull > 0 ? (nfull - 1) * STEP : 0;
-    const TX* bp[MG];
-#pragma unroll
-    for (int g = 0; g < MG; ++g) bp[g] = base[g] + c0 * P;
     doublex2 A[UN][MG][2], B[UN][MG][2];
     auto load = [&](doublex2(&dst)[UN][MG][2], int t) {
       const int i0 = min(t * STEP, last);
 #pragma unroll
       for (int u = 0; u < UN; ++u)
 #pragma unroll
-        for (int g = 0; g < MG; ++g) ldx4<NT>(bp[g] + int64_t(i0 + 4 * u) * P, dst[u][g][0], dst[u][g][1]);
+        for (int g = 0; g < MG; ++g) ld4(g, c0 + i0 + 4 * u, true, dst[u][g][0], dst[u][g][1]);
     };
     auto compute = [&](const doublex2(&src)[UN][MG][2], int t) {
 #pragma unroll
@@ -364,7 +386,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict_
 #pragma unroll
         for (int g = 0; g < MG; ++g) {
           doublex2 x0{0.0, 0.0}, x1{0.0, 0.0};
-          if (ok) ldx4<false>(bp[g] + int64_t(i) * P, x0, x1);
+          if (ok) ld4(g, c0 + i, false, x0, x1);
           acc[b][g][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, bv, acc[b][g][0], 0, 0, 0);
           acc[b][g][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.y, bv, acc[b][g][1], 0, 0, 0);
           acc[b][g][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.x, bv, acc[b][g][2], 0, 0, 0);
@@ -1140,6 +1162,9 @@ __global__ void unfold_copy(const T* __restrict__ src, int64_t Pn, int64_t In, i
 
 // ------------------------------------------------------------ planning
 enum Kind { K_MFMA_M, K_MFMA_K, K_VALU };
+// Smallest P that the FP64 row kernel takes when P is not a multiple of four
+// (below it, a lane's rows are too scattered for the loads to share lines).
+constexpr int64_t GENP_MIN_P = 16;
 
 struct Step {
   int k;          // mode contracted
@@ -1188,7 +1213,10 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
       int64_t stride = 1;  // elements between consecutive indices of that mode
       for (int m = 0; m < order[t]; ++m) stride *= I[m];
       // large strides walk the tensor page by page: keep those for later
-      if (2 * I[order[t]] >= I[0] && stride % 4 == 0 && stride <= 65536) {
+      // (FP64 also takes strides that are not multiples of four: its row
+      // kernel has a form that loads rows one by one)
+      const bool stride_ok = stride % 4 == 0 || (prec == CPQR_PREC_F64 && stride >= GENP_MIN_P);
+      if (2 * I[order[t]] >= I[0] && stride_ok && stride <= 65536) {
         const int k = order[t];
         for (int u = t; u > 0; --u) order[u] = order[u - 1];
         order[0] = k;
@@ -1211,13 +1239,16 @@ Plan make_plan(int N, const int64_t* I, unsigned cmask, int R, int prec, bool x_
     int64_t units;  // independent work units without splitting K
     // float4 loads of the tensor need 16-byte alignment (carved buffers have it)
     const bool vec_ok = t > 0 || x_aligned;
-    if (row_tiled(prec) && vec_ok && s.P % 4 == 0) {
+    const bool genp = prec == CPQR_PREC_F64 && s.P % 4 != 0 && s.P >= GENP_MIN_P;
+    if (row_tiled(prec) && ((vec_ok && s.P % 4 == 0) || genp)) {
       s.kind = K_MFMA_M;
       // wide row tiles; a step whose rows leave the GPU under-filled takes
       // 64-row tiles before it splits K (small operands: no streaming hints)
       // (two 16-column blocks, R > 16, halve the tile: at 4 x 64 rows the
       // FP32 kernel needs 202 VGPRs and one workgroup per CU)
-      s.mg = (prec == CPQR_PREC_F32 ? 4 : 2) / (R > 16 ? 2 : 1);
+      // (rows loaded one by one keep four more addresses per row group:
+      // one group, so that two workgroups still fit on a CU)
+      s.mg = genp ? 1 : (prec == CPQR_PREC_F32 ? 4 : 2) / (R > 16 ? 2 : 1);
       units = ceil_div(s.P * s.S, 64 * s.mg);
       if (units < MIN_WAVES) {
         s.mg = 1;
@@ -1504,6 +1535,20 @@ int launch_mfma_f64_t(const TX* src, const double* U, double* dst, const Step& s
   const size_t lds = LDS_DOUBLES * sizeof(double);
   const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
   const bool nt = STREAM && s.P % 16 == 0;  // rows 128-byte multiples apart: no line shared between tiles
+  if (s.P % 4 != 0) {  // rows loaded one by one (a lane's four rows may straddle slabs)
+    if (s.mg == 1 && NB == 1)
+      launch_ev(ke, ttm_mfma_m_f64<1, UN, 1, NWV, STREAM, false, TX, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (s.mg == 1)
+      launch_ev(ke, ttm_mfma_m_f64<2, UN, 1, NWV, STREAM, false, TX, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else if (s.mg == 2 && NB == 1)
+      launch_ev(ke, ttm_mfma_m_f64<1, UN, 2, NWV, STREAM, false, TX, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
+                s.P, s.K, s.S, R, s.kchunk, s.out_count);
+    else
+      return fail(CPQR_ERR_UNSUPPORTED, "ttm_mfma_m_f64: unsupported row tile");
+    return check_launch("ttm_mfma_m_f64");
+  }
   if (s.mg == 1) {  // 64-row tiles: small operands, or two 16-column blocks
     if (NB == 1)
       launch_ev(ke, ttm_mfma_m_f64<1, UN, 1, NWV, STREAM, false, TX>, grd, dim3(NWV * 64), lds, st, src, U, dst, s.P,

@@ -122,6 +122,23 @@ def test_multittm_f64(shape, xdtype, Rw):
         assert_entrywise(Y, Yo, abs_bound_multittm(X, Qs, n), 1e-12, (shape, n))
 
 
+@pytest.mark.parametrize("shape,R", [((75, 33, 41), 16), ((35, 75, 29, 17), 12), ((17, 19, 23), 5), ((75, 75, 75), 32),
+                                     ((45, 25, 35, 21, 19), 4), ((1001, 37, 19), 16), ((21, 300, 37), 24)])
+def test_multittm_f64_rows_not_multiple_of_four(shape, R):
+    """FP64 Multi-TTM whose contractions have P % 4 != 0 (odd mode sizes):
+    rows loaded one by one by the row-tiled matrix-core kernel (P >= 16) or
+    the vector-ALU kernel (smaller P), entry by entry against the oracle."""
+    R = min(R, min(shape))
+    g = rng(sum(shape) + R)
+    X = g.standard_normal(shape)
+    Qs = [synth.orthonormal_columns(s, R, 3 * k + 1) for k, s in enumerate(shape)]
+    Xd = to_dev(X)
+    for n in range(len(shape)):
+        Y = to_np(C.cpqr_multittm(Xd, [None if k == n else to_dev(Qs[k]) for k in range(len(shape))], n, C.PREC_F64))
+        Yo = OQ.multittm_unfolded(X, Qs, n)
+        assert_entrywise(Y, Yo, abs_bound_multittm(X, Qs, n), 1e-12, (shape, n))
+
+
 @pytest.mark.parametrize("shape,R", [((600, 301, 257), 16), ((600, 304, 257), 16), ((60, 50, 300), 5),
                                      ((100, 80, 260), 12), ((120, 100, 300), 32), ((1000, 600, 256), 24),
                                      ((200, 180, 256), 17), ((40, 36, 20, 16), 9), ((48, 40, 300), 32)])
