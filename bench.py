@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--fit-n", type=int, default=200, help="mode size of the time-to-fit study (--workload fit)")
     ap.add_argument("--krp-chain", type=int, default=-1,
                     help="QR of the Khatri-Rao product: 1 structured, 0 dense, -1 structured for N >= 4")
+    ap.add_argument("--ratio-cases", default="",
+                    help="--workload ratio: comma-separated NxI cases (default 3x700,4x300,5x75)")
     ap.add_argument("--graph", action="store_true",
                     help="time one HIP graph launch of the sweeps as the value (default: eager sweeps; the graph "
                          "launch is then reported beside)")
@@ -207,6 +209,8 @@ def run_ratio(args):
 
     ranks = (4, 8, 16, 32)
     cases = [(3, 700), (4, 300), (5, 75)]
+    if args.ratio_cases:  # e.g. "5x75": a subset, for profiling
+        cases = [tuple(int(v) for v in c.split("x")) for c in args.ratio_cases.split(",")]
     rows = []
     for N, n in cases:
         g = torch.Generator(device="cuda")
@@ -239,7 +243,7 @@ def run_ratio(args):
             rows.append(row)
         del X
         torch.cuda.empty_cache()
-    top = rows[len(ranks) * 2 - 1]  # 300^4 at the highest rank
+    top = rows[min(len(rows), len(ranks) * 2) - 1]  # 300^4 at the highest rank (the last case of a subset)
     out = {
         "metric": "CP-ALS-QR / CP-ALS time per sweep (slowdown ratio)", "value": top["slowdown_qr_over_als"],
         "unit": "ratio", "n_gpus": 1, "steps": 10, "warmup": 1, "ms_per_step": top["qr_ms_per_sweep"],
