@@ -461,7 +461,7 @@ def run_batch(args):
     log("generated %d tensors (%.2f GB) in %.1f s" % (len(shapes), nbytes / 1e9, time.time() - t0))
     nsw = args.steps
     B = C.AlsBatch(Xs, inits, nsw + 1, autotune=True)
-    log("autotuned: %d columns per thread, %d steps in flight, row blocks of %d" % B.config)
+    log("autotuned: %d rows per lane, %d steps in flight, row blocks of %d" % B.config)
     B.run(1, init=True, graph=True)  # warm-up: init + one sweep (captured, replayed below)
     torch.cuda.synchronize()
     B2 = C.AlsBatch(Xs, inits, nsw)
@@ -482,7 +482,7 @@ def run_batch(args):
         "n_gpus": 1, "steps": nsw, "warmup": 1, "ms_per_step": round(ms / nsw, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "cp_als_qr_batch%d_3way_20to160_r2to12" % len(shapes), "tensors": len(shapes),
-                   "total_bytes": nbytes, "sweeps": nsw, "cols_unroll_rows": list(B.config),
+                   "total_bytes": nbytes, "sweeps": nsw, "rows_depth_rowblock": list(B.config),
                    "launch": "one persistent kernel per call, replayed from a hipGraph"},
         "batch_ms_total": round(ms, 3),
         "tensor_pass_gbps": round(pass_bytes * nsw / (ms / 1e3) / 1e9, 1),

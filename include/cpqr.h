@@ -403,18 +403,23 @@ int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* 
  * launch: one workgroup runs every sweep of one tensor, tensors taken
  * largest first, no waits between workgroups.  The contraction X x_3 Q_3^T
  * is shared by the updates of modes 1 and 2 (reuse of partial TTMs across
- * modes), so a sweep reads each tensor twice.  Contractions in FP32, all
- * else FP64.  Limits: R <= 16, R <= I[k] <= 256; X 4-byte aligned.
+ * modes), so a sweep reads each tensor twice.  Contractions in FP32 on the
+ * matrix cores, all else FP64.  Limits: R <= 16, R <= I[k] <= 256; X
+ * 4-byte aligned.
  *
  * Ownership: every pointer in an item is caller-owned device memory that
  * must stay valid while the prepared work buffer is used; A[0] is written
- * only.  relerr (nullable) must hold sweep_offset + nsweeps doubles.
+ * only.  relerr (nullable) must hold sweep_offset + nsweeps doubles.  The
+ * streaming passes read 16-byte runs along the first mode: a tensor whose
+ * I[0] is not a multiple of 4, or that is not 16-byte aligned, is streamed
+ * from a copy in the work buffer with its first mode zero-padded, taken by
+ * prepare; X must not change between prepare and the runs that use it.
  *
  * cpqr_als_batch_work returns the work-buffer size (0 for invalid items).
  * cpqr_als_batch_prepare writes the per-tensor descriptors into the work
  * buffer (synchronous: it returns after the stream has drained).  With
- * autotune != 0 it picks the streaming-pass shape (tensor columns per
- * thread, contraction steps in flight) and the row-block height by timing
+ * autotune != 0 it picks the streaming-pass depth (contraction steps in
+ * flight per lane: 8, 16 or 24) and the row-block height by timing
  * an init + one sweep of each candidate on the batch itself (the initial
  * factors are restored afterwards); choices are cached per (architecture,
  * batch shape) in the file named by CPQR_AUTOTUNE_CACHE (default
@@ -441,7 +446,10 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
                            size_t work_bytes, void* stream);
 int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream);
 int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream);
-/* the configuration chosen by prepare (any output may be NULL) */
+/* the configuration chosen by prepare (any output may be NULL): tensor rows
+ * a lane carries through the streaming pass (4), contraction steps in flight,
+ * and the requested row-block height (the kernel rounds it down to a multiple
+ * of 16 that fits its Y-row buffer) */
 int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* rows);
 
 /*

@@ -16,9 +16,10 @@
 // across modes (dimension trees) that the paper names for Multi-TTM.  The
 // results equal the per-mode Multi-TTMs up to FP32 rounding order.
 //
-// Arithmetic: contractions in FP32 on FP32 copies of Q_k, everything else
-// in FP64.  Limits: R <= 16, R <= I_k <= 256 (the factor QR keeps one row
-// per thread).
+// Arithmetic: contractions in FP32 on FP32 copies of Q_k (on the matrix
+// cores, v_mfma_f32_16x16x4f32, 16 output columns >= R), everything else in
+// FP64.  Limits: R <= 16, R <= I_k <= 256 (the factor QR keeps one row per
+// thread).
 
 #include <sys/stat.h>
 
@@ -42,14 +43,17 @@ constexpr int NT = 256;    // threads per workgroup
 constexpr int NW = NT / WAVE;
 constexpr int RB = 16;     // register width for rank-indexed rows (R <= 16)
 constexpr int IMAX = 256;  // largest mode size
-constexpr int YS = 4096;   // floats of Y rows held per row block
+constexpr int K0P = RB * RB + 1;  // longest Y row (R^2) plus one float of padding
+constexpr int YSF = 16 * K0P;     // floats of Y rows held per row block (16 rows at R = 16)
+constexpr int WROWS = 64;         // most rows per block
 
 struct BItem {
   int64_t I[3];
   int R;
   int nB[3];     // row blocks per mode
   int rows[3];   // rows per block per mode
-  const float* X;
+  const float* X;  // streamed copy: first mode padded to I0p (zeros), 16-byte aligned
+  int64_t I0p;     // I[0] rounded up to a multiple of 4
   double* A[3];
   double* lam;
   double* relerr;
@@ -58,22 +62,32 @@ struct BItem {
   double* Rf[3];   // R_k, column-major R x R
   double* Q0b[3];  // Q_0 for mode n, row-major R^2 x R
   double* R0b[3];  // R_0 for mode n, column-major R x R
-  float* Z;        // Z[i1 + I1 i2 + I1 I2 r3]
-  float* T;        // T[i1 + I1 r2 + I1 R i3]
+  float* Z;        // Z[i1 + I0p i2 + I0p I1 r3] (rows i1 >= I0 zero)
+  float* T;        // T[i1 + I0p r2 + I0p R i3]
   double* lamp;    // [block][RB] column sums of squares of A rows per block
   double* ipp;     // [block] <W, A R_0^T> per block (mode 3)
   double* xnorm2;  // ||X||^2
 };
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// The descriptors hold generic pointers; tensor traffic goes through these
+// global-memory views so that it compiles to global (not flat) loads and
+// stores, which the LDS counter does not wait on.
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ inline gcfloat* gview(const float* p) { return (gcfloat*)p; }
+__device__ inline gfloat* gview(float* p) { return (gfloat*)p; }
+
+// 77 KB: two workgroups share a CU's 160 KB.
 struct BShared {
+  alignas(16) float us[IMAX * RB];  // contraction operand U (FP32, k-major, 16 columns)
   union alignas(16) {
-    float us[IMAX * RB];  // contraction operand (FP32), later W rows (FP64)
-    double ws[IMAX * RB / 2];
-  };
-  union alignas(16) {
-    float ys[YS];  // Y rows of a block, row-major nb x R^2
+    float ys[YSF];  // Y rows of a block, row stride R^2 + 1
     Shared<RB, NT> qr;
   };
+  double q0[RB * RB * RB];  // Q_0 of the current mode, row-major R^2 x R
+  double ws[WROWS * RB];    // W rows of a block (FP64)
   double r0[RB][RB + 1];
   double rn[RB][RB + 1];
   double lam[RB];
@@ -81,110 +95,192 @@ struct BShared {
   double res[RB];
 };
 
-__device__ inline void stage_qf(const float* Qf, int rows, float* us, int tid) {
+// U rows [0, rows) into LDS (row-major, 16 floats a row, zero past R) and
+// zero rows up to the next multiple of 4, so that a 4-step MFMA over the
+// contraction index reads zeros past its end.
+__device__ inline void stage_u(const float* Qf, int rows, float* us, int tid) {
   const float4* src = reinterpret_cast<const float4*>(Qf);
   float4* dst = reinterpret_cast<float4*>(us);
-  for (int e = tid; e < rows * (RB / 4); e += NT) dst[e] = src[e];
+  const int n = rows * (RB / 4), n4 = ((rows + 3) & ~3) * (RB / 4);
+  for (int e = tid; e < n4; e += NT) dst[e] = e < n ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int RR>
-__device__ inline void fma_row(float (&acc)[RR], float x, const float* urow) {
-  const float4* ur = reinterpret_cast<const float4*>(urow);
-#pragma unroll
-  for (int q = 0; q < RR / 4; ++q) {
-    const float4 uv = ur[q];
-    acc[4 * q] = fmaf(x, uv.x, acc[4 * q]);
-    acc[4 * q + 1] = fmaf(x, uv.y, acc[4 * q + 1]);
-    acc[4 * q + 2] = fmaf(x, uv.z, acc[4 * q + 2]);
-    acc[4 * q + 3] = fmaf(x, uv.w, acc[4 * q + 3]);
-  }
-}
+// ------------------------------------------------- streaming pass (AZ, AT)
+// out[p + P r + P R s] = sum_k X[p + P k + P K s] U[k, r] for every row
+// m = p + P s < M = P S of the [M, K] matrix (P a multiple of 4, X and out
+// 16-byte aligned), U (K x R, rows zero past K) in LDS.  Rows go on the M
+// dimension of v_mfma_f32_16x16x4f32 in 64-row tiles, tiles dealt to the
+// waves round robin.  In step t of a tile, lane (l16, kq) loads the 16-byte
+// run of rows m0 + 4 l16 .. + 3 at k = 4 t + kq and feeds its four values to
+// four MFMAs that share the B operand U[k, l16]; at the end the lane holds
+// rows m0 + 16 kq + 4 v + j (v, j = 0..3) of column l16.  The loads go
+// through a buffer resource, so k >= K (and rows past M) read zeros from
+// its range check.  The steps of all of a wave's tiles form one sequence
+// whose loads run D steps ahead of the MFMAs; a tile's results leave when
+// its last step is done.  The order of every sum is fixed by the layout
+// alone, so any D gives the same bits.  SQ: xx += the sum of x^2.
+constexpr uint32_t OOB = 0x80000000u;  // a byte offset past any tensor here (at most 64 MB)
 
-// ------------------------------------------------- streaming tile (AZ, AT)
-// out[p + P r + P R s] = sum_k X[p + P k + P K s] U[k, r] for the columns
-// m = p + P s in [m0, m1); U rows in LDS.  xx += sum of x^2 when want_sq.
-template <int RR, int CPT, int U>
-__device__ void stream_tile(const float* __restrict__ X, float* __restrict__ out, int64_t P, int K, int R,
-                            int64_t m0, int64_t m1, const float* us, bool want_sq, double& xx, int tid) {
-  for (int64_t base = m0; base < m1; base += NT * CPT) {
-    const float* xp[CPT];
-    int64_t ob[CPT];
-    bool valid[CPT];
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      const int64_t m = base + tid + NT * j;
-      valid[j] = m < m1;
-      const int64_t mm = valid[j] ? m : m0;
-      const int64_t s = mm / P, p = mm - s * P;
-      xp[j] = X + p + P * K * s;
-      ob[j] = p + P * R * s;
+template <int D, bool SQ>
+__device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out, uint32_t P, int K, uint32_t S,
+                            int R, const float* us, double& xx, int tid) {
+  const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
+  const uint32_t M = P * S;
+  const int ntile = int((M + 63) / 64);
+  const int nks = (K + 3) >> 2;
+  const int mytiles = ntile > w ? (ntile - w + NW - 1) / NW : 0;
+  if (mytiles == 0) return;
+  const int nsteps = mytiles * nks;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), short(0), int(M * uint32_t(K) * 4u), 0x00020000);
+  const uint32_t step_bytes = P * 16u;
+
+  // load side: tile lt of this wave, step lk within it; past the last step
+  // the loads repeat the last tile (their values are not used)
+  int lt = 0, lk = 0;
+  auto run_off = [&](int t) -> uint32_t {  // byte offset of the lane's run at k = kq
+    const uint32_t m = uint32_t(w + t * NW) * 64u + 4u * uint32_t(l16);
+    if (m >= M) return OOB;
+    const uint32_t s = m / P, p = m - s * P;
+    return (p + P * (uint32_t(K) * s + uint32_t(kq))) * 4u;
+  };
+  uint32_t lvo = run_off(0);
+  auto load = [&](u32x4& dst) {
+    const uint32_t vo = 4 * lk + kq < K ? lvo : OOB;
+    dst = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, uint32_t(lk) * step_bytes, 0);
+    if (++lk == nks) {
+      lk = 0;
+      if (lt + 1 < mytiles) lvo = run_off(++lt);
     }
-    float acc[CPT][RR], sq[CPT];
+  };
+
+  // compute side: tile ct, step ck
+  int ct = 0, ck = 0;
+  floatx4 acc[4];
+  float sq = 0.f;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      sq[j] = 0.f;
+  for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  gfloat* const og = gview(out);
+  auto finish_tile = [&]() {
+    if (l16 < R) {
+      const uint32_t m0 = uint32_t(w + ct * NW) * 64u + 16u * uint32_t(kq);
 #pragma unroll
-      for (int r = 0; r < RR; ++r) acc[j][r] = 0.f;
-    }
-    int k = 0;
-    for (; k + U <= K; k += U) {
-      float x[CPT][U];
-#pragma unroll
-      for (int j = 0; j < CPT; ++j)
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[j][u] = valid[j] ? xp[j][int64_t(k + u) * P] : 0.f;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-          fma_row<RR>(acc[j], x[j][u], us + (k + u) * RB);
-          sq[j] = fmaf(x[j][u], x[j][u], sq[j]);
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t m = m0 + 4u * uint32_t(v);
+        if (m < M) {
+          const uint32_t s = m / P, p = m - s * P;
+          *reinterpret_cast<__attribute__((address_space(1))) floatx4*>(og + p + size_t(P) * (size_t(l16) + size_t(R) * s)) =
+              floatx4{acc[0][v], acc[1][v], acc[2][v], acc[3][v]};
         }
       }
     }
-    for (; k < K; ++k) {
+    if (SQ) xx += double(sq);
+    sq = 0.f;
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) {
-        const float xv = valid[j] ? xp[j][int64_t(k) * P] : 0.f;
-        fma_row<RR>(acc[j], xv, us + k * RB);
-        sq[j] = fmaf(xv, xv, sq[j]);
-      }
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto compute = [&](const u32x4& xu) {
+    const floatx4 x = __builtin_bit_cast(floatx4, xu);
+    const float bv = us[(4 * ck + kq) * RB + l16];
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, bv, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, bv, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, bv, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, bv, acc[3], 0, 0, 0);
+    if (SQ) {
+      sq = fmaf(x.x, x.x, sq);
+      sq = fmaf(x.y, x.y, sq);
+      sq = fmaf(x.z, x.z, sq);
+      sq = fmaf(x.w, x.w, sq);
     }
+    if (++ck == nks) {
+      finish_tile();
+      ck = 0;
+      ++ct;
+    }
+  };
+
+  u32x4 xr[D];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      if (!valid[j]) continue;
-      if (want_sq) xx += double(sq[j]);
+  for (int u = 0; u < D; ++u) load(xr[u]);
+  const int nfull = nsteps / D;
+  for (int q = 0; q < nfull; ++q) {
 #pragma unroll
-      for (int r = 0; r < RR; ++r)
-        if (r < R) out[ob[j] + P * r] = acc[j][r];
+    for (int u = 0; u < D; ++u) {
+      compute(xr[u]);
+      load(xr[u]);
     }
   }
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+    if (u < nsteps - nfull * D) compute(xr[u]);
 }
 
 // ---------------------------------------------------- Y rows of a block
-// ys[rl R^2 + ru + R rt] = sum_i U[i, ru] src[(a + rl) srow + i si + rt srt]
-template <int RR>
-__device__ void y_rows(const float* __restrict__ src, int64_t srow, int64_t si, int64_t srt, int Kc, int a,
-                       int nb, int R, const float* us, float* ys, int tid) {
-  for (int e = tid; e < nb * R; e += NT) {
-    const int rl = e % nb, rt = e / nb;
-    const float* ptr = src + int64_t(a + rl) * srow + int64_t(rt) * srt;
-    float acc[RR];
+// ys[rl (R^2 + 1) + ru + R rt] = sum_i U[i, ru] src[(a + rl) srow + i si + rt srt]
+// for rl < nb, i < Kc, on the matrix cores: items (16-row group g, rt) are
+// dealt to the waves four at a time, the four sharing the B operand
+// U[i, l16]; lane (l16, kq) loads row a + 16 g + l16 (clamped to the mode,
+// the extra rows are dropped) at i = 4 t + kq.
+__device__ void y_rows_mfma(const float* __restrict__ src, int64_t srow, int64_t si, int64_t srt, int Kc, int a,
+                            int nb, int64_t In, int R, const float* us, float* ys, int tid) {
+  const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
+  const int nitem = ((nb + 15) >> 4) * R;
+  const int nks = (Kc + 3) >> 2;
+  const int K0p = R * R + 1;
+  for (int e0 = 4 * w; e0 < nitem; e0 += 4 * NW) {
+    gcfloat* base[4];
 #pragma unroll
-    for (int r = 0; r < RR; ++r) acc[r] = 0.f;
-    int i = 0;
-    for (; i + 4 <= Kc; i += 4) {
-      float x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = ptr[int64_t(i + u) * si];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) fma_row<RR>(acc, x[u], us + (i + u) * RB);
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + q < nitem ? e0 + q : e0;
+      const int g = e / R, rt = e - g * R;
+      int64_t row = a + 16 * g + l16;
+      row = row < In ? row : In - 1;
+      base[q] = gview(src) + row * srow + int64_t(rt) * srt;
     }
-    for (; i < Kc; ++i) fma_row<RR>(acc, ptr[int64_t(i) * si], us + i * RB);
-    float* yr = ys + rl * R * R + R * rt;
+    floatx4 acc[4];
 #pragma unroll
-    for (int r = 0; r < RR; ++r)
-      if (r < R) yr[r] = acc[r];
+    for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // i >= Kc reads the element at Kc - 1 again; its U row is zero
+    auto step = [&](int t) {
+      const int kk = 4 * t + kq;
+      const int64_t off = int64_t(kk < Kc ? kk : Kc - 1) * si;
+      return floatx4{base[0][off], base[1][off], base[2][off], base[3][off]};
+    };
+    int t = 0;
+    for (; t + 4 <= nks; t += 4) {
+      floatx4 xs[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = step(t + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float bv = us[(4 * (t + u) + kq) * RB + l16];
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].x, bv, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].y, bv, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].z, bv, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].w, bv, acc[3], 0, 0, 0);
+      }
+    }
+    for (; t < nks; ++t) {
+      const floatx4 xv = step(t);
+      const float bv = us[(4 * t + kq) * RB + l16];
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[3], 0, 0, 0);
+    }
+    if (l16 < R) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q;
+        if (e >= nitem) continue;
+        const int g = e / R, rt = e - g * R;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rl = 16 * g + 4 * kq + v;
+          if (rl < nb) ys[rl * K0p + l16 + R * rt] = acc[q][v];
+        }
+      }
+    }
   }
 }
 
@@ -199,45 +295,63 @@ __device__ inline double wg_sum1(double v, BShared& sh, int tid) {
 }
 
 // ------------------------------------------------------------- B task
-// Rows [a, a + nb) of mode n: Y rows, W = Y Q_0, A R_0^T = W, partials.
-__device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, int a, int nb, int slot, BShared& sh, int tid) {
-  const int R = it.R;
-  const int64_t I0 = it.I[0], I1 = it.I[1];
+// The source of mode n's Y rows: Y_(n)(row, ru + R rt) = sum_i U[i, ru]
+// src[row srow + i si + rt srt], U = Q_um (FP32 copy), i < Kc.
+struct YSrc {
   const float* src;
   int64_t srow, si, srt;
   int Kc, um;
-  if (n == 0) {         // Y_(1)(i1, r2 + R r3) = sum_i2 Q_2(i2, r2) Z(i1, i2, r3)
-    src = it.Z, srow = 1, si = I0, srt = I0 * I1, Kc = int(I1), um = 1;
-  } else if (n == 1) {  // Y_(2)(i2, r1 + R r3) = sum_i1 Q_1(i1, r1) Z(i1, i2, r3)
-    src = it.Z, srow = I0, si = 1, srt = I0 * I1, Kc = int(I0), um = 0;
-  } else {              // Y_(3)(i3, r1 + R r2) = sum_i1 Q_1(i1, r1) T(i1, r2, i3)
-    src = it.T, srow = I0 * R, si = 1, srt = I0, Kc = int(I0), um = 0;
-  }
-  stage_qf(it.Qf[um], Kc, sh.us, tid);
-  const int K0 = R * R;
+};
+
+__device__ inline YSrc y_source(const BItem& it, int n) {
+  const int R = it.R;
+  const int64_t I0 = it.I[0], I1 = it.I[1];
+  const int64_t L0 = it.I0p;  // row stride of Z and T
+  if (n == 0) return YSrc{it.Z, 1, L0, L0 * I1, int(I1), 1};      // Y_(1)(i1, r2 + R r3) = sum_i2 Q_2(i2, r2) Z(i1, i2, r3)
+  if (n == 1) return YSrc{it.Z, L0, 1, L0 * I1, int(I0), 0};      // Y_(2)(i2, r1 + R r3) = sum_i1 Q_1(i1, r1) Z(i1, i2, r3)
+  return YSrc{it.T, L0 * R, 1, L0, int(I0), 0};                   // Y_(3)(i3, r1 + R r2) = sum_i1 Q_1(i1, r1) T(i1, r2, i3)
+}
+
+// Operands of mode n's row steps into LDS: U, Q_0 (R^2 x R, FP64) and R_0.
+__device__ __attribute__((always_inline)) void mode_begin(const BItem& it, int n, BShared& sh, int tid) {
+  const int R = it.R;
+  const YSrc ysrc = y_source(it, n);
+  stage_u(it.Qf[ysrc.um], ysrc.Kc, sh.us, tid);
+  const double* q0 = it.Q0b[n];
+  for (int e = tid; e < R * R * R; e += NT) sh.q0[e] = q0[e];
   for (int e = tid; e < R * R; e += NT) sh.r0[e % R][e / R] = it.R0b[n][e];
   __syncthreads();
-  if (R <= 4) y_rows<4>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
-  else if (R <= 8) y_rows<8>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
-  else if (R <= 12) y_rows<12>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
-  else y_rows<16>(src, srow, si, srt, Kc, a, nb, R, sh.us, sh.ys, tid);
+}
+
+// Rows [a, a + nb) of mode n: Y rows, W = Y Q_0, A R_0^T = W, partials.
+__device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, int a, int nb, int slot, BShared& sh, int tid) {
+  const int R = it.R;
+  const YSrc ys = y_source(it, n);
+  const int64_t In = it.I[n];
+  y_rows_mfma(ys.src, ys.srow, ys.si, ys.srt, ys.Kc, a, nb, In, R, sh.us, sh.ys, tid);
   __syncthreads();
-  // W rows (FP64) into sh.ws, row-major nb x RB (the U operand is dead now);
-  // Q_0 (at most 32 KB) is read through the caches
-  const double* q0 = it.Q0b[n];
+  // W rows (FP64) into sh.ws, row-major nb x RB; four partial sums per entry
+  const int K0 = R * R, K0p = K0 + 1;
   for (int e = tid; e < nb * R; e += NT) {
     const int rl = e % nb, c = e / nb;
-    const float* yr = sh.ys + rl * K0;
-    double w = 0.0;
-    for (int rho = 0; rho < K0; ++rho) w += double(yr[rho]) * q0[rho * R + c];
-    sh.ws[rl * RB + c] = w;
+    const float* yr = sh.ys + rl * K0p;
+    const double* qc = sh.q0 + c;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+    int rho = 0;
+    for (; rho + 4 <= K0; rho += 4) {
+      w0 = fma(double(yr[rho]), qc[rho * R], w0);
+      w1 = fma(double(yr[rho + 1]), qc[(rho + 1) * R], w1);
+      w2 = fma(double(yr[rho + 2]), qc[(rho + 2) * R], w2);
+      w3 = fma(double(yr[rho + 3]), qc[(rho + 3) * R], w3);
+    }
+    for (; rho < K0; ++rho) w0 = fma(double(yr[rho]), qc[rho * R], w0);
+    sh.ws[rl * RB + c] = (w0 + w1) + (w2 + w3);
   }
   __syncthreads();
   double arow[RB], x[RB];
 #pragma unroll
   for (int c = 0; c < RB; ++c) arow[c] = 0.0;
   double ip = 0.0;
-  const int64_t In = it.I[n];
   if (tid < nb) {
     const double* w = sh.ws + tid * RB;
 #pragma unroll
@@ -398,37 +512,28 @@ __device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, in
   krp_qr(it, n == 2 ? 0 : n + 1, sh, tid);
 }
 
-template <int RR, int CPT, int U>
-__device__ void task_a_r(const BItem& it, bool isz, BShared& sh, int tid) {
-  const int64_t I0 = it.I[0], I1 = it.I[1], I2 = it.I[2];
-  const int64_t P = isz ? I0 * I1 : I0;
-  const int K = int(isz ? I2 : I1);
-  const int64_t M = isz ? I0 * I1 : I0 * I2;
+// Streaming contraction over the whole tensor: Z = X x_3 Q_3^T (isz) or
+// T = X x_2 Q_2^T.  Z also yields ||X||^2.
+template <int D>
+__device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz, BShared& sh, int tid) {
+  const int k = isz ? 2 : 1;
+  stage_u(it.Qf[k], int(it.I[k]), sh.us, tid);
+  __syncthreads();
+  const uint32_t L0 = uint32_t(it.I0p), I1 = uint32_t(it.I[1]), I2 = uint32_t(it.I[2]);
   double xx = 0.0;
-  stream_tile<RR, CPT, U>(it.X, isz ? it.Z : it.T, P, K, it.R, 0, M, sh.us, isz, xx, tid);
+  if (isz)
+    stream_mfma<D, true>(it.X, it.Z, L0 * I1, int(I2), 1u, it.R, sh.us, xx, tid);
+  else
+    stream_mfma<D, false>(it.X, it.T, L0, int(I1), I2, it.R, sh.us, xx, tid);
   if (isz) {
     xx = wg_sum1(xx, sh, tid);
     if (tid == 0) *it.xnorm2 = xx;
   }
 }
 
-// First contraction over the whole tensor: Z = X x_3 Q_3^T (isz) or
-// T = X x_2 Q_2^T.  Z also yields ||X||^2.
-template <int CPT, int U>
-__device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz, BShared& sh, int tid) {
-  const int k = isz ? 2 : 1;
-  stage_qf(it.Qf[k], int(it.I[k]), sh.us, tid);
-  __syncthreads();
-  const int R = it.R;
-  if (R <= 4) task_a_r<4, CPT, U>(it, isz, sh, tid);
-  else if (R <= 8) task_a_r<8, CPT, U>(it, isz, sh, tid);
-  else if (R <= 12) task_a_r<12, CPT, U>(it, isz, sh, tid);
-  else task_a_r<16, CPT, U>(it, isz, sh, tid);
-}
-
-// One sweep schedule per tensor; CPT tensor columns per thread and U
-// contraction steps in flight per column in the streaming passes.
-template <int CPT, int U>
+// One sweep schedule per tensor; D contraction steps in flight per lane in
+// the streaming passes.
+template <int D>
 __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restrict__ items,
                                                           const int* __restrict__ order, int nsweeps, int do_init,
                                                           int offset) {
@@ -442,9 +547,10 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
   for (int s = 0; s < nsweeps; ++s) {
     for (int n = 0; n < 3; ++n) {
       if (n == 0 || n == 2) {
-        task_a<CPT, U>(it, n == 0, sh, tid);
+        task_a<D>(it, n == 0, sh, tid);
         __syncthreads();
       }
+      mode_begin(it, n, sh, tid);
       for (int blk = 0; blk < it.nB[n]; ++blk) {
         const int a = blk * it.rows[n];
         const int cnt = int(it.I[n] - a < it.rows[n] ? it.I[n] - a : it.rows[n]);
@@ -458,22 +564,34 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
 }
 
 // ------------------------------------------------------------ host side
-// Streaming-pass shapes the autotuner chooses from: (CPT, U).
+// Streaming-pass depths the autotuner chooses from (steps in flight).
 constexpr int NVAR = 3;
-constexpr int VAR_CPT[NVAR] = {4, 4, 2};
-constexpr int VAR_U[NVAR] = {4, 8, 8};
-constexpr int ROWS_MIN = 32;
+constexpr int VAR_D[NVAR] = {8, 16, 24};
+constexpr int ROWS_PER_LANE = 4;  // tensor rows a lane carries through the MFMAs
+constexpr int ROWS_MIN = 16;
 
 struct Config {
   int var;   // streaming-pass shape
   int rows;  // rows per block of the row steps (before the LDS cap)
 };
 
-int rows_for(int rows_cfg, int R) { return std::max(1, std::min(rows_cfg, YS / (R * R))); }
+// Rows per block: a multiple of 16 (one MFMA row group), at most WROWS, and
+// no more Y rows (R^2 + 1 floats each) than the LDS buffer holds.
+int rows_for(int rows_cfg, int R) {
+  const int cap = std::min(YSF / (R * R + 1), WROWS);
+  return std::max(16, std::min(rows_cfg, cap) / 16 * 16);
+}
 
 int blocks_max(const cpqr_batch_item& b) {
   const int r = rows_for(ROWS_MIN, b.R);
   return int(ceil_div(std::max(b.I[0], std::max(b.I[1], b.I[2])), int64_t(r)));
+}
+
+// The streaming passes read 16-byte runs along the first mode: a tensor is
+// streamed in place when its first mode is a multiple of 4 and it is
+// 16-byte aligned, else from a copy whose first mode is zero-padded.
+bool needs_copy(const cpqr_batch_item& b) {
+  return b.I[0] % 4 != 0 || reinterpret_cast<uintptr_t>(b.X) % 16 != 0;
 }
 
 size_t item_scratch(const cpqr_batch_item& b) {
@@ -486,8 +604,10 @@ size_t item_scratch(const cpqr_batch_item& b) {
   for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R);       // Rf
   for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R * R);   // Q0b
   for (int m = 0; m < 3; ++m) cv.take<double>(size_t(R) * R);       // R0b
-  cv.take<float>(size_t(i0 * i1 * R));                             // Z
-  cv.take<float>(size_t(i0 * R * i2));                             // T
+  const int64_t l0 = (i0 + 3) / 4 * 4;
+  cv.take<float>(size_t(l0 * i1 * R));                             // Z
+  cv.take<float>(size_t(l0 * R * i2));                             // T
+  if (needs_copy(b)) cv.take<float>(size_t(l0 * i1 * i2));         // padded copy of X
   cv.take<double>(size_t(nbmax) * RB);                             // lamp
   cv.take<double>(size_t(nbmax));                                  // ipp
   cv.take<double>(1);                                              // xnorm2
@@ -522,15 +642,15 @@ int launch_batch(const BatchState& st, int var, int nsweeps, int do_init, int of
   const dim3 grd(unsigned(st.n)), blk(NT);
   switch (var) {
     case 0:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[0], VAR_U[0]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[0]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
     case 1:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[1], VAR_U[1]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[1]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
     default:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_CPT[2], VAR_U[2]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[2]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
   }
@@ -601,7 +721,7 @@ std::string tune_key(const cpqr_batch_item* items, int n) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[256];
-  snprintf(buf, sizeof(buf), "batch2|%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n,
+  snprintf(buf, sizeof(buf), "batch3|%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n,
            (long long)((maxi + 31) / 32 * 32), maxr, lg);
   return buf;
 }
@@ -683,8 +803,16 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
     for (int k = 0; k < 3; ++k) d.Rf[k] = c2.take<double>(size_t(R) * R);
     for (int k = 0; k < 3; ++k) d.Q0b[k] = c2.take<double>(size_t(R) * R * R);
     for (int k = 0; k < 3; ++k) d.R0b[k] = c2.take<double>(size_t(R) * R);
-    d.Z = c2.take<float>(size_t(it.I[0] * it.I[1] * R));
-    d.T = c2.take<float>(size_t(it.I[0] * R * it.I[2]));
+    d.I0p = (it.I[0] + 3) / 4 * 4;
+    d.Z = c2.take<float>(size_t(d.I0p * it.I[1] * R));
+    d.T = c2.take<float>(size_t(d.I0p * R * it.I[2]));
+    if (needs_copy(it)) {
+      float* xp = c2.take<float>(size_t(d.I0p * it.I[1] * it.I[2]));
+      CPQR_HIP(hipMemsetAsync(xp, 0, sizeof(float) * size_t(d.I0p * it.I[1] * it.I[2]), s));
+      CPQR_HIP(hipMemcpy2DAsync(xp, sizeof(float) * size_t(d.I0p), it.X, sizeof(float) * size_t(it.I[0]),
+                                sizeof(float) * size_t(it.I[0]), size_t(it.I[1] * it.I[2]), hipMemcpyDeviceToDevice, s));
+      d.X = xp;
+    }
     d.lamp = c2.take<double>(size_t(nbmax) * RB);
     d.ipp = c2.take<double>(size_t(nbmax));
     d.xnorm2 = c2.take<double>(1);
@@ -807,8 +935,8 @@ int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* ro
   BatchState* st;
   int var;
   CPQR_TRY(batch_lookup(work, 0, st, var));
-  if (cols_per_thread) *cols_per_thread = VAR_CPT[var];
-  if (unroll) *unroll = VAR_U[var];
+  if (cols_per_thread) *cols_per_thread = ROWS_PER_LANE;
+  if (unroll) *unroll = VAR_D[var];
   if (rows) *rows = st->cfg.rows;
   return CPQR_OK;
 }
