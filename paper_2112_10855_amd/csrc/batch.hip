@@ -69,6 +69,8 @@ struct BItem {
   double* xnorm2;  // ||X||^2
 };
 
+static_assert(sizeof(BItem) % sizeof(int) == 0, "the kernel copies BItem into LDS word by word");
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // The descriptors hold generic pointers; tensor traffic goes through these
@@ -77,6 +79,19 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const float gcfloat;
 typedef __attribute__((address_space(1))) float gfloat;
 __device__ inline gcfloat* gview(const float* p) { return (gcfloat*)p; }
+// Descriptor fields come from LDS, which the compiler does not know to be
+// the same in every lane; these declare a value wave-uniform so that it
+// stays in scalar registers (a buffer resource must).
+__device__ inline uint32_t uni(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni(int64_t v) {
+  const uint64_t u = uint64_t(v);
+  return int64_t((uint64_t(uni(uint32_t(u >> 32))) << 32) | uni(uint32_t(u)));
+}
+template <class T>
+__device__ inline T* uni(T* p) {
+  return reinterpret_cast<T*>(uni(int64_t(reinterpret_cast<uintptr_t>(p))));
+}
 __device__ inline gfloat* gview(float* p) { return (gfloat*)p; }
 
 // 77 KB: two workgroups share a CU's 160 KB.
@@ -108,111 +123,123 @@ __device__ inline void stage_u(const float* Qf, int rows, float* us, int tid) {
 // ------------------------------------------------- streaming pass (AZ, AT)
 // out[p + P r + P R s] = sum_k X[p + P k + P K s] U[k, r] for every row
 // m = p + P s < M = P S of the [M, K] matrix (P a multiple of 4, X and out
-// 16-byte aligned), U (K x R, rows zero past K) in LDS.  Rows go on the M
-// dimension of v_mfma_f32_16x16x4f32 in 64-row tiles, tiles dealt to the
-// waves round robin.  In step t of a tile, lane (l16, kq) loads the 16-byte
-// run of rows m0 + 4 l16 .. + 3 at k = 4 t + kq and feeds its four values to
-// four MFMAs that share the B operand U[k, l16]; at the end the lane holds
-// rows m0 + 16 kq + 4 v + j (v, j = 0..3) of column l16.  The loads go
-// through a buffer resource, so k >= K (and rows past M) read zeros from
-// its range check.  The steps of all of a wave's tiles form one sequence
-// whose loads run D steps ahead of the MFMAs; a tile's results leave when
-// its last step is done.  The order of every sum is fixed by the layout
-// alone, so any D gives the same bits.  SQ: xx += the sum of x^2.
+// 16-byte aligned), U (K x R, rows zero from K to the next multiple of 4) in
+// LDS.  Rows go on the M dimension of v_mfma_f32_16x16x4f32 in 64-row
+// groups, dealt to the waves round robin; a wave works on MG of its groups
+// at a time (a tile), in the same group order for every MG.  In step t, lane
+// (l16, kq) loads the 16-byte run of rows 4 l16 .. 4 l16 + 3 of each group
+// at k = 4 t + kq and feeds its four values to four MFMAs that share the B
+// operand U[k, l16]; at the end the lane holds rows 16 kq + 4 v + j (v, j =
+// 0..3) of each group, column l16.  Loads go through a buffer resource, so
+// k >= K and rows past M read zeros from its range check, and run D steps
+// ahead of the MFMAs within a tile.  A tile's results are stored after its
+// last step: loads and stores in flight together would force the wait
+// before every use down to zero, so each tile drains once instead.  The
+// order of every sum is fixed by the layout alone (the sum of squares goes
+// group by group in the wave's group order), so D and MG do not change the
+// bits.  SQ: xx += the sum of x^2.
 constexpr uint32_t OOB = 0x80000000u;  // a byte offset past any tensor here (at most 64 MB)
 
-template <int D, bool SQ>
+template <int D, int MG, bool SQ>
 __device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out, uint32_t P, int K, uint32_t S,
                             int R, const float* us, double& xx, int tid) {
+  X = uni(X);
+  out = uni(out);
+  P = uni(P);
+  K = uni(K);
+  S = uni(S);
+  R = uni(R);
   const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
   const uint32_t M = P * S;
-  const int ntile = int((M + 63) / 64);
+  const int ngrp = int((M + 63) / 64);
+  const int mygrp = ngrp > w ? (ngrp - w + NW - 1) / NW : 0;
   const int nks = (K + 3) >> 2;
-  const int mytiles = ntile > w ? (ntile - w + NW - 1) / NW : 0;
-  if (mytiles == 0) return;
-  const int nsteps = mytiles * nks;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), short(0), int(M * uint32_t(K) * 4u), 0x00020000);
   const uint32_t step_bytes = P * 16u;
-
-  // load side: tile lt of this wave, step lk within it; past the last step
-  // the loads repeat the last tile (their values are not used)
-  int lt = 0, lk = 0;
-  auto run_off = [&](int t) -> uint32_t {  // byte offset of the lane's run at k = kq
-    const uint32_t m = uint32_t(w + t * NW) * 64u + 4u * uint32_t(l16);
-    if (m >= M) return OOB;
-    const uint32_t s = m / P, p = m - s * P;
-    return (p + P * (uint32_t(K) * s + uint32_t(kq))) * 4u;
-  };
-  uint32_t lvo = run_off(0);
-  auto load = [&](u32x4& dst) {
-    const uint32_t vo = 4 * lk + kq < K ? lvo : OOB;
-    dst = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, uint32_t(lk) * step_bytes, 0);
-    if (++lk == nks) {
-      lk = 0;
-      if (lt + 1 < mytiles) lvo = run_off(++lt);
-    }
-  };
-
-  // compute side: tile ct, step ck
-  int ct = 0, ck = 0;
-  floatx4 acc[4];
-  float sq = 0.f;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
   gfloat* const og = gview(out);
-  auto finish_tile = [&]() {
-    if (l16 < R) {
-      const uint32_t m0 = uint32_t(w + ct * NW) * 64u + 16u * uint32_t(kq);
+  // Drain every memory operation of the earlier phases (some are flat, which
+  // count on both counters): with one pending here, the compiler could only
+  // wait for zero outstanding loads at the top of every step group.
+  __builtin_amdgcn_s_waitcnt(0);
+  for (int t0 = 0; t0 < mygrp; t0 += MG) {
+    uint32_t mg0[MG];  // first row of each group (M when the tile has no such group)
+    uint32_t vo[MG];   // byte offset of the lane's run of each group at k = kq
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t m = m0 + 4u * uint32_t(v);
-        if (m < M) {
-          const uint32_t s = m / P, p = m - s * P;
-          *reinterpret_cast<__attribute__((address_space(1))) floatx4*>(og + p + size_t(P) * (size_t(l16) + size_t(R) * s)) =
-              floatx4{acc[0][v], acc[1][v], acc[2][v], acc[3][v]};
+    for (int g = 0; g < MG; ++g) {
+      mg0[g] = t0 + g < mygrp ? uint32_t(w + NW * (t0 + g)) * 64u : M;
+      const uint32_t m = mg0[g] + 4u * uint32_t(l16);
+      const uint32_t s = m / P, p = m - s * P;
+      vo[g] = m < M ? (p + P * (uint32_t(K) * s + uint32_t(kq))) * 4u : OOB;
+    }
+    auto load = [&](u32x4 (&dst)[MG], int st) {
+      const bool kin = 4 * st + kq < K;
+#pragma unroll
+      for (int g = 0; g < MG; ++g)
+        dst[g] = __builtin_amdgcn_raw_buffer_load_b128(rs, kin ? vo[g] : OOB, uint32_t(st) * step_bytes, 0);
+    };
+    floatx4 acc[MG][4];
+    float sq[MG];
+#pragma unroll
+    for (int g = 0; g < MG; ++g) {
+      sq[g] = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    auto compute = [&](const u32x4 (&xu)[MG], int st) {
+      const float bv = us[(4 * st + kq) * RB + l16];
+#pragma unroll
+      for (int g = 0; g < MG; ++g) {
+        const floatx4 x = __builtin_bit_cast(floatx4, xu[g]);
+        acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, bv, acc[g][0], 0, 0, 0);
+        acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, bv, acc[g][1], 0, 0, 0);
+        acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, bv, acc[g][2], 0, 0, 0);
+        acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, bv, acc[g][3], 0, 0, 0);
+        if (SQ) {
+          sq[g] = fmaf(x.x, x.x, sq[g]);
+          sq[g] = fmaf(x.y, x.y, sq[g]);
+          sq[g] = fmaf(x.z, x.z, sq[g]);
+          sq[g] = fmaf(x.w, x.w, sq[g]);
         }
       }
-    }
-    if (SQ) xx += double(sq);
-    sq = 0.f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  };
-  auto compute = [&](const u32x4& xu) {
-    const floatx4 x = __builtin_bit_cast(floatx4, xu);
-    const float bv = us[(4 * ck + kq) * RB + l16];
-    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, bv, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, bv, acc[1], 0, 0, 0);
-    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, bv, acc[2], 0, 0, 0);
-    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, bv, acc[3], 0, 0, 0);
-    if (SQ) {
-      sq = fmaf(x.x, x.x, sq);
-      sq = fmaf(x.y, x.y, sq);
-      sq = fmaf(x.z, x.z, sq);
-      sq = fmaf(x.w, x.w, sq);
-    }
-    if (++ck == nks) {
-      finish_tile();
-      ck = 0;
-      ++ct;
-    }
-  };
-
-  u32x4 xr[D];
-#pragma unroll
-  for (int u = 0; u < D; ++u) load(xr[u]);
-  const int nfull = nsteps / D;
-  for (int q = 0; q < nfull; ++q) {
+    };
+    u32x4 xr[D][MG];
+    // The loads leave in step order (no rescheduling across the barriers), so
+    // that each wait in the loop is for the oldest loads only.
 #pragma unroll
     for (int u = 0; u < D; ++u) {
-      compute(xr[u]);
-      load(xr[u]);
+      load(xr[u], u);
+      __builtin_amdgcn_sched_barrier(0);
     }
-  }
+    for (int q = 0; q < nks; q += D) {
 #pragma unroll
-  for (int u = 0; u < D; ++u)
-    if (u < nsteps - nfull * D) compute(xr[u]);
+      for (int u = 0; u < D; ++u) {
+        if (q + u < nks) compute(xr[u], q + u);
+        load(xr[u], q + u + D);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (l16 < R) {
+#pragma unroll
+      for (int g = 0; g < MG; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t m = mg0[g] + 16u * uint32_t(kq) + 4u * uint32_t(v);
+          if (m < M) {
+            const uint32_t s = m / P, p = m - s * P;
+            *reinterpret_cast<__attribute__((address_space(1))) floatx4*>(og + p + size_t(P) * (size_t(l16) + size_t(R) * s)) =
+                floatx4{acc[g][0][v], acc[g][1][v], acc[g][2][v], acc[g][3][v]};
+          }
+        }
+    }
+    if (SQ) {
+#pragma unroll
+      for (int g = 0; g < MG; ++g) xx += double(sq[g]);  // a missing group adds zero
+    }
+    // Let the stores finish before the next tile's loads go out, so that no
+    // load waits behind a store of unknown order.
+    __builtin_amdgcn_s_waitcnt(0);
+  }
 }
 
 // ---------------------------------------------------- Y rows of a block
@@ -223,6 +250,15 @@ __device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out
 // the extra rows are dropped) at i = 4 t + kq.
 __device__ void y_rows_mfma(const float* __restrict__ src, int64_t srow, int64_t si, int64_t srt, int Kc, int a,
                             int nb, int64_t In, int R, const float* us, float* ys, int tid) {
+  src = uni(src);
+  srow = uni(srow);
+  si = uni(si);
+  srt = uni(srt);
+  Kc = uni(Kc);
+  nb = uni(nb);
+  In = uni(In);
+  R = uni(R);
+  __builtin_amdgcn_s_waitcnt(0);  // as in stream_mfma: no earlier flat access left pending
   const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
   const int nitem = ((nb + 15) >> 4) * R;
   const int nks = (Kc + 3) >> 2;
@@ -514,7 +550,7 @@ __device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, in
 
 // Streaming contraction over the whole tensor: Z = X x_3 Q_3^T (isz) or
 // T = X x_2 Q_2^T.  Z also yields ||X||^2.
-template <int D>
+template <int D, int MG>
 __device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz, BShared& sh, int tid) {
   const int k = isz ? 2 : 1;
   stage_u(it.Qf[k], int(it.I[k]), sh.us, tid);
@@ -522,24 +558,33 @@ __device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz,
   const uint32_t L0 = uint32_t(it.I0p), I1 = uint32_t(it.I[1]), I2 = uint32_t(it.I[2]);
   double xx = 0.0;
   if (isz)
-    stream_mfma<D, true>(it.X, it.Z, L0 * I1, int(I2), 1u, it.R, sh.us, xx, tid);
+    stream_mfma<D, MG, true>(it.X, it.Z, L0 * I1, int(I2), 1u, it.R, sh.us, xx, tid);
   else
-    stream_mfma<D, false>(it.X, it.T, L0, int(I1), I2, it.R, sh.us, xx, tid);
+    stream_mfma<D, MG, false>(it.X, it.T, L0, int(I1), I2, it.R, sh.us, xx, tid);
   if (isz) {
     xx = wg_sum1(xx, sh, tid);
     if (tid == 0) *it.xnorm2 = xx;
   }
 }
 
-// One sweep schedule per tensor; D contraction steps in flight per lane in
-// the streaming passes.
-template <int D>
+// One sweep schedule per tensor; the streaming passes keep D contraction
+// steps of MG row groups in flight per lane.
+template <int D, int MG>
 __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restrict__ items,
                                                           const int* __restrict__ order, int nsweeps, int do_init,
                                                           int offset) {
   __shared__ BShared sh;
+  // The descriptor lives in LDS: its fields are read where they are used
+  // instead of being held in registers for the whole launch.
+  __shared__ BItem itl;
   const int tid = threadIdx.x;
-  const BItem& it = items[order[blockIdx.x]];
+  {
+    const int* src = reinterpret_cast<const int*>(items + order[blockIdx.x]);
+    int* dst = reinterpret_cast<int*>(&itl);
+    for (int e = tid; e < int(sizeof(BItem) / sizeof(int)); e += NT) dst[e] = src[e];
+  }
+  __syncthreads();
+  const BItem& it = itl;
   if (do_init) {
     task_init(it, sh, tid);
     __syncthreads();
@@ -547,7 +592,7 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
   for (int s = 0; s < nsweeps; ++s) {
     for (int n = 0; n < 3; ++n) {
       if (n == 0 || n == 2) {
-        task_a<D>(it, n == 0, sh, tid);
+        task_a<D, MG>(it, n == 0, sh, tid);
         __syncthreads();
       }
       mode_begin(it, n, sh, tid);
@@ -564,10 +609,11 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
 }
 
 // ------------------------------------------------------------ host side
-// Streaming-pass depths the autotuner chooses from (steps in flight).
+// Streaming-pass shapes the autotuner chooses from: steps in flight (D) and
+// 64-row groups per wave tile (MG).
 constexpr int NVAR = 3;
-constexpr int VAR_D[NVAR] = {8, 16, 24};
-constexpr int ROWS_PER_LANE = 4;  // tensor rows a lane carries through the MFMAs
+constexpr int VAR_D[NVAR] = {8, 4, 16};
+constexpr int VAR_MG[NVAR] = {2, 4, 1};
 constexpr int ROWS_MIN = 16;
 
 struct Config {
@@ -642,15 +688,15 @@ int launch_batch(const BatchState& st, int var, int nsweeps, int do_init, int of
   const dim3 grd(unsigned(st.n)), blk(NT);
   switch (var) {
     case 0:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_D[0]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[0], VAR_MG[0]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
     case 1:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_D[1]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[1], VAR_MG[1]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
     default:
-      hipLaunchKernelGGL((als_batch_kernel<VAR_D[2]>), grd, blk, 0, s, st.items_dev, st.order_dev,
+      hipLaunchKernelGGL((als_batch_kernel<VAR_D[2], VAR_MG[2]>), grd, blk, 0, s, st.items_dev, st.order_dev,
                          nsweeps, do_init, offset);
       break;
   }
@@ -935,7 +981,7 @@ int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* ro
   BatchState* st;
   int var;
   CPQR_TRY(batch_lookup(work, 0, st, var));
-  if (cols_per_thread) *cols_per_thread = ROWS_PER_LANE;
+  if (cols_per_thread) *cols_per_thread = 4 * VAR_MG[var];
   if (unroll) *unroll = VAR_D[var];
   if (rows) *rows = st->cfg.rows;
   return CPQR_OK;

@@ -1,57 +1,63 @@
-// Workgroup-level Householder QR building blocks (device code), shared by
-// the tall-skinny QR kernels and the batched CP-ALS-QR kernel.  One
-// workgroup of NT threads factorizes a block of at most NT rows, one row per
-// thread, R <= RMAX columns in registers.  See tsqr.hip for the algorithm.
+// Workgroup-level Householder QR building blocks (device code) for the
+// batched CP-ALS-QR kernel.  One workgroup of NT threads factorizes a block
+// of at most NT rows, one row per thread, R <= RMAX columns in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "wave.h"
+
 namespace cpqr {
 namespace wgqr {
 
+using wave::ilog2;
 constexpr int WAVE = 64;
 
-constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
-
-// Sum over all threads of the workgroup of each x[i] (V a power of two <= 32).
-// Result in res[0..V-1] (LDS), visible to every thread on return.
+// Sum over all threads of the workgroup of each x[i] (V a power of two <=
+// 32): a reduce-scatter within each wave (DPP and lane swaps, no LDS), the
+// wave partials through LDS.  Result in res[0..V-1] (LDS), visible to every
+// thread on return.  The wave partials are added in wave order.
 template <int V, int NW>
 __device__ inline void block_sum_vec(double (&x)[V], double* red, double* res, int tid) {
   const int lane = tid % WAVE, w = tid / WAVE;
-  constexpr int L = ilog2(V);
-  int idx = 0;
-#pragma unroll
-  for (int l = 0; l < L; ++l) {
-    const int mask = 32 >> l;
-    const int half = V >> (l + 1);
-    const bool hi = (lane & mask) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const double send = hi ? x[i] : x[half + i];
-      const double got = __shfl_xor(send, mask, WAVE);
-      x[i] = (hi ? x[half + i] : x[i]) + got;
-    }
-    idx += hi ? half : 0;
-  }
-#pragma unroll
-  for (int mask = 32 >> L; mask >= 1; mask >>= 1) x[0] += __shfl_xor(x[0], mask, WAVE);
-  if ((lane & ((64 >> L) - 1)) == 0) red[w * V + idx] = x[0];
+  const double s = wave::wave_sum<V>(x, lane);
+  if ((lane & (WAVE / V - 1)) == 0) red[w * V + (lane >> (6 - ilog2(V)))] = s;
   __syncthreads();
   if (tid < V) {
-    double s = 0.0;
+    double t = 0.0;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) s += red[ww * V + tid];
-    res[tid] = s;
+    for (int ww = 0; ww < NW; ++ww) t += red[ww * V + tid];
+    res[tid] = t;
   }
   __syncthreads();
+}
+
+// The same sums returned in x[] of every thread after a single barrier: each
+// thread adds the NW wave partials itself.  red holds two buffers of NW V
+// doubles ([buf][i][wave]); consecutive calls must alternate buf, so that
+// a call never overwrites partials a slower thread may still be reading
+// (the barrier of the call in between orders the two).
+template <int V, int NW>
+__device__ inline void block_allsum(double (&x)[V], double* red, int buf, int tid) {
+  const int lane = tid % WAVE, w = tid / WAVE;
+  double* rb = red + buf * NW * V;
+  const double s = wave::wave_sum<V>(x, lane);
+  if ((lane & (WAVE / V - 1)) == 0) rb[(lane >> (6 - ilog2(V))) * NW + w] = s;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) t += rb[i * NW + ww];
+    x[i] = t;
+  }
 }
 
 // LDS workspace of one node.
 template <int RMAX, int NT>
 struct Shared {
-  double red[(NT / WAVE) * RMAX];
-  double res[RMAX];
-  double alpha;
+  double red[2 * (NT / WAVE) * RMAX];
+  double rowj[2][RMAX];       // row j of the block while column j is reduced
   double tau[RMAX];
   double G[RMAX][RMAX + 1];   // reflector Gram (strict upper part), later V1^T C
   double T[RMAX][RMAX + 1];   // compact WY factor
@@ -69,7 +75,13 @@ __device__ inline double vcomp(const double (&a)[RMAX], int c, int row, int m) {
 // Householder QR of the node block (row `tid` in a[], rows >= m are zero).
 // On return rows < R hold R's rows (entries at c >= row), rows > c hold
 // reflector c below the diagonal in a[c]; sh.tau and the strict upper part of
-// sh.G are filled.
+// sh.G are filled.  Column j takes one workgroup reduction: with the
+// unscaled subcolumn a_(i>j, j) it sums, for every c, a_ij a_ic over the rows
+// below j.  Entry j is the squared norm that fixes the reflector
+// v = e_j + s a_(i>j, j) (s = 1 / (alpha - beta)); for c > j, row j of A plus
+// s times entry c is v^T a_c, the coefficient of the rank-one update; for
+// c < j, row j's v_c(j) plus s times entry c is v_c^T v, the reflector Gram
+// entry that the compact WY factor needs.  Row j itself goes through LDS.
 template <int RMAX, int NT>
 __device__ void wg_factor(double (&a)[RMAX], int tid, int m, int R, Shared<RMAX, NT>& sh) {
   constexpr int NW = NT / WAVE;
@@ -77,13 +89,23 @@ __device__ void wg_factor(double (&a)[RMAX], int tid, int m, int R, Shared<RMAX,
   // chains so the register array is only ever indexed by constants.
 #pragma unroll 1
   for (int j = 0; j < R; ++j) {
+    const int buf = j & 1;
     double aj = 0.0;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) aj = (c == j) ? a[c] : aj;
-    if (tid == j) sh.alpha = aj;
-    double x1[1] = {(tid > j && tid < m) ? aj * aj : 0.0};
-    block_sum_vec<1, NW>(x1, sh.red, sh.res, tid);
-    const double alpha = sh.alpha, sub2 = sh.res[0];
+    if (tid == j) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) sh.rowj[buf][c] = a[c];
+    }
+    const bool below = tid > j && tid < m;
+    double x[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) x[c] = (below && c < R) ? aj * a[c] : 0.0;
+    block_allsum<RMAX, NW>(x, sh.red, buf, tid);
+    double sub2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sub2 = (c == j) ? x[c] : sub2;
+    const double alpha = sh.rowj[buf][j];
     double t = 0.0, beta = alpha, scal = 0.0;
     if (sub2 > 0.0) {
       const double nrm = sqrt(alpha * alpha + sub2);
@@ -91,20 +113,21 @@ __device__ void wg_factor(double (&a)[RMAX], int tid, int m, int R, Shared<RMAX,
       t = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    const double v = (tid == j) ? 1.0 : ((tid > j && tid < m) ? aj * scal : 0.0);
+    const double v = (tid == j) ? 1.0 : (below ? aj * scal : 0.0);
+    const double tv = t * v;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c)
+      if (c > j && c < R) a[c] -= tv * (sh.rowj[buf][c] + scal * x[c]);
     const double newj = (tid == j) ? beta : ((tid > j) ? v : aj);
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) a[c] = (c == j) ? newj : a[c];
     if (tid == 0) sh.tau[j] = t;
-    double x[RMAX];
+    if (tid < j) {
+      double xk = 0.0;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c)
-      x[c] = (c < j) ? vcomp<RMAX>(a, c, tid, m) * v : ((c > j && c < R) ? v * a[c] : 0.0);
-    block_sum_vec<RMAX, NW>(x, sh.red, sh.res, tid);
-    const double tv = t * v;
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[c] = (c > j && c < R) ? a[c] - tv * sh.res[c] : a[c];
-    if (tid < j) sh.G[tid][j] = sh.res[tid];
+      for (int c = 0; c < RMAX; ++c) xk = (c == tid) ? x[c] : xk;
+      sh.G[tid][j] = sh.rowj[buf][tid] + scal * xk;
+    }
   }
   __syncthreads();
 }
