@@ -461,7 +461,7 @@ def run_batch(args):
     log("generated %d tensors (%.2f GB) in %.1f s" % (len(shapes), nbytes / 1e9, time.time() - t0))
     nsw = args.steps
     B = C.AlsBatch(Xs, inits, nsw + 1, autotune=True)
-    log("autotuned: %d rows per lane, %d steps in flight, row blocks of %d" % B.config)
+    log("autotuned: %d rows per lane, %d steps in flight (row blocks %d: whole modes)" % B.config)
     B.run(1, init=True, graph=True)  # warm-up: init + one sweep (captured, replayed below)
     torch.cuda.synchronize()
     B2 = C.AlsBatch(Xs, inits, nsw)

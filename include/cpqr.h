@@ -419,8 +419,7 @@ int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* 
  * cpqr_als_batch_prepare writes the per-tensor descriptors into the work
  * buffer (synchronous: it returns after the stream has drained).  With
  * autotune != 0 it picks the streaming-pass shape (contraction steps in
- * flight and 64-row groups per wave tile: 8 x 2, 4 x 4 or 16 x 1) and the
- * row-block height by timing
+ * flight and 64-row groups per wave tile: 8 x 2, 4 x 4 or 16 x 1) by timing
  * an init + one sweep of each candidate on the batch itself (the initial
  * factors are restored afterwards); choices are cached per (architecture,
  * batch shape) in the file named by CPQR_AUTOTUNE_CACHE (default
@@ -449,8 +448,8 @@ int cpqr_als_batch_run(void* work, int nsweeps, int init, int sweep_offset, int 
 int cpqr_als_batch_graph(void* work, int nsweeps, int init, int sweep_offset, int variant, void* stream);
 /* the configuration chosen by prepare (any output may be NULL): tensor rows
  * a lane carries through the streaming pass (4 per 64-row group), contraction
- * steps in flight, and the requested row-block height (the kernel rounds it
- * down to a multiple of 16 that fits its Y-row buffer) */
+ * steps in flight, and 0 for the row-block height (the row steps take a whole
+ * mode at once) */
 int cpqr_als_batch_config(void* work, int* cols_per_thread, int* unroll, int* rows);
 
 /*

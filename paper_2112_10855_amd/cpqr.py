@@ -795,7 +795,7 @@ class AlsBatch:
 
     @property
     def config(self):
-        """(tensor rows per lane, steps in flight, requested row-block height)."""
+        """(tensor rows per lane, steps in flight, 0: the row steps take whole modes)."""
         c, u, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _call("cpqr_als_batch_config", self._w, ctypes.byref(c), ctypes.byref(u), ctypes.byref(r))
         return c.value, u.value, r.value

@@ -6,7 +6,7 @@
 // all sweeps of all tensors with workgroup barriers only.  Tensors are taken
 // largest first.  A sweep (modes counted from 1 as in the paper):
 //   Z = X x_3 Q_3^T                        streams X (and gives ||X||^2)
-//   mode 1: Y_(1) = Z x_2 Q_2^T by row blocks, W = Y Q_0, solve A R_0^T = W,
+//   mode 1: Y_(1) = Z x_2 Q_2^T, W = Y Q_0, solve A R_0^T = W,
 //           then normalize, factor QR of A_1, Khatri-Rao QR for mode 2
 //   mode 2: Y_(2) = Z x_1 Q_1^T (new Q_1), W, solve, normalize, QRs
 //   T = X x_2 Q_2^T (new Q_2)              streams X
@@ -43,9 +43,6 @@ constexpr int NT = 256;    // threads per workgroup
 constexpr int NW = NT / WAVE;
 constexpr int RB = 16;     // register width for rank-indexed rows (R <= 16)
 constexpr int IMAX = 256;  // largest mode size
-constexpr int K0P = RB * RB + 1;  // longest Y row (R^2) plus one float of padding
-constexpr int YSF = 16 * K0P;     // floats of Y rows held per row block (16 rows at R = 16)
-constexpr int WROWS = 64;         // most rows per block
 
 struct BItem {
   int64_t I[3];
@@ -64,6 +61,7 @@ struct BItem {
   double* R0b[3];  // R_0 for mode n, column-major R x R
   float* Z;        // Z[i1 + I0p i2 + I0p I1 r3] (rows i1 >= I0 zero)
   float* T;        // T[i1 + I0p r2 + I0p R i3]
+  float* Y;        // Y_(n) of the current mode (layout per mode, see task_y)
   double* lamp;    // [block][RB] column sums of squares of A rows per block
   double* ipp;     // [block] <W, A R_0^T> per block (mode 3)
   double* xnorm2;  // ||X||^2
@@ -71,13 +69,44 @@ struct BItem {
 
 static_assert(sizeof(BItem) % sizeof(int) == 0, "the kernel copies BItem into LDS word by word");
 
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) double gdouble;
+
+// The kernel's view of a BItem: the same bytes, every pointer typed as
+// global memory.  Generic (flat) accesses count on the LDS counter as well,
+// so a flat access pending anywhere makes the compiler wait for all LDS and
+// global traffic before the next LDS read; global pointers keep the two
+// apart.
+struct GItem {
+  int64_t I[3];
+  int R;
+  int nB[3];
+  int rows[3];
+  gcfloat* X;
+  int64_t I0p;
+  gdouble* A[3];
+  gdouble* lam;
+  gdouble* relerr;
+  gdouble* Q[3];
+  gfloat* Qf[3];
+  gdouble* Rf[3];
+  gdouble* Q0b[3];
+  gdouble* R0b[3];
+  gfloat* Z;
+  gfloat* T;
+  gfloat* Y;
+  gdouble* lamp;
+  gdouble* ipp;
+  gdouble* xnorm2;
+};
+static_assert(sizeof(GItem) == sizeof(BItem), "GItem mirrors BItem");
+static_assert(offsetof(GItem, xnorm2) == offsetof(BItem, xnorm2), "GItem mirrors BItem");
+static_assert(offsetof(GItem, Z) == offsetof(BItem, Z) && offsetof(GItem, X) == offsetof(BItem, X),
+              "GItem mirrors BItem");
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-// The descriptors hold generic pointers; tensor traffic goes through these
-// global-memory views so that it compiles to global (not flat) loads and
-// stores, which the LDS counter does not wait on.
-typedef __attribute__((address_space(1))) const float gcfloat;
-typedef __attribute__((address_space(1))) float gfloat;
 __device__ inline gcfloat* gview(const float* p) { return (gcfloat*)p; }
 // Descriptor fields come from LDS, which the compiler does not know to be
 // the same in every lane; these declare a value wave-uniform so that it
@@ -94,15 +123,11 @@ __device__ inline T* uni(T* p) {
 }
 __device__ inline gfloat* gview(float* p) { return (gfloat*)p; }
 
-// 77 KB: two workgroups share a CU's 160 KB.
+// About 62 KB: two workgroups share a CU's 160 KB.
 struct BShared {
-  alignas(16) float us[IMAX * RB];  // contraction operand U (FP32, k-major, 16 columns)
-  union alignas(16) {
-    float ys[YSF];  // Y rows of a block, row stride R^2 + 1
-    Shared<RB, NT> qr;
-  };
+  alignas(16) float us[IMAX * RB];  // contraction operand U (FP32, 16 columns; layout per use)
+  Shared<RB, NT> qr;
   double q0[RB * RB * RB];  // Q_0 of the current mode, row-major R^2 x R
-  double ws[WROWS * RB];    // W rows of a block (FP64)
   double r0[RB][RB + 1];
   double rn[RB][RB + 1];
   double lam[RB];
@@ -113,11 +138,22 @@ struct BShared {
 // U rows [0, rows) into LDS (row-major, 16 floats a row, zero past R) and
 // zero rows up to the next multiple of 4, so that a 4-step MFMA over the
 // contraction index reads zeros past its end.
-__device__ inline void stage_u(const float* Qf, int rows, float* us, int tid) {
-  const float4* src = reinterpret_cast<const float4*>(Qf);
-  float4* dst = reinterpret_cast<float4*>(us);
+__device__ inline void stage_u(gcfloat* Qf, int rows, float* us, int tid) {
+  const __attribute__((address_space(1))) floatx4* src = reinterpret_cast<const __attribute__((address_space(1))) floatx4*>(Qf);
+  floatx4* dst = reinterpret_cast<floatx4*>(us);
   const int n = rows * (RB / 4), n4 = ((rows + 3) & ~3) * (RB / 4);
-  for (int e = tid; e < n4; e += NT) dst[e] = e < n ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int e = tid; e < n4; e += NT) dst[e] = e < n ? src[e] : floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// U for stream_k: us4[(k / 4) * 64 + 4 c + k % 4] = U[k, c] (the four k of a
+// lane's 16-byte run next to each other), zero for k >= rows up to the next
+// multiple of 16.
+__device__ inline void stage_u4(gcfloat* Qf, int rows, float* us4, int tid) {
+  const int n16 = (rows + 15) & ~15;
+  for (int e = tid; e < n16 * RB; e += NT) {
+    const int j = e & 3, c = (e >> 2) & (RB - 1), k = 4 * (e >> 6) + j;
+    us4[e] = k < rows ? Qf[k * RB + c] : 0.f;
+  }
 }
 
 // ------------------------------------------------- streaming pass (AZ, AT)
@@ -141,7 +177,7 @@ __device__ inline void stage_u(const float* Qf, int rows, float* us, int tid) {
 constexpr uint32_t OOB = 0x80000000u;  // a byte offset past any tensor here (at most 64 MB)
 
 template <int D, int MG, bool SQ>
-__device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out, uint32_t P, int K, uint32_t S,
+__device__ void stream_mfma(gcfloat* __restrict__ X, gfloat* __restrict__ out, uint32_t P, int K, uint32_t S,
                             int R, const float* us, double& xx, int tid) {
   X = uni(X);
   out = uni(out);
@@ -155,9 +191,9 @@ __device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out
   const int mygrp = ngrp > w ? (ngrp - w + NW - 1) / NW : 0;
   const int nks = (K + 3) >> 2;
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), short(0), int(M * uint32_t(K) * 4u), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc((void*)(const float*)X, short(0), int(M * uint32_t(K) * 4u), 0x00020000);
   const uint32_t step_bytes = P * 16u;
-  gfloat* const og = gview(out);
+  gfloat* const og = out;
   // Drain every memory operation of the earlier phases (some are flat, which
   // count on both counters): with one pending here, the compiler could only
   // wait for zero outstanding loads at the top of every step group.
@@ -242,81 +278,91 @@ __device__ void stream_mfma(const float* __restrict__ X, float* __restrict__ out
   }
 }
 
-// ---------------------------------------------------- Y rows of a block
-// ys[rl (R^2 + 1) + ru + R rt] = sum_i U[i, ru] src[(a + rl) srow + i si + rt srt]
-// for rl < nb, i < Kc, on the matrix cores: items (16-row group g, rt) are
-// dealt to the waves four at a time, the four sharing the B operand
-// U[i, l16]; lane (l16, kq) loads row a + 16 g + l16 (clamped to the mode,
-// the extra rows are dropped) at i = 4 t + kq.
-__device__ void y_rows_mfma(const float* __restrict__ src, int64_t srow, int64_t si, int64_t srt, int Kc, int a,
-                            int nb, int64_t In, int R, const float* us, float* ys, int tid) {
-  src = uni(src);
-  srow = uni(srow);
-  si = uni(si);
-  srt = uni(srt);
-  Kc = uni(Kc);
-  nb = uni(nb);
-  In = uni(In);
+// ------------------------------------- contraction over the contiguous index
+// out[p + P r + P R s] = sum_k X[k + L m] U[k, r] for the rows m = p + P s <
+// M = P S (L a multiple of 4 and >= K, X 16-byte aligned), U in LDS as us4
+// (zero for k >= K).  Tiles of 16 rows go on the M dimension of
+// v_mfma_f32_16x16x4f32, MG tiles of a wave at a time (tiles dealt round
+// robin).  In step t, lane (l16, kq) loads the 16-byte run k = 16 t + 4 kq
+// .. + 3 of row l16 of each tile and feeds value j to MFMA j of the tile,
+// whose k slots are 16 t + 4 kq + j; the four MFMAs of a tile add into the
+// same accumulator.  Loads run D steps ahead within the MG tiles; runs past
+// the row (k >= L) and rows past M read zeros (buffer range check).  The
+// order of every sum is fixed by the layout, whatever D and MG.
+template <int D, int MG>
+__device__ void stream_k(gcfloat* __restrict__ X, gfloat* __restrict__ out, uint32_t L, int K, uint32_t P,
+                         uint32_t S, int R, const float* us4, int tid) {
+  X = uni(X);
+  out = uni(out);
+  L = uni(L);
+  K = uni(K);
+  P = uni(P);
+  S = uni(S);
   R = uni(R);
-  __builtin_amdgcn_s_waitcnt(0);  // as in stream_mfma: no earlier flat access left pending
   const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
-  const int nitem = ((nb + 15) >> 4) * R;
-  const int nks = (Kc + 3) >> 2;
-  const int K0p = R * R + 1;
-  for (int e0 = 4 * w; e0 < nitem; e0 += 4 * NW) {
-    gcfloat* base[4];
+  const uint32_t M = P * S;
+  const int ntile = int((M + 15) / 16);
+  const int mytiles = ntile > w ? (ntile - w + NW - 1) / NW : 0;
+  const int nks = (K + 15) >> 4;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(const float*)X, short(0), int(M * L * 4u), 0x00020000);
+  __builtin_amdgcn_s_waitcnt(0);  // as in stream_mfma
+  for (int t0 = 0; t0 < mytiles; t0 += MG) {
+    uint32_t m0[MG];  // first row of each tile (M when the wave has no such tile)
+    uint32_t vo[MG];  // byte offset of the lane's run at k = 4 kq
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = e0 + q < nitem ? e0 + q : e0;
-      const int g = e / R, rt = e - g * R;
-      int64_t row = a + 16 * g + l16;
-      row = row < In ? row : In - 1;
-      base[q] = gview(src) + row * srow + int64_t(rt) * srt;
+    for (int g = 0; g < MG; ++g) {
+      m0[g] = t0 + g < mytiles ? uint32_t(w + NW * (t0 + g)) * 16u : M;
+      const uint32_t m = m0[g] + uint32_t(l16);
+      vo[g] = m < M ? (m * L + 4u * uint32_t(kq)) * 4u : OOB;
     }
-    floatx4 acc[4];
+    auto load = [&](u32x4 (&dst)[MG], int st) {
+      const bool kin = 16 * st + 4 * kq < int(L);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // i >= Kc reads the element at Kc - 1 again; its U row is zero
-    auto step = [&](int t) {
-      const int kk = 4 * t + kq;
-      const int64_t off = int64_t(kk < Kc ? kk : Kc - 1) * si;
-      return floatx4{base[0][off], base[1][off], base[2][off], base[3][off]};
+      for (int g = 0; g < MG; ++g)
+        dst[g] = __builtin_amdgcn_raw_buffer_load_b128(rs, kin ? vo[g] : OOB, uint32_t(st) * 64u, 0);
     };
-    int t = 0;
-    for (; t + 4 <= nks; t += 4) {
-      floatx4 xs[4];
+    floatx4 acc[MG];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = step(t + u);
+    for (int g = 0; g < MG; ++g) acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](const u32x4 (&xu)[MG], int st) {
+      const floatx4 bv = *reinterpret_cast<const floatx4*>(us4 + ((4 * st + kq) * RB + l16) * 4);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float bv = us[(4 * (t + u) + kq) * RB + l16];
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].x, bv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].y, bv, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].z, bv, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[u].w, bv, acc[3], 0, 0, 0);
+      for (int g = 0; g < MG; ++g) {
+        const floatx4 x = __builtin_bit_cast(floatx4, xu[g]);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, bv.x, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, bv.y, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, bv.z, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, bv.w, acc[g], 0, 0, 0);
       }
+    };
+    u32x4 xr[D][MG];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      load(xr[u], u);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    for (; t < nks; ++t) {
-      const floatx4 xv = step(t);
-      const float bv = us[(4 * t + kq) * RB + l16];
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv, acc[1], 0, 0, 0);
-      acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv, acc[2], 0, 0, 0);
-      acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv, acc[3], 0, 0, 0);
+    for (int q = 0; q < nks; q += D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        if (q + u < nks) compute(xr[u], q + u);
+        load(xr[u], q + u + D);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     if (l16 < R) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = e0 + q;
-        if (e >= nitem) continue;
-        const int g = e / R, rt = e - g * R;
+      for (int g = 0; g < MG; ++g)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rl = 16 * g + 4 * kq + v;
-          if (rl < nb) ys[rl * K0p + l16 + R * rt] = acc[q][v];
+        for (int v = 0; v < 4; ++v) {  // value v of the tile: row 4 kq + v, column l16
+          const uint32_t m = m0[g] + 4u * uint32_t(kq) + uint32_t(v);
+          if (m < M) {
+            const uint32_t s = m / P, p = m - s * P;
+            out[p + size_t(P) * (size_t(l16) + size_t(R) * s)] = acc[g][v];
+          }
         }
-      }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // as in stream_mfma
   }
 }
 
@@ -330,66 +376,113 @@ __device__ inline double wg_sum1(double v, BShared& sh, int tid) {
   return sh.res[0];
 }
 
-// ------------------------------------------------------------- B task
-// The source of mode n's Y rows: Y_(n)(row, ru + R rt) = sum_i U[i, ru]
-// src[row srow + i si + rt srt], U = Q_um (FP32 copy), i < Kc.
-struct YSrc {
-  const float* src;
-  int64_t srow, si, srt;
-  int Kc, um;
+// ------------------------------------------------------------- row steps
+// Y_(n)(i, ru + R rt) = sum over the contracted index of U[., ru] times the
+// source, U = Q_2 for mode 1 and Q_1 for modes 2 and 3 (new Q_1 for mode 2);
+// ru, rt index the modes of Q_0's rows (ru fastest).  Y goes to global
+// scratch at Y[i si + ru su + rt st]:
+//   mode 1: from Z(i1, i2, r3), contract i2 (rows i1 of each r3 slab)
+//   mode 2: from Z(i1, i2, r3), contract i1 (rows (i2, r3), i1 contiguous)
+//   mode 3: from T(i1, r2, i3), contract i1 (rows (r2, i3), i1 contiguous)
+struct YLayout {
+  int64_t si, su, st;
 };
 
-__device__ inline YSrc y_source(const BItem& it, int n) {
-  const int R = it.R;
-  const int64_t I0 = it.I[0], I1 = it.I[1];
-  const int64_t L0 = it.I0p;  // row stride of Z and T
-  if (n == 0) return YSrc{it.Z, 1, L0, L0 * I1, int(I1), 1};      // Y_(1)(i1, r2 + R r3) = sum_i2 Q_2(i2, r2) Z(i1, i2, r3)
-  if (n == 1) return YSrc{it.Z, L0, 1, L0 * I1, int(I0), 0};      // Y_(2)(i2, r1 + R r3) = sum_i1 Q_1(i1, r1) Z(i1, i2, r3)
-  return YSrc{it.T, L0 * R, 1, L0, int(I0), 0};                   // Y_(3)(i3, r1 + R r2) = sum_i1 Q_1(i1, r1) T(i1, r2, i3)
+__device__ inline YLayout y_layout(const GItem& it, int n) {
+  const int64_t R = it.R, L0 = it.I0p, I1 = it.I[1];
+  if (n == 0) return YLayout{1, L0, L0 * R};
+  if (n == 1) return YLayout{1, I1, I1 * R};
+  return YLayout{R * R, R, 1};
 }
 
-// Operands of mode n's row steps into LDS: U, Q_0 (R^2 x R, FP64) and R_0.
-__device__ __attribute__((always_inline)) void mode_begin(const BItem& it, int n, BShared& sh, int tid) {
+// Operands of mode n's row steps into LDS: U (in the layout its contraction
+// reads), Q_0 (R^2 x R, FP64) and R_0.
+__device__ __attribute__((always_inline)) void mode_begin(const GItem& it, int n, BShared& sh, int tid) {
   const int R = it.R;
-  const YSrc ysrc = y_source(it, n);
-  stage_u(it.Qf[ysrc.um], ysrc.Kc, sh.us, tid);
-  const double* q0 = it.Q0b[n];
+  if (n == 0)
+    stage_u(it.Qf[1], int(it.I[1]), sh.us, tid);
+  else
+    stage_u4(it.Qf[0], int(it.I[0]), sh.us, tid);
+  gdouble* q0 = it.Q0b[n];
   for (int e = tid; e < R * R * R; e += NT) sh.q0[e] = q0[e];
   for (int e = tid; e < R * R; e += NT) sh.r0[e % R][e / R] = it.R0b[n][e];
   __syncthreads();
 }
 
-// Rows [a, a + nb) of mode n: Y rows, W = Y Q_0, A R_0^T = W, partials.
-__device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, int a, int nb, int slot, BShared& sh, int tid) {
+// Y_(n) of the whole mode into it.Y.
+template <int D, int MG>
+__device__ __attribute__((always_inline)) void task_y(const GItem& it, int n, BShared& sh, int tid) {
+  const uint32_t L0 = uint32_t(it.I0p), I1 = uint32_t(it.I[1]), I2 = uint32_t(it.I[2]), R = uint32_t(it.R);
+  double unused = 0.0;
+  if (n == 0)       // out[i1 + L0 r2 + L0 R r3] = sum_i2 Z[i1 + L0 i2 + L0 I1 r3] Q_2[i2, r2]
+    stream_mfma<D, MG, false>(it.Z, it.Y, L0, int(I1), R, int(R), sh.us, unused, tid);
+  else if (n == 1)  // out[i2 + I1 r1 + I1 R r3] = sum_i1 Z[i1 + L0 (i2 + I1 r3)] Q_1[i1, r1]
+    stream_k<D, MG>(it.Z, it.Y, L0, int(it.I[0]), I1, R, int(R), sh.us, tid);
+  else              // out[r2 + R r1 + R^2 i3] = sum_i1 T[i1 + L0 (r2 + R i3)] Q_1[i1, r1]
+    stream_k<D, MG>(it.T, it.Y, L0, int(it.I[0]), R, I2, int(R), sh.us, tid);
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// W = Y Q_0 for all rows of mode n on v_mfma_f64_16x16x4f64 (Y's FP32
+// entries widened, FP64 products and sums), written into A[n] (column-major),
+// which the substitution then overwrites row by row.  Tiles of 16 rows are
+// dealt to the waves; step t takes Q_0 rows rho = 4 t + kq (lane (l16, kq)
+// loads Y(row l16, rho) and Q_0(rho, l16), zero past R^2 and R), four steps
+// of loads at a time.  The f64 MFMA returns row kq + 4 v of its tile in value
+// v of lane (l16, kq).
+__device__ __attribute__((always_inline)) void task_w(const GItem& it, int n, BShared& sh, int tid) {
   const int R = it.R;
-  const YSrc ys = y_source(it, n);
   const int64_t In = it.I[n];
-  y_rows_mfma(ys.src, ys.srow, ys.si, ys.srt, ys.Kc, a, nb, In, R, sh.us, sh.ys, tid);
-  __syncthreads();
-  // W rows (FP64) into sh.ws, row-major nb x RB; four partial sums per entry
-  const int K0 = R * R, K0p = K0 + 1;
-  for (int e = tid; e < nb * R; e += NT) {
-    const int rl = e % nb, c = e / nb;
-    const float* yr = sh.ys + rl * K0p;
-    const double* qc = sh.q0 + c;
-    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-    int rho = 0;
-    for (; rho + 4 <= K0; rho += 4) {
-      w0 = fma(double(yr[rho]), qc[rho * R], w0);
-      w1 = fma(double(yr[rho + 1]), qc[(rho + 1) * R], w1);
-      w2 = fma(double(yr[rho + 2]), qc[(rho + 2) * R], w2);
-      w3 = fma(double(yr[rho + 3]), qc[(rho + 3) * R], w3);
+  const YLayout yl = y_layout(it, n);
+  const int lane = tid & (WAVE - 1), w = tid / WAVE, l16 = lane & 15, kq = lane >> 4;
+  const int K0 = R * R, nst = (K0 + 3) / 4;
+  const int ntile = int((In + 15) / 16);
+  gdouble* An = it.A[n];
+  for (int t = w; t < ntile; t += NW) {
+    const int64_t row = int64_t(t) * 16 + l16 < In ? int64_t(t) * 16 + l16 : In - 1;
+    gcfloat* yr = it.Y + row * yl.si;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int st = 0; st < nst; st += 4) {
+      float y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int rho = 4 * (st + u) + kq;
+        rho = rho < K0 ? rho : K0 - 1;
+        const int rt = rho / R, ru = rho - rt * R;
+        y[u] = yr[ru * yl.su + rt * yl.st];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rho = 4 * (st + u) + kq;
+        const double b = (rho < K0 && l16 < R) ? sh.q0[rho * R + l16] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(double(y[u]), b, acc, 0, 0, 0);
+      }
     }
-    for (; rho < K0; ++rho) w0 = fma(double(yr[rho]), qc[rho * R], w0);
-    sh.ws[rl * RB + c] = (w0 + w1) + (w2 + w3);
+    if (l16 < R) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = int64_t(t) * 16 + kq + 4 * v;
+        if (i < In) An[i + In * l16] = acc[v];
+      }
+    }
   }
-  __syncthreads();
+}
+
+// All rows of mode n, one per thread: the row of W from A[n], A R_0^T = W by
+// substitution, then the column sums of squares of A (and for mode 3
+// <W, A R_0^T>) as the single partial of slot 0.
+__device__ __attribute__((always_inline)) void task_rows(const GItem& it, int n, BShared& sh, int tid) {
+  const int R = it.R;
+  const int64_t In = it.I[n];
+  double w[RB];
+#pragma unroll
+  for (int c = 0; c < RB; ++c) w[c] = (tid < In && c < R) ? it.A[n][tid + In * c] : 0.0;
   double arow[RB], x[RB];
 #pragma unroll
   for (int c = 0; c < RB; ++c) arow[c] = 0.0;
   double ip = 0.0;
-  if (tid < nb) {
-    const double* w = sh.ws + tid * RB;
+  if (tid < In) {
 #pragma unroll
     for (int j = RB - 1; j >= 0; --j) {
       if (j < R) {
@@ -400,7 +493,7 @@ __device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, in
         arow[j] = v / sh.r0[j][j];
       }
     }
-    double* An = it.A[n] + a + tid;
+    gdouble* An = it.A[n] + tid;
 #pragma unroll
     for (int c = 0; c < RB; ++c)
       if (c < R) An[int64_t(c) * In] = arow[c];
@@ -419,10 +512,10 @@ __device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, in
 #pragma unroll
   for (int c = 0; c < RB; ++c) x[c] = arow[c] * arow[c];
   wg_sum16(x, sh, tid);
-  if (tid < RB) it.lamp[slot * RB + tid] = sh.res[tid];
+  if (tid < RB) it.lamp[tid] = sh.res[tid];
   if (n == 2) {
     ip = wg_sum1(ip, sh, tid);
-    if (tid == 0) it.ipp[slot] = ip;
+    if (tid == 0) it.ipp[0] = ip;
   }
 }
 
@@ -430,8 +523,8 @@ __device__ __attribute__((always_inline)) void task_b(const BItem& it, int n, in
 // Householder QR of a (one row per thread, m rows).  Writes R (column-major
 // R x R) to Rout and, if keep_rn, into sh.rn; Q as requested: column-major
 // FP64 (ld m), row-major FP32 padded to RB, row-major FP64 (ld R).
-__device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, int R, BShared& sh, double* Qcm, float* Qf, double* Qrm,
-                         double* Rout, bool keep_rn, int tid) {
+__device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, int R, BShared& sh, gdouble* Qcm, gfloat* Qf, gdouble* Qrm,
+                         gdouble* Rout, bool keep_rn, int tid) {
   wg_factor<RB, NT>(a, tid, m, R, sh.qr);
   wg_build_t<RB, NT>(tid, R, sh.qr);
   if (tid < R) {
@@ -453,15 +546,11 @@ __device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, 
       if (Qrm && c < R) Qrm[tid * R + c] = q[c];
     }
     if (Qf) {
-      float4* dst = reinterpret_cast<float4*>(Qf + tid * RB);
+      __attribute__((address_space(1))) floatx4* dst = reinterpret_cast<__attribute__((address_space(1))) floatx4*>(Qf + tid * RB);
 #pragma unroll
       for (int g = 0; g < RB / 4; ++g) {
-        float4 v;
-        v.x = 4 * g < R ? float(q[4 * g]) : 0.f;
-        v.y = 4 * g + 1 < R ? float(q[4 * g + 1]) : 0.f;
-        v.z = 4 * g + 2 < R ? float(q[4 * g + 2]) : 0.f;
-        v.w = 4 * g + 3 < R ? float(q[4 * g + 3]) : 0.f;
-        dst[g] = v;
+        dst[g] = floatx4{4 * g < R ? float(q[4 * g]) : 0.f, 4 * g + 1 < R ? float(q[4 * g + 1]) : 0.f,
+                         4 * g + 2 < R ? float(q[4 * g + 2]) : 0.f, 4 * g + 3 < R ? float(q[4 * g + 3]) : 0.f};
       }
     }
   }
@@ -469,7 +558,7 @@ __device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, 
 }
 
 // QR of V_n = R_mb (.) R_ma (rows: index of ma fastest) into Q0b[n], R0b[n].
-__device__ __attribute__((always_inline)) void krp_qr(const BItem& it, int n, BShared& sh, int tid) {
+__device__ __attribute__((always_inline)) void krp_qr(const GItem& it, int n, BShared& sh, int tid) {
   const int R = it.R;
   const int ma = n == 0 ? 1 : 0, mb = n == 2 ? 1 : 2;
   const int K0 = R * R;
@@ -481,7 +570,7 @@ __device__ __attribute__((always_inline)) void krp_qr(const BItem& it, int n, BS
   qr_store(a, K0, R, sh, nullptr, nullptr, it.Q0b[n], it.R0b[n], false, tid);
 }
 
-__device__ __attribute__((always_inline)) void task_init(const BItem& it, BShared& sh, int tid) {
+__device__ __attribute__((always_inline)) void task_init(const GItem& it, BShared& sh, int tid) {
   const int R = it.R;
   for (int k = 1; k < 3; ++k) {
     const int64_t Ik = it.I[k];
@@ -496,15 +585,10 @@ __device__ __attribute__((always_inline)) void task_init(const BItem& it, BShare
 
 // Normalize A_n, factor QR of A_n, efficient error after mode 3, Khatri-Rao
 // QR for the next mode.
-__device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, int sweep, int offset, BShared& sh, int tid) {
+__device__ __attribute__((always_inline)) void task_c(const GItem& it, int n, int sweep, int offset, BShared& sh, int tid) {
   const int R = it.R;
   const int64_t In = it.I[n];
-  const int nb = it.nB[n];
-  if (tid < RB) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += it.lamp[b * RB + tid];
-    sh.lam[tid] = tid < R ? sqrt(s) : 0.0;
-  }
+  if (tid < RB) sh.lam[tid] = tid < R ? sqrt(it.lamp[tid]) : 0.0;
   __syncthreads();
   double a[RB];
 #pragma unroll
@@ -523,8 +607,10 @@ __device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, in
   if (n == 2) {  // ||X||^2 - 2 <W, A R_0^T> + <R_0^T R_0, L R_3^T R_3 L>   (section 3.3.1)
     for (int e = tid; e < R * R; e += NT) sh.r0[e % R][e / R] = it.R0b[2][e];
     double ip = 0.0, x2 = 0.0;
-    for (int b = tid; b < nb; b += NT) ip += it.ipp[b];
-    if (tid == 0) x2 = *it.xnorm2;
+    if (tid == 0) {
+      ip = it.ipp[0];
+      x2 = *it.xnorm2;
+    }
     __syncthreads();
     double nn = 0.0;
     for (int e = tid; e < R * R; e += NT) {
@@ -551,7 +637,7 @@ __device__ __attribute__((always_inline)) void task_c(const BItem& it, int n, in
 // Streaming contraction over the whole tensor: Z = X x_3 Q_3^T (isz) or
 // T = X x_2 Q_2^T.  Z also yields ||X||^2.
 template <int D, int MG>
-__device__ __attribute__((always_inline)) void task_a(const BItem& it, bool isz, BShared& sh, int tid) {
+__device__ __attribute__((always_inline)) void task_a(const GItem& it, bool isz, BShared& sh, int tid) {
   const int k = isz ? 2 : 1;
   stage_u(it.Qf[k], int(it.I[k]), sh.us, tid);
   __syncthreads();
@@ -576,15 +662,15 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
   __shared__ BShared sh;
   // The descriptor lives in LDS: its fields are read where they are used
   // instead of being held in registers for the whole launch.
-  __shared__ BItem itl;
+  __shared__ GItem itl;
   const int tid = threadIdx.x;
   {
     const int* src = reinterpret_cast<const int*>(items + order[blockIdx.x]);
     int* dst = reinterpret_cast<int*>(&itl);
-    for (int e = tid; e < int(sizeof(BItem) / sizeof(int)); e += NT) dst[e] = src[e];
+    for (int e = tid; e < int(sizeof(GItem) / sizeof(int)); e += NT) dst[e] = src[e];
   }
   __syncthreads();
-  const BItem& it = itl;
+  const GItem& it = itl;
   if (do_init) {
     task_init(it, sh, tid);
     __syncthreads();
@@ -596,12 +682,12 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
         __syncthreads();
       }
       mode_begin(it, n, sh, tid);
-      for (int blk = 0; blk < it.nB[n]; ++blk) {
-        const int a = blk * it.rows[n];
-        const int cnt = int(it.I[n] - a < it.rows[n] ? it.I[n] - a : it.rows[n]);
-        task_b(it, n, a, cnt, blk, sh, tid);
-        __syncthreads();
-      }
+      task_y<D, MG>(it, n, sh, tid);
+      __syncthreads();
+      task_w(it, n, sh, tid);
+      __syncthreads();
+      task_rows(it, n, sh, tid);
+      __syncthreads();
       task_c(it, n, s, offset, sh, tid);
       __syncthreads();
     }
@@ -614,24 +700,12 @@ __global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restric
 constexpr int NVAR = 3;
 constexpr int VAR_D[NVAR] = {8, 4, 16};
 constexpr int VAR_MG[NVAR] = {2, 4, 1};
-constexpr int ROWS_MIN = 16;
 
 struct Config {
   int var;   // streaming-pass shape
-  int rows;  // rows per block of the row steps (before the LDS cap)
+  int rows;  // kept for the cache file format; the row steps take whole modes (0)
 };
 
-// Rows per block: a multiple of 16 (one MFMA row group), at most WROWS, and
-// no more Y rows (R^2 + 1 floats each) than the LDS buffer holds.
-int rows_for(int rows_cfg, int R) {
-  const int cap = std::min(YSF / (R * R + 1), WROWS);
-  return std::max(16, std::min(rows_cfg, cap) / 16 * 16);
-}
-
-int blocks_max(const cpqr_batch_item& b) {
-  const int r = rows_for(ROWS_MIN, b.R);
-  return int(ceil_div(std::max(b.I[0], std::max(b.I[1], b.I[2])), int64_t(r)));
-}
 
 // The streaming passes read 16-byte runs along the first mode: a tensor is
 // streamed in place when its first mode is a multiple of 4 and it is
@@ -643,7 +717,6 @@ bool needs_copy(const cpqr_batch_item& b) {
 size_t item_scratch(const cpqr_batch_item& b) {
   const int64_t R = b.R;
   const int64_t i0 = b.I[0], i1 = b.I[1], i2 = b.I[2];
-  const int nbmax = blocks_max(b);
   Carver cv(nullptr);
   for (int m = 0; m < 3; ++m) cv.take<double>(size_t(b.I[m]) * R);  // Q
   for (int m = 0; m < 3; ++m) cv.take<float>(size_t(b.I[m]) * RB);  // Qf
@@ -654,8 +727,9 @@ size_t item_scratch(const cpqr_batch_item& b) {
   cv.take<float>(size_t(l0 * i1 * R));                             // Z
   cv.take<float>(size_t(l0 * R * i2));                             // T
   if (needs_copy(b)) cv.take<float>(size_t(l0 * i1 * i2));         // padded copy of X
-  cv.take<double>(size_t(nbmax) * RB);                             // lamp
-  cv.take<double>(size_t(nbmax));                                  // ipp
+  cv.take<float>(size_t(std::max(l0, std::max(i1, i2)) * R * R));  // Y
+  cv.take<double>(size_t(RB));                                     // lamp
+  cv.take<double>(1);                                              // ipp
   cv.take<double>(1);                                              // xnorm2
   return cv.bytes();
 }
@@ -675,8 +749,8 @@ std::map<const void*, BatchState> g_batch;
 int upload(BatchState& st, hipStream_t s) {
   for (auto& d : st.h) {
     for (int m = 0; m < 3; ++m) {
-      d.rows[m] = rows_for(st.cfg.rows, d.R);
-      d.nB[m] = int(ceil_div(d.I[m], int64_t(d.rows[m])));
+      d.rows[m] = int(d.I[m]);  // the row steps take a whole mode at once
+      d.nB[m] = 1;
     }
   }
   CPQR_HIP(hipMemcpyAsync(st.items_dev, st.h.data(), sizeof(BItem) * st.n, hipMemcpyHostToDevice, s));
@@ -767,7 +841,7 @@ std::string tune_key(const cpqr_batch_item* items, int n) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   char buf[256];
-  snprintf(buf, sizeof(buf), "batch3|%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n,
+  snprintf(buf, sizeof(buf), "batch4|%s|n%d|imax%lld|rmax%d|elems2^%d", arch.c_str(), n,
            (long long)((maxi + 31) / 32 * 32), maxr, lg);
   return buf;
 }
@@ -834,7 +908,6 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
   for (int b = 0; b < nitems; ++b) {
     const cpqr_batch_item& it = items[b];
     Carver c2(cv.take<char>(item_scratch(it)));
-    const int nbmax = blocks_max(it);
     BItem& d = st.h[b];
     d = BItem{};
     for (int k = 0; k < 3; ++k) d.I[k] = it.I[k];
@@ -859,8 +932,9 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
                                 sizeof(float) * size_t(it.I[0]), size_t(it.I[1] * it.I[2]), hipMemcpyDeviceToDevice, s));
       d.X = xp;
     }
-    d.lamp = c2.take<double>(size_t(nbmax) * RB);
-    d.ipp = c2.take<double>(size_t(nbmax));
+    d.Y = c2.take<float>(size_t(std::max(d.I0p, std::max(it.I[1], it.I[2])) * R * R));
+    d.lamp = c2.take<double>(size_t(RB));
+    d.ipp = c2.take<double>(1);
     d.xnorm2 = c2.take<double>(1);
   }
   // larger tensors first (longest-processing-time order)
@@ -877,14 +951,14 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
     CPQR_HIP(hipMemcpyAsync(saved[2 * b + 1], items[b].A[2], sizeof(double) * items[b].I[2] * items[b].R,
                             hipMemcpyDeviceToDevice, s));
   }
-  st.cfg = Config{1, 64};
+  st.cfg = Config{1, 0};
   if (autotune) {
     const std::string key = tune_key(items, nitems);
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load();
     auto found = g_tune.find(key);
     if (found != g_tune.end() && found->second.var >= 0 && found->second.var < NVAR &&
-        found->second.rows >= ROWS_MIN) {
+        found->second.rows == 0) {
       st.cfg = found->second;
     } else {
       // time one init + sweep per candidate, restoring the initial factors after each
@@ -894,26 +968,24 @@ int cpqr_als_batch_prepare(const cpqr_batch_item* items, int nitems, int autotun
       float best = 1e30f;
       Config bestc = st.cfg;
       for (int var = 0; var < NVAR; ++var) {
-        for (int rows : {32, 64}) {
-          st.cfg = Config{var, rows};
-          CPQR_TRY(upload(st, s));
-          CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));  // warm
-          CPQR_HIP(hipEventRecord(e0, s));
-          CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));
-          CPQR_HIP(hipEventRecord(e1, s));
-          CPQR_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          CPQR_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (ms < best) {
-            best = ms;
-            bestc = st.cfg;
-          }
-          for (int b = 0; b < nitems; ++b) {
-            CPQR_HIP(hipMemcpyAsync(items[b].A[1], saved[2 * b], sizeof(double) * items[b].I[1] * items[b].R,
-                                    hipMemcpyDeviceToDevice, s));
-            CPQR_HIP(hipMemcpyAsync(items[b].A[2], saved[2 * b + 1], sizeof(double) * items[b].I[2] * items[b].R,
-                                    hipMemcpyDeviceToDevice, s));
-          }
+        st.cfg = Config{var, 0};
+        CPQR_TRY(upload(st, s));
+        CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));  // warm
+        CPQR_HIP(hipEventRecord(e0, s));
+        CPQR_TRY(launch_batch(st, var, 1, 1, 0, s));
+        CPQR_HIP(hipEventRecord(e1, s));
+        CPQR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CPQR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          bestc = st.cfg;
+        }
+        for (int b = 0; b < nitems; ++b) {
+          CPQR_HIP(hipMemcpyAsync(items[b].A[1], saved[2 * b], sizeof(double) * items[b].I[1] * items[b].R,
+                                  hipMemcpyDeviceToDevice, s));
+          CPQR_HIP(hipMemcpyAsync(items[b].A[2], saved[2 * b + 1], sizeof(double) * items[b].I[2] * items[b].R,
+                                  hipMemcpyDeviceToDevice, s));
         }
       }
       (void)hipEventDestroy(e0);

@@ -96,7 +96,7 @@ def test_autotune_picks_a_valid_size(batch, tmp_path, monkeypatch):
     sub = batch[:8]
     B = run_batch(sub, 3, autotune=True)
     cpt, unroll, rows = B.config
-    assert (cpt, unroll) in ((8, 8), (16, 4), (4, 16)) and rows in (32, 64)
+    assert (cpt, unroll) in ((8, 8), (16, 4), (4, 16)) and rows == 0
     assert (tmp_path / "tune.txt").exists()
 
 
