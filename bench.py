@@ -46,6 +46,8 @@ def parse():
                     help="dense3: n^3 rank-16 benchmark (default); dense4: 200^4 rank-32 precision "
                          "study; batch: 512 uneven 3-way tensors in one persistent launch")
     ap.add_argument("--count", type=int, default=512, help="batch size for --workload batch")
+    ap.add_argument("--batch-variant", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="--workload batch: streaming shape, 0 = autotuned, 1..3 forced (profiling runs)")
     ap.add_argument("--method", default="qr", choices=["qr", "qr-svd", "als", "als-pinv"],
                     help="dense3 only: qr = CP-ALS-QR (Alg. 2, default); qr-svd = CP-ALS-QR-SVD (Alg. 2 with the "
                          "SVD solve); als = CP-ALS with the normal equations (Alg. 1, Cholesky); als-pinv = "
@@ -460,23 +462,26 @@ def run_batch(args):
     torch.cuda.synchronize()
     log("generated %d tensors (%.2f GB) in %.1f s" % (len(shapes), nbytes / 1e9, time.time() - t0))
     nsw = args.steps
-    B = C.AlsBatch(Xs, inits, nsw + 1, autotune=True)
-    log("autotuned: %d rows per lane, %d steps in flight (row blocks %d: whole modes)" % B.config)
-    B.run(1, init=True, graph=True)  # warm-up: init + one sweep (captured, replayed below)
+    var = args.batch_variant  # 0: the autotuner's choice; 1..3 force a streaming shape (no tuning launches)
+    B = C.AlsBatch(Xs, inits, nsw + 1, autotune=var == 0)
+    log("streaming shape: %d rows per lane, %d steps in flight (row blocks %d: whole modes)%s"
+        % (B.config + ("" if var == 0 else " [forced variant %d]" % var,)))
+    B.run(1, init=True, graph=True, variant=var)  # warm-up: init + one sweep (captured, replayed below)
     torch.cuda.synchronize()
     B2 = C.AlsBatch(Xs, inits, nsw)
-    B2.run(nsw, init=True, graph=True)  # capture
+    B2.run(nsw, init=True, graph=True, variant=var)  # capture
     torch.cuda.synchronize()
     B2 = C.AlsBatch(Xs, inits, nsw)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    B2.run(nsw, init=True, graph=True)
+    B2.run(nsw, init=True, graph=True, variant=var)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     rel = np.array([B2.relerr[b][-1].item() for b in range(len(shapes))])
     pass_bytes = 2.0 * nbytes  # two tensor-streaming contractions per sweep (Z shared by modes 1, 2)
+    gbps = pass_bytes * nsw / (ms / 1e3) / 1e9
     out = {
         "metric": METRIC, "value": round(len(shapes) * nsw / (ms / 1e3), 1), "unit": "tensor-sweeps/s",
         "n_gpus": 1, "steps": nsw, "warmup": 1, "ms_per_step": round(ms / nsw, 4), "higher_is_better": True,
@@ -485,7 +490,11 @@ def run_batch(args):
                    "total_bytes": nbytes, "sweeps": nsw, "rows_depth_rowblock": list(B.config),
                    "launch": "one persistent kernel per call, replayed from a hipGraph"},
         "batch_ms_total": round(ms, 3),
-        "tensor_pass_gbps": round(pass_bytes * nsw / (ms / 1e3) / 1e9, 1),
+        "tensor_pass_gbps": round(gbps, 1),
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                     "note": "algorithmic bytes 2 x 4 x sum |X_b| per sweep (two streaming passes) over the "
+                             "event-timed launch, which includes every small step of every tensor"},
         "relerr_median": float(np.median(rel)), "relerr_max": float(np.max(rel)),
     }
     print(json.dumps(out), flush=True)
