@@ -443,15 +443,19 @@ def dense3_f64_record(d, Xd32, steps, warmup):
 
 
 def run_batch(args):
-    """512 independent 3-way FP32 tensors, sizes uniform in [20, 160], ranks in
-    [2, 12], rank-R Gaussian ground truth plus 1e-3 noise; every sweep of every
-    tensor in one persistent launch replayed from a hipGraph."""
+    print(json.dumps(batch_record(args.count, args.steps, args.batch_variant)), flush=True)
+
+
+def batch_record(count, steps, variant):
+    """count independent 3-way FP32 tensors, sizes uniform in [20, 160], ranks
+    in [2, 12], rank-R Gaussian ground truth plus 1e-3 noise; every sweep of
+    every tensor in one persistent launch replayed from a hipGraph."""
     import torch
 
     from paper_2112_10855_amd import cpqr as C
     from paper_2112_10855_amd import synth
 
-    shapes = synth.batch_shapes(args.count)
+    shapes = synth.batch_shapes(count)
     t0 = time.time()
     Xs, inits, nbytes = [], [], 0
     for b, (shape, R) in enumerate(shapes):
@@ -461,8 +465,8 @@ def run_batch(args):
         nbytes += d["X"].nbytes
     torch.cuda.synchronize()
     log("generated %d tensors (%.2f GB) in %.1f s" % (len(shapes), nbytes / 1e9, time.time() - t0))
-    nsw = args.steps
-    var = args.batch_variant  # 0: the autotuner's choice; 1..3 force a streaming shape (no tuning launches)
+    nsw = steps
+    var = variant  # 0: the autotuner's choice; 1..3 force a streaming shape (no tuning launches)
     B = C.AlsBatch(Xs, inits, nsw + 1, autotune=var == 0)
     log("streaming shape: %d rows per lane, %d steps in flight (row blocks %d: whole modes)%s"
         % (B.config + ("" if var == 0 else " [forced variant %d]" % var,)))
@@ -497,7 +501,7 @@ def run_batch(args):
                              "event-timed launch, which includes every small step of every tensor"},
         "relerr_median": float(np.median(rel)), "relerr_max": float(np.max(rel)),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_learned(args):
@@ -857,6 +861,9 @@ def main():
                 data4 = (d4, torch.from_numpy(d4["X"].reshape(-1, order="F")).to("cuda")
                          .view(200, 200, 200, 200).permute(3, 2, 1, 0))
             subs["dense4_200_r32_" + p4] = dense4_record(p4, 20, 2, data4)
+        data4 = None
+        torch.cuda.empty_cache()
+        subs["batch512_3way"] = batch_record(512, 5, 0)
         out["sub_records"] = subs
     print(json.dumps(out), flush=True)
 
