@@ -39,7 +39,7 @@ namespace {
 
 using namespace wgqr;
 
-constexpr int NT = 256;    // threads per workgroup
+constexpr int NT = 512;    // threads per workgroup (eight waves: two per SIMD, one workgroup per CU)
 constexpr int NW = NT / WAVE;
 constexpr int RB = 16;     // register width for rank-indexed rows (R <= 16)
 constexpr int IMAX = 256;  // largest mode size
@@ -656,7 +656,7 @@ __device__ __attribute__((always_inline)) void task_a(const GItem& it, bool isz,
 // One sweep schedule per tensor; the streaming passes keep D contraction
 // steps of MG row groups in flight per lane.
 template <int D, int MG>
-__global__ __launch_bounds__(NT, 2) void als_batch_kernel(const BItem* __restrict__ items,
+__global__ __launch_bounds__(NT, 1) void als_batch_kernel(const BItem* __restrict__ items,
                                                           const int* __restrict__ order, int nsweeps, int do_init,
                                                           int offset) {
   __shared__ BShared sh;
