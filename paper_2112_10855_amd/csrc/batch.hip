@@ -123,10 +123,10 @@ __device__ inline T* uni(T* p) {
 }
 __device__ inline gfloat* gview(float* p) { return (gfloat*)p; }
 
-// About 62 KB: two workgroups share a CU's 160 KB.
+// About 103 KB (one workgroup per CU).
 struct BShared {
   alignas(16) float us[IMAX * RB];  // contraction operand U (FP32, 16 columns; layout per use)
-  Shared<RB, NT> qr;
+  Shared<RB, NT, IMAX> qr;
   double q0[RB * RB * RB];  // Q_0 of the current mode, row-major R^2 x R
   double r0[RB][RB + 1];
   double rn[RB][RB + 1];
@@ -520,17 +520,22 @@ __device__ __attribute__((always_inline)) void task_rows(const GItem& it, int n,
 }
 
 // ------------------------------------------------------------ QR helper
-// Householder QR of a (one row per thread, m rows).  Writes R (column-major
-// R x R) to Rout and, if keep_rn, into sh.rn; Q as requested: column-major
-// FP64 (ld m), row-major FP32 padded to RB, row-major FP64 (ld R).
+// Householder QR of the rows a (row tid of thread tid, m rows; zero past
+// column R and past row m), factorized in LDS.  Writes R (column-major R x R)
+// to Rout and, if keep_rn, into sh.rn; Q as requested: column-major FP64
+// (ld m), row-major FP32 padded to RB, row-major FP64 (ld R).
 __device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, int R, BShared& sh, gdouble* Qcm, gfloat* Qf, gdouble* Qrm,
                          gdouble* Rout, bool keep_rn, int tid) {
-  wg_factor<RB, NT>(a, tid, m, R, sh.qr);
-  wg_build_t<RB, NT>(tid, R, sh.qr);
+  if (tid < IMAX) {
+#pragma unroll
+    for (int c = 0; c < RB; ++c) sh.qr.am[tid][c] = a[c];
+  }
+  wg_factor(tid, m, R, sh.qr);
+  wg_build_t(tid, R, sh.qr);
   if (tid < R) {
 #pragma unroll
     for (int c = 0; c < RB; ++c) {
-      const double v = (c >= tid && c < R) ? a[c] : 0.0;
+      const double v = (c >= tid && c < R) ? sh.qr.am[tid][c] : 0.0;
       if (keep_rn) sh.rn[tid][c] = v;
       if (c < R) Rout[tid + c * R] = v;
     }
@@ -538,7 +543,7 @@ __device__ __attribute__((always_inline)) void qr_store(double (&a)[RB], int m, 
   for (int e = tid; e < RB * RB; e += NT) sh.qr.C[e / RB][e % RB] = (e / RB == e % RB) ? 1.0 : 0.0;
   __syncthreads();
   double q[RB];
-  wg_form_q<RB, NT>(a, q, tid, m, R, sh.qr);
+  wg_form_q(q, tid, m, R, sh.qr);
   if (tid < m) {
 #pragma unroll
     for (int c = 0; c < RB; ++c) {
