@@ -26,6 +26,7 @@
 //  The last contraction lands in the tensor layout [P_n, I_n, S_n]; unless
 //  n is the first mode a permute kernel writes the unfolding Y_(n).
 
+#include <type_traits>
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -65,6 +66,12 @@ __device__ __forceinline__ float4 ldx(const float* p) {
 constexpr int WAVE = 64;
 constexpr int TARGET_WAVES = 2048;  // wavefronts wanted when K is split (8 per CU)
 constexpr int MIN_WAVES = 1024;     // below this many wavefronts, split K
+
+// Steps of a row-tile kernel's load ring: three where the accumulators leave
+// room (two 16-column blocks of one row group or fewer), else two; 0 (a
+// plain pair of load buffers) for steps of more than four 16-byte loads per
+// lane, whose ring would not fit four wavefronts per SIMD.
+constexpr int ring_depth(int NB, int UN, int MG) { return UN * MG > 4 ? 0 : NB * MG <= 2 ? 3 : 2; }
 
 // ------------------------------------------------------------ U preparation
 // Row-major K x RP, zero padded: U[i*RP + r] = Q[i + r*ldq] (r < R).
@@ -179,8 +186,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
     const float* bp[MG];
 #pragma unroll
     for (int g = 0; g < MG; ++g) bp[g] = base[g] + c0 * P;
-    float4 A[UN][MG], B[UN][MG];
-    auto load = [&](float4(&dst)[UN][MG], int t) {
+    auto load = [&](float4(&dst)[UN][MG], int t) {  // steps past the last full one re-read it
       const int i0 = min(t * STEP, last);
 #pragma unroll
       for (int u = 0; u < UN; ++u)
@@ -203,13 +209,35 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
           }
         }
     };
-    if (nfull > 0) {
-      load(A, 0);
-      for (int t = 0; t < nfull; t += 2) {
-        load(B, t + 1);
-        compute(A, t);
-        load(A, t + 2);
-        if (t + 1 < nfull) compute(B, t + 1);
+    // A ring of D steps in flight (D > 0).  The loads leave in step order (no
+    // rescheduling across the barriers) and are unconditional, so that the
+    // wait before each step is for that step's loads only.
+    constexpr int D = ring_depth(NB, UN, MG);
+    if constexpr (D == 0) {
+      float4 A[UN][MG], B[UN][MG];
+      if (nfull > 0) {
+        load(A, 0);
+        for (int t = 0; t < nfull; t += 2) {
+          load(B, t + 1);
+          compute(A, t);
+          load(A, t + 2);
+          if (t + 1 < nfull) compute(B, t + 1);
+        }
+      }
+    } else if (nfull > 0) {
+      float4 xr[D][UN][MG];
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        load(xr[u], u);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int q = 0; q < nfull; q += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+          if (q + u < nfull) compute(xr[u], q + u);
+          load(xr[u], q + u + D);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     for (int i = nfull * STEP; i < cn; i += 4) {  // chunk tail
@@ -539,31 +567,83 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab_m(const float* __restrict__
 // out[r1 + R r2 + R^2 s] = sum_{i1, i2} X[i1, i2, s] U1[i1, r1] U2[i2, r2],
 // i.e. the contraction of the middle mode of the [P = I_1, K = I_2, S]
 // tensor followed by that of the first mode, for P <= 64 MG NWV, one
-// workgroup per slab s.  The slab's rows stream through LDS as in
-// ttm_slab_m and T1 = X(:, :, s) U2 (P x R) stays in registers in the MFMA
-// D layout: lane (l16, kq) holds T1(16 kq + 4 v + j, 16 b + l16) of each
-// 64-row group in acc[b][g][j][v].  For fixed (v, j) those values are the B
-// operand of a 16 x 16 x 4 MFMA whose K index kq runs over rows
-// 16 kq + 4 v + j, so U1^T T1 needs no data movement: the A operand is
-// U1(row, 16 b1 + l16).  Each wavefront sums its rows into an R x R partial,
-// the partials are added in LDS in wavefront order, and the slab writes its
-// R x R block.  The P x R x S intermediate never leaves the workgroup.
+// workgroup per slab s.  The slab streams through LDS in stretches of KC of
+// its K rows (KC P contiguous floats), together with the matching KC rows of
+// U2, NRS stretches in flight in registers.  The loads are buffer loads with
+// the slab (and U2) as their range: a lane past the stretch reads zeros
+// without a memory request, so every load is unconditional and the waits
+// before each LDS copy are for the oldest stretch only.  T1 = X(:, :, s) U2
+// (P x R) is built in 16-row blocks (block j of 64-row group g holds rows
+// 64 (MG slot + g) + 16 j + l16 in its A operand); blocks wholly past P are
+// skipped, and the wavefront slot that holds the slab's partial group
+// rotates with s so that the shortfall spreads over the SIMDs.  T1 stays in
+// registers in the MFMA D layout: lane (l16, kq) holds
+// T1(64 (MG slot + g) + 16 j + 4 kq + v, 16 b + l16) in acc[b][g][j][v].
+// For fixed (g, j, v) those values are the B operand of a 16 x 16 x 4 MFMA
+// whose K index kq runs over four rows of T1, so U1^T T1 needs no data
+// movement: the A operand is U1(row, 16 b1 + l16).  Each wavefront sums its
+// rows into an R x R partial, the partials are added in LDS in slot order,
+// and the slab writes its R x R block.  The P x R x S intermediate never
+// leaves the workgroup.
+constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past every range used here (< 2 GB)
+
 template <int NB, int MG, int NWV, int KC, int NRS, bool NT>
-__global__ __launch_bounds__(NWV * 64) void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
+__global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(NWV >= 8 && NB == 1 ? 4 : 1)))
+void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
                                                         const float* __restrict__ U1, float* __restrict__ out,
                                                         int64_t P, int64_t K, int64_t S, int R) {
-  constexpr int NTH = NWV * 64, RP = 16 * NB;
-  constexpr int LPT = (KC * 64 * MG * NWV / 4 + NTH - 1) / NTH;  // float4 loads per thread per stretch
+  constexpr int NTH = NWV * 64, RP = 16 * NB, PMAX = 64 * MG * NWV;
+  constexpr int LPT = (KC * PMAX / 4 + NTH - 1) / NTH;  // X float4 loads per thread per stretch
+  constexpr int UPT = (KC * RP + NTH - 1) / NTH;        // U2 loads per thread per stretch
+  constexpr int XS = LPT * NTH * 4, US = UPT * NTH;     // floats of one stretch buffer
   extern __shared__ float sm[];
-  const int Pi = int(P);
-  float* xb0 = sm;                    // [2][KC * P]
-  float* ub0 = sm + 2 * KC * Pi;      // [2][KC * RP]
-  float* red = ub0 + 2 * KC * RP;     // [NWV][RP * RP]
+  const int Pi = int(P), Ki = int(K);
+  float* xb0 = sm;           // [2][XS]
+  float* ub0 = sm + 2 * XS;  // [2][US]
+  float* red = sm;           // [NWV][RP * RP], after the stream (the stretch buffers are done)
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int l16 = lane % 16, kq = lane / 16;
   const int64_t s = blockIdx.x;
-  const float* Xs = X + s * P * K;
-  const int nch = int((K + KC - 1) / KC);
+  const int slot = __builtin_amdgcn_readfirstlane(int((w + s) % NWV));  // uniform: skipped blocks branch on scalars
+  const int nch = (Ki + KC - 1) / KC;
+  const __amdgpu_buffer_rsrc_t rx =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(X + s * P * K), short(0), int(P * K * 4), 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru =
+      __builtin_amdgcn_make_buffer_rsrc((void*)U2, short(0), int(K * RP * 4), 0x00020000);
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 xr[NRS][LPT];
+  unsigned int ur[NRS][UPT];
+  auto load = [&](int q, int c) {  // stretch c into register set q (zeros past the slab)
+    const bool in = c < nch;
+    const int kc = in ? min(KC, Ki - c * KC) : 0;
+    const int n4 = kc * Pi / 4, nu = kc * RP;
+    const uint32_t sx = in ? uint32_t(c) * uint32_t(KC * Pi) * 4u : 0u;
+    const uint32_t su = in ? uint32_t(c) * uint32_t(KC * RP) * 4u : 0u;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int e = tid + i * NTH;
+      xr[q][i] = __builtin_amdgcn_raw_buffer_load_b128(rx, e < n4 ? uint32_t(e) * 16u : OOB, sx, NT ? 2 : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int e = tid + i * NTH;
+      ur[q][i] = __builtin_amdgcn_raw_buffer_load_b32(ru, e < nu ? uint32_t(e) * 4u : OOB, su, 0);
+    }
+  };
+  auto store = [&](int q, int c) {  // register set q into LDS buffer c & 1
+    float* xb = xb0 + (c & 1) * XS;
+    float* ub = ub0 + (c & 1) * US;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) *reinterpret_cast<u32x4*>(xb + 4 * (tid + i * NTH)) = xr[q][i];
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) ub[tid + i * NTH] = __builtin_bit_cast(float, ur[q][i]);
+  };
+  int nblk[MG];  // 16-row blocks of each group that hold rows < P (uniform)
+#pragma unroll
+  for (int g = 0; g < MG; ++g) {
+    const int r0 = 64 * (MG * slot + g);
+    nblk[g] = r0 >= Pi ? 0 : min(4, (Pi - r0 + 15) / 16);
+  }
   floatx4 acc[NB][MG][4];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -571,72 +651,67 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab2_m(const float* __restrict_
     for (int g = 0; g < MG; ++g)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  float4 rs[NRS][LPT];
-  auto kcount = [&](int c) { return int(min<int64_t>(KC, K - int64_t(c) * KC)); };
-  auto load = [&](float4(&r)[LPT], int c) {
-    const float* src = Xs + int64_t(c) * KC * P;
-    const int n4 = kcount(c) * Pi / 4;
+  bool full = true;  // every block of the wavefront's groups holds rows < P (uniform)
 #pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const int e = tid + i * NTH;
-      r[i] = e < n4 ? ldx<NT>(src + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  };
-  auto store = [&](const float4(&r)[LPT], int c) {
-    float* xb = xb0 + (c & 1) * KC * Pi;
-    float* ub = ub0 + (c & 1) * KC * RP;
-    const int kc = kcount(c), n4 = kc * Pi / 4;
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const int e = tid + i * NTH;
-      if (e < n4) *reinterpret_cast<float4*>(xb + 4 * e) = r[i];
-    }
-    for (int e = tid; e < kc * RP; e += NTH) ub[e] = U2[int64_t(c) * KC * RP + e];
-  };
-  const int prow = w * 64 * MG + 4 * l16;  // first of the lane's four rows in group 0
-  auto compute = [&](int c) {
-    const float* xb = xb0 + (c & 1) * KC * Pi;
-    const float* ub = ub0 + (c & 1) * KC * RP;
-    const int kc = kcount(c);
+  for (int g = 0; g < MG; ++g) full = full && nblk[g] == 4;
+  // FULL: no block to skip, straight-line MFMAs
+  auto compute = [&](int c, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const float* xb = xb0 + (c & 1) * XS;
+    const float* ub = ub0 + (c & 1) * US;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      const int k = kk + kq;
-      const bool ok = k < kc;
+      const int k = kk + kq;  // rows past the stretch hold zeros
       float bv[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = ok ? ub[k * RP + b * 16 + l16] : 0.f;
+      for (int b = 0; b < NB; ++b) bv[b] = ub[k * RP + b * 16 + l16];
+      float xv[MG][4];  // read for every block (in range of the buffer), used for the live ones
 #pragma unroll
-      for (int g = 0; g < MG; ++g) {
-        const int pr = prow + 64 * g;
-        const float4 xv = (ok && pr < Pi) ? *reinterpret_cast<const float4*>(xb + k * Pi + pr)
-                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int g = 0; g < MG; ++g)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[b][g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv[b], acc[b][g][0], 0, 0, 0);
-          acc[b][g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv[b], acc[b][g][1], 0, 0, 0);
-          acc[b][g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv[b], acc[b][g][2], 0, 0, 0);
-          acc[b][g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv[b], acc[b][g][3], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const int row = 64 * (MG * slot + g) + 16 * j + l16;
+          const float x = xb[k * Pi + row];
+          xv[g][j] = (FULL || row < Pi) ? x : 0.f;
         }
-      }
+#pragma unroll
+      for (int g = 0; g < MG; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (FULL || j < nblk[g]) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              acc[b][g][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[g][j], bv[b], acc[b][g][j], 0, 0, 0);
+          }
     }
   };
+  // The loads leave in stretch order (no rescheduling across the barriers).
+  // The two forms of the loop differ only in the block guards.
+  auto stream = [&](auto full_tag) {
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-  for (int j = 0; j < NRS; ++j)
-    if (j < nch) load(rs[j], j);
-  store(rs[0], 0);
-  __syncthreads();
-  for (int c0 = 0; c0 < nch; c0 += NRS) {
+    for (int q = 0; q < NRS; ++q) {
+      load(q, q);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    store(0, 0);
+    __syncthreads();
+    for (int c0 = 0; c0 < nch; c0 += NRS) {
 #pragma unroll
-    for (int j = 0; j < NRS; ++j) {
-      const int c = c0 + j;
-      if (c < nch) {  // uniform over the workgroup
-        if (c + NRS < nch) load(rs[j], c + NRS);
-        compute(c);
-        if (c + 1 < nch) store(rs[(j + 1) % NRS], c + 1);
+      for (int q = 0; q < NRS; ++q) {
+        const int c = c0 + q;
+        load(q, c + NRS);  // register set q held stretch c, already in LDS
+        __builtin_amdgcn_sched_barrier(0);
+        if (c < nch) compute(c, full_tag);
+        store((q + 1) % NRS, c + 1);
         __syncthreads();
       }
     }
-  }
+  };
+  if (full)
+    stream(std::true_type{});
+  else
+    stream(std::false_type{});
   // U1^T T1 over this wavefront's rows (rows past P hold zeros in T1)
   floatx4 acc2[NB][NB];
 #pragma unroll
@@ -646,20 +721,22 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab2_m(const float* __restrict_
 #pragma unroll
   for (int g = 0; g < MG; ++g)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < 4; ++j)
+      if (j < nblk[g]) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = w * 64 * MG + 64 * g + 16 * kq + 4 * v + j;
+        for (int v = 0; v < 4; ++v) {
+          const int row = 64 * (MG * slot + g) + 16 * j + 4 * kq + v;
 #pragma unroll
-        for (int b1 = 0; b1 < NB; ++b1) {
-          const float a = row < Pi ? U1[int64_t(row) * RP + b1 * 16 + l16] : 0.f;
+          for (int b1 = 0; b1 < NB; ++b1) {
+            const float a = row < Pi ? U1[int64_t(row) * RP + b1 * 16 + l16] : 0.f;
 #pragma unroll
-          for (int b2 = 0; b2 < NB; ++b2)
-            acc2[b1][b2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, acc[b2][g][j][v], acc2[b1][b2], 0, 0, 0);
+            for (int b2 = 0; b2 < NB; ++b2)
+              acc2[b1][b2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, acc[b2][g][j][v], acc2[b1][b2], 0, 0, 0);
+          }
         }
       }
   // lane (l16, kq) holds partial(16 b1 + 4 kq + vv, 16 b2 + l16)
-  float* rw = red + w * RP * RP;
+  float* rw = red + slot * RP * RP;
 #pragma unroll
   for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
@@ -675,6 +752,16 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab2_m(const float* __restrict_
     for (int ww = 0; ww < NWV; ++ww) t += red[ww * RP * RP + r1 + RP * r2];
     o[e] = t;
   }
+}
+
+// LDS bytes of ttm_slab2_m: two stretch buffers of X and U2, or the
+// wavefront partials, whichever is larger.
+template <int NB, int MG, int NWV, int KC>
+constexpr size_t slab2_lds() {
+  constexpr int NTH = NWV * 64, RP = 16 * NB, PMAX = 64 * MG * NWV;
+  constexpr int LPT = (KC * PMAX / 4 + NTH - 1) / NTH, UPT = (KC * RP + NTH - 1) / NTH;
+  constexpr int st = 2 * LPT * NTH * 4 + 2 * UPT * NTH, rd = NWV * RP * RP;
+  return size_t(st > rd ? st : rd) * sizeof(float);
 }
 
 // ---------------- P == 1: out[r + R*s] = sum_i U[i, r] X[i + K*s]
@@ -1149,15 +1236,33 @@ __global__ void sum_splits(const T* __restrict__ part, int splits, int64_t count
   dst[e] = acc;
 }
 
-// Y_(n)[i + In*(p + Pn*s)] = T[p + Pn*i + Pn*In*s]
+// Y_(n)[i + In*(p + Pn*s)] = T[p + Pn*i + Pn*In*s]: for each s the In x Pn
+// block (p contiguous) is transposed, 32 x 32 tiles through LDS so that both
+// the reads (along p) and the writes (along i) are coalesced.  One
+// workgroup of 256 threads per tile, the tiles of all s in one flat grid.
+constexpr int UT = 32;
 template <class T>
-__global__ void unfold_copy(const T* __restrict__ src, int64_t Pn, int64_t In, int64_t Sn,
-                            T* __restrict__ dst) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= Pn * In * Sn) return;
-  const int64_t i = e % In, c = e / In;
-  const int64_t p = c % Pn, s = c / Pn;
-  dst[e] = src[p + Pn * i + Pn * In * s];
+__global__ __launch_bounds__(256) void unfold_copy(const T* __restrict__ src, int64_t Pn, int64_t In, int64_t Sn,
+                                                   T* __restrict__ dst) {
+  __shared__ T tile[UT][UT + 1];
+  const int64_t tp = (Pn + UT - 1) / UT, ti = (In + UT - 1) / UT;
+  const int64_t b = blockIdx.x;
+  const int64_t s = b / (tp * ti), r = b % (tp * ti);
+  const int64_t i0 = (r / tp) * UT, p0 = (r % tp) * UT;
+  const int tx = threadIdx.x % UT, ty = threadIdx.x / UT;  // 32 x 8
+  const T* S = src + Pn * In * s;
+  T* Dd = dst + Pn * In * s;
+#pragma unroll
+  for (int k = 0; k < UT; k += 8) {
+    const int64_t i = i0 + ty + k, p = p0 + tx;
+    if (i < In && p < Pn) tile[ty + k][tx] = S[p + Pn * i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < UT; k += 8) {
+    const int64_t p = p0 + ty + k, i = i0 + tx;
+    if (i < In && p < Pn) Dd[i + In * p] = tile[tx][ty + k];
+  }
 }
 
 // ------------------------------------------------------------ planning
@@ -1476,8 +1581,9 @@ bool fused_pair(const Plan& pl, int prec, bool streams_tensor, bool x_aligned) {
   if (prec != CPQR_PREC_F32 || !streams_tensor || !x_aligned || pl.nsteps < 2) return false;
   const Step& a = pl.st[0];
   const Step& b = pl.st[1];
+  // The slab and U_2 are the ranges of 32-bit buffer loads.
   return a.k == 1 && b.k == 0 && a.kind == K_MFMA_M && a.splits == 1 && a.P % 4 == 0 && a.P <= 1024 &&
-         a.S >= 256;
+         a.S >= 256 && a.P * a.K * 4 < (int64_t(1) << 31) && a.K * 32 * 4 < (int64_t(1) << 31);
 }
 
 // Slab stretch depth (rows of the slab staged per step) and stretches in
@@ -1496,7 +1602,7 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
   if (a.P <= 256) {
     constexpr int MG = 1, NWV = 4, KC = CPQR_SLAB2_SMALL_KC, NRS = CPQR_SLAB2_SMALL_NRS;
     const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;  // stretches start on line boundaries
-    const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
+    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>() : slab2_lds<2, MG, NWV, KC>();
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
                 a.S, R);
@@ -1510,9 +1616,9 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
       launch_ev(ke, ttm_slab2_m<2, MG, NWV, KC, NRS, false>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P,
                 a.K, a.S, R);
   } else {
-    constexpr int MG = 2, NWV = 8, KC = 8, NRS = 3;
+    constexpr int MG = 2, NWV = 8, KC = 8, NRS = 2;
     const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;
-    const size_t lds = size_t(2 * KC * a.P + 2 * KC * RP + NWV * RP * RP) * sizeof(float);
+    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>() : slab2_lds<2, MG, NWV, KC>();
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
                 a.S, R);
@@ -1705,8 +1811,8 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     int64_t Pn = 1, Sn = 1;
     for (int m = 0; m < n; ++m) Pn *= D[m];
     for (int m = n + 1; m < N; ++m) Sn *= D[m];
-    const int64_t cnt = Pn * D[n] * Sn;
-    const dim3 grd(unsigned(ceil_div(cnt, 256)));
+    const int64_t tiles = ceil_div(Pn, UT) * ceil_div(D[n], UT) * Sn;
+    const dim3 grd(static_cast<unsigned>(tiles));
     if (cur_dtype == CPQR_F64)
       hipLaunchKernelGGL(unfold_copy<double>, grd, dim3(256), 0, st, static_cast<const double*>(cur),
                          Pn, D[n], Sn, static_cast<double*>(Y));
