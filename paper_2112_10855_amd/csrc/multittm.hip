@@ -67,6 +67,30 @@ constexpr int WAVE = 64;
 constexpr int TARGET_WAVES = 2048;  // wavefronts wanted when K is split (8 per CU)
 constexpr int MIN_WAVES = 1024;     // below this many wavefronts, split K
 
+// n floats (a multiple of 4, 16-byte aligned) from global memory into LDS
+// by the NTH threads of a workgroup; every load of a batch is issued before
+// the first LDS store, so the batch costs one round trip, not one per load.
+template <int NTH>
+__device__ __forceinline__ void stage_lds(const float* __restrict__ src, float* dst, int n, int tid) {
+  constexpr int B = 8;
+  const int n4 = n / 4;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+  for (int e0 = 0; e0 < n4; e0 += B * NTH) {
+    float4 t[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int e = e0 + tid + i * NTH;
+      t[i] = e < n4 ? s4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int e = e0 + tid + i * NTH;
+      if (e < n4) d4[e] = t[i];
+    }
+  }
+}
+
 // Steps of a row-tile kernel's load ring: three where the accumulators leave
 // room (two 16-column blocks of one row group or fewer), else two; 0 (a
 // plain pair of load buffers) for steps of more than four 16-byte loads per
@@ -261,7 +285,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
   if constexpr (ONE) {  // the workgroup's K range fits in LDS: stage once, no chunk loop
     const int cn = int(kb1 > kb0 ? kb1 - kb0 : 0);
     const float* Uc = U + kb0 * RP;
-    for (int e = tid; e < cn * RP; e += NWV * 64) us[e] = Uc[e];
+    stage_lds<NWV * 64>(Uc, us, cn * RP, tid);
     __syncthreads();
     if (!active) return;
     chunk(kb0, cn);
@@ -271,7 +295,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m(const float* __restrict__
       const int cn = int(min<int64_t>(kb1 - c0, KC));
       __syncthreads();
       const float* Uc = U + c0 * RP;
-      for (int e = tid; e < cn * RP; e += NWV * 64) us[e] = Uc[e];
+      stage_lds<NWV * 64>(Uc, us, cn * RP, tid);
       __syncthreads();
       if (active) chunk(c0, cn);
     }
@@ -428,7 +452,7 @@ __global__ __launch_bounds__(NWV * 64) void ttm_mfma_m_f64(const TX* __restrict_
     const int cn = int(min<int64_t>(kb1 - c0, KC));
     __syncthreads();
     const double* Uc = U + c0 * RP;
-    for (int e = tid; e < cn * RP; e += NWV * 64) usd[e] = Uc[e];
+    stage_lds<NWV * 64>(reinterpret_cast<const float*>(Uc), reinterpret_cast<float*>(usd), 2 * cn * RP, tid);
     __syncthreads();
     if (active) chunk(c0, cn);
   }
@@ -587,6 +611,27 @@ __global__ __launch_bounds__(NWV * 64) void ttm_slab_m(const float* __restrict__
 // leaves the workgroup.
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past every range used here (< 2 GB)
 
+// LDS strides of the fused slab kernel.  The four K rows that a wavefront
+// reads at once (lane groups kq = 0..3) start 16 banks apart, so its 64
+// lanes hit 64 distinct banks: X rows at a stride P' >= P with
+// P' = 16 (mod 64), U2 rows at 48 floats for two 16-column blocks (16 for
+// one).
+__host__ __device__ constexpr int slab2_xstride(int P) { return P + ((16 - P) % 64 + 64) % 64; }
+__host__ __device__ constexpr int slab2_ustride(int NB) { return NB == 1 ? 16 : 48; }
+// Floats of one stretch buffer.  Every load of a stretch is stored (no
+// branch around a store, so that no load sinks behind later ones): the
+// loads past row KC hold zeros and land in rows KC and up.  The buffer also
+// covers the reads of the rows past P of the last 64-row group (masked).
+__host__ __device__ constexpr int slab2_xbuf(int P, int MG, int NWV, int KC) {
+  const int ps = slab2_xstride(P), nf = 4 * ((KC * MG + 3) / 4) * NWV * 64;  // floats loaded per stretch
+  const int a = (nf - 4) / P * ps + P, b = (KC - 1) * ps + 64 * MG * NWV;
+  return ((a > b ? a : b) + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int slab2_ubuf(int NB, int NWV, int KC) {
+  const int nu = (KC * 16 * NB + NWV * 64 - 1) / (NWV * 64) * (NWV * 64);  // U2 values loaded per stretch
+  return (nu + 16 * NB - 1) / (16 * NB) * slab2_ustride(NB);
+}
+
 template <int NB, int MG, int NWV, int KC, int NRS, bool NT>
 __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(NWV >= 8 && NB == 1 ? 4 : 1)))
 void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
@@ -595,11 +640,12 @@ void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
   constexpr int NTH = NWV * 64, RP = 16 * NB, PMAX = 64 * MG * NWV;
   constexpr int LPT = (KC * PMAX / 4 + NTH - 1) / NTH;  // X float4 loads per thread per stretch
   constexpr int UPT = (KC * RP + NTH - 1) / NTH;        // U2 loads per thread per stretch
-  constexpr int XS = LPT * NTH * 4, US = UPT * NTH;     // floats of one stretch buffer
+  constexpr int RPS = slab2_ustride(NB), US = slab2_ubuf(NB, NWV, KC);
   extern __shared__ float sm[];
   const int Pi = int(P), Ki = int(K);
-  float* xb0 = sm;           // [2][XS]
-  float* ub0 = sm + 2 * XS;  // [2][US]
+  const int PS = slab2_xstride(Pi), XS = slab2_xbuf(Pi, MG, NWV, KC);
+  float* xb0 = sm;           // [2][XS], stretch row k at k PS
+  float* ub0 = sm + 2 * XS;  // [2][US], U2 row k at k RPS
   float* red = sm;           // [NWV][RP * RP], after the stream (the stretch buffers are done)
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int l16 = lane % 16, kq = lane / 16;
@@ -630,13 +676,26 @@ void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
       ur[q][i] = __builtin_amdgcn_raw_buffer_load_b32(ru, e < nu ? uint32_t(e) * 4u : OOB, su, 0);
     }
   };
+  // LDS place of each of the thread's loads (the same in every stretch);
+  // rows kc and up of a stretch receive zeros
+  int xo[LPT], uo[UPT];
+#pragma unroll
+  for (int i = 0; i < LPT; ++i) {
+    const int f = 4 * (tid + i * NTH), row = f / Pi;
+    xo[i] = row * PS + (f - row * Pi);
+  }
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    const int e = tid + i * NTH;
+    uo[i] = (e / RP) * RPS + e % RP;
+  }
   auto store = [&](int q, int c) {  // register set q into LDS buffer c & 1
     float* xb = xb0 + (c & 1) * XS;
     float* ub = ub0 + (c & 1) * US;
 #pragma unroll
-    for (int i = 0; i < LPT; ++i) *reinterpret_cast<u32x4*>(xb + 4 * (tid + i * NTH)) = xr[q][i];
+    for (int i = 0; i < LPT; ++i) *reinterpret_cast<u32x4*>(xb + xo[i]) = xr[q][i];
 #pragma unroll
-    for (int i = 0; i < UPT; ++i) ub[tid + i * NTH] = __builtin_bit_cast(float, ur[q][i]);
+    for (int i = 0; i < UPT; ++i) ub[uo[i]] = __builtin_bit_cast(float, ur[q][i]);
   };
   int nblk[MG];  // 16-row blocks of each group that hold rows < P (uniform)
 #pragma unroll
@@ -651,9 +710,9 @@ void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
     for (int g = 0; g < MG; ++g)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[b][g][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  bool full = true;  // every block of the wavefront's groups holds rows < P (uniform)
+  bool full = true;  // every row of the wavefront's groups is < P (uniform): no masks, no skips
 #pragma unroll
-  for (int g = 0; g < MG; ++g) full = full && nblk[g] == 4;
+  for (int g = 0; g < MG; ++g) full = full && 64 * (MG * slot + g) + 64 <= Pi;
   // FULL: no block to skip, straight-line MFMAs
   auto compute = [&](int c, auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
@@ -664,14 +723,14 @@ void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
       const int k = kk + kq;  // rows past the stretch hold zeros
       float bv[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = ub[k * RP + b * 16 + l16];
+      for (int b = 0; b < NB; ++b) bv[b] = ub[k * RPS + b * 16 + l16];
       float xv[MG][4];  // read for every block (in range of the buffer), used for the live ones
 #pragma unroll
       for (int g = 0; g < MG; ++g)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = 64 * (MG * slot + g) + 16 * j + l16;
-          const float x = xb[k * Pi + row];
+          const float x = xb[k * PS + row];
           xv[g][j] = (FULL || row < Pi) ? x : 0.f;
         }
 #pragma unroll
@@ -757,10 +816,8 @@ void ttm_slab2_m(const float* __restrict__ X, const float* __restrict__ U2,
 // LDS bytes of ttm_slab2_m: two stretch buffers of X and U2, or the
 // wavefront partials, whichever is larger.
 template <int NB, int MG, int NWV, int KC>
-constexpr size_t slab2_lds() {
-  constexpr int NTH = NWV * 64, RP = 16 * NB, PMAX = 64 * MG * NWV;
-  constexpr int LPT = (KC * PMAX / 4 + NTH - 1) / NTH, UPT = (KC * RP + NTH - 1) / NTH;
-  constexpr int st = 2 * LPT * NTH * 4 + 2 * UPT * NTH, rd = NWV * RP * RP;
+size_t slab2_lds(int P) {
+  const int st = 2 * slab2_xbuf(P, MG, NWV, KC) + 2 * slab2_ubuf(NB, NWV, KC), rd = NWV * 16 * NB * 16 * NB;
   return size_t(st > rd ? st : rd) * sizeof(float);
 }
 
@@ -1602,7 +1659,7 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
   if (a.P <= 256) {
     constexpr int MG = 1, NWV = 4, KC = CPQR_SLAB2_SMALL_KC, NRS = CPQR_SLAB2_SMALL_NRS;
     const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;  // stretches start on line boundaries
-    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>() : slab2_lds<2, MG, NWV, KC>();
+    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>(int(a.P)) : slab2_lds<2, MG, NWV, KC>(int(a.P));
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
                 a.S, R);
@@ -1618,7 +1675,7 @@ int launch_slab2(const float* X, const float* U2, const float* U1, float* dst, c
   } else {
     constexpr int MG = 2, NWV = 8, KC = 8, NRS = 2;
     const bool nt = (KC * a.P) % 32 == 0 && (a.P * a.K) % 32 == 0;
-    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>() : slab2_lds<2, MG, NWV, KC>();
+    const size_t lds = NB == 1 ? slab2_lds<1, MG, NWV, KC>(int(a.P)) : slab2_lds<2, MG, NWV, KC>(int(a.P));
     if (NB == 1 && nt)
       launch_ev(ke, ttm_slab2_m<1, MG, NWV, KC, NRS, true>, grd, dim3(NWV * 64), lds, st, X, U2, U1, dst, a.P, a.K,
                 a.S, R);
