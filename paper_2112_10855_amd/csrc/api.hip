@@ -164,6 +164,11 @@ struct AlsWs {
   void* krp_sub;  // scratch of the Khatri-Rao QR, which runs beside the Multi-TTM
   void* Wt;       // X contracted over one half of the modes (dimension-tree reuse)
   double* err_part;  // partial sums of the efficient error (side stream)
+  // FP32 contraction operands of each Q_k written by its normalizing factor
+  // QR (rows and four-row layouts; null where not kept), padding urp (0: none)
+  float* ur[CPQR_MAX_MODES];
+  float* uq[CPQR_MAX_MODES];
+  int urp;
 };
 
 // Split point of the dimension-tree reuse (0 = off).
@@ -366,22 +371,22 @@ size_t ne_carve(Carver& cv, const cpqr_problem* p, NeWs* ws) {
 // Y = X contracted with U_k^T over every mode but n, unfolded along n, with the
 // dimension-tree reuse of the mode split h (shared by both algorithms).
 int ttm_for_mode(const cpqr_problem* p, int h, int n, const double* const* U, void* Y, void* Wt, void* sub,
-                 hipStream_t s) {
+                 hipStream_t s, const UCache* uc) {
   const int N = p->N, R = p->R;
   const int ydt = p->prec == CPQR_PREC_F64 ? CPQR_F64 : CPQR_F32;
   const int lo = (h > 0 && n >= h) ? h : 0, hi = (h > 0 && n < h) ? h : N;
   if (h == 0 || hi - lo == 1)
-    return multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, U, p->prec, Y, sub, s);
+    return multittm_enqueue(N, p->I, p->xdtype, p->X, n, R, U, p->prec, Y, sub, s, uc);
   // X contracted over the modes outside [lo, hi) once (when the first mode of
   // the half is updated; those factors do not change while the half is
   // updated), then the remaining modes of the half for each n
   if (n == lo)
     CPQR_TRY(multittm_general_enqueue(N, p->I, p->xdtype, p->X, ~range_mask(lo, hi) & range_mask(0, N), -1, R, U,
-                                      p->prec, Wt, sub, s, true));
+                                      p->prec, Wt, sub, s, true, uc));
   int64_t D[CPQR_MAX_MODES];
   half_dims(p, lo, hi, D);
   return multittm_general_enqueue(N, D, ydt, Wt, range_mask(lo, hi) & ~(1u << n), n, R, U, p->prec, Y, sub, s,
-                                  false);
+                                  false, uc);
 }
 
 size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
@@ -404,6 +409,15 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
   w.krp_sub = cv.take<char>(std::max(tsqr_work(K, R), krp_chain_work(R)));
   w.Wt = cv.take<double>(size_t(dt_elems(p)));  // sized for FP64
   w.err_part = cv.take<double>(error_efficient_work(p->I[N - 1]) / sizeof(double));
+  // the FP32 operands need the factor QR's padded rank to equal the
+  // contraction kernels' column padding (R > 8)
+  const int rp = (R + 15) / 16 * 16;
+  w.urp = p->prec != CPQR_PREC_F64 && round_rank(R) == rp ? rp : 0;
+  for (int k = 0; k < N; ++k) {  // (take() returns null while only sizing: test the conditions, not pointers)
+    const bool keep = w.urp && norm_qr_fits(p->I[k], R);
+    w.ur[k] = keep ? cv.take<float>(size_t(p->I[k] + 4) * rp) : nullptr;
+    w.uq[k] = keep && p->I[k] % 4 == 0 ? cv.take<float>(size_t(p->I[k] + 4) * rp) : nullptr;
+  }
   if (ws) *ws = w;
   return cv.bytes();
 }
@@ -1058,6 +1072,7 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   AlsWs w;
   Carver c2(work);
   als_carve(c2, p, &w);
+  if (c2.bytes() > work_bytes) return fail(CPQR_ERR_WORKSPACE, "als_sweep: workspace layout exceeds its size");
   hipStream_t s = as_stream(stream);
   const int N = p->N, R = p->R;
   const int64_t K = ipow(R, N - 1);
@@ -1067,6 +1082,8 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   const int h = dt_split(p);
   const bool chain = use_chain(p);
   bool r_marked = false;  // side.ready marks the last factor QR's R
+  UCache uc;  // FP32 operands of the Q_k refreshed by this call's factor QRs
+  uc.RP = w.urp;
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
       // Khatri-Rao QR (reads R_k) on the side stream, Multi-TTM (reads Q_k)
@@ -1080,20 +1097,22 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       } else
         CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
       CPQR_HIP(hipEventRecord(side.done, side.s));
-      CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s));
+      CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s, &uc));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
       // normalization and factor QR in one launch where one workgroup takes A_n
       const bool fuse = norm_qr_fits(p->I[n], R);
       CPQR_TRY(apply_solve_enqueue(p->I[n], K, R, ydt, w.Y, w.Q0, w.R0, p->use_svd, p->rtol, w.W, p->A[n],
                                    p->lambda, p->status, w.sub, s, !fuse));
+      bool done = false;
       if (fuse) {
-        bool done = false;
         CPQR_TRY(normalize_factor_qr_enqueue(p->I[n], R, p->A[n], p->lambda, p->status, p->Q[n], p->Rf[n], w.sub,
-                                             s, side.ready, &done));
+                                             s, side.ready, &done, w.ur[n], w.uq[n], w.urp));
       } else {
         CPQR_TRY(factor_qr_enqueue(p->I[n], R, p->A[n], p->I[n], p->Q[n], p->I[n], p->Rf[n], R, w.sub, s,
                                    side.ready));
       }
+      uc.rows[n] = done ? w.ur[n] : nullptr;
+      uc.quads[n] = done ? w.uq[n] : nullptr;
       r_marked = true;
     }
     double* out = relerr ? relerr + sw : w.relerr_tmp;
@@ -1170,7 +1189,7 @@ int cpqr_als_ne_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* 
   const int h = dt_split(p);
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
-      CPQR_TRY(ttm_for_mode(p, h, n, Ap, w.Y, w.Wt, w.sub, s));
+      CPQR_TRY(ttm_for_mode(p, h, n, Ap, w.Y, w.Wt, w.sub, s, nullptr));
       CPQR_TRY(ne_update_enqueue(p->I[n], N, n, R, ydt, w.Y, w.G, p->use_svd, p->rtol, w.S, w.F, w.M, p->A[n],
                                  p->lambda, p->status, w.sub, s));
     }

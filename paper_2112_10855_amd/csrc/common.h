@@ -97,10 +97,23 @@ bool norm_qr_fits(int64_t I, int R);
 // Column normalization (lambda, A scaled in place, zero-column status) and
 // factor QR of A (leading dimensions I, I and R) in one launch; *fused is
 // false (and nothing is enqueued) when norm_qr_fits(I, R) does not hold.
+// urows / uquads (optional, round_rank(R) must equal the column padding RP):
+// FP32 copies of Q in the layouts of the FP32 contraction kernels (see UCache).
 int normalize_factor_qr_enqueue(int64_t I, int R, double* A, double* lambda, int* status, double* Q, double* Rk,
-                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused);
+                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused,
+                                float* urows = nullptr, float* uquads = nullptr, int RP = 0);
 
 // multittm.hip
+// FP32 contraction operands already prepared from the factor Q's: rows[k] is
+// I_k x RP row-major, U[i RP + r] = Q_k(i, r); quads[k] interleaves four rows,
+// U4[((i/4) RP + r) 4 + i%4] = Q_k(i, r); zero for r >= R.  A null entry is
+// prepared from Q_k by the Multi-TTM itself.  Used by FP32 and bfloat16
+// Multi-TTMs with padding RP only.
+struct UCache {
+  int RP = 0;
+  const float* rows[CPQR_MAX_MODES] = {};
+  const float* quads[CPQR_MAX_MODES] = {};
+};
 size_t multittm_work(int N, const int64_t* I, int n, int R, int prec);
 // Contract the modes in cmask (bit k = mode k) of a tensor with sizes I (modes
 // already contracted have size R and are left alone); write the result in its
@@ -110,9 +123,10 @@ size_t multittm_work(int N, const int64_t* I, int n, int R, int prec);
 size_t multittm_general_work(int N, const int64_t* I, unsigned cmask, int R, int prec);
 int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X, unsigned cmask, int n_unfold,
                              int R, const double* const* Q, int prec, void* Y, void* work, hipStream_t st,
-                             bool streams_tensor);
+                             bool streams_tensor, const UCache* uc = nullptr);
 int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
-                     const double* const* Q, int prec, void* Y, void* work, hipStream_t s);
+                     const double* const* Q, int prec, void* Y, void* work, hipStream_t s,
+                     const UCache* uc = nullptr);
 
 // small.hip
 size_t apply_q0_work(int64_t In, int64_t K, int R);

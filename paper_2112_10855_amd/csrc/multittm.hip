@@ -1766,7 +1766,7 @@ size_t multittm_general_work(int N, const int64_t* I, unsigned cmask, int R, int
 
 int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X, unsigned cmask, int n_unfold,
                              int R, const double* const* Q, int prec, void* Y, void* work, hipStream_t st,
-                             bool streams_tensor) {
+                             bool streams_tensor, const UCache* uc) {
   PhaseTimer whole(streams_tensor ? PH_MULTITTM : -1, st);
   const bool x_aligned = reinterpret_cast<uintptr_t>(X) % 16 == 0;
   const Plan pl = make_plan(N, I, cmask, R, prec, x_aligned);
@@ -1777,15 +1777,23 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
   const bool f64 = prec == CPQR_PREC_F64;
   const bool fused = fused_pair(pl, prec, streams_tensor, x_aligned);
 
-  // operand preparation
+  // operand preparation (skipped for operands the caller already holds)
+  const void* Uk[CPQR_MAX_MODES];
+  for (int k = 0; k < N; ++k) Uk[k] = b.U[k];
   for (int t = 0; t < pl.nsteps; ++t) {
     const Step& s = pl.st[t];
     const int64_t cnt = s.K * RP;
     const dim3 grd(unsigned(ceil_div(cnt, 256)));
+    const bool quads = !f64 && s.kind == K_MFMA_K && prec == CPQR_PREC_F32 && !(fused && t == 1);
+    const float* pre = (uc && !f64 && uc->RP == RP) ? (quads ? uc->quads[s.k] : uc->rows[s.k]) : nullptr;
+    if (pre) {
+      Uk[s.k] = pre;
+      continue;
+    }
     if (f64)
       hipLaunchKernelGGL(prep_u_rows<double>, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<double*>(b.U[s.k]));
-    else if (s.kind == K_MFMA_K && prec == CPQR_PREC_F32 && !(fused && t == 1))
+    else if (quads)
       hipLaunchKernelGGL(prep_u_quads, grd, dim3(256), 0, st, Q[s.k], s.K, s.K, R, RP,
                          static_cast<float*>(b.U[s.k]));
     else
@@ -1803,8 +1811,8 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     void* dst = (pl.nsteps == 2 && direct) ? Y : b.buf[1];
     PhaseTimer ph_first(PH_TTM_FIRST, st);
     const KernelEvents ke = kernel_events(PH_TTM_STREAM_M, st);
-    CPQR_TRY(launch_slab2(static_cast<const float*>(X), static_cast<const float*>(b.U[pl.st[0].k]),
-                          static_cast<const float*>(b.U[pl.st[1].k]), static_cast<float*>(dst), pl.st[0], R, RP,
+    CPQR_TRY(launch_slab2(static_cast<const float*>(X), static_cast<const float*>(Uk[pl.st[0].k]),
+                          static_cast<const float*>(Uk[pl.st[1].k]), static_cast<float*>(dst), pl.st[0], R, RP,
                           st, ke));
     kernel_events_done(ke);
     cur = dst;
@@ -1824,21 +1832,21 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
         // (the unfolded Y of the structured Q_0 application) is widened as it loads
         const KernelEvents ke = kernel_events(first ? PH_TTM_STREAM_M : -1, st);
         if (cur_dtype == CPQR_F64)
-          CPQR_TRY(launch_mfma_f64(first, static_cast<const double*>(cur), static_cast<const double*>(b.U[s.k]),
+          CPQR_TRY(launch_mfma_f64(first, static_cast<const double*>(cur), static_cast<const double*>(Uk[s.k]),
                                    static_cast<double*>(kout), s, R, RP, st, ke));
         else
-          CPQR_TRY(launch_mfma_f64(first, static_cast<const float*>(cur), static_cast<const double*>(b.U[s.k]),
+          CPQR_TRY(launch_mfma_f64(first, static_cast<const float*>(cur), static_cast<const double*>(Uk[s.k]),
                                    static_cast<double*>(kout), s, R, RP, st, ke));
         kernel_events_done(ke);
       } else if (f64) {
-        CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(b.U[s.k]),
+        CPQR_TRY((launch_valu_r<double, 0>(cur, cur_dtype, static_cast<const double*>(Uk[s.k]),
                                            static_cast<double*>(kout), s, R, RP, st)));
       } else if (s.kind == K_VALU) {
-        CPQR_TRY(launch_valu_f32(prec, cur, cur_dtype, static_cast<const float*>(b.U[s.k]),
+        CPQR_TRY(launch_valu_f32(prec, cur, cur_dtype, static_cast<const float*>(Uk[s.k]),
                                  static_cast<float*>(kout), s, R, RP, st));
       } else {
         const KernelEvents ke = kernel_events(first && s.kind == K_MFMA_M ? PH_TTM_STREAM_M : -1, st);
-        CPQR_TRY(launch_mfma(prec, first, static_cast<const float*>(cur), static_cast<const float*>(b.U[s.k]),
+        CPQR_TRY(launch_mfma(prec, first, static_cast<const float*>(cur), static_cast<const float*>(Uk[s.k]),
                              static_cast<float*>(kout), s, R, RP, st, ke));
         kernel_events_done(ke);
       }
@@ -1886,8 +1894,8 @@ size_t multittm_work(int N, const int64_t* I, int n, int R, int prec) {
 }
 
 int multittm_enqueue(int N, const int64_t* I, int xdtype, const void* X, int n, int R,
-                     const double* const* Q, int prec, void* Y, void* work, hipStream_t st) {
-  return multittm_general_enqueue(N, I, xdtype, X, all_but(N, n), n, R, Q, prec, Y, work, st, true);
+                     const double* const* Q, int prec, void* Y, void* work, hipStream_t st, const UCache* uc) {
+  return multittm_general_enqueue(N, I, xdtype, X, all_but(N, n), n, R, Q, prec, Y, work, st, true, uc);
 }
 
 }  // namespace cpqr

@@ -324,10 +324,12 @@ __device__ __forceinline__ void node_v1(const double (&a)[P][CW], int R, int w, 
 // Q rows of a node: [C; 0] - V M with M = T V1^T C (C in sh.C, T in sh.T,
 // V1 in sh.V1, all visible).  The rows go to the output (leaf: Qout at
 // `start`) or, as C blocks, to children c0 ... of the stacked level S.
+// A leaf may also write FP32 copies of its Q rows: urows[i RMAX + c] and
+// uquads[((i/4) RMAX + c) 4 + i%4] for global row i (zero for c >= R).
 template <bool SCALED, int RMAX, int P>
 __device__ __forceinline__ void node_q(const double (&a)[P][CW], int R, int m, int w, int lane,
                                        Shared<RMAX, P>& sh, bool leaf, int64_t start, double* Qout, int64_t ldq,
-                                       double* S, int64_t c0) {
+                                       double* S, int64_t c0, float* urows = nullptr, float* uquads = nullptr) {
   constexpr int NT = RMAX / CW * W;
   const int tid = w * W + lane;
   for (int e = tid; e < RMAX * RMAX; e += NT) {  // B = V1^T C
@@ -396,6 +398,21 @@ __device__ __forceinline__ void node_q(const double (&a)[P][CW], int R, int m, i
           for (int j = 0; j < CW; ++j) {
             const int c = w * CW + j;
             if (c < R) Qout[start + r + c * ldq] = q[u][j];
+          }
+          const int64_t i = start + r;
+          if (urows) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+              const int c = w * CW + j;
+              urows[i * RMAX + c] = c < R ? float(q[u][j]) : 0.f;
+            }
+          }
+          if (uquads) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+              const int c = w * CW + j;
+              uquads[((i >> 2) * RMAX + c) * 4 + (i & 3)] = c < R ? float(q[u][j]) : 0.f;
+            }
           }
         } else {
           const int child = r / R, i = r % R;
@@ -473,7 +490,8 @@ template <int RMAX, int P, int SRC, bool NORM = false>
 __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, const double* A, int64_t lda,
                                                          KrpSrc krp, double* Qout, int64_t ldq, double* Rout,
                                                          int64_t ldr, double* work, double* lambda = nullptr,
-                                                         int* status = nullptr) {
+                                                         int* status = nullptr, float* urows = nullptr,
+                                                         float* uquads = nullptr) {
   __shared__ Shared<RMAX, P> sh;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W;
   const int top = level_count(rows, R, P) - 1;
@@ -533,7 +551,7 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, co
     sh.C[i][c] = (i < R && i == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  node_q<true, RMAX>(a, R, m, w, lane, sh, top == 0, start, Qout, ldq, work + L.s, 0);
+  node_q<true, RMAX>(a, R, m, w, lane, sh, top == 0, start, Qout, ldq, work + L.s, 0, urows, uquads);
 }
 
 // Down-sweep below the root, one launch per level: each node applies its
@@ -644,15 +662,18 @@ bool norm_qr_fits(int64_t I, int R) {
 }
 
 int normalize_factor_qr_enqueue(int64_t I, int R, double* A, double* lambda, int* status, double* Q, double* Rk,
-                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused) {
+                                void* work, hipStream_t s, hipEvent_t r_ready, bool* fused, float* urows,
+                                float* uquads, int RP) {
   *fused = false;
   if (!norm_qr_fits(I, R)) return CPQR_OK;
+  if ((urows || uquads) && RP != round_rank(R)) return fail(CPQR_ERR_ARG, "factor QR: FP32 copies need RP = RMAX");
+  if (uquads && I % 4 != 0) return fail(CPQR_ERR_ARG, "factor QR: the four-row layout needs I % 4 == 0");
   PhaseTimer pt(PH_FACTOR_QR, s);
   KrpSrc none{};
   const bool small = bn_slots(I) == 4;
 #define NQR(RM, PP)                                                                                               \
   hipLaunchKernelGGL((bn::bn_root<RM, PP, SRC_MATRIX, true>), dim3(1), dim3(RM / bn::CW * bn::W), 0, s, I, R, A, I, \
-                     none, Q, I, Rk, int64_t(R), static_cast<double*>(work), lambda, status)
+                     none, Q, I, Rk, int64_t(R), static_cast<double*>(work), lambda, status, urows, uquads)
   switch (round_rank(R)) {
     case 8: if (small) NQR(8, 4); else NQR(8, 16); break;
     case 16: if (small) NQR(16, 4); else NQR(16, 16); break;

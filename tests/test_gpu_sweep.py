@@ -197,3 +197,30 @@ def test_structured_krp_qr_in_sweeps(shape, R, chain, use_svd):
     lo, Ao, ho = OQ.cp_als_qr(X, init, maxiters=8, solver="svd" if use_svd else "qr")
     np.testing.assert_allclose(hist, ho, rtol=0, atol=1e-10)
     assert model_diff(lam, Ag, lo, Ao) < 1e-9
+
+
+@pytest.mark.gpu
+def test_several_sweeps_one_call_fp32_operands():
+    """Several sweeps in one call, FP32 with R = 12 (the factor QRs hand the
+    contractions their FP32 operands from the second mode on): the errors
+    equal those of one sweep per call and of the FP64 oracle (Alg. 2), and
+    the relerr entries past nsweeps are left alone (the sweep writes nothing
+    outside its workspace and its outputs)."""
+    shape, R = (40, 36, 64), 12
+    d = synth.cp_tensor(shape, R, 77, noise=1e-3, dtype=np.float32)
+    init = synth.init_factors(shape, R, 78)
+    X = d["X"]
+    st1 = C.AlsState(to_dev(X, torch.float32), init, prec=C.PREC_F32, error_mode=C.ERROR_DIRECT)
+    st1.init()
+    rel = torch.full((8,), -7.0, dtype=torch.float64, device="cuda")
+    st1.sweep(3, rel)
+    st2 = C.AlsState(to_dev(X, torch.float32), init, prec=C.PREC_F32, error_mode=C.ERROR_DIRECT)
+    st2.init()
+    h2 = [float(st2.sweep(1)[0].item()) for _ in range(3)]
+    torch.cuda.synchronize()
+    r = to_np(rel)
+    assert np.all(r[3:] == -7.0), r
+    np.testing.assert_allclose(r[:3], h2, rtol=0, atol=1e-6)
+    _, _, ho = OQ.cp_als_qr(X.astype(np.float64), init, maxiters=3, error="direct")
+    np.testing.assert_allclose(r[:3], ho, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(to_np(st1.lam), to_np(st2.lam), rtol=1e-5, atol=0)
