@@ -1563,6 +1563,10 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
   const size_t lds = LDS_FLOATS * sizeof(float);
   if (s.kind == K_MFMA_M) {
     constexpr int UN = 2, MG = 4;
+    // an input well past the last-level cache (256 MB) streams like the
+    // tensor itself: non-temporal row tiles (e.g. the 1 GB mode-3 result at
+    // 200^4 rank 32 that the next contraction reads once)
+    const bool cold = s.P * s.K * s.S * int64_t(sizeof(float)) > (int64_t(256) << 20);
     const dim3 grd(unsigned(ceil_div(ceil_div(s.P * s.S, 64 * s.mg), NWV)), unsigned(s.splits));
     const bool one = s.kchunk <= (LDS_FLOATS / RP) / (4 * UN) * (4 * UN);  // K range fits in LDS
     if (s.mg == 1) {
@@ -1581,7 +1585,7 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
       return check_launch("ttm_mfma_m");
     }
     if (s.mg == 2 && NB == 2) {  // two 16-column blocks: 2 x 64-row tiles
-      const bool nt2 = STREAM && s.P % 32 == 0;
+      const bool nt2 = (STREAM || cold) && s.P % 32 == 0;
       if (one && nt2)
         launch_ev(ke, ttm_mfma_m<2, UN, 2, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                   s.P, s.K, s.S, R, s.kchunk, s.out_count);
@@ -1608,7 +1612,7 @@ int launch_mfma_t(const float* src, const float* U, float* dst, const Step& s, i
                   src, U, dst, s.P, s.K, s.S, R);
       return check_launch("ttm_slab_m");
     }
-    const bool nt = STREAM && s.P % 32 == 0;  // see ldx
+    const bool nt = (STREAM || cold) && s.P % 32 == 0;  // see ldx
     if (one && nt)
       launch_ev(ke, ttm_mfma_m<1, UN, MG, NWV, STREAM, true, true>, grd, dim3(NWV * 64), lds, st, src, U, dst,
                 s.P, s.K, s.S, R, s.kchunk, s.out_count);
@@ -1777,7 +1781,13 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
   const bool f64 = prec == CPQR_PREC_F64;
   const bool fused = fused_pair(pl, prec, streams_tensor, x_aligned);
 
-  // operand preparation (skipped for operands the caller already holds)
+  // operand preparation, skipped for operands the caller already holds
+  // except those of the launch that streams the tensor: the short
+  // preparation launches ahead of it let work on a second stream (the
+  // sweep's Khatri-Rao QR) take compute units before the streaming kernel's
+  // thousands of workgroups fill them (200^4 rank 32: without them the QR's
+  // first level stretched over the whole 1.5 ms launch and its later levels
+  // landed on the critical path, +60..130 us per sweep)
   const void* Uk[CPQR_MAX_MODES];
   for (int k = 0; k < N; ++k) Uk[k] = b.U[k];
   for (int t = 0; t < pl.nsteps; ++t) {
@@ -1785,7 +1795,9 @@ int multittm_general_enqueue(int N, const int64_t* I, int xdtype, const void* X,
     const int64_t cnt = s.K * RP;
     const dim3 grd(unsigned(ceil_div(cnt, 256)));
     const bool quads = !f64 && s.kind == K_MFMA_K && prec == CPQR_PREC_F32 && !(fused && t == 1);
-    const float* pre = (uc && !f64 && uc->RP == RP) ? (quads ? uc->quads[s.k] : uc->rows[s.k]) : nullptr;
+    const bool streaming = streams_tensor && (t == 0 || (fused && t == 1));
+    const float* pre = (uc && !f64 && uc->RP == RP && !streaming) ? (quads ? uc->quads[s.k] : uc->rows[s.k])
+                                                                   : nullptr;
     if (pre) {
       Uk[s.k] = pre;
       continue;
