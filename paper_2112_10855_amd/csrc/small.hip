@@ -132,6 +132,96 @@ __global__ __launch_bounds__(BLK) void apply_q0_tile(const TY* __restrict__ Y, c
   }
 }
 
+// The same long-K product on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// a workgroup of eight wavefronts forms 128 rows x 16 NB columns of one
+// split's partial.  Wavefront w owns rows 16 w .. 16 w + 15 of the 128: its
+// A operand is Y (widened to FP64), lane (l16, kq) holding row l16 of K-row
+// kq of a step; the B operand is Q_0, 64 rows at a time in one of two LDS
+// buffers.  The next block's Y (in registers) and Q_0 (in registers, then
+// LDS) are loaded while the current block is multiplied, so each block waits
+// for loads issued one block earlier.  The MFMA leaves row kq + 4 v of its
+// 16 x 16 result in value v of lane (l16, kq).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <class TY, int NB>
+__global__ __launch_bounds__(512) void apply_q0_mfma(const TY* __restrict__ Y, const double* __restrict__ Q0,
+                                                     double* __restrict__ part, int64_t In, int64_t K, int R,
+                                                     int64_t kchunk) {
+  constexpr int RMP = 16 * NB, KB = 64, NT = 512, QPT = KB * RMP / NT;
+  __shared__ double qs[2][KB][RMP];
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64, l16 = lane % 16, kq = lane / 16;
+  const int64_t r0 = int64_t(blockIdx.x) * 128 + 16 * w;  // first row of the wavefront's block
+  const int64_t i = r0 + l16;
+  const bool irow = i < In;
+  const int64_t k0 = int64_t(blockIdx.y) * kchunk, k1 = min(K, k0 + kchunk);
+  doublex4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = doublex4{0.0, 0.0, 0.0, 0.0};
+  // rows past k1 (or past the block's end) read as zeros, without a memory request
+  auto load_y = [&](TY(&dst)[KB / 4], int64_t kb) {
+#pragma unroll
+    for (int st = 0; st < KB / 4; ++st) {
+      const int64_t k = kb + 4 * st + kq;
+      dst[st] = (irow && k < k1) ? Y[i + k * In] : TY(0);
+    }
+  };
+  auto load_q = [&](double(&dst)[QPT], int64_t kb) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      const int e = tid + u * NT, kk = e % KB, c = e / KB;
+      const int64_t k = kb + kk;
+      dst[u] = (c < R && k < k1) ? Q0[k + int64_t(c) * K] : 0.0;
+    }
+  };
+  auto store_q = [&](const double(&src)[QPT], int b) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      const int e = tid + u * NT;
+      qs[b][e % KB][e / KB] = src[u];
+    }
+  };
+  auto mult = [&](const TY(&ya)[KB / 4], int b) {
+#pragma unroll
+    for (int st = 0; st < KB / 4; ++st) {
+      const double a = double(ya[st]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, qs[b][4 * st + kq][16 * nb + l16], acc[nb], 0, 0, 0);
+    }
+  };
+  TY ya0[KB / 4], ya1[KB / 4];
+  double qv[QPT];
+  load_y(ya0, k0);
+  load_q(qv, k0);
+  store_q(qv, 0);
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += 2 * KB) {
+    // block kb (LDS buffer 0, ya0) is ready; fetch block kb + KB meanwhile
+    load_y(ya1, kb + KB);
+    load_q(qv, kb + KB);
+    mult(ya0, 0);
+    store_q(qv, 1);
+    __syncthreads();
+    if (kb + KB >= k1) break;  // uniform
+    // block kb + KB (buffer 1, ya1) is ready; fetch block kb + 2 KB meanwhile
+    load_y(ya0, kb + 2 * KB);
+    load_q(qv, kb + 2 * KB);
+    mult(ya1, 1);
+    store_q(qv, 0);
+    __syncthreads();
+  }
+  double* o = part + int64_t(blockIdx.y) * In * R;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int c = 16 * nb + l16;
+    if (c >= R) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t ii = r0 + kq + 4 * v;
+      if (ii < In) o[ii + int64_t(c) * In] = acc[nb][v];
+    }
+  }
+}
+
 // Kernel choice and split of the apply-Q_0 sum: the tiled product once K
 // exceeds 1024, with about 1024 workgroups and at most 128 splits.
 struct ApplyPlan {
@@ -603,6 +693,19 @@ ApplyPlan apply_plan(int64_t In, int64_t K, int R) {
 void launch_apply(const ApplyPlan& ap, int64_t In, int64_t K, int R, int ydtype, const void* Y, const double* Q0,
                   double* out, hipStream_t s) {
   const int RM = round_rank(R);
+  if (ap.tiled && RM >= 16) {  // FP64 matrix cores, 128 rows per workgroup
+    const dim3 grd(unsigned(ceil_div(In, 128)), unsigned(ap.splits));
+#define APPLYM(TY, NBV)                                                                                     \
+  hipLaunchKernelGGL((apply_q0_mfma<TY, NBV>), grd, dim3(512), 0, s, static_cast<const TY*>(Y), Q0, out, In, K, R, \
+                     ap.kchunk)
+    if (ydtype == CPQR_F64) {
+      if (RM == 16) APPLYM(double, 1); else APPLYM(double, 2);
+    } else {
+      if (RM == 16) APPLYM(float, 1); else APPLYM(float, 2);
+    }
+#undef APPLYM
+    return;
+  }
   if (ap.tiled) {
     const dim3 grd(unsigned(ceil_div(In, 64)), unsigned(ap.splits));
 #define APPLYT(TY, RMV)                                                                                    \
