@@ -164,6 +164,7 @@ struct AlsWs {
   void* krp_sub;  // scratch of the Khatri-Rao QR, which runs beside the Multi-TTM
   void* Wt;       // X contracted over one half of the modes (dimension-tree reuse)
   double* err_part;  // partial sums of the efficient error (side stream)
+  double* Tmid;      // the chain's last-but-one triangle, kept between the split chain's parts
   // FP32 contraction operands of each Q_k written by its normalizing factor
   // QR (rows and four-row layouts; null where not kept), padding urp (0: none)
   float* ur[CPQR_MAX_MODES];
@@ -232,8 +233,12 @@ size_t krp_chain_work(int R) {
   return cv.bytes();
 }
 
-int krp_chain_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
-                      void* work, hipStream_t s) {
+// Steps [j0, j1) of the chain (1 <= j0 < j1 <= N - 1): step j factors
+// R_{a_j} (.) T_{j-1} (T_0 = R_{a_0}; T_{j0-1} read from tkeep when j0 > 1).
+// T_{j1-1} goes to tkeep when the chain goes on (j1 < N - 1), else to R0; so
+// a chain can be split where its later factors are not final yet.
+int krp_chain_steps(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
+                    double* tkeep, int j0, int j1, void* work, hipStream_t s) {
   Carver cv(work);
   double* T[2] = {cv.take<double>(size_t(R) * R), cv.take<double>(size_t(R) * R)};
   double* F[2] = {cv.take<double>(size_t(R) * R), cv.take<double>(size_t(R) * R)};
@@ -252,17 +257,22 @@ int krp_chain_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr,
     *out = buf;
     return CPQR_OK;
   };
-  const double* t = nullptr;
-  CPQR_TRY(packed(Rk[a[0]], F[0], &t));
-  for (int j = 1; j < na; ++j) {
+  const double* t = tkeep;
+  if (j0 == 1) CPQR_TRY(packed(Rk[a[0]], F[0], &t));
+  for (int j = j0; j < j1; ++j) {
     const double* f = nullptr;
     CPQR_TRY(packed(Rk[a[j]], F[1], &f));
-    double* tout = j == na - 1 ? R0 : T[j % 2];
+    double* tout = j == na - 1 ? R0 : (j == j1 - 1 ? tkeep : T[j % 2]);
     const double* fac[3] = {t, f, nullptr};  // R_{a_j} (.) T_{j-1}, T's index fastest
     CPQR_TRY(krp_qr_enqueue(3, 2, R, fac, R, Qc + size_t(j - 1) * R * R * R, tout, qw, s));
     t = tout;
   }
   return CPQR_OK;
+}
+
+int krp_chain_enqueue(int N, int n, int R, const double* const* Rk, int64_t ldr, double* Qc, double* R0,
+                      void* work, hipStream_t s) {
+  return krp_chain_steps(N, n, R, Rk, ldr, Qc, R0, nullptr, 1, N - 1, work, s);
 }
 
 // W = Y_(n) Q_0 with Q_0 = (I kron Q_2) .. Q_{N-1}: step j contracts the two
@@ -409,6 +419,7 @@ size_t als_carve(Carver& cv, const cpqr_problem* p, AlsWs* ws) {
   w.krp_sub = cv.take<char>(std::max(tsqr_work(K, R), krp_chain_work(R)));
   w.Wt = cv.take<double>(size_t(dt_elems(p)));  // sized for FP64
   w.err_part = cv.take<double>(error_efficient_work(p->I[N - 1]) / sizeof(double));
+  w.Tmid = cv.take<double>(size_t(R) * R);
   // the FP32 operands need the factor QR's padded rank to equal the
   // contraction kernels' column padding (R > 8)
   const int rp = (R + 15) / 16 * 16;
@@ -1084,6 +1095,12 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   bool r_marked = false;  // side.ready marks the last factor QR's R
   UCache uc;  // FP32 operands of the Q_k refreshed by this call's factor QRs
   uc.RP = w.urp;
+  // With the dense Khatri-Rao QR (N >= 4), the last mode's V_N-1 is factored
+  // as a chain (section 3.3.3 structure, older factors first): its steps up
+  // to the newest factor R_{N-2} run beside the update of mode N-2, so that
+  // after that mode's factor QR only one R^2 x R QR and the expansion of Q_0
+  // remain before mode N-1 can apply Q_0.
+  const bool split = !chain && N >= 4;
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
       // Khatri-Rao QR (reads R_k) on the side stream, Multi-TTM (reads Q_k)
@@ -1094,9 +1111,15 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       if (chain) {  // structured QR, then Q_0 formed from its factors (both on the side stream)
         CPQR_TRY(krp_chain_enqueue(N, n, R, p->Rf, R, w.Qc, w.R0, w.krp_sub, side.s));
         CPQR_TRY(expand_q0_enqueue(N, R, w.Qc, w.Q0, w.Qx, side.s));
-      } else
+      } else if (split && n == N - 1) {  // the chain's last step, with the newest R, and Q_0
+        CPQR_TRY(krp_chain_steps(N, n, R, p->Rf, R, w.Qc, w.R0, w.Tmid, N - 2, N - 1, w.krp_sub, side.s));
+        CPQR_TRY(expand_q0_enqueue(N, R, w.Qc, w.Q0, w.Qx, side.s));
+      } else {
         CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
+      }
       CPQR_HIP(hipEventRecord(side.done, side.s));
+      if (split && n == N - 2)  // the last mode's chain up to its newest factor, off this mode's path
+        CPQR_TRY(krp_chain_steps(N, N - 1, R, p->Rf, R, w.Qc, w.R0, w.Tmid, 1, N - 2, w.krp_sub, side.s));
       CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s, &uc));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
       // normalization and factor QR in one launch where one workgroup takes A_n
