@@ -1099,7 +1099,10 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
   // as a chain (section 3.3.3 structure, older factors first): its steps up
   // to the newest factor R_{N-2} run beside the update of mode N-2, so that
   // after that mode's factor QR only one R^2 x R QR and the expansion of Q_0
-  // remain before mode N-1 can apply Q_0.
+  // remain before mode N-1 can apply Q_0.  For N = 4 mode 1 likewise: its
+  // newest factor R_0 is the fastest index of V_1 = R_3 (.) R_2 (.) R_0, so
+  // R_3 (.) R_2 = Q_a T_a is factored beside mode 0, and after R_0 only
+  // T_a (.) R_0 = Q_b R_0' remains, Q_0 = (Q_a kron I) Q_b.
   const bool split = !chain && N >= 4;
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (int n = 0; n < N; ++n) {
@@ -1114,12 +1117,20 @@ int cpqr_als_sweep(const cpqr_problem* p, int nsweeps, double* relerr, void* wor
       } else if (split && n == N - 1) {  // the chain's last step, with the newest R, and Q_0
         CPQR_TRY(krp_chain_steps(N, n, R, p->Rf, R, w.Qc, w.R0, w.Tmid, N - 2, N - 1, w.krp_sub, side.s));
         CPQR_TRY(expand_q0_enqueue(N, R, w.Qc, w.Q0, w.Qx, side.s));
+      } else if (split && N == 4 && n == 1) {  // (Q_a T_a) (.) R_0 = (Q_a kron I)(T_a (.) R_0)
+        const double* fac[3] = {p->Rf[0], w.Tmid, nullptr};  // R_0's index fastest
+        CPQR_TRY(krp_qr_enqueue(3, 2, R, fac, R, w.Qc + size_t(R) * R * R, w.R0, w.krp_sub, side.s));
+        CPQR_TRY(expand_kron_right_enqueue(R, w.Qc, w.Qc + size_t(R) * R * R, w.Q0, side.s));
       } else {
         CPQR_TRY(krp_qr_enqueue(N, n, R, p->Rf, R, w.Q0, w.R0, w.krp_sub, side.s));
       }
       CPQR_HIP(hipEventRecord(side.done, side.s));
       if (split && n == N - 2)  // the last mode's chain up to its newest factor, off this mode's path
         CPQR_TRY(krp_chain_steps(N, N - 1, R, p->Rf, R, w.Qc, w.R0, w.Tmid, 1, N - 2, w.krp_sub, side.s));
+      if (split && N == 4 && n == 0) {  // mode 1's V = R_3 (.) R_2 (.) R_0: the older part R_3 (.) R_2 = Q_a T_a
+        const double* fac[3] = {p->Rf[2], p->Rf[3], nullptr};  // R_2's index fastest
+        CPQR_TRY(krp_qr_enqueue(3, 2, R, fac, R, w.Qc, w.Tmid, w.krp_sub, side.s));
+      }
       CPQR_TRY(ttm_for_mode(p, h, n, p->Q, w.Y, w.Wt, w.sub, s, &uc));
       CPQR_HIP(hipStreamWaitEvent(s, side.done, 0));
       // normalization and factor QR in one launch where one workgroup takes A_n

@@ -156,6 +156,8 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
 // Q_0 (R^{N-1} x R) formed from the factors of the structured QR of V_n
 // (Qc: Q_2 .. Q_{N-1}, each R^2 x R); buf holds 2 R^{N-1} R doubles (N >= 5)
 int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, hipStream_t s);
+// Q_0 = (Q_a kron I_R) Q_b (both R^2 x R, column-major), Q_0 R^3 x R.
+int expand_kron_right_enqueue(int R, const double* Qa, const double* Qb, double* Q0, hipStream_t s);
 // W (In x R, FP64) = the columns of Y_(n) (In x R^{N-1}) whose every Kronecker
 // index is r (the MTTKRP part of a Multi-TTM)
 int diag_cols_enqueue(int64_t In, int N, int R, int ydtype, const void* Y, double* W, hipStream_t s);

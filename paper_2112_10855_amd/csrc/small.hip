@@ -1083,6 +1083,29 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
   return check_launch("error_efficient_final");
 }
 
+// Q_0 = (Q_a kron I_R) Q_b for Q_a (R^2 x R) and Q_b (R^2 x R), column-major:
+// Q_0(r + R j, c) = sum_t Q_a(j, t) Q_b(r + R t, c), r < R, j < R^2, c < R (the
+// orthonormal factor of (Q_a T) (.) F = (Q_a kron I)(T (.) F) once
+// T (.) F = Q_b T_b).  One thread per entry of Q_0.
+__global__ __launch_bounds__(BLK) void expand_kron_right_kernel(const double* __restrict__ Qa,
+                                                                const double* __restrict__ Qb, int R,
+                                                                double* __restrict__ Q0) {
+  const int64_t R2 = int64_t(R) * R, R3 = R2 * R;
+  const int64_t e = int64_t(blockIdx.x) * BLK + threadIdx.x;
+  if (e >= R3 * R) return;
+  const int64_t row = e % R3, c = e / R3;
+  const int64_t r = row % R, j = row / R;
+  double acc = 0.0;
+  for (int t = 0; t < R; ++t) acc += Qa[j + R2 * t] * Qb[r + R * t + R2 * c];
+  Q0[e] = acc;
+}
+
+int expand_kron_right_enqueue(int R, const double* Qa, const double* Qb, double* Q0, hipStream_t s) {
+  const int64_t cnt = int64_t(R) * R * R * R;
+  hipLaunchKernelGGL(expand_kron_right_kernel, dim3(unsigned(ceil_div(cnt, BLK))), dim3(BLK), 0, s, Qa, Qb, R, Q0);
+  return check_launch("expand_kron_right");
+}
+
 int expand_q0_enqueue(int N, int R, const double* Qc, double* Q0, double* buf, hipStream_t s) {
   const size_t blk = size_t(R) * R * R;  // doubles per factor Q_j
   if (N == 3) {
