@@ -227,23 +227,57 @@ __device__ __forceinline__ void reflect(const double (&a)[P][CW], int J, int lan
   }
 }
 
-// Compact WY factor T from sh.tau and sh.G: lane i of wavefront 0 forms row
-// i, T(i, J) = -tau_J sum_k T(i, k) G(k, J) (i < J), T(J, J) = tau_J, so
-// the lanes need no exchange.  Zero beyond R.
-template <int RMAX, int P>
-__device__ __forceinline__ void node_t(int R, int w, int lane, Shared<RMAX, P>& sh) {
-  if (w != 0 || lane >= RMAX) return;
-  double t[RMAX];
+// Compact WY factor T of columns [b, b + NC) from sh.tau and sh.G into
+// sh.T: lane i < NC forms row b + i, T(i, J) = -tau_J sum_k T(i, k) G(k, J)
+// (i < J), T(J, J) = tau_J, so the lanes need no exchange.  Zero beyond R.
+template <int NC, int RMAX, int P>
+__device__ __forceinline__ void t_block(int R, int b, int lane, Shared<RMAX, P>& sh) {
+  double t[NC];
 #pragma unroll
-  for (int J = 0; J < RMAX; ++J) {
+  for (int J = 0; J < NC; ++J) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < J; ++k) acc[k % 4] += t[k] * sh.G[k][J];
-    const double tj = J < R ? sh.tau[J] : 0.0;
+    for (int k = 0; k < J; ++k) acc[k % 4] += t[k] * sh.G[b + k][b + J];
+    const double tj = b + J < R ? sh.tau[b + J] : 0.0;
     t[J] = lane < J ? -tj * ((acc[0] + acc[1]) + (acc[2] + acc[3])) : (lane == J ? tj : 0.0);
   }
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c) sh.T[lane][c] = t[c];
+  for (int c = 0; c < NC; ++c) sh.T[b + lane][b + c] = t[c];
+}
+
+// T of the whole node (all threads call it).  For RMAX >= 16 the columns
+// split in halves, V = [V1 V2]: the product of the reflectors is
+// (I - V1 T11 V1^T)(I - V2 T22 V2^T), so T = [T11, -T11 (V1^T V2) T22; 0,
+// T22], where T11 and T22 follow the recurrence within their halves
+// (wavefronts 0 and 1 at once) and V1^T V2 is the block G(0:H, H:RMAX).
+// This halves the recurrence's dependent chain; V1^T V2 T22 goes to sh.B,
+// which is free until Q is formed.
+template <int RMAX, int P>
+__device__ __forceinline__ void node_t(int R, int w, int lane, Shared<RMAX, P>& sh) {
+  if constexpr (RMAX < 16) {
+    if (w == 0 && lane < RMAX) t_block<RMAX>(R, 0, lane, sh);
+  } else {
+    constexpr int H = RMAX / 2;
+    static_assert(RMAX / CW >= 2 && RMAX / CW * W >= H * H, "two wavefronts and H^2 threads");
+    if (w < 2 && lane < H) t_block<H>(R, w * H, lane, sh);
+    const int tid = w * W + lane;
+    const int i = tid / H, c = tid % H;
+    if (tid < H * H) sh.T[H + i][c] = 0.0;  // below the diagonal blocks
+    __syncthreads();
+    if (tid < H * H) {  // B = G(0:H, H:RMAX) T22 (T22 upper triangular)
+      double acc = 0.0;
+#pragma unroll 4
+      for (int j = 0; j <= c; ++j) acc += sh.G[i][H + j] * sh.T[H + j][H + c];
+      sh.B[i][c] = acc;
+    }
+    __syncthreads();
+    if (tid < H * H) {  // T12 = -T11 B (T11 upper triangular)
+      double acc = 0.0;
+#pragma unroll 4
+      for (int k = i; k < H; ++k) acc += sh.T[i][k] * sh.B[k][c];
+      sh.T[i][H + c] = -acc;
+    }
+  }
 }
 
 // Householder QR of the node (rows beyond it zero).  On return the
