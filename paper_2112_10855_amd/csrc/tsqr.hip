@@ -356,29 +356,32 @@ __device__ __forceinline__ void node_v1(const double (&a)[P][CW], int R, int w, 
 }
 
 // Q rows of a node: [C; 0] - V M with M = T V1^T C (C in sh.C, T in sh.T,
-// V1 in sh.V1, all visible).  The rows go to the output (leaf: Qout at
-// `start`) or, as C blocks, to children c0 ... of the stacked level S.
+// V1 in sh.V1, all visible; IDENT: C is the identity, so V1^T C is V1^T
+// and is not formed).  The rows go to the output (leaf: Qout at `start`)
+// or, as C blocks, to children c0 ... of the stacked level S.
 // A leaf may also write FP32 copies of its Q rows: urows[i RMAX + c] and
 // uquads[((i/4) RMAX + c) 4 + i%4] for global row i (zero for c >= R).
-template <bool SCALED, int RMAX, int P>
+template <bool SCALED, int RMAX, bool IDENT = false, int P>
 __device__ __forceinline__ void node_q(const double (&a)[P][CW], int R, int m, int w, int lane,
                                        Shared<RMAX, P>& sh, bool leaf, int64_t start, double* Qout, int64_t ldq,
                                        double* S, int64_t c0, float* urows = nullptr, float* uquads = nullptr) {
   constexpr int NT = RMAX / CW * W;
   const int tid = w * W + lane;
-  for (int e = tid; e < RMAX * RMAX; e += NT) {  // B = V1^T C
-    const int k = e / RMAX, c = e % RMAX;
-    double acc = 0.0;
+  if constexpr (!IDENT) {
+    for (int e = tid; e < RMAX * RMAX; e += NT) {  // B = V1^T C
+      const int k = e / RMAX, c = e % RMAX;
+      double acc = 0.0;
 #pragma unroll 8
-    for (int i = 0; i < RMAX; ++i) acc += sh.V1[i][k] * sh.C[i][c];
-    sh.B[k][c] = acc;
+      for (int i = 0; i < RMAX; ++i) acc += sh.V1[i][k] * sh.C[i][c];
+      sh.B[k][c] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < RMAX * RMAX; e += NT) {  // M = T B
+  for (int e = tid; e < RMAX * RMAX; e += NT) {  // M = T B; with C = I, B(i, c) = V1(c, i)
     const int k = e / RMAX, c = e % RMAX;
     double acc = 0.0;
 #pragma unroll 8
-    for (int i = 0; i < RMAX; ++i) acc += sh.T[k][i] * sh.B[i][c];
+    for (int i = 0; i < RMAX; ++i) acc += sh.T[k][i] * (IDENT ? sh.V1[c][i] : sh.B[i][c]);
     sh.M[k][c] = acc;
   }
   __syncthreads();
@@ -585,7 +588,7 @@ __global__ __launch_bounds__(RMAX / CW * W) void bn_root(int64_t rows, int R, co
     sh.C[i][c] = (i < R && i == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  node_q<true, RMAX>(a, R, m, w, lane, sh, top == 0, start, Qout, ldq, work + L.s, 0, urows, uquads);
+  node_q<true, RMAX, true>(a, R, m, w, lane, sh, top == 0, start, Qout, ldq, work + L.s, 0, urows, uquads);
 }
 
 // Down-sweep below the root, one launch per level: each node applies its
