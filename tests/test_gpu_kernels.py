@@ -36,7 +36,9 @@ def rng(seed):
                                  (5000, 7), (100, 1), (2000, 32), (32, 32), (4097, 12), (129, 16), (257, 16),
                                  (2048, 16), (6000, 8), (1024, 8), (64, 32), (65, 32), (20000, 16),
                                  (100000, 3), (256, 16), (1024, 16), (1025, 16), (257, 32), (70000, 16),
-                                 (70000, 32), (33000, 32)])
+                                 (70000, 32), (33000, 32),
+                                 # ranks that fill the second half of the split WY factor only in part
+                                 (64, 9), (150, 17), (300, 20), (1000, 24), (500, 31), (3000, 20)])
 def test_factor_qr(I, R):
     A = rng(I * 100 + R).standard_normal((I, R))
     Q, Rk = C.cpqr_factor_qr(to_dev(A))
