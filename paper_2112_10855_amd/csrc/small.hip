@@ -335,6 +335,89 @@ __global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict
   if (live) A[i + int64_t(c) * In] = ws[c][ri];
 }
 
+// Apply Q_0 and solve in one launch when the product is split over at most
+// KG parts of K: group g of BLK threads forms the partial of rows
+// [g kchunk, (g + 1) kchunk) of Q_0 (the split kernel's chunk, in the same
+// order), the partials meet in LDS and are added in split order, so W and A
+// are those of the split product followed by sum_solve_kernel.  The
+// solve is sum_solve_kernel's: each row's back substitution in LDS.
+template <class TY, int RM, int KG>
+__global__ __launch_bounds__(KG * BLK) void apply_solve_kernel(const TY* __restrict__ Y,
+                                                               const double* __restrict__ Q0,
+                                                               const double* __restrict__ R0, double* W,
+                                                               double* A, int64_t In, int64_t K, int R,
+                                                               int64_t kchunk, int* status) {
+  constexpr int RPB = BLK / RM, KC = 32;
+  __shared__ double q0s[KG][KC][RM + 1];
+  __shared__ double red[KG][RM][RPB + 1];
+  __shared__ double r0[RM][RM + 1];
+  __shared__ double ws[RM][RPB + 1];
+  const int g = threadIdx.x / BLK, tl = threadIdx.x % BLK;
+  const int ri = tl % RPB, c = tl / RPB;
+  const int64_t i = int64_t(blockIdx.x) * RPB + ri;
+  const bool live = i < In && c < R;
+  const int64_t k0 = int64_t(g) * kchunk, k1 = min(K, k0 + kchunk);
+  const int64_t nsteps = (kchunk + KC - 1) / KC;  // the same in every group
+  double acc = 0.0;
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int64_t t0 = k0 + st * KC;
+    const int nt = int(max<int64_t>(0, min<int64_t>(KC, k1 - t0)));
+    __syncthreads();
+    for (int e = tl; e < KC * RM; e += BLK) {
+      const int rr = e % KC, cc = e / KC;
+      q0s[g][rr][cc] = (rr < nt && cc < R) ? Q0[t0 + rr + int64_t(cc) * K] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      const TY* y = Y + i + t0 * In;
+#pragma unroll 8
+      for (int rr = 0; rr < nt; ++rr) acc += double(y[rr * In]) * q0s[g][rr][c];
+    }
+  }
+  red[g][c][ri] = acc;
+  for (int e = threadIdx.x; e < R * R; e += KG * BLK) r0[e % R][e / R] = R0[e];
+  __syncthreads();
+  if (g == 0) {
+    double w = 0.0;
+#pragma unroll
+    for (int t = 0; t < KG; ++t) w += red[t][c][ri];
+    if (live) W[i + int64_t(c) * In] = w;
+    ws[c][ri] = live ? w : 0.0;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && status) {
+    int bad = 0;
+    for (int j = 0; j < R; ++j) {
+      const double d = r0[j][j];
+      if (d == 0.0 || !isfinite(d)) bad = 1;
+    }
+    if (bad) atomicOr(status, CPQR_STATUS_SINGULAR);
+  }
+  if (threadIdx.x < RPB && i < In) {
+    double a[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) a[k] = ws[k][ri];
+#pragma unroll
+    for (int j = RM - 1; j >= 0; --j) {
+      if (j >= R) continue;
+      double v = a[j];
+#pragma unroll
+      for (int k = j + 1; k < RM; ++k)
+        if (k < R) v -= r0[j][k] * a[k];
+      a[j] = v / r0[j][j];
+    }
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      ws[k][ri] = a[k];
+      if (k < R) nonfinite |= !isfinite(a[k]);
+    }
+    if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
+  }
+  __syncthreads();
+  if (g == 0 && live) A[i + int64_t(c) * In] = ws[c][ri];
+}
+
 // One-sided Jacobi SVD of an R x R matrix B (R <= RM <= 32) in one wavefront,
 // then M = U S^+ V^T = sum over kept j of (B v_j) v_j^T / sigma_j^2, with
 // singular values <= rtol * sigma_max dropped (B = R_0: the transposed
@@ -979,10 +1062,27 @@ int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y,
     CPQR_TRY(apply_q0_enqueue(In, K, R, ydtype, Y, Q0, W, work, s));
     return solve_enqueue(In, R, W, R0, use_svd, rtol, A, lambda, status, work, s, normalize);
   }
+  const int RM = round_rank(R);
+  if (!ap.tiled && splits <= 4) {  // product and solve in one launch
+    PhaseTimer pt(PH_SOLVE, s);
+    const dim3 grd(unsigned(ceil_div(In, BLK / RM)));
+#define APSOLVE(TY, RMV)                                                                                   \
+  hipLaunchKernelGGL((apply_solve_kernel<TY, RMV, 4>), grd, dim3(4 * BLK), 0, s, static_cast<const TY*>(Y), Q0, R0, \
+                     W, A, In, K, R, ap.kchunk, status)
+    if (ydtype == CPQR_F64) {
+      if (RM == 8) APSOLVE(double, 8); else if (RM == 16) APSOLVE(double, 16); else APSOLVE(double, 32);
+    } else {
+      if (RM == 8) APSOLVE(float, 8); else if (RM == 16) APSOLVE(float, 16); else APSOLVE(float, 32);
+    }
+#undef APSOLVE
+    CPQR_TRY(check_launch("apply_solve"));
+    if (!normalize) return CPQR_OK;
+    hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
+    return check_launch("normalize");
+  }
   // the solve adds up the partial W's itself (one kernel fewer)
   Carver cv(work);
   double* part = cv.take<double>(size_t(splits) * In * R);
-  const int RM = round_rank(R);
   {
     PhaseTimer pt(PH_APPLY_Q0, s);
     launch_apply(ap, In, K, R, ydtype, Y, Q0, part, s);
