@@ -793,7 +793,8 @@ def main():
         },
         "multittm_gbps": round(mt_gbs, 1),
         "phases_ms_per_sweep": {k: round(v[0] / nb, 4) for k, v in phases.items()},
-        "phases_note": "separate pass of %d sweeps with events between phases (slower than the timed sweeps)" % nb,
+        "phases_note": ("separate pass of %d sweeps with events between phases (slower than the timed sweeps); "
+                        "where one launch forms the apply-Q_0 product and solves, its time is under solve") % nb,
         "timed_region": ("one HIP graph launch of the %d sweeps (cpqr_als_graph_create); the dominant kernel's "
                          "launches timed by dispatch events on an eager pass of the same sweeps right after"
                          % args.steps) if args.graph else "eager sweeps; the dominant kernel by events attached to "
