@@ -282,25 +282,34 @@ __global__ __launch_bounds__(BLK) void solve_tri_kernel(const double* __restrict
 // (row, column) of W adds up that entry's partials (stride In R) and stores
 // W; each row's back substitution then reads its W row from LDS, and the
 // solved rows leave through LDS so that the stores of A stay coalesced.
-template <int RM>
-__global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict__ part, int splits,
-                                                        const double* __restrict__ R0, double* W,
-                                                        double* A, int64_t In, int R, int* status) {
+template <int RM, int KG = 1>
+__global__ __launch_bounds__(KG * BLK) void sum_solve_kernel(const double* __restrict__ part, int splits,
+                                                             const double* __restrict__ R0, double* W,
+                                                             double* A, int64_t In, int R, int* status) {
   constexpr int RPB = BLK / RM;
   __shared__ double r0[RM][RM + 1];
   __shared__ double ws[RM][RPB + 1];
-  for (int e = threadIdx.x; e < R * R; e += BLK) r0[e % R][e / R] = R0[e];
-  const int ri = threadIdx.x % RPB, c = threadIdx.x / RPB;
+  __shared__ double red[KG][RM][RPB + 1];
+  for (int e = threadIdx.x; e < R * R; e += KG * BLK) r0[e % R][e / R] = R0[e];
+  const int g = threadIdx.x / BLK, tl = threadIdx.x % BLK;  // KG groups of BLK threads
+  const int ri = tl % RPB, c = tl / RPB;
   const int64_t i = int64_t(blockIdx.x) * RPB + ri;
   const bool live = i < In && c < R;
+  const int64_t e = i + int64_t(c) * In;
   double w = 0.0;
-  if (live) {
-    const int64_t e = i + int64_t(c) * In;
+  if (live) {  // group g adds partials g, g + KG, ...; one group adds them all in order
 #pragma unroll 8
-    for (int t = 0; t < splits; ++t) w += part[int64_t(t) * In * R + e];
-    W[e] = w;
+    for (int t = g; t < splits; t += KG) w += part[int64_t(t) * In * R + e];
   }
-  ws[c][ri] = w;
+  red[g][c][ri] = w;
+  __syncthreads();
+  if (g == 0) {
+    double sum = red[0][c][ri];
+#pragma unroll
+    for (int u = 1; u < KG; ++u) sum += red[u][c][ri];
+    if (live) W[e] = sum;
+    ws[c][ri] = sum;
+  }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0 && status) {
     int bad = 0;
@@ -332,7 +341,7 @@ __global__ __launch_bounds__(BLK) void sum_solve_kernel(const double* __restrict
     if (nonfinite && status) atomicOr(status, CPQR_STATUS_NONFINITE);
   }
   __syncthreads();
-  if (live) A[i + int64_t(c) * In] = ws[c][ri];
+  if (g == 0 && live) A[i + int64_t(c) * In] = ws[c][ri];
 }
 
 // Apply Q_0 and solve in one launch when the product is split over at most
@@ -1090,12 +1099,16 @@ int apply_solve_enqueue(int64_t In, int64_t K, int R, int ydtype, const void* Y,
   }
   PhaseTimer pt(PH_SOLVE, s);
   const dim3 grd(unsigned(ceil_div(In, BLK / RM)));
-  if (RM == 8)
-    hipLaunchKernelGGL((sum_solve_kernel<8>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
-  else if (RM == 16)
-    hipLaunchKernelGGL((sum_solve_kernel<16>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
-  else
-    hipLaunchKernelGGL((sum_solve_kernel<32>), grd, dim3(BLK), 0, s, part, int(splits), R0, W, A, In, R, status);
+  // many partials per entry (the tiled product over a long K): four groups add them
+#define SUMSOLVE(RMV, KGV)                                                                                  \
+  hipLaunchKernelGGL((sum_solve_kernel<RMV, KGV>), grd, dim3(KGV * BLK), 0, s, part, int(splits), R0, W, A, In, R, \
+                     status)
+  if (splits >= 8) {
+    if (RM == 8) SUMSOLVE(8, 4); else if (RM == 16) SUMSOLVE(16, 4); else SUMSOLVE(32, 4);
+  } else {
+    if (RM == 8) SUMSOLVE(8, 1); else if (RM == 16) SUMSOLVE(16, 1); else SUMSOLVE(32, 1);
+  }
+#undef SUMSOLVE
   CPQR_TRY(check_launch("sum_solve"));
   if (!normalize) return CPQR_OK;
   hipLaunchKernelGGL(normalize_kernel, dim3(R), dim3(BLK), 0, s, A, lambda, In, status);
