@@ -1198,8 +1198,8 @@ int error_efficient_enqueue(int64_t In, int R, const double* W, const double* A,
 
 // Q_0 = (Q_a kron I_R) Q_b for Q_a (R^2 x R) and Q_b (R^2 x R), column-major:
 // Q_0(r + R j, c) = sum_t Q_a(j, t) Q_b(r + R t, c), r < R, j < R^2, c < R (the
-// orthonormal factor of (Q_a T) (.) F = (Q_a kron I)(T (.) F) once
-// T (.) F = Q_b T_b).  One thread per entry of Q_0.
+// orthonormal factor of (Q_a T) (.) F = (Q_a kron I)(T (.) F), eq. (kr-id),
+// once T (.) F = Q_b T_b).  One thread per entry of Q_0.
 __global__ __launch_bounds__(BLK) void expand_kron_right_kernel(const double* __restrict__ Qa,
                                                                 const double* __restrict__ Qb, int R,
                                                                 double* __restrict__ Q0) {
